@@ -1,0 +1,190 @@
+/*
+ * gvof.h -- C interface of the MI355X library for unsplit geometric VOF
+ * advection with LSGIR reconstruction and face-matched (FMFPA) flux polyhedra.
+ *
+ * Method: J. Lopez and J. Hernandez, "gVOF: An open-source package for
+ * unsplit geometric volume of fluid methods on arbitrary grids",
+ * arXiv 2111.01524.  Section and equation names below refer to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: every int-returning call returns GVOF_OK (0) or a negative
+ *    GVOF_E_* code; gvof_last_error() then holds a message.  Argument and mesh
+ *    errors are detected on the host before anything is enqueued.  Geometry
+ *    failures found on the device (a flux polyhedron whose apex cannot be
+ *    placed) set a sticky flag read by gvof_status() after the stream has
+ *    been synchronised.
+ *  - Memory: arrays passed to gvof_mesh_create are HOST arrays, copied.  All
+ *    per-call arrays are DEVICE pointers owned by the caller; the library
+ *    never retains them past the call's stream-ordered work.  Vectors are
+ *    structure-of-arrays: component k of item i at [k * count + i].
+ *  - Device memory of a mesh: the library allocates none.  The caller queries
+ *    gvof_mesh_workspace_bytes() and passes one device buffer of at least that
+ *    size (256-byte aligned) to gvof_mesh_bind(); it must outlive the mesh.
+ *  - Ordering: every call enqueues on the stream given to gvof_mesh_bind()
+ *    (or gvof_set_stream()) and returns without synchronising, except the
+ *    calls documented as synchronous.  A handle is not thread-safe.
+ *  - Precision: all floating point is IEEE FP64.
+ */
+#ifndef GVOF_H
+#define GVOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GVOF_OK = 0,
+  GVOF_E_ARG = -1,     /* bad argument (null pointer, size, order of calls) */
+  GVOF_E_MESH = -2,    /* mesh fails validation */
+  GVOF_E_NOMEM = -3,   /* workspace too small */
+  GVOF_E_HIP = -4,     /* HIP runtime error */
+  GVOF_E_GEOM = -5,    /* device-detected geometric failure (sticky, see gvof_status) */
+  GVOF_E_LIMIT = -6    /* a mesh entity exceeds a compiled-in capacity */
+};
+
+/* Flags for gvof_params.flags */
+#define GVOF_FLAG_NONE 0u
+
+typedef struct gvof_params {
+  double eps;         /* volume-fraction tolerance (Sec. "Interface reconstruction"); 1e-12 as in all tests */
+  double beta;        /* LSGIR weight exponent of Eq. (lsgir-beta); 1.5 */
+  double fmfpa_degen; /* FMFPA: two lateral planes count as parallel when |d|^2 <= degen |m1|^2 |m2|^2; 1e-12 */
+  uint32_t flags;     /* GVOF_FLAG_* */
+} gvof_params;
+
+/* Fills the defaults quoted above. */
+void gvof_params_default(gvof_params* p);
+
+typedef struct gvof_mesh gvof_mesh;
+
+/*
+ * Mesh (Sec. "Grid construction"): nv vertices; nf planar polygonal faces,
+ * face f having vertices fv_idx[fv_ptr[f] .. fv_ptr[f+1]-1] ordered
+ * counter-clockwise seen from outside its owner cell; owner[f] in [0, nc),
+ * neigh[f] in [0, nc) or -1 on the domain boundary.  Faces with 3 vertices
+ * are used as they are; larger polygons are fanned from their vertex mean.
+ *
+ * Validates (ranges, >= 3 and <= GVOF_MAX_FACE_VERTS vertices per face,
+ * owner != neigh) and builds the topology on the host: cell -> face lists,
+ * cell -> vertex lists, vertex -> cell lists and the vertex-sharing neighbour
+ * list of every cell (the paper's neigbcell).  Closedness and positive
+ * volumes are checked on the device by gvof_mesh_bind.  All arrays are
+ * host memory, copied; on failure *out is NULL and the status says why.
+ */
+#define GVOF_MAX_FACE_VERTS 8
+int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double* vy, const double* vz,
+                     int32_t nf, const int32_t* fv_ptr, const int32_t* fv_idx, const int32_t* owner,
+                     const int32_t* neigh, int32_t nc, const gvof_params* params);
+
+/* Bytes of device workspace the mesh needs (geometry, topology, per-step state). */
+int gvof_mesh_workspace_bytes(const gvof_mesh* m, size_t* bytes);
+
+/*
+ * Uploads the mesh into dev_workspace (device pointer, >= workspace bytes,
+ * 256-byte aligned), computes the grid geometry on the device (the paper's
+ * compgrid: face area vectors and vertex means, cell volumes, vertex means,
+ * enclosing boxes) and checks that every cell is closed and has positive
+ * volume.  `stream` is a hipStream_t (NULL = default stream).  Synchronous.
+ */
+int gvof_mesh_bind(gvof_mesh* m, void* dev_workspace, size_t ws_bytes, void* stream);
+
+/* Changes the stream later calls enqueue on. */
+int gvof_set_stream(gvof_mesh* m, void* stream);
+
+void gvof_mesh_destroy(gvof_mesh* m);
+
+/* Counts of the mesh: nv, nf, nc, and the largest vertex-neighbour list. */
+int gvof_mesh_sizes(const gvof_mesh* m, int32_t* nv, int32_t* nf, int32_t* nc, int32_t* max_neigh);
+
+/*
+ * Copies the device-computed geometry into caller device buffers (any may be
+ * NULL): S (3 x nf) face area vectors = 1/2 sum (x_i - c) x (x_{i+1} - c),
+ * fc (3 x nf) face vertex means, V (nc) cell volumes, cc (3 x nc) cell vertex
+ * means, bbmin/bbmax (3 x nc) enclosing boxes, isbox (nc) 1 for axis-aligned
+ * box cells.
+ */
+int gvof_get_geometry(gvof_mesh* m, double* S, double* fc, double* V, double* cc, double* bbmin,
+                      double* bbmax, int8_t* isbox);
+
+/*
+ * Refinement initialisation (Sec. "Fluid volume fraction initialization"):
+ * F_out (device, nc) receives the fraction of every cell inside the body.
+ * Each cell's enclosing box is split into n_div^3 sub-boxes; a sub-box with
+ * all 8 corners inside counts its part inside the cell whole, one with none
+ * inside counts nothing, and a mixed one counts its part inside the cell and
+ * on the inner side of the body's tangent plane at the sub-box centre.
+ * Cells whose vertices are all inside are full; cells whose vertices are all
+ * outside and whose box misses the body are empty.
+ */
+typedef struct gvof_shape {
+  int32_t kind;     /* GVOF_SHAPE_SPHERE: p = (cx, cy, cz, r); GVOF_SHAPE_PLANE: inside n.x + C >= 0, p = (nx, ny, nz, C) */
+  double p[4];
+} gvof_shape;
+#define GVOF_SHAPE_SPHERE 0
+#define GVOF_SHAPE_PLANE 1
+int gvof_init_fraction(gvof_mesh* m, const gvof_shape* shape, int32_t n_div, double* F_out);
+
+/*
+ * Reconstruction (Sec. "Interface reconstruction", Sec. "Grid tagging"):
+ *  1. node values F* by inverse-distance weighting (weights 1/|x_v - x_c|^2)
+ *     of the cells sharing the node, node tags, face tags, cell tags, all in
+ *     {-1, 0, 1} with tolerance eps;
+ *  2. cut-off of F in place: F < eps -> 0, F > 1 - eps -> 1;
+ *  3. for every cell tagged 0: LSGIR normal n = grad F / |grad F| with grad F
+ *     the weighted least-squares solution of Eqs. (lsgir1), (lsgir2),
+ *     (lsgir-beta) over the vertex-sharing neighbours, and the constant C of
+ *     the PLIC plane n.x + C = 0 (Eq. plic-eq), fluid on n.x + C >= 0, such
+ *     that the fluid part of the cell has volume F V.
+ * F_inout (device, nc) in: fractions, out: cut-off fractions.  Optional
+ * device outputs (may be NULL): cell_tag_out (nc), plane_out (4 x nc: nx, ny,
+ * nz, C; zero for cells not tagged 0).  The tags and planes are also kept in
+ * the workspace for the next gvof_advect_step.
+ */
+int gvof_reconstruct(gvof_mesh* m, double* F_inout, int8_t* cell_tag_out, double* plane_out);
+
+/*
+ * Tags and node values of the last reconstruction into caller device buffers
+ * (any may be NULL): node_value (nv), node_tag (nv), face_tag (nf), cell_tag (nc).
+ */
+int gvof_get_tags(gvof_mesh* m, double* node_value, int8_t* node_tag, int8_t* face_tag, int8_t* cell_tag);
+
+/*
+ * Advection step (Sec. "Fluid advected through cell faces"):
+ *  - V_d = dt u_f . S_f per face (Eq. a-donacion, u_f the face velocity at
+ *    t^{n+1/2}); upwind cell = owner if V_d >= 0 else neighbour (-1 outside);
+ *  - V_F per face: 0 for faces tagged -1 and for inflow boundary faces; V_d
+ *    for faces tagged 1; otherwise the signed fluid volume of the FMFPA flux
+ *    polyhedron (Sec. "Face-matched flux polyhedron") built from the vertex
+ *    velocities u_vert, truncated by the PLIC half-spaces of the cells it
+ *    overlaps (candidates: the owner, the neighbour and every cell sharing a
+ *    vertex with either);
+ *  - F_out = Eq. (fnext) with the face sums over each cell, clamped to [0, 1].
+ * u_face (3 x nf), u_vert (3 x nv), F_in, F_out (nc): device.  F_out may alias
+ * F_in.  Optional device outputs (may be NULL): upwind_out (nf, int32),
+ * vd_out (nf), vf_out (nf).  Needs a preceding gvof_reconstruct (it uses the
+ * tags and planes made there).  dt must be finite; a negative dt advects
+ * with the velocity reversed.
+ */
+int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, double dt, const double* F_in,
+                     double* F_out, int32_t* upwind_out, double* vd_out, double* vf_out);
+
+/*
+ * Number of interfacial cells and of faces needing flux polyhedra in the last
+ * reconstruction / advection.  Synchronous (reads two device counters).
+ */
+int gvof_interface_counts(gvof_mesh* m, int32_t* n_cells, int32_t* n_faces);
+
+/* Synchronises the stream and returns GVOF_OK or the sticky GVOF_E_GEOM. */
+int gvof_status(gvof_mesh* m);
+
+/* Message of the last error on this handle (or of the last failed create when m is NULL). */
+const char* gvof_last_error(const gvof_mesh* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GVOF_H */

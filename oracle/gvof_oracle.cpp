@@ -99,12 +99,29 @@ inline V3 cut_point(V3 pin, real sin_, V3 pout, real sout) {
   return pin + t * (pout - pin);
 }
 
+// Signed distances within a few rounding errors of zero count as exactly on
+// the plane: a face that lies on the plane in exact arithmetic then neither
+// cuts off a sliver nor produces a degenerate cap (the rounding-level sliver
+// it would remove has volume far below the parity tolerance).
+real snap_tol(const Poly& P, V3 n, real d) {
+  real scale = 0.0;
+  for (auto& f : P.faces)
+    for (auto& p : f) scale = std::max(scale, std::max(fabs(p.x), std::max(fabs(p.y), fabs(p.z))));
+  return real(4e-15) * (sqrt(dot(n, n)) * scale + fabs(d));
+}
+
+inline real sdist(V3 n, real d, V3 p, real tol) {
+  real s = dot(n, p) + d;
+  return fabs(s) <= tol ? real(0.0) : s;
+}
+
 // Keep the part of P where n.x + d >= 0.
 void clip(Poly& P, V3 n, real d) {
+  real tol = snap_tol(P, n, d);
   bool any_in = false, any_out = false;
   for (auto& f : P.faces)
     for (auto& p : f) {
-      real s = dot(n, p) + d;
+      real s = sdist(n, d, p, tol);
       if (s > real(0.0)) any_in = true;
       if (s < real(0.0)) any_out = true;
     }
@@ -117,7 +134,7 @@ void clip(Poly& P, V3 n, real d) {
     size_t k = f.size();
     for (size_t i = 0; i < k; ++i) {
       V3 a = f[i], b = f[(i + 1) % k];
-      real sa = dot(n, a) + d, sb = dot(n, b) + d;
+      real sa = sdist(n, d, a, tol), sb = sdist(n, d, b, tol);
       bool ia = sa >= real(0.0), ib = sb >= real(0.0);
       if (ia) {
         g.push_back(a);

@@ -1,0 +1,198 @@
+// Exact volume of a tetrahedron clipped by a convex container (an axis-aligned
+// box or another tetrahedron) and optionally by one more half-space.
+//
+// The container's planes are applied by splitting: a tetrahedron cut by a
+// plane keeps one tetrahedron (one vertex on the kept side), three (three
+// vertices kept: a truncated prism) or three (two kept: a wedge).  Only the
+// planes that cut the original tetrahedron are visited, depth first, with an
+// explicit stack.  The last half-space is not split at all: every leaf adds
+// its closed-form kept fraction (halfspace_fraction).
+#pragma once
+#include "gvof_dev.h"
+
+namespace gvof {
+
+struct BoxCont {
+  d3 lo, hi;
+  static constexpr int np = 6;
+  // plane l: axis l/2, l even -> x_a - lo_a >= 0, l odd -> hi_a - x_a >= 0
+  __host__ __device__ inline double dist(int l, d3 p) const {
+    int a = l >> 1;
+    double v = a == 0 ? p.x : (a == 1 ? p.y : p.z);
+    double b = (l & 1) ? (a == 0 ? hi.x : (a == 1 ? hi.y : hi.z)) : (a == 0 ? lo.x : (a == 1 ? lo.y : lo.z));
+    return (l & 1) ? b - v : v - b;
+  }
+};
+
+struct TetCont {
+  d3 n0, n1, n2, n3;
+  double d0, d1, d2, d3_;
+  static constexpr int np = 4;
+  __host__ __device__ inline double dist(int l, d3 p) const {
+    d3 n = l == 0 ? n0 : (l == 1 ? n1 : (l == 2 ? n2 : n3));
+    double d = l == 0 ? d0 : (l == 1 ? d1 : (l == 2 ? d2 : d3_));
+    return dotf(n, p) + d;
+  }
+};
+
+// Inward half-spaces of the tetrahedron (a, b, c, d) as a point set.
+__host__ __device__ inline TetCont tet_container(d3 a, d3 b, d3 c, d3 d) {
+  if (det3f(b - a, c - a, d - a) < 0.0) {
+    d3 t = c;
+    c = d;
+    d = t;
+  }
+  // outward faces (a,c,b), (a,b,d), (a,d,c), (b,c,d); inward normal = -(q-p)x(r-p)
+  TetCont C;
+  d3 N;
+  N = crossf(c - a, b - a);
+  C.n0 = mk3(-N.x, -N.y, -N.z);
+  C.d0 = dotf(N, a);
+  N = crossf(b - a, d - a);
+  C.n1 = mk3(-N.x, -N.y, -N.z);
+  C.d1 = dotf(N, a);
+  N = crossf(d - a, c - a);
+  C.n2 = mk3(-N.x, -N.y, -N.z);
+  C.d2 = dotf(N, a);
+  N = crossf(c - b, d - b);
+  C.n3 = mk3(-N.x, -N.y, -N.z);
+  C.d3_ = dotf(N, b);
+  return C;
+}
+
+__host__ __device__ inline d3 cut_pt(d3 pin, double sin_, d3 pout, double sout) {
+  double t = sin_ / (sin_ - sout);
+  return axpy(t, pout - pin, pin);
+}
+
+__host__ __device__ inline void cs_pt(double& sa, d3& pa, double& sb, d3& pb) {
+  bool sw = sb > sa;
+  double ts = sw ? sb : sa;
+  sb = sw ? sa : sb;
+  sa = ts;
+  d3 tp = sw ? pb : pa;
+  pb = sw ? pa : pb;
+  pa = tp;
+}
+
+struct Leaf {
+  bool useH;
+  d3 hn;
+  double hd;
+  __host__ __device__ inline double operator()(const Tet& t) const {
+    double v = fabs(tet6(t)) * (1.0 / 6.0);
+    if (!useH) return v;
+    return v * halfspace_fraction(dotf(hn, t.p0) + hd, dotf(hn, t.p1) + hd, dotf(hn, t.p2) + hd,
+                                  dotf(hn, t.p3) + hd);
+  }
+};
+
+constexpr int kClipStack = 16;
+
+// vol(T ∩ container ∩ {hn.x + hd >= 0 if useH}).  Returns -1 on stack overflow
+// (cannot happen for <= 7 planes: depth-first keeps at most 2 siblings per level).
+template <class Cont>
+__host__ __device__ double clip_volume(const Tet& T, const Cont& C, const Leaf& leaf) {
+  unsigned cut = 0;
+  for (int l = 0; l < Cont::np; ++l) {
+    double s0 = C.dist(l, T.p0), s1 = C.dist(l, T.p1), s2 = C.dist(l, T.p2), s3 = C.dist(l, T.p3);
+    double mx = fmax(fmax(s0, s1), fmax(s2, s3)), mn = fmin(fmin(s0, s1), fmin(s2, s3));
+    if (mx <= 0.0) return 0.0;
+    if (mn < 0.0) cut |= 1u << l;
+  }
+  if (cut == 0) return leaf(T);
+  Tet stk[kClipStack];
+  unsigned char lvl[kClipStack];
+  int sp = 1;
+  stk[0] = T;
+  lvl[0] = 0;
+  double acc = 0.0;
+  while (sp > 0) {
+    --sp;
+    Tet t = stk[sp];
+    int l = lvl[sp];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    bool dropped = false;
+    for (; l < Cont::np; ++l) {
+      if (!((cut >> l) & 1u)) continue;
+      s0 = C.dist(l, t.p0);
+      s1 = C.dist(l, t.p1);
+      s2 = C.dist(l, t.p2);
+      s3 = C.dist(l, t.p3);
+      double mx = fmax(fmax(s0, s1), fmax(s2, s3)), mn = fmin(fmin(s0, s1), fmin(s2, s3));
+      if (mx <= 0.0) {
+        dropped = true;
+        break;
+      }
+      if (mn < 0.0) break;
+    }
+    if (dropped) continue;
+    if (l >= Cont::np) {
+      acc += leaf(t);
+      continue;
+    }
+    // split t by plane l, keep s >= 0; vertices sorted by s, descending
+    d3 a = t.p0, b = t.p1, c = t.p2, d = t.p3;
+    double sa = s0, sb = s1, sc = s2, sd = s3;
+    cs_pt(sa, a, sb, b);
+    cs_pt(sc, c, sd, d);
+    cs_pt(sa, a, sc, c);
+    cs_pt(sb, b, sd, d);
+    cs_pt(sb, b, sc, c);
+    unsigned char nl = (unsigned char)(l + 1);
+    if (sp + 3 > kClipStack) return -1.0;
+    if (sb <= 0.0) {  // only a kept
+      stk[sp] = Tet{a, cut_pt(a, sa, b, sb), cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd)};
+      lvl[sp++] = nl;
+    } else if (sc >= 0.0) {  // a, b, c kept, d dropped: truncated prism
+      d3 pa = cut_pt(a, sa, d, sd), pb = cut_pt(b, sb, d, sd), pc = cut_pt(c, sc, d, sd);
+      stk[sp] = Tet{a, b, c, pa};
+      lvl[sp++] = nl;
+      stk[sp] = Tet{b, c, pa, pb};
+      lvl[sp++] = nl;
+      stk[sp] = Tet{c, pa, pb, pc};
+      lvl[sp++] = nl;
+    } else {  // a, b kept, c, d dropped: wedge (a, P1, P2 | b, P3, P4)
+      d3 P1 = cut_pt(a, sa, c, sc), P2 = cut_pt(a, sa, d, sd), P3 = cut_pt(b, sb, c, sc),
+         P4 = cut_pt(b, sb, d, sd);
+      stk[sp] = Tet{a, P1, P2, b};
+      lvl[sp++] = nl;
+      stk[sp] = Tet{P1, P2, b, P4};
+      lvl[sp++] = nl;
+      stk[sp] = Tet{P1, b, P4, P3};
+      lvl[sp++] = nl;
+    }
+  }
+  return acc;
+}
+
+// Volume of an axis-aligned box cut by {n.x >= s}: six Kuhn tetrahedra along
+// the lo-hi diagonal, each V/6, closed form per tetrahedron.  lev[i] = n.corner_i
+// with corner i = (i&1 ? hi.x : lo.x, i&2 ? hi.y : lo.y, i&4 ? hi.z : lo.z).
+__host__ __device__ inline double box_level_volume(const double* lev, double V, double s) {
+  double l0 = lev[0] - s, l7 = lev[7] - s;
+  double l1 = lev[1] - s, l2 = lev[2] - s, l4 = lev[4] - s;
+  double l3 = lev[3] - s, l5 = lev[5] - s, l6 = lev[6] - s;
+  // paths 0 -> (1 | 2 | 4) -> (3 | 5 | 6) -> 7
+  double f = halfspace_fraction(l0, l1, l3, l7) + halfspace_fraction(l0, l1, l5, l7) +
+             halfspace_fraction(l0, l2, l3, l7) + halfspace_fraction(l0, l2, l6, l7) +
+             halfspace_fraction(l0, l4, l5, l7) + halfspace_fraction(l0, l4, l6, l7);
+  return V * (1.0 / 6.0) * f;
+}
+
+__host__ __device__ inline Tet kuhn_tet(d3 lo, d3 hi, int k) {
+  // k: 0 x,y ; 1 x,z ; 2 y,x ; 3 y,z ; 4 z,x ; 5 z,y (first two axes of the path)
+  int a1 = k >> 1;
+  int a2 = (k == 0) ? 1 : (k == 1) ? 2 : (k == 2) ? 0 : (k == 3) ? 2 : (k == 4) ? 0 : 1;
+  d3 p1 = lo, p2;
+  if (a1 == 0) p1.x = hi.x;
+  else if (a1 == 1) p1.y = hi.y;
+  else p1.z = hi.z;
+  p2 = p1;
+  if (a2 == 0) p2.x = hi.x;
+  else if (a2 == 1) p2.y = hi.y;
+  else p2.z = hi.z;
+  return Tet{lo, p1, p2, hi};
+}
+
+}  // namespace gvof

@@ -1,0 +1,455 @@
+// C interface of the gVOF HIP library (declarations and contracts: include/gvof.h).
+//
+// The host side validates the mesh and builds its integer topology (cell ->
+// faces, cell -> vertices, vertex -> cells, vertex-sharing neighbours, the
+// paper's neigbcell) with counting passes; everything floating point runs in
+// the device kernels.  Device memory is one caller-owned workspace carved
+// into 256-byte-aligned structure-of-arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gvof.h"
+#include "gvof_dev.h"
+#include "gvof_launch.h"
+
+using gvof::DevMesh;
+
+struct gvof_mesh {
+  int nv = 0, nf = 0, nc = 0;
+  gvof_params p{};
+  // host copies / topology (kept until bind)
+  std::vector<double> vx, vy, vz;
+  std::vector<int> fv_ptr, fv_idx, owner, neigh;
+  std::vector<int> cf_ptr, cf_idx, cv_ptr, cv_idx, vc_ptr, vc_idx, nb_ptr, nb_idx;
+  int max_nb = 0;
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  DevMesh dm{};
+  bool bound = false, reconstructed = false;
+  std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+static int fail(gvof_mesh* m, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (m) m->err = buf;
+  else g_create_err = buf;
+  return code;
+}
+
+#define HIPCHECK(m, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(m, GVOF_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+void gvof_params_default(gvof_params* p) {
+  if (!p) return;
+  p->eps = 1e-12;
+  p->beta = 1.5;
+  p->fmfpa_degen = 1e-12;
+  p->flags = GVOF_FLAG_NONE;
+}
+
+int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double* vy, const double* vz, int32_t nf,
+                     const int32_t* fv_ptr, const int32_t* fv_idx, const int32_t* owner, const int32_t* neigh,
+                     int32_t nc, const gvof_params* params) {
+  if (!out) return fail(nullptr, GVOF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (nv <= 0 || nf <= 0 || nc <= 0) return fail(nullptr, GVOF_E_ARG, "empty mesh (nv=%d nf=%d nc=%d)", nv, nf, nc);
+  if (!vx || !vy || !vz || !fv_ptr || !fv_idx || !owner || !neigh) return fail(nullptr, GVOF_E_ARG, "NULL mesh array");
+  if (fv_ptr[0] != 0) return fail(nullptr, GVOF_E_MESH, "fv_ptr[0] must be 0");
+  for (int f = 0; f < nf; ++f) {
+    int k = fv_ptr[f + 1] - fv_ptr[f];
+    if (k < 3 || k > GVOF_MAX_FACE_VERTS)
+      return fail(nullptr, GVOF_E_MESH, "face %d has %d vertices (3..%d allowed)", f, k, GVOF_MAX_FACE_VERTS);
+    if (owner[f] < 0 || owner[f] >= nc) return fail(nullptr, GVOF_E_MESH, "face %d owner %d out of range", f, owner[f]);
+    if (neigh[f] < -1 || neigh[f] >= nc || neigh[f] == owner[f])
+      return fail(nullptr, GVOF_E_MESH, "face %d neighbour %d invalid", f, neigh[f]);
+  }
+  long nfv = fv_ptr[nf];
+  for (long i = 0; i < nfv; ++i)
+    if (fv_idx[i] < 0 || fv_idx[i] >= nv) return fail(nullptr, GVOF_E_MESH, "fv_idx[%ld]=%d out of range", i, fv_idx[i]);
+  for (int v = 0; v < nv; ++v)
+    if (!std::isfinite(vx[v]) || !std::isfinite(vy[v]) || !std::isfinite(vz[v]))
+      return fail(nullptr, GVOF_E_MESH, "vertex %d not finite", v);
+
+  gvof_mesh* m = new gvof_mesh;
+  m->nv = nv;
+  m->nf = nf;
+  m->nc = nc;
+  if (params) m->p = *params;
+  else gvof_params_default(&m->p);
+  m->vx.assign(vx, vx + nv);
+  m->vy.assign(vy, vy + nv);
+  m->vz.assign(vz, vz + nv);
+  m->fv_ptr.assign(fv_ptr, fv_ptr + nf + 1);
+  m->fv_idx.assign(fv_idx, fv_idx + nfv);
+  m->owner.assign(owner, owner + nf);
+  m->neigh.assign(neigh, neigh + nf);
+
+  // cell -> faces (ascending face id; ~f marks the neighbour side)
+  m->cf_ptr.assign(nc + 1, 0);
+  for (int f = 0; f < nf; ++f) {
+    m->cf_ptr[owner[f] + 1]++;
+    if (neigh[f] >= 0) m->cf_ptr[neigh[f] + 1]++;
+  }
+  for (int c = 0; c < nc; ++c) m->cf_ptr[c + 1] += m->cf_ptr[c];
+  m->cf_idx.assign(m->cf_ptr[nc], 0);
+  {
+    std::vector<int> fill(m->cf_ptr.begin(), m->cf_ptr.end() - 1);
+    for (int f = 0; f < nf; ++f) {
+      m->cf_idx[fill[owner[f]]++] = f;
+      if (neigh[f] >= 0) m->cf_idx[fill[neigh[f]]++] = ~f;
+    }
+  }
+  for (int c = 0; c < nc; ++c)
+    if (m->cf_ptr[c + 1] - m->cf_ptr[c] < 4) {
+      delete m;
+      return fail(nullptr, GVOF_E_MESH, "cell %d has fewer than 4 faces", c);
+    }
+  // cell -> distinct vertices (ascending)
+  m->cv_ptr.assign(nc + 1, 0);
+  std::vector<int> tmp;
+  std::vector<int> cv;
+  cv.reserve(nfv * 2);
+  for (int c = 0; c < nc; ++c) {
+    tmp.clear();
+    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+      int e = m->cf_idx[i];
+      int f = e >= 0 ? e : ~e;
+      for (int j = fv_ptr[f]; j < fv_ptr[f + 1]; ++j) tmp.push_back(fv_idx[j]);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    int npoly = 0;
+    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+      int e = m->cf_idx[i];
+      int f = e >= 0 ? e : ~e;
+      if (fv_ptr[f + 1] - fv_ptr[f] > 3) ++npoly;
+    }
+    if ((int)tmp.size() > gvof::kMaxCellVerts || (int)tmp.size() + 1 + npoly > gvof::kMaxLevels) {
+      delete m;
+      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %zu vertices and %d polygon faces (limits %d / %d levels)", c,
+                  tmp.size(), npoly, gvof::kMaxCellVerts, gvof::kMaxLevels);
+    }
+    cv.insert(cv.end(), tmp.begin(), tmp.end());
+    m->cv_ptr[c + 1] = (int)cv.size();
+  }
+  m->cv_idx.swap(cv);
+  // vertex -> cells (ascending)
+  m->vc_ptr.assign(nv + 1, 0);
+  for (int v : m->cv_idx) m->vc_ptr[v + 1]++;
+  for (int v = 0; v < nv; ++v) m->vc_ptr[v + 1] += m->vc_ptr[v];
+  m->vc_idx.assign(m->vc_ptr[nv], 0);
+  {
+    std::vector<int> fill(m->vc_ptr.begin(), m->vc_ptr.end() - 1);
+    for (int c = 0; c < nc; ++c)
+      for (int i = m->cv_ptr[c]; i < m->cv_ptr[c + 1]; ++i) m->vc_idx[fill[m->cv_idx[i]]++] = c;
+  }
+  for (int v = 0; v < nv; ++v)
+    if (m->vc_ptr[v + 1] == m->vc_ptr[v]) {
+      delete m;
+      return fail(nullptr, GVOF_E_MESH, "vertex %d belongs to no cell", v);
+    }
+  // vertex-sharing neighbours (ascending, itself excluded)
+  m->nb_ptr.assign(nc + 1, 0);
+  std::vector<int> nb;
+  nb.reserve((size_t)nc * 27);
+  for (int c = 0; c < nc; ++c) {
+    tmp.clear();
+    for (int i = m->cv_ptr[c]; i < m->cv_ptr[c + 1]; ++i) {
+      int v = m->cv_idx[i];
+      for (int j = m->vc_ptr[v]; j < m->vc_ptr[v + 1]; ++j)
+        if (m->vc_idx[j] != c) tmp.push_back(m->vc_idx[j]);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    if ((int)tmp.size() > gvof::kMaxNeighbours) {
+      delete m;
+      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %zu vertex neighbours (limit %d)", c, tmp.size(),
+                  gvof::kMaxNeighbours);
+    }
+    m->max_nb = std::max(m->max_nb, (int)tmp.size());
+    nb.insert(nb.end(), tmp.begin(), tmp.end());
+    m->nb_ptr[c + 1] = (int)nb.size();
+  }
+  m->nb_idx.swap(nb);
+  *out = m;
+  return GVOF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ workspace layout
+namespace {
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
+  Carver C{base};
+  DevMesh d{};
+  size_t nv = m->nv, nf = m->nf, nc = m->nc;
+  d.nv = m->nv;
+  d.nf = m->nf;
+  d.nc = m->nc;
+  double* vxyz = C.take<double>(3 * nv);
+  d.vx = vxyz;
+  d.vy = vxyz ? vxyz + nv : nullptr;
+  d.vz = vxyz ? vxyz + 2 * nv : nullptr;
+  d.fv_ptr = C.take<int>(nf + 1);
+  d.fv_idx = C.take<int>(m->fv_idx.size());
+  d.owner = C.take<int>(nf);
+  d.neigh = C.take<int>(nf);
+  d.cf_ptr = C.take<int>(nc + 1);
+  d.cf_idx = C.take<int>(m->cf_idx.size());
+  d.cv_ptr = C.take<int>(nc + 1);
+  d.cv_idx = C.take<int>(m->cv_idx.size());
+  d.vc_ptr = C.take<int>(nv + 1);
+  d.vc_idx = C.take<int>(m->vc_idx.size());
+  d.nb_ptr = C.take<int>(nc + 1);
+  d.nb_idx = C.take<int>(std::max<size_t>(m->nb_idx.size(), 1));
+  double* S = C.take<double>(3 * nf);
+  double* fc = C.take<double>(3 * nf);
+  d.Sx = S;
+  d.Sy = S ? S + nf : nullptr;
+  d.Sz = S ? S + 2 * nf : nullptr;
+  d.fcx = fc;
+  d.fcy = fc ? fc + nf : nullptr;
+  d.fcz = fc ? fc + 2 * nf : nullptr;
+  d.V = C.take<double>(nc);
+  double* cc = C.take<double>(3 * nc);
+  double* lo = C.take<double>(3 * nc);
+  double* hi = C.take<double>(3 * nc);
+  d.ccx = cc;
+  d.ccy = cc ? cc + nc : nullptr;
+  d.ccz = cc ? cc + 2 * nc : nullptr;
+  d.lox = lo;
+  d.loy = lo ? lo + nc : nullptr;
+  d.loz = lo ? lo + 2 * nc : nullptr;
+  d.hix = hi;
+  d.hiy = hi ? hi + nc : nullptr;
+  d.hiz = hi ? hi + 2 * nc : nullptr;
+  d.isbox = C.take<int8_t>(nc);
+  d.Fstar = C.take<double>(nv);
+  d.tag_node = C.take<int8_t>(nv);
+  d.tag_face = C.take<int8_t>(nf);
+  d.tag_cell = C.take<int8_t>(nc);
+  double* pl = C.take<double>(4 * nc);
+  d.pnx = pl;
+  d.pny = pl ? pl + nc : nullptr;
+  d.pnz = pl ? pl + 2 * nc : nullptr;
+  d.pC = pl ? pl + 3 * nc : nullptr;
+  d.Vd = C.take<double>(nf);
+  d.VF = C.take<double>(nf);
+  d.upwind = C.take<int>(nf);
+  d.list_cells = C.take<int>(nc);
+  d.list_faces = C.take<int>(nf);
+  d.counters = C.take<int>(gvof::CNT_N);
+  d.eps = m->p.eps;
+  d.beta = m->p.beta;
+  d.degen = m->p.fmfpa_degen;
+  if (dm) *dm = d;
+  return (C.off + 255) & ~size_t(255);
+}
+}  // namespace
+
+extern "C" {
+
+int gvof_mesh_workspace_bytes(const gvof_mesh* m, size_t* bytes) {
+  if (!m || !bytes) return GVOF_E_ARG;
+  *bytes = carve(const_cast<gvof_mesh*>(m), nullptr, nullptr);
+  return GVOF_OK;
+}
+
+int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
+  if (!m) return GVOF_E_ARG;
+  if (!ws) return fail(m, GVOF_E_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(m, GVOF_E_ARG, "workspace must be 256-byte aligned");
+  size_t need = carve(m, nullptr, nullptr);
+  if (ws_bytes < need) return fail(m, GVOF_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  m->ws = static_cast<char*>(ws);
+  m->ws_bytes = ws_bytes;
+  m->stream = static_cast<hipStream_t>(stream);
+  carve(m, m->ws, &m->dm);
+  DevMesh& d = m->dm;
+  hipStream_t s = m->stream;
+  size_t nv = m->nv;
+  auto up = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, s);
+  };
+  HIPCHECK(m, up(d.vx, m->vx.data(), nv * 8));
+  HIPCHECK(m, up(d.vy, m->vy.data(), nv * 8));
+  HIPCHECK(m, up(d.vz, m->vz.data(), nv * 8));
+  HIPCHECK(m, up(d.fv_ptr, m->fv_ptr.data(), m->fv_ptr.size() * 4));
+  HIPCHECK(m, up(d.fv_idx, m->fv_idx.data(), m->fv_idx.size() * 4));
+  HIPCHECK(m, up(d.owner, m->owner.data(), m->owner.size() * 4));
+  HIPCHECK(m, up(d.neigh, m->neigh.data(), m->neigh.size() * 4));
+  HIPCHECK(m, up(d.cf_ptr, m->cf_ptr.data(), m->cf_ptr.size() * 4));
+  HIPCHECK(m, up(d.cf_idx, m->cf_idx.data(), m->cf_idx.size() * 4));
+  HIPCHECK(m, up(d.cv_ptr, m->cv_ptr.data(), m->cv_ptr.size() * 4));
+  HIPCHECK(m, up(d.cv_idx, m->cv_idx.data(), m->cv_idx.size() * 4));
+  HIPCHECK(m, up(d.vc_ptr, m->vc_ptr.data(), m->vc_ptr.size() * 4));
+  HIPCHECK(m, up(d.vc_idx, m->vc_idx.data(), m->vc_idx.size() * 4));
+  HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
+  if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
+  HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
+  HIPCHECK(m, gvof::launch_geometry(d, s));
+  int cnt[gvof::CNT_N];
+  HIPCHECK(m, hipMemcpyAsync(cnt, d.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  if (cnt[gvof::CNT_ERR] & gvof::ERR_MESH) {
+    m->bound = false;
+    return fail(m, GVOF_E_MESH, "a cell is not closed or has non-positive volume");
+  }
+  HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  m->bound = true;
+  m->reconstructed = false;
+  return GVOF_OK;
+}
+
+int gvof_set_stream(gvof_mesh* m, void* stream) {
+  if (!m) return GVOF_E_ARG;
+  m->stream = static_cast<hipStream_t>(stream);
+  return GVOF_OK;
+}
+
+void gvof_mesh_destroy(gvof_mesh* m) { delete m; }
+
+int gvof_mesh_sizes(const gvof_mesh* m, int32_t* nv, int32_t* nf, int32_t* nc, int32_t* max_neigh) {
+  if (!m) return GVOF_E_ARG;
+  if (nv) *nv = m->nv;
+  if (nf) *nf = m->nf;
+  if (nc) *nc = m->nc;
+  if (max_neigh) *max_neigh = m->max_nb;
+  return GVOF_OK;
+}
+
+static int need_bound(gvof_mesh* m) {
+  if (!m) return GVOF_E_ARG;
+  if (!m->bound) return fail(m, GVOF_E_ARG, "mesh is not bound to a workspace");
+  return GVOF_OK;
+}
+
+static int d2d(gvof_mesh* m, void* dst, const void* src, size_t bytes) {
+  if (!dst) return GVOF_OK;
+  HIPCHECK(m, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, m->stream));
+  return GVOF_OK;
+}
+
+int gvof_get_geometry(gvof_mesh* m, double* S, double* fc, double* V, double* cc, double* bbmin, double* bbmax,
+                      int8_t* isbox) {
+  int r = need_bound(m);
+  if (r) return r;
+  const DevMesh& d = m->dm;
+  size_t nf = m->nf, nc = m->nc;
+  if ((r = d2d(m, S, d.Sx, 3 * nf * 8))) return r;
+  if ((r = d2d(m, fc, d.fcx, 3 * nf * 8))) return r;
+  if ((r = d2d(m, V, d.V, nc * 8))) return r;
+  if ((r = d2d(m, cc, d.ccx, 3 * nc * 8))) return r;
+  if ((r = d2d(m, bbmin, d.lox, 3 * nc * 8))) return r;
+  if ((r = d2d(m, bbmax, d.hix, 3 * nc * 8))) return r;
+  return d2d(m, isbox, d.isbox, nc);
+}
+
+int gvof_init_fraction(gvof_mesh* m, const gvof_shape* shape, int32_t n_div, double* F_out) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!shape || !F_out) return fail(m, GVOF_E_ARG, "NULL shape or F_out");
+  if (n_div < 1 || n_div > 64) return fail(m, GVOF_E_ARG, "n_div=%d outside 1..64", n_div);
+  if (shape->kind != GVOF_SHAPE_SPHERE && shape->kind != GVOF_SHAPE_PLANE)
+    return fail(m, GVOF_E_ARG, "unknown shape kind %d", shape->kind);
+  if (shape->kind == GVOF_SHAPE_SPHERE && !(shape->p[3] > 0.0)) return fail(m, GVOF_E_ARG, "sphere radius <= 0");
+  HIPCHECK(m, gvof::launch_init(m->dm, shape->kind, shape->p, n_div, F_out, m->stream));
+  return GVOF_OK;
+}
+
+int gvof_reconstruct(gvof_mesh* m, double* F, int8_t* cell_tag_out, double* plane_out) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!F) return fail(m, GVOF_E_ARG, "F is NULL");
+  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->stream));
+  m->reconstructed = true;
+  if ((r = d2d(m, cell_tag_out, m->dm.tag_cell, m->nc))) return r;
+  return d2d(m, plane_out, m->dm.pnx, 4 * (size_t)m->nc * 8);
+}
+
+int gvof_get_tags(gvof_mesh* m, double* node_value, int8_t* node_tag, int8_t* face_tag, int8_t* cell_tag) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!m->reconstructed) return fail(m, GVOF_E_ARG, "no reconstruction yet");
+  if ((r = d2d(m, node_value, m->dm.Fstar, (size_t)m->nv * 8))) return r;
+  if ((r = d2d(m, node_tag, m->dm.tag_node, m->nv))) return r;
+  if ((r = d2d(m, face_tag, m->dm.tag_face, m->nf))) return r;
+  return d2d(m, cell_tag, m->dm.tag_cell, m->nc);
+}
+
+int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, double dt, const double* F_in,
+                     double* F_out, int32_t* upwind_out, double* vd_out, double* vf_out) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!m->reconstructed) return fail(m, GVOF_E_ARG, "gvof_advect_step needs a preceding gvof_reconstruct");
+  if (!u_face || !u_vert || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
+  if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
+  HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->stream));
+  if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
+  if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;
+  return d2d(m, vf_out, m->dm.VF, (size_t)m->nf * 8);
+}
+
+int gvof_interface_counts(gvof_mesh* m, int32_t* n_cells, int32_t* n_faces) {
+  int r = need_bound(m);
+  if (r) return r;
+  int cnt[gvof::CNT_N];
+  HIPCHECK(m, hipMemcpyAsync(cnt, m->dm.counters, sizeof cnt, hipMemcpyDeviceToHost, m->stream));
+  HIPCHECK(m, hipStreamSynchronize(m->stream));
+  if (n_cells) *n_cells = cnt[gvof::CNT_CELLS];
+  if (n_faces) *n_faces = cnt[gvof::CNT_FACES];
+  return GVOF_OK;
+}
+
+int gvof_status(gvof_mesh* m) {
+  int r = need_bound(m);
+  if (r) return r;
+  int cnt[gvof::CNT_N];
+  HIPCHECK(m, hipMemcpyAsync(cnt, m->dm.counters, sizeof cnt, hipMemcpyDeviceToHost, m->stream));
+  HIPCHECK(m, hipStreamSynchronize(m->stream));
+  int e = cnt[gvof::CNT_ERR];
+  if (e) {
+    return fail(m, GVOF_E_GEOM, "device geometry error flags 0x%x (%s%s%s)", e,
+                (e & gvof::ERR_APEX) ? "flux-polyhedron apex degenerate " : "",
+                (e & gvof::ERR_LEVELS) ? "too many vertex levels " : "",
+                (e & gvof::ERR_STACK) ? "clip stack overflow" : "");
+  }
+  return GVOF_OK;
+}
+
+const char* gvof_last_error(const gvof_mesh* m) { return m ? m->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Device-side data layout and geometry primitives of the gVOF HIP library.
+//
+// All arrays are structure-of-arrays in one caller-provided workspace.  The
+// whole library is compiled with -ffp-contract=off: expressions that decide
+// an integer result (tags, upwind cell, the FMFPA fallback test, box
+// detection) are written with plain operators in a fixed order, so they are
+// reproducible bit for bit by any IEEE FP64 implementation that evaluates
+// them in the same order.  Volume arithmetic, whose result is continuous in
+// its inputs, uses explicit fma().
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gvof {
+
+struct DevMesh {
+  int nv, nf, nc;
+  // vertices, faces, connectivity (uploaded once)
+  const double *vx, *vy, *vz;
+  const int *fv_ptr, *fv_idx, *owner, *neigh;
+  const int *cf_ptr, *cf_idx;  // cell -> faces ascending; entry f (cell owns f) or ~f (cell is f's neighbour)
+  const int *cv_ptr, *cv_idx;  // cell -> distinct vertices ascending
+  const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
+  const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
+  // geometry (computed on the device at bind)
+  double *Sx, *Sy, *Sz, *fcx, *fcy, *fcz;
+  double *V, *ccx, *ccy, *ccz, *lox, *loy, *loz, *hix, *hiy, *hiz;
+  int8_t* isbox;
+  // per-step state
+  double* Fstar;
+  int8_t *tag_node, *tag_face, *tag_cell;
+  double *pnx, *pny, *pnz, *pC;  // PLIC planes of tag-0 cells
+  double *Vd, *VF;
+  int* upwind;
+  int *list_cells, *list_faces;
+  int* counters;  // [0] tag-0 cells, [1] tag-0 faces, [2] geometry error flags, [3] refine cells
+  double eps, beta, degen;
+};
+
+enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_N = 8 };
+enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16 };
+
+constexpr int kMaxFaceVerts = 8;
+constexpr int kMaxNeighbours = 62;  // vertex-sharing neighbours of one cell
+constexpr int kMaxCellVerts = 30;   // distinct vertices of one cell
+constexpr int kMaxLevels = 40;      // sorted vertex levels used by the plane-constant search
+
+// ---------------------------------------------------------------- vectors
+struct d3 {
+  double x, y, z;
+};
+__host__ __device__ inline d3 mk3(double x, double y, double z) { return d3{x, y, z}; }
+__host__ __device__ inline d3 operator+(d3 a, d3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline d3 operator-(d3 a, d3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline d3 operator*(double s, d3 a) { return mk3(s * a.x, s * a.y, s * a.z); }
+// exact-order forms (integer decisions depend on them)
+__host__ __device__ inline double dot_x(d3 a, d3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__host__ __device__ inline d3 cross_x(d3 a, d3 b) {
+  return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// fused forms (continuous results)
+__host__ __device__ inline double dotf(d3 a, d3 b) { return fma(a.z, b.z, fma(a.y, b.y, a.x * b.x)); }
+__host__ __device__ inline d3 crossf(d3 a, d3 b) {
+  return mk3(fma(a.y, b.z, -a.z * b.y), fma(a.z, b.x, -a.x * b.z), fma(a.x, b.y, -a.y * b.x));
+}
+__host__ __device__ inline double det3f(d3 a, d3 b, d3 c) { return dotf(a, crossf(b, c)); }
+__host__ __device__ inline d3 axpy(double t, d3 d, d3 p) { return mk3(fma(t, d.x, p.x), fma(t, d.y, p.y), fma(t, d.z, p.z)); }
+__host__ __device__ inline d3 vmin(d3 a, d3 b) { return mk3(fmin(a.x, b.x), fmin(a.y, b.y), fmin(a.z, b.z)); }
+__host__ __device__ inline d3 vmax(d3 a, d3 b) { return mk3(fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)); }
+
+__device__ inline d3 vert(const DevMesh& M, int v) { return mk3(M.vx[v], M.vy[v], M.vz[v]); }
+__device__ inline d3 cell_centre(const DevMesh& M, int c) { return mk3(M.ccx[c], M.ccy[c], M.ccz[c]); }
+
+// ---------------------------------------------------------------- tetrahedra and half-spaces
+struct Tet {
+  d3 p0, p1, p2, p3;
+};
+
+__host__ __device__ inline double tet6(const Tet& t) { return det3f(t.p1 - t.p0, t.p2 - t.p0, t.p3 - t.p0); }
+
+__host__ __device__ inline void cswap_desc(double& a, double& b) {
+  double hi = fmax(a, b), lo = fmin(a, b);
+  a = hi;
+  b = lo;
+}
+
+// Fraction of a tetrahedron's volume where the affine function with vertex
+// values s0..s3 is >= 0.  The fraction depends only on the four values: with
+// them sorted a >= b >= c >= d,
+//   one positive:  a^3 / ((a-b)(a-c)(a-d))
+//   one negative:  1 - (-d)^3 / ((a-d)(b-d)(c-d))
+//   two and two:   t_ac t_ad + t_ac t_bd (1 - t_ad) + t_bc t_bd (1 - t_ac),
+//                  t_xy = x / (x - y)  (the kept wedge split in three tetrahedra).
+// Every denominator is a difference of values of opposite sign.
+__host__ __device__ inline double halfspace_fraction(double s0, double s1, double s2, double s3) {
+  double a = s0, b = s1, c = s2, d = s3;
+  cswap_desc(a, b);
+  cswap_desc(c, d);
+  cswap_desc(a, c);
+  cswap_desc(b, d);
+  cswap_desc(b, c);
+  if (d >= 0.0) return 1.0;
+  if (a <= 0.0) return 0.0;
+  if (b <= 0.0) {
+    double den = (a - b) * (a - c) * (a - d);
+    return (a * a * a) / den;
+  }
+  if (c >= 0.0) {
+    double m = -d;
+    double den = (a - d) * (b - d) * (c - d);
+    return 1.0 - (m * m * m) / den;
+  }
+  double tac = a / (a - c), tad = a / (a - d), tbc = b / (b - c), tbd = b / (b - d);
+  return fma(tac, tad, fma(tac * tbd, 1.0 - tad, tbc * tbd * (1.0 - tac)));
+}
+
+}  // namespace gvof

@@ -1,0 +1,865 @@
+// gVOF hot path on gfx950: grid geometry, tagging + cut-off, LSGIR + plane
+// constant, face flux volumes, FMFPA flux polyhedra with signed truncation,
+// and the volume-fraction update (Lopez & Hernandez, arXiv 2111.01524).
+//
+// Sweeps over faces / cells / vertices use one lane per item in coalesced SoA
+// order.  Interfacial cells and faces are compacted into work lists with
+// wave-aggregated atomics; the geometric kernels walk those lists.  No
+// floating-point atomics: every sum has a fixed order, so results are
+// reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "clip.h"
+#include "gvof_dev.h"
+#include "gvof_launch.h"
+
+namespace gvof {
+
+__device__ inline int grid_stride_start() { return blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ inline int grid_stride() { return gridDim.x * blockDim.x; }
+
+// Wave-aggregated append of `item` when `pred`: one atomic per wave, slots in lane order.
+__device__ inline void wave_append(bool pred, int item, int* counter, int* list) {
+  unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  int lane = __lane_id();
+  int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader);
+  if (pred) {
+    unsigned long long below = m & ((1ull << lane) - 1ull);
+    list[base + __popcll(below)] = item;
+  }
+}
+
+__global__ void k_zero(int* p, int n) {
+  int i = grid_stride_start();
+  if (i < n) p[i] = 0;
+}
+
+// ============================================================== grid geometry
+// Face vertex mean c and area vector S = 1/2 sum (x_i - c) x (x_{i+1} - c),
+// evaluated in vertex order with separate roundings (bitwise reproducible).
+__global__ void k_face_geom(DevMesh M) {
+  for (int f = grid_stride_start(); f < M.nf; f += grid_stride()) {
+    int b = M.fv_ptr[f], k = M.fv_ptr[f + 1] - b;
+    d3 s = mk3(0.0, 0.0, 0.0);
+    for (int i = 0; i < k; ++i) s = s + vert(M, M.fv_idx[b + i]);
+    double dk = (double)k;
+    d3 c = mk3(s.x / dk, s.y / dk, s.z / dk);
+    d3 A = mk3(0.0, 0.0, 0.0);
+    for (int i = 0; i < k; ++i) {
+      int j = (i + 1 == k) ? 0 : i + 1;
+      A = A + cross_x(vert(M, M.fv_idx[b + i]) - c, vert(M, M.fv_idx[b + j]) - c);
+    }
+    M.fcx[f] = c.x;
+    M.fcy[f] = c.y;
+    M.fcz[f] = c.z;
+    M.Sx[f] = 0.5 * A.x;
+    M.Sy[f] = 0.5 * A.y;
+    M.Sz[f] = 0.5 * A.z;
+  }
+}
+
+// i-th surface triangle of cell-face entry e (outward for the cell).
+__device__ inline void face_triangle(const DevMesh& M, int e, int i, d3& t0, d3& t1, d3& t2) {
+  int f = e >= 0 ? e : ~e;
+  int b = M.fv_ptr[f], k = M.fv_ptr[f + 1] - b;
+  if (k == 3) {
+    t0 = vert(M, M.fv_idx[b]);
+    t1 = vert(M, M.fv_idx[b + 1]);
+    t2 = vert(M, M.fv_idx[b + 2]);
+    if (e < 0) {
+      d3 t = t1;
+      t1 = t2;
+      t2 = t;
+    }
+  } else {
+    int j = (i + 1 == k) ? 0 : i + 1;
+    t0 = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
+    t1 = vert(M, M.fv_idx[b + i]);
+    t2 = vert(M, M.fv_idx[b + j]);
+    if (e < 0) {
+      d3 t = t1;
+      t1 = t2;
+      t2 = t;
+    }
+  }
+}
+
+__device__ inline int face_triangle_count(const DevMesh& M, int e) {
+  int f = e >= 0 ? e : ~e;
+  int k = M.fv_ptr[f + 1] - M.fv_ptr[f];
+  return k == 3 ? 1 : k;
+}
+
+// Cell vertex mean (distinct vertices, ascending id), enclosing box, box
+// detection, and volume as signed tetrahedra from the vertex mean over the
+// surface triangles.  Flags cells that are not closed or not positive.
+__global__ void k_cell_geom(DevMesh M) {
+  for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
+    int vb = M.cv_ptr[c], vn = M.cv_ptr[c + 1] - vb;
+    d3 s = mk3(0.0, 0.0, 0.0);
+    d3 lo = vert(M, M.cv_idx[vb]), hi = lo;
+    for (int i = 0; i < vn; ++i) {
+      d3 p = vert(M, M.cv_idx[vb + i]);
+      s = s + p;
+      lo = vmin(lo, p);
+      hi = vmax(hi, p);
+    }
+    double dn = (double)vn;
+    d3 cen = mk3(s.x / dn, s.y / dn, s.z / dn);
+    int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+    bool box = vn == 8 && fn == 6;
+    if (box) {
+      int mask = 0;
+      for (int i = 0; i < vn; ++i) {
+        d3 p = vert(M, M.cv_idx[vb + i]);
+        bool ok = (p.x == lo.x || p.x == hi.x) && (p.y == lo.y || p.y == hi.y) && (p.z == lo.z || p.z == hi.z);
+        if (!ok) box = false;
+        mask |= 1 << ((p.x == hi.x ? 1 : 0) + (p.y == hi.y ? 2 : 0) + (p.z == hi.z ? 4 : 0));
+      }
+      if (mask != 255) box = false;
+      if (!(lo.x < hi.x && lo.y < hi.y && lo.z < hi.z)) box = false;
+      for (int i = 0; i < fn; ++i) {
+        int e = M.cf_idx[fb + i];
+        int f = e >= 0 ? e : ~e;
+        if (M.fv_ptr[f + 1] - M.fv_ptr[f] != 4) box = false;
+      }
+    }
+    double vol = 0.0, amag = 0.0;
+    d3 net = mk3(0.0, 0.0, 0.0);
+    for (int i = 0; i < fn; ++i) {
+      int e = M.cf_idx[fb + i];
+      int f = e >= 0 ? e : ~e;
+      double sg = e >= 0 ? 1.0 : -1.0;
+      net = net + sg * mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+      amag += fabs(M.Sx[f]) + fabs(M.Sy[f]) + fabs(M.Sz[f]);
+      int nt = face_triangle_count(M, e);
+      for (int t = 0; t < nt; ++t) {
+        d3 t0, t1, t2;
+        face_triangle(M, e, t, t0, t1, t2);
+        vol += det3f(t0 - cen, t1 - cen, t2 - cen);
+      }
+    }
+    vol *= (1.0 / 6.0);
+    M.ccx[c] = cen.x;
+    M.ccy[c] = cen.y;
+    M.ccz[c] = cen.z;
+    M.lox[c] = lo.x;
+    M.loy[c] = lo.y;
+    M.loz[c] = lo.z;
+    M.hix[c] = hi.x;
+    M.hiy[c] = hi.y;
+    M.hiz[c] = hi.z;
+    M.V[c] = vol;
+    M.isbox[c] = box ? 1 : 0;
+    double nn = fabs(net.x) + fabs(net.y) + fabs(net.z);
+    if (!(vol > 0.0) || !(nn <= 1e-12 * amag)) atomicOr(&M.counters[CNT_ERR], ERR_MESH);
+  }
+}
+
+// ============================================================== tagging and cut-off
+// Node value F* = sum w F / sum w over the cells sharing the node (ascending
+// cell id), w = 1/|x_v - x_c|^2; node tag in {-1, 0, 1}.
+__global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
+  const double eps = M.eps, one_m = 1.0 - M.eps;
+  for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
+    d3 x = vert(M, v);
+    double num = 0.0, den = 0.0;
+    for (int i = M.vc_ptr[v]; i < M.vc_ptr[v + 1]; ++i) {
+      int c = M.vc_idx[i];
+      d3 d = x - cell_centre(M, c);
+      double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
+      double w = 1.0 / d2;
+      num = num + w * F[c];
+      den = den + w;
+    }
+    double fs = num / den;
+    M.Fstar[v] = fs;
+    M.tag_node[v] = fs < eps ? -1 : (fs > one_m ? 1 : 0);
+  }
+}
+
+__global__ void k_face_tag(DevMesh M) {
+  for (int f = grid_stride_start(); f < M.nf; f += grid_stride()) {
+    bool allm = true, allp = true;
+    for (int i = M.fv_ptr[f]; i < M.fv_ptr[f + 1]; ++i) {
+      int t = M.tag_node[M.fv_idx[i]];
+      allm = allm && t == -1;
+      allp = allp && t == 1;
+    }
+    M.tag_face[f] = allm ? -1 : (allp ? 1 : 0);
+  }
+}
+
+// Cell tag, cut-off of F in place, compaction of the interfacial cells.
+__global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
+  const double eps = M.eps, one_m = 1.0 - M.eps;
+  int n = M.nc;
+  int stride = grid_stride();
+  // every lane of a wave runs the same number of iterations (wave_append needs all lanes)
+  int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int b = base0; b < n; b += stride) {
+    int c = b + (threadIdx.x & 63);
+    bool inter = false;
+    if (c < n) {
+      double f = F[c];
+      int8_t t = f < eps ? -1 : (f > one_m ? 1 : 0);
+      M.tag_cell[c] = t;
+      if (t == -1) F[c] = 0.0;
+      if (t == 1) F[c] = 1.0;
+      inter = t == 0;
+      if (!inter) {
+        M.pnx[c] = 0.0;
+        M.pny[c] = 0.0;
+        M.pnz[c] = 0.0;
+        M.pC[c] = 0.0;
+      }
+    }
+    wave_append(inter, c, &M.counters[CNT_CELLS], M.list_cells);
+  }
+}
+
+// ============================================================== LSGIR + plane constant
+struct CellLevels {
+  // general cell: volume of {n.x >= s} as signed tetrahedra from the vertex mean
+  __device__ static double general(const DevMesh& M, int c, d3 n, d3 cen, double s) {
+    double lc = dotf(n, cen) - s;
+    double acc = 0.0;
+    int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+    for (int i = 0; i < fn; ++i) {
+      int e = M.cf_idx[fb + i];
+      int nt = face_triangle_count(M, e);
+      for (int t = 0; t < nt; ++t) {
+        d3 t0, t1, t2;
+        face_triangle(M, e, t, t0, t1, t2);
+        double v6 = det3f(t0 - cen, t1 - cen, t2 - cen);
+        double fr = halfspace_fraction(lc, dotf(n, t0) - s, dotf(n, t1) - s, dotf(n, t2) - s);
+        acc = fma(v6, fr, acc);
+      }
+    }
+    return acc * (1.0 / 6.0);
+  }
+};
+
+__device__ inline void insert_sorted(double* a, int& n, double v) {
+  int i = n++;
+  while (i > 0 && a[i - 1] > v) {
+    a[i] = a[i - 1];
+    --i;
+  }
+  a[i] = v;
+}
+
+// Solves g(s) = T for s in [s0, s0 + w] where g is the cubic through
+// (s0, y0), (s0 + w/3, y1), (s0 + 2w/3, y2), (s0 + w, y3) and decreasing.
+__device__ inline double cubic_root(double s0, double w, double y0, double y1, double y2, double y3, double T) {
+  double D1 = y1 - y0, D2 = (y2 - 2.0 * y1) + y0, D3 = ((y3 - 3.0 * y2) + 3.0 * y1) - y0;
+  double q3 = D3 * (1.0 / 6.0), q2 = 0.5 * D2;
+  double ua = 0.0, ub = 3.0;
+  double u = (y0 - y3) != 0.0 ? 3.0 * (y0 - T) / (y0 - y3) : 1.5;
+  u = fmin(fmax(u, 0.0), 3.0);
+  for (int it = 0; it < 64; ++it) {
+    // p(u) = y0 + u (D1 + (u-1) (q2 + (u-2) q3))
+    double qq = fma(u - 2.0, q3, q2);
+    double r = fma(u - 1.0, qq, D1);
+    double p = fma(u, r, y0) - T;
+    double dr = fma(u - 1.0, q3, qq);
+    double dp = fma(u, dr, r);
+    if (p > 0.0) ua = u;
+    else if (p < 0.0) ub = u;
+    else break;
+    double un = u - p / dp;
+    if (!(un > ua && un < ub)) un = 0.5 * (ua + ub);
+    if (fabs(un - u) <= 1e-16 * 3.0) {
+      u = un;
+      break;
+    }
+    u = un;
+  }
+  return fma(u, w * (1.0 / 3.0), s0);
+}
+
+__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F) {
+  int ncell = M.counters[CNT_CELLS];
+  const double beta = M.beta;
+  const bool beta15 = beta == 1.5;
+  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
+    int c = M.list_cells[it];
+    d3 xc = cell_centre(M, c);
+    double Fc = F[c];
+    // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta
+    double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, r0 = 0, r1 = 0, r2 = 0;
+    for (int i = M.nb_ptr[c]; i < M.nb_ptr[c + 1]; ++i) {
+      int k = M.nb_idx[i];
+      d3 d = cell_centre(M, k) - xc;
+      double d2 = dotf(d, d);
+      double w2 = beta15 ? 1.0 / (d2 * sqrt(d2)) : pow(d2, -beta);
+      double df = (F[k] - Fc) * w2;
+      a00 = fma(w2 * d.x, d.x, a00);
+      a01 = fma(w2 * d.x, d.y, a01);
+      a02 = fma(w2 * d.x, d.z, a02);
+      a11 = fma(w2 * d.y, d.y, a11);
+      a12 = fma(w2 * d.y, d.z, a12);
+      a22 = fma(w2 * d.z, d.z, a22);
+      r0 = fma(df, d.x, r0);
+      r1 = fma(df, d.y, r1);
+      r2 = fma(df, d.z, r2);
+    }
+    // adjugate solve (A symmetric positive definite): g ~ adj(A) r
+    double c00 = fma(a11, a22, -a12 * a12), c01 = fma(a02, a12, -a01 * a22), c02 = fma(a01, a12, -a02 * a11);
+    double c11 = fma(a00, a22, -a02 * a02), c12 = fma(a01, a02, -a00 * a12), c22 = fma(a00, a11, -a01 * a01);
+    double det = fma(a00, c00, fma(a01, c01, a02 * c02));
+    d3 g = mk3(fma(c00, r0, fma(c01, r1, c02 * r2)), fma(c01, r0, fma(c11, r1, c12 * r2)),
+               fma(c02, r0, fma(c12, r1, c22 * r2)));
+    if (det < 0.0) g = mk3(-g.x, -g.y, -g.z);
+    double gg = dotf(g, g);
+    d3 n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
+    // ---- plane constant: g(s) = vol(cell ∩ {n.x >= s}) = F V
+    double Vc = M.V[c];
+    double T = Fc * Vc;
+    double lev[kMaxLevels];
+    int nl = 0;
+    bool box = M.isbox[c] != 0;
+    double blev[8];
+    d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+    if (box) {
+      for (int q = 0; q < 8; ++q) {
+        d3 p = mk3((q & 1) ? hi.x : lo.x, (q & 2) ? hi.y : lo.y, (q & 4) ? hi.z : lo.z);
+        blev[q] = dotf(n, p);
+        insert_sorted(lev, nl, blev[q]);
+      }
+    } else {
+      insert_sorted(lev, nl, dotf(n, xc));
+      for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i) insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
+      int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+      for (int i = 0; i < fn && nl < kMaxLevels; ++i) {
+        int e = M.cf_idx[fb + i];
+        int f = e >= 0 ? e : ~e;
+        if (M.fv_ptr[f + 1] - M.fv_ptr[f] > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
+      }
+      if (M.cv_ptr[c + 1] - M.cv_ptr[c] + 1 > kMaxLevels) atomicOr(&M.counters[CNT_ERR], ERR_LEVELS);
+    }
+    auto G = [&](double s) -> double {
+      return box ? box_level_volume(blev, Vc, s) : CellLevels::general(M, c, n, xc, s);
+    };
+    int lo_i = 0, hi_i = nl - 1;
+    double glo = G(lev[0]), ghi = 0.0;
+    while (hi_i - lo_i > 1) {
+      int mid = (lo_i + hi_i) >> 1;
+      double gm = G(lev[mid]);
+      if (gm >= T) {
+        lo_i = mid;
+        glo = gm;
+      } else {
+        hi_i = mid;
+        ghi = gm;
+      }
+    }
+    double s0 = lev[lo_i], w = lev[hi_i] - s0;
+    double s;
+    if (!(w > 0.0)) {
+      s = s0;
+    } else {
+      double y1 = G(fma(w, 1.0 / 3.0, s0)), y2 = G(fma(w, 2.0 / 3.0, s0));
+      s = cubic_root(s0, w, glo, y1, y2, ghi, T);
+    }
+    M.pnx[c] = n.x;
+    M.pny[c] = n.y;
+    M.pnz[c] = n.z;
+    M.pC[c] = -s;
+  }
+}
+
+// ============================================================== face sweep
+// V_d = dt u.S, upwind cell, the flux of faces that need no geometry, and the
+// list of faces that need a flux polyhedron.
+__global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt) {
+  int n = M.nf;
+  int stride = grid_stride();
+  int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int b = base0; b < n; b += stride) {
+    int f = b + (threadIdx.x & 63);
+    bool geo = false;
+    if (f < n) {
+      d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
+      d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+      double vd = dt * dot_x(u, S);
+      int nb = M.neigh[f];
+      M.Vd[f] = vd;
+      M.upwind[f] = vd >= 0.0 ? M.owner[f] : nb;
+      int8_t t = M.tag_face[f];
+      if (nb < 0 && vd < 0.0) M.VF[f] = 0.0;
+      else if (t == -1) M.VF[f] = 0.0;
+      else if (t == 1) M.VF[f] = vd;
+      else geo = true;
+    }
+    wave_append(geo, f, &M.counters[CNT_FACES], M.list_faces);
+  }
+}
+
+// ============================================================== FMFPA + truncation
+constexpr int kFluxLanes = 64;
+constexpr int kMaxPts = 2 * kMaxFaceVerts + 1;
+constexpr int kMaxCand = 2 + 2 * kMaxNeighbours;
+constexpr int kQueue = 512;
+
+__device__ inline bool box_overlap(d3 alo, d3 ahi, d3 blo, d3 bhi) {
+  return alo.x < bhi.x && blo.x < ahi.x && alo.y < bhi.y && blo.y < ahi.y && alo.z < bhi.z && blo.z < ahi.z;
+}
+
+__device__ inline bool sorted_contains(const int* a, int n, int key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    int v = a[mid];
+    if (v == key) return true;
+    if (v < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return false;
+}
+
+// surface triangle m of cell k (walks the face list when faces are polygons)
+__device__ inline void cell_piece(const DevMesh& M, int k, int m, d3& t0, d3& t1, d3& t2) {
+  int fb = M.cf_ptr[k], fn = M.cf_ptr[k + 1] - fb;
+  for (int i = 0; i < fn; ++i) {
+    int e = M.cf_idx[fb + i];
+    int nt = face_triangle_count(M, e);
+    if (m < nt) {
+      face_triangle(M, e, m, t0, t1, t2);
+      return;
+    }
+    m -= nt;
+  }
+  t0 = t1 = t2 = mk3(0.0, 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __restrict__ uv, double dt) {
+  __shared__ double px[kMaxPts], py[kMaxPts], pz[kMaxPts];
+  __shared__ double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
+  __shared__ double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
+  __shared__ int cand[kMaxCand];
+  __shared__ int cpre[kMaxCand + 1];
+  __shared__ unsigned queue[kQueue];
+
+  const int lane = threadIdx.x;
+  const int nv = M.nv;
+  const int nfaces = M.counters[CNT_FACES];
+  for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
+    const int f = M.list_faces[it];
+    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
+    // ---- flux polyhedron: lanes 0..I-1 own face vertex i
+    if (lane < I) {
+      int v = M.fv_idx[b0 + lane];
+      px[lane] = M.vx[v];
+      py[lane] = M.vy[v];
+      pz[lane] = M.vz[v];
+      ux[lane] = uv[v];
+      uy[lane] = uv[nv + v];
+      uz[lane] = uv[2 * nv + v];
+    }
+    __syncthreads();
+    if (lane < I) {
+      int j = (lane + 1 == I) ? 0 : lane + 1;
+      d3 ub = mk3(0.5 * (ux[lane] + ux[j]), 0.5 * (uy[lane] + uy[j]), 0.5 * (uz[lane] + uz[j]));
+      d3 e = mk3(px[j] - px[lane], py[j] - py[lane], pz[j] - pz[lane]);
+      d3 m = cross_x(e, ub);  // lateral plane through edge i, parallel to the edge-centre velocity
+      mx[lane] = m.x;
+      my[lane] = m.y;
+      mz[lane] = m.z;
+    }
+    __syncthreads();
+    if (lane < I) {
+      int i = lane, ip = (lane == 0) ? I - 1 : lane - 1;
+      d3 m0 = mk3(mx[ip], my[ip], mz[ip]), m1 = mk3(mx[i], my[i], mz[i]);
+      d3 d = cross_x(m0, m1);
+      double dd = dot_x(d, d), q0 = dot_x(m0, m0), q1 = dot_x(m1, m1);
+      bool fallback = (q0 == 0.0) || (q1 == 0.0) || (dd <= (M.degen * q0) * q1);
+      d3 x = mk3(px[i], py[i], pz[i]), u = mk3(ux[i], uy[i], uz[i]);
+      d3 bv;
+      if (fallback) bv = x - dt * u;  // back-trace along the streak line
+      else {
+        double t = dotf(u, d) / dd;  // projection of x - dt u on the line of the two lateral planes
+        bv = x - (dt * t) * d;
+      }
+      px[I + i] = bv.x;
+      py[I + i] = bv.y;
+      pz[I + i] = bv.z;
+    }
+    __syncthreads();
+    const d3 c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
+    const d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+    {
+      // apex: back-vertex mean moved along S until the signed volume equals V_d (all lanes, same values)
+      d3 g = mk3(0.0, 0.0, 0.0);
+      for (int i = 0; i < I; ++i) g = g + mk3(px[I + i], py[I + i], pz[I + i]);
+      double dI = (double)I;
+      g = mk3(g.x / dI, g.y / dI, g.z / dI);
+      double V0 = 0.0, W = 0.0;
+      for (int i = 0; i < I; ++i) {
+        int j = (i + 1 == I) ? 0 : i + 1;
+        d3 xi = mk3(px[i], py[i], pz[i]) - c, xj = mk3(px[j], py[j], pz[j]) - c;
+        d3 bi = mk3(px[I + i], py[I + i], pz[I + i]) - c, bj = mk3(px[I + j], py[I + j], pz[I + j]) - c;
+        V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
+        W += det3f(S, bj, bi);
+      }
+      V0 *= (1.0 / 6.0);
+      W *= (1.0 / 6.0);
+      double mu = 0.0;
+      if (fabs(W) <= 1e-12 * dotf(S, S)) {
+        if (lane == 0) atomicOr(&M.counters[CNT_ERR], ERR_APEX);
+      } else {
+        mu = (M.Vd[f] - V0) / W;
+      }
+      if (lane == 0) {
+        px[2 * I] = fma(mu, S.x, g.x);
+        py[2 * I] = fma(mu, S.y, g.y);
+        pz[2 * I] = fma(mu, S.z, g.z);
+      }
+    }
+    __syncthreads();
+    // bounding box of the polyhedron
+    d3 plo = c, phi = c;
+    for (int i = 0; i <= 2 * I; ++i) {
+      d3 p = mk3(px[i], py[i], pz[i]);
+      plo = vmin(plo, p);
+      phi = vmax(phi, p);
+    }
+    // ---- candidate cells: owner, neighbour and their vertex-sharing cells, minus empty / far ones
+    const int o = M.owner[f], nbr = M.neigh[f];
+    const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
+    const int nbb = nbr >= 0 ? M.nb_ptr[nbr] : 0, nbn = nbr >= 0 ? M.nb_ptr[nbr + 1] - nbb : 0;
+    const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
+    int ncand = 0;
+    for (int j0 = 0; j0 < L; j0 += kFluxLanes) {
+      int j = j0 + lane;
+      bool keep = false;
+      int k = -1;
+      if (j < L) {
+        bool second = j > on;
+        if (j == 0) k = o;
+        else if (j <= on) k = M.nb_idx[ob + j - 1];
+        else if (j == on + 1) k = nbr;
+        else k = M.nb_idx[nbb + j - on - 2];
+        keep = M.tag_cell[k] != -1;
+        if (keep && second) keep = !(k == o || sorted_contains(M.nb_idx + ob, on, k));
+        if (keep) {
+          d3 klo = mk3(M.lox[k], M.loy[k], M.loz[k]), khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+          keep = box_overlap(plo, phi, klo, khi);
+        }
+      }
+      unsigned long long bm = __ballot(keep);
+      if (keep) cand[ncand + __popcll(bm & ((1ull << lane) - 1ull))] = k;
+      ncand += __popcll(bm);
+    }
+    __syncthreads();
+    // pieces per candidate: a box is one piece, any other cell one per surface tetrahedron
+    for (int kc = lane; kc < ncand; kc += kFluxLanes) {
+      int k = cand[kc];
+      int np = 1;
+      if (!M.isbox[k]) {
+        np = 0;
+        for (int i = M.cf_ptr[k]; i < M.cf_ptr[k + 1]; ++i) np += face_triangle_count(M, M.cf_idx[i]);
+      }
+      cpre[kc + 1] = np;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      cpre[0] = 0;
+      for (int kc = 0; kc < ncand; ++kc) cpre[kc + 1] += cpre[kc];
+    }
+    __syncthreads();
+    const int T3 = 3 * I;
+    const int total = cpre[ncand] * T3;
+    double acc = 0.0;
+    int qn = 0;
+    for (int q0 = 0; q0 < total || qn > 0; q0 += kFluxLanes) {
+      // ---- enumerate (tet t, candidate kc, piece m), keep overlapping boxes
+      if (q0 < total) {
+        int q = q0 + lane;
+        bool keep = false;
+        unsigned code = 0;
+        if (q < total) {
+          int t = q % T3, r = q / T3;
+          int lo = 0, hi = ncand;  // cpre[lo] <= r < cpre[lo+1]
+          while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (cpre[mid] <= r) lo = mid;
+            else hi = mid;
+          }
+          int kc = lo, m = r - cpre[lo];
+          int i = t / 3, kind = t - 3 * i;
+          int j = (i + 1 == I) ? 0 : i + 1;
+          int i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
+          int i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
+          int i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
+          d3 p1 = mk3(px[i1], py[i1], pz[i1]), p2 = mk3(px[i2], py[i2], pz[i2]), p3 = mk3(px[i3], py[i3], pz[i3]);
+          d3 tlo = vmin(vmin(c, p1), vmin(p2, p3)), thi = vmax(vmax(c, p1), vmax(p2, p3));
+          int k = cand[kc];
+          d3 klo, khi;
+          if (M.isbox[k]) {
+            klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
+            khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+          } else {
+            d3 t0, t1, t2;
+            cell_piece(M, k, m, t0, t1, t2);
+            d3 cc = cell_centre(M, k);
+            klo = vmin(vmin(cc, t0), vmin(t1, t2));
+            khi = vmax(vmax(cc, t0), vmax(t1, t2));
+          }
+          keep = box_overlap(tlo, thi, klo, khi);
+          code = ((unsigned)m << 12) | ((unsigned)kc << 5) | (unsigned)t;
+        }
+        unsigned long long bm = __ballot(keep);
+        if (keep) queue[qn + __popcll(bm & ((1ull << lane) - 1ull))] = code;
+        qn += __popcll(bm);
+      }
+      __syncthreads();
+      bool flush = (q0 + kFluxLanes >= total) || (qn + kFluxLanes > kQueue);
+      if (!flush) continue;
+      // ---- clip the queued pairs
+      for (int qi = lane; qi < qn; qi += kFluxLanes) {
+        unsigned code = queue[qi];
+        int t = code & 31, kc = (code >> 5) & 127, m = (int)(code >> 12);
+        int i = t / 3, kind = t - 3 * i;
+        int j = (i + 1 == I) ? 0 : i + 1;
+        int i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
+        int i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
+        int i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
+        Tet T{c, mk3(px[i1], py[i1], pz[i1]), mk3(px[i2], py[i2], pz[i2]), mk3(px[i3], py[i3], pz[i3])};
+        double sT = tet6(T);
+        if (sT == 0.0) continue;
+        int k = cand[kc];
+        Leaf leaf;
+        leaf.useH = M.tag_cell[k] == 0;
+        leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+        leaf.hd = M.pC[k];
+        double v;
+        if (M.isbox[k]) {
+          BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
+          v = clip_volume(T, B, leaf);
+        } else {
+          d3 t0, t1, t2;
+          cell_piece(M, k, m, t0, t1, t2);
+          d3 cc = cell_centre(M, k);
+          double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+          if (s6 == 0.0) continue;
+          TetCont TC = tet_container(cc, t0, t1, t2);
+          v = clip_volume(T, TC, leaf);
+          if (v == -1.0) {
+            atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+            v = 0.0;
+          }
+          if (s6 < 0.0) v = -v;
+        }
+        if (v == -1.0) {
+          atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+          v = 0.0;
+        }
+        acc += sT > 0.0 ? v : -v;
+      }
+      qn = 0;
+      __syncthreads();
+    }
+    // ---- fixed-order wave reduction
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) M.VF[f] = acc;
+    __syncthreads();
+  }
+}
+
+// ============================================================== update
+// Eq. (fnext) with face sums in ascending face order, then the clamp.
+__global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __restrict__ Fout) {
+  for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
+    double VdT = 0.0, VFT = 0.0;
+    for (int i = M.cf_ptr[c]; i < M.cf_ptr[c + 1]; ++i) {
+      int e = M.cf_idx[i];
+      if (e >= 0) {
+        VdT = VdT + M.Vd[e];
+        VFT = VFT + M.VF[e];
+      } else {
+        VdT = VdT - M.Vd[~e];
+        VFT = VFT - M.VF[~e];
+      }
+    }
+    double V = M.V[c];
+    double h = VdT / (2.0 * V);
+    double Fn = (Fin[c] * (1.0 + h) - VFT / V) / (1.0 - h);
+    Fout[c] = fmin(fmax(Fn, 0.0), 1.0);
+  }
+}
+
+// ============================================================== refinement initialisation
+struct Shape {
+  int kind;
+  double a, b, c, d;
+};
+
+__device__ inline bool shape_inside(const Shape& s, d3 p) {
+  if (s.kind == 0) {
+    d3 q = p - mk3(s.a, s.b, s.c);
+    return (q.x * q.x + q.y * q.y) + q.z * q.z <= s.d * s.d;
+  }
+  return dot_x(mk3(s.a, s.b, s.c), p) + s.d >= 0.0;
+}
+
+__global__ void k_init_classify(DevMesh M, Shape sh, double* __restrict__ F) {
+  int n = M.nc;
+  int stride = grid_stride();
+  int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int b = base0; b < n; b += stride) {
+    int c = b + (threadIdx.x & 63);
+    bool refine = false;
+    if (c < n) {
+      bool allin = true, allout = true;
+      for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1]; ++i) {
+        if (shape_inside(sh, vert(M, M.cv_idx[i]))) allout = false;
+        else allin = false;
+      }
+      double val = 0.0;
+      if (allin) val = 1.0;
+      else if (allout && sh.kind == 1) val = 0.0;
+      else if (allout) {
+        d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+        d3 ctr = mk3(sh.a, sh.b, sh.c);
+        d3 q = mk3(fmin(fmax(ctr.x, lo.x), hi.x), fmin(fmax(ctr.y, lo.y), hi.y), fmin(fmax(ctr.z, lo.z), hi.z));
+        d3 dd = ctr - q;
+        if ((dd.x * dd.x + dd.y * dd.y) + dd.z * dd.z > sh.d * sh.d) val = 0.0;
+        else refine = true;
+      } else refine = true;
+      F[c] = val;
+    }
+    wave_append(refine, c, &M.counters[CNT_REFINE], M.list_cells);
+  }
+}
+
+// vol(cell ∩ sub-box [∩ half-space])
+__device__ inline double cell_subbox_volume(const DevMesh& M, int c, d3 a, d3 b, const Leaf& leaf) {
+  if (M.isbox[c]) {
+    double v = 0.0;
+    for (int k = 0; k < 6; ++k) v += leaf(kuhn_tet(a, b, k));
+    return v;
+  }
+  double acc = 0.0;
+  d3 cen = cell_centre(M, c);
+  int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+  for (int i = 0; i < fn; ++i) {
+    int e = M.cf_idx[fb + i];
+    int nt = face_triangle_count(M, e);
+    for (int t = 0; t < nt; ++t) {
+      d3 t0, t1, t2;
+      face_triangle(M, e, t, t0, t1, t2);
+      d3 tlo = vmin(vmin(cen, t0), vmin(t1, t2)), thi = vmax(vmax(cen, t0), vmax(t1, t2));
+      if (!box_overlap(tlo, thi, a, b)) continue;
+      double s6 = det3f(t0 - cen, t1 - cen, t2 - cen);
+      if (s6 == 0.0) continue;
+      TetCont TC = tet_container(cen, t0, t1, t2);
+      double v = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        double w = clip_volume(kuhn_tet(a, b, k), TC, leaf);
+        if (w == -1.0) atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+        else v += w;
+      }
+      acc += s6 > 0.0 ? v : -v;
+    }
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(64) void k_init_refine(DevMesh M, Shape sh, int ndiv, double* __restrict__ F) {
+  int ncell = M.counters[CNT_REFINE];
+  const int lane = threadIdx.x;
+  for (int it = blockIdx.x; it < ncell; it += gridDim.x) {
+    int c = M.list_cells[it];
+    d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+    double nd = (double)ndiv;
+    d3 hs = mk3((hi.x - lo.x) / nd, (hi.y - lo.y) / nd, (hi.z - lo.z) / nd);
+    double acc = 0.0;
+    int nsub = ndiv * ndiv * ndiv;
+    for (int q = lane; q < nsub; q += 64) {
+      int kx = q % ndiv, ky = (q / ndiv) % ndiv, kz = q / (ndiv * ndiv);
+      d3 a = mk3(lo.x + (double)kx * hs.x, lo.y + (double)ky * hs.y, lo.z + (double)kz * hs.z);
+      d3 b = mk3(lo.x + (double)(kx + 1) * hs.x, lo.y + (double)(ky + 1) * hs.y, lo.z + (double)(kz + 1) * hs.z);
+      int nin = 0;
+      for (int r = 0; r < 8; ++r) {
+        d3 p = mk3((r & 1) ? b.x : a.x, (r & 2) ? b.y : a.y, (r & 4) ? b.z : a.z);
+        nin += shape_inside(sh, p) ? 1 : 0;
+      }
+      if (nin == 0) continue;
+      Leaf leaf;
+      leaf.useH = false;
+      leaf.hn = mk3(0.0, 0.0, 0.0);
+      leaf.hd = 0.0;
+      if (nin < 8) {
+        if (sh.kind == 0) {
+          d3 cs = mk3(0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z));
+          d3 r = cs - mk3(sh.a, sh.b, sh.c);
+          double rl = sqrt(dotf(r, r));
+          if (rl > 0.0) {
+            leaf.useH = true;
+            leaf.hn = mk3(-r.x / rl, -r.y / rl, -r.z / rl);
+            leaf.hd = (sh.d - rl) - dotf(leaf.hn, cs);
+          }
+        } else {
+          leaf.useH = true;
+          leaf.hn = mk3(sh.a, sh.b, sh.c);
+          leaf.hd = sh.d;
+        }
+      }
+      acc += cell_subbox_volume(M, c, a, b, leaf);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) F[c] = acc / M.V[c];
+  }
+}
+
+// ============================================================== launchers
+static inline int blocks_for(long n, int threads, int cap = 1 << 16) {
+  long b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+hipError_t launch_zero(int* p, int n, hipStream_t s) {
+  k_zero<<<blocks_for(n, 256), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
+  k_face_geom<<<blocks_for(M.nf, 256), 256, 0, s>>>(M);
+  k_cell_geom<<<blocks_for(M.nc, 256), 256, 0, s>>>(M);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s) {
+  k_zero<<<1, 64, 0, s>>>(M.counters + CNT_CELLS, 1);
+  k_node_tag<<<blocks_for(M.nv, 256), 256, 0, s>>>(M, F);
+  k_face_tag<<<blocks_for(M.nf, 256), 256, 0, s>>>(M);
+  k_cell_tag<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, F);
+  k_recon<<<blocks_for(M.nc, 128, 2048), 128, 0, s>>>(M, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
+                         double* Fout, hipStream_t s) {
+  k_zero<<<1, 64, 0, s>>>(M.counters + CNT_FACES, 1);
+  k_face_sweep<<<blocks_for(M.nf, 256), 256, 0, s>>>(M, uf, dt);
+  k_flux<<<blocks_for(M.nf, 1, 4096), kFluxLanes, 0, s>>>(M, uv, dt);
+  k_update<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, Fin, Fout);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s) {
+  Shape sh{kind, p[0], p[1], p[2], p[3]};
+  k_zero<<<1, 64, 0, s>>>(M.counters + CNT_REFINE, 1);
+  k_init_classify<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, sh, F);
+  k_init_refine<<<blocks_for(M.nc, 1, 4096), 64, 0, s>>>(M, sh, ndiv, F);
+  return hipGetLastError();
+}
+
+}  // namespace gvof

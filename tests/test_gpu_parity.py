@@ -1,0 +1,160 @@
+"""HIP library vs CPU oracle, element by element, through the C interface.
+
+Bars: integer outputs (tags, upwind cells, box flags) and the quantities that
+decide them (face area vectors, face and cell vertex means, node values) bit
+for bit; volume fractions within 1e-12 per cell; planes and face volumes
+within round-off scaled tolerances stated in each test.  Parity of the
+advection is teacher-forced: both sides step from the oracle's F^n.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2111_01524_amd import inputs
+from tests.gpu_common import host, log, max_abs, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+SPHERE = [0.35, 0.35, 0.35, 0.15]
+
+
+def make_mesh(kind, n, seed=1):
+    return inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=seed)
+
+
+@pytest.fixture(scope="module")
+def gv():
+    from paper_2111_01524_amd import gvof
+    gvof.lib()
+    return gvof
+
+
+@pytest.mark.parametrize("kind,n", [("cartesian", 9), ("jittered", 7)])
+def test_geometry_bitwise(oracle_mod, gv, kind, n):
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    log(f"geometry {kind} n={n}")
+    g = gv.GvofMesh(m, dev)
+    G = {k: host(v) for k, v in g.geometry().items()}
+    torch.cuda.synchronize()
+    R = oracle_mod.OracleMesh(m).geometry()
+    for k in ("S", "fc", "cc", "bbmin", "bbmax"):
+        assert np.array_equal(G[k], R[k]), k
+    assert np.array_equal(G["isbox"], R["isbox"])
+    assert max_abs(G["V"], R["V"]) <= 1e-15 * R["V"].max()
+
+
+@pytest.mark.parametrize("kind,n,ndiv", [("cartesian", 16, 10), ("jittered", 10, 4)])
+def test_init_fraction_parity(oracle_mod, gv, kind, n, ndiv):
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    log(f"init {kind} n={n} ndiv={ndiv}")
+    g = gv.GvofMesh(m, dev)
+    Fg = host(g.init_fraction("sphere", SPHERE, ndiv))
+    Fo = oracle_mod.OracleMesh(m).init_fraction("sphere", SPHERE, ndiv)
+    assert np.array_equal(Fg == 0, Fo == 0) and np.array_equal(Fg == 1, Fo == 1)
+    assert max_abs(Fg, Fo) <= 1e-12
+    g.status()
+
+
+def reconstruct_both(oracle_mod, g, om, F, torch, dev):
+    Fd = to_dev(torch, dev, F)
+    tags_c, planes = g.reconstruct(Fd, want_tags=True, want_planes=True)
+    T = {k: host(v) for k, v in g.tags().items()}
+    Fcut_g = host(Fd)
+    Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
+    return (Fd, T, host(tags_c), host(planes), Fcut_g), (Fc, Fs, tn, tf, tc, pl)
+
+
+@pytest.mark.parametrize("kind,n", [("cartesian", 16), ("jittered", 12)])
+def test_reconstruct_parity(oracle_mod, gv, kind, n):
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    log(f"reconstruct {kind} n={n}")
+    om = oracle_mod.OracleMesh(m)
+    g = gv.GvofMesh(m, dev)
+    F = om.init_fraction("sphere", [0.47, 0.52, 0.49, 0.31], 6)
+    rng = np.random.default_rng(4)
+    F = np.where(rng.uniform(size=F.shape) < 0.02, rng.choice([1e-13, 1 - 1e-13, 0.5], F.shape), F)
+    (Fd, T, tc_g, pl_g, Fcut_g), (Fc, Fs, tn, tf, tc, pl) = reconstruct_both(oracle_mod, g, om, F, torch, dev)
+    assert np.array_equal(T["node_value"], Fs)
+    assert np.array_equal(T["node"], tn)
+    assert np.array_equal(T["face"], tf)
+    assert np.array_equal(T["cell"], tc) and np.array_equal(tc_g, tc)
+    assert np.array_equal(Fcut_g, Fc)
+    sel = tc == 0
+    assert sel.sum() > 50
+    dn = np.abs(pl_g[:3, sel] - pl[:3, sel]).max()
+    dC = np.abs(pl_g[3, sel] - pl[3, sel]).max()
+    log(f"  interfacial={sel.sum()} max|dn|={dn:.2e} max|dC|={dC:.2e}")
+    assert dn <= 1e-12 and dC <= 1e-12
+    assert np.all(pl_g[:, ~sel] == 0)
+    nc, nfc = g.interface_counts()
+    assert nc == sel.sum()
+    g.status()
+
+
+def _velocity(kind_field, m):
+    if kind_field == "uniform":
+        return inputs.velocity_uniform(m, (1.0, 1.0, 1.0))
+    return inputs.velocity_enright(m)
+
+
+@pytest.mark.parametrize("kind,n,field,steps", [
+    ("cartesian", 16, "uniform", 20),     # the 16^3 translation workload, every step
+    ("cartesian", 20, "enright", 6),
+    ("jittered", 12, "enright", 4),
+    ("jittered", 10, "uniform", 4),
+])
+def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps):
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    om = oracle_mod.OracleMesh(m)
+    g = gv.GvofMesh(m, dev)
+    uf, uv = _velocity(field, m)
+    dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
+    ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
+    F = om.init_fraction("sphere", SPHERE, 10 if kind == "cartesian" else 4)
+    V = om.geometry()["V"]
+    worst = 0.0
+    for s in range(steps):
+        log(f"advect {kind} n={n} {field} step {s}")
+        sgn = 1.0 if field == "uniform" else inputs.enright_time_factor((s + 0.5) * dt, 3.0)
+        dts = dt * sgn
+        (Fd, T, tc_g, pl_g, Fcut_g), (Fc, Fs, tn, tf, tc, pl) = reconstruct_both(oracle_mod, g, om, F, torch, dev)
+        assert np.array_equal(T["cell"], tc) and np.array_equal(T["face"], tf)
+        Fout = torch.empty_like(Fd)
+        up_g, vd_g, vf_g = g.advect_step(ufd, uvd, dts, Fd, Fout, want_faces=True)
+        F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dts, Fc)
+        assert bad == 0
+        g.status()
+        assert np.array_equal(host(vd_g), Vd)
+        assert np.array_equal(host(up_g), up)
+        dVF = np.abs(host(vf_g) - VF).max() / V.max()
+        dF = max_abs(host(Fout), F1)
+        worst = max(worst, dF)
+        log(f"  tag0 faces={(tf == 0).sum()} max|dVF|/V={dVF:.2e} max|dF|={dF:.2e}")
+        assert dVF <= 1e-12
+        assert dF <= 1e-12
+        F = F1
+    log(f"worst |dF| = {worst:.2e}")
+
+
+def test_step_is_deterministic(gv):
+    torch, dev = torch_dev()
+    m = make_mesh("jittered", 10)
+    g = gv.GvofMesh(m, dev)
+    uf, uv = inputs.velocity_enright(m)
+    ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
+    F0 = g.init_fraction("sphere", SPHERE, 4)
+    outs = []
+    for rep in range(2):
+        F = F0.clone()
+        for s in range(3):
+            g.reconstruct(F)
+            Fn = torch.empty_like(F)
+            g.advect_step(ufd, uvd, 0.01, F, Fn)
+            F = Fn
+        outs.append(host(F))
+    assert np.array_equal(outs[0], outs[1])

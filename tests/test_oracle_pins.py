@@ -447,3 +447,17 @@ def test_enright_conserves_volume(oracle_mod, kind):
         else:  # vertex over/underlaps of face-matched polyhedra on a coarse distorted grid
             assert abs(clamp_loss) <= 1e-3 * vol0
         F = F1
+
+
+def test_clipper_rounding_level_contact(oracle_mod):
+    """A flux tetrahedron with a face lying on a cell-tetrahedron plane up to rounding
+    (a shared mesh triangle): the exact volume has no sliver there.  Inputs recorded
+    from a 12^3 distorted-grid deformation step; the expected value is recomputed in
+    exact rationals."""
+    T = np.array([0.25438910915938712, 0.3936346767856771, 0.45914580084155115, 0.25820769469695148, 0.36605516730025078, 0.45604842573951176, 0.23412822235164393, 0.40676801814042912, 0.49518297329079636, 0.25375636046171085, 0.37298229732976285, 0.46739071612756167], float).reshape(4, 3)
+    planes = [[-0.0029462024602198347, -0.0030208098374758245, -0.001625192051542691, 0.0027233254077199415], [0.0028596259646193303, 0.00022456637755758171, 0.0015259035976204463, -0.0015164670444518173], [0.5098622381097111, -0.19180476092881607, -0.83860087755427226, 0.32755541738498162]]
+    Tq = tuple(tuple(Q(float(v)) for v in row) for row in T)
+    pq = [((Q(p[0]), Q(p[1]), Q(p[2])), Q(p[3])) for p in planes]
+    ref = float(XR.clip_volume(Tq, pq))
+    got = oracle_mod.tet_clip_volume(T, planes)
+    assert abs(got - ref) <= 1e-13 * abs(ref), (got, ref)
