@@ -1,0 +1,180 @@
+"""Throughput of the LSGIR + FMFPA VOF step on one MI355X.
+
+Workload (default): 64^3 uniform hexahedra on the unit cube, sphere r=0.15 at
+(0.35, 0.35, 0.35) initialised by refinement (10 divisions), Enright 3D
+deformation field with period T=3, CFL 0.5 (constant dt from the largest face
+velocity, last step shortened to land on T), FP64.  One "step" is one pass of
+the whole hot path: reconstruction (tags, cut-off, LSGIR, plane constants)
+followed by the advection step (face flux volumes, FMFPA flux polyhedra with
+truncation, update).  The field is u0(x) cos(pi t/T): the library receives
+u0 at faces and vertices (resident in HBM) and dt * cos(pi t^{n+1/2}/T).
+
+Prints one JSON line.  `value` = faces x steps / wall time of the timed steps
+(all faces, boundary included), inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP64 operations per face that needs a flux polyhedron (FMFPA
+# construction + truncation) and per interfacial cell (LSGIR + plane
+# constant) on this workload, counted by the FLOP-counting build of the CPU
+# reference over a sample of the trajectory (oracle/count_flops.py).
+FLOPS_PER_FLUX_FACE = 38766.0
+FLOPS_PER_RECON_CELL = 53202.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=748)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2111_01524_amd import gvof, inputs
+
+    dev = torch.device("cuda:0")
+    n, T_end, cfl = args.n, 3.0, 0.5
+    mesh = inputs.cartesian_mesh(n) if args.kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
+    g = gvof.GvofMesh(mesh, dev)
+    uf, uv = inputs.velocity_enright(mesh)
+    dt = inputs.cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
+    sched = inputs.step_schedule(T_end, dt)
+    times = np.concatenate([[0.0], np.cumsum(sched)])
+    dteff = [sched[s] * inputs.enright_time_factor(times[s] + 0.5 * sched[s], T_end) for s in range(len(sched))]
+    ufd = torch.from_numpy(uf).to(dev)
+    uvd = torch.from_numpy(uv).to(dev)
+    F0 = g.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
+    torch.cuda.synchronize()
+    state = {"s": 0}
+
+    # ping-pong without copies
+    bufs = [F0.clone(), torch.empty_like(F0)]
+
+    def step_pp():
+        s = state["s"]
+        if s == len(sched):
+            bufs[0].copy_(F0)
+            s = 0
+        g.reconstruct(bufs[0])
+        g.advect_step(ufd, uvd, dteff[s], bufs[0], bufs[1])
+        bufs[0], bufs[1] = bufs[1], bufs[0]
+        state["s"] = s + 1
+
+    for _ in range(args.warmup):
+        step_pp()
+    torch.cuda.synchronize()
+    g.status()
+    c0, f0 = gvof.gvof_work_totals(g.h)
+    mask = (1 << 7) - 1 if args.profile_all else (1 << 5)  # k_flux
+    gvof.gvof_profile_enable(g.h, mask)
+    gvof.gvof_profile_read(g.h)  # clear
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step_pp()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = e0.elapsed_time(e1)
+    prof = gvof.gvof_profile_read(g.h)
+    gvof.gvof_profile_enable(g.h, 0)
+    g.status()
+    c1, f1 = gvof.gvof_work_totals(g.h)
+    ncells_work, nfaces_work = c1 - c0, f1 - f0
+    K = args.steps
+    value = mesh.nf * K / (ms_total / 1e3)
+    flux_ms, flux_n = prof["k_flux"]
+    flux_ms_avg = flux_ms / max(flux_n, 1)
+    flux_flops_per_launch = FLOPS_PER_FLUX_FACE * nfaces_work / max(flux_n, 1)
+    achieved_tflops = flux_flops_per_launch / (flux_ms_avg / 1e3) / 1e12 if flux_ms_avg > 0 else 0.0
+    out = {
+        "metric": "face·step flux updates/s",
+        "value": value,
+        "unit": "face·steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_total / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.kind} {n}^3 unit cube, sphere r=0.15 at 0.35, Enright deformation T=3, CFL 0.5, "
+                        f"LSGIR+FMFPA, {len(sched)} steps per trajectory",
+            "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
+        },
+        "cells_per_s": mesh.nc * K / (ms_total / 1e3),
+        "interfacial_faces_per_step": nfaces_work / K,
+        "interfacial_cells_per_step": ncells_work / K,
+        "wall_s": t_wall,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_flux",
+            "achieved": achieved_tflops,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": flux_ms_avg,
+            "flops_per_flux_face": FLOPS_PER_FLUX_FACE,
+        },
+    }
+    if args.profile_all:
+        out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s):
+    """The CPU reference (as it stands) on the host cores: the first steps of the same trajectory."""
+    from oracle import oracle as O
+    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
+    om = O.OracleMesh(mesh)
+    F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
+    t0 = time.perf_counter()
+    done = 0
+    while done < len(sched):
+        Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
+        F, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dteff[done], Fc)
+        done += 1
+        if time.perf_counter() - t0 > budget_s and done >= 2:
+            break
+    el = time.perf_counter() - t0
+    return {"value": mesh.nf * done / el, "unit": "face·steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} steps of the same trajectory from t=0 on the full mesh ({el:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

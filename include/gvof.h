@@ -178,6 +178,25 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
  */
 int gvof_interface_counts(gvof_mesh* m, int32_t* n_cells, int32_t* n_faces);
 
+/*
+ * Cumulative work counters since bind (device-side, no synchronisation per
+ * step): interfacial cells reconstructed and faces given flux polyhedra,
+ * summed over every call.  Synchronous read.
+ */
+int gvof_work_totals(gvof_mesh* m, int64_t* cells, int64_t* faces);
+
+/*
+ * Kernel timing instrumentation (not part of the method).  While enabled, the
+ * kernels selected by `mask` (bit k = kernel k of gvof_kernel_name) are
+ * bracketed by HIP events recorded on the handle's stream.  gvof_profile_read
+ * synchronises, writes for every kernel k < n the summed milliseconds and the
+ * number of timed launches, and clears the record.
+ */
+#define GVOF_NUM_KERNELS 7
+int gvof_profile_enable(gvof_mesh* m, uint32_t mask);
+int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches);
+const char* gvof_kernel_name(int32_t k);
+
 /* Synchronises the stream and returns GVOF_OK or the sticky GVOF_E_GEOM. */
 int gvof_status(gvof_mesh* m);
 

@@ -21,6 +21,39 @@
 
 using gvof::DevMesh;
 
+// Per-kernel HIP event pairs recorded on the handle's stream.
+struct EventProf : gvof::Prof {
+  hipStream_t stream = nullptr;
+  uint32_t mask = 0;
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t pending = nullptr;
+  void before(int k) override {
+    if (!((mask >> k) & 1u)) return;
+    hipEventCreate(&pending);
+    hipEventRecord(pending, stream);
+  }
+  void after(int k) override {
+    if (!((mask >> k) & 1u) || !pending) return;
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, stream);
+    recs.push_back({k, pending, e});
+    pending = nullptr;
+  }
+  void clear() {
+    for (auto& r : recs) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+  ~EventProf() override { clear(); }
+};
+
 struct gvof_mesh {
   int nv = 0, nf = 0, nc = 0;
   gvof_params p{};
@@ -36,6 +69,7 @@ struct gvof_mesh {
   DevMesh dm{};
   bool bound = false, reconstructed = false;
   std::string err;
+  EventProf prof;
 };
 
 static thread_local std::string g_create_err;
@@ -271,6 +305,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.list_cells = C.take<int>(nc);
   d.list_faces = C.take<int>(nf);
   d.counters = C.take<int>(gvof::CNT_N);
+  d.totals = C.take<unsigned long long>(2);
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
@@ -319,6 +354,7 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
   if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
+  HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 4, s));
   HIPCHECK(m, gvof::launch_geometry(d, s));
   int cnt[gvof::CNT_N];
   HIPCHECK(m, hipMemcpyAsync(cnt, d.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
@@ -394,7 +430,8 @@ int gvof_reconstruct(gvof_mesh* m, double* F, int8_t* cell_tag_out, double* plan
   int r = need_bound(m);
   if (r) return r;
   if (!F) return fail(m, GVOF_E_ARG, "F is NULL");
-  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->stream));
+  m->prof.stream = m->stream;
+  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->stream, m->prof.mask ? &m->prof : nullptr));
   m->reconstructed = true;
   if ((r = d2d(m, cell_tag_out, m->dm.tag_cell, m->nc))) return r;
   return d2d(m, plane_out, m->dm.pnx, 4 * (size_t)m->nc * 8);
@@ -417,7 +454,9 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
   if (!m->reconstructed) return fail(m, GVOF_E_ARG, "gvof_advect_step needs a preceding gvof_reconstruct");
   if (!u_face || !u_vert || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
   if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
-  HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->stream));
+  m->prof.stream = m->stream;
+  HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->stream,
+                                  m->prof.mask ? &m->prof : nullptr));
   if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
   if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;
   return d2d(m, vf_out, m->dm.VF, (size_t)m->nf * 8);
@@ -451,5 +490,48 @@ int gvof_status(gvof_mesh* m) {
 }
 
 const char* gvof_last_error(const gvof_mesh* m) { return m ? m->err.c_str() : g_create_err.c_str(); }
+
+int gvof_work_totals(gvof_mesh* m, int64_t* cells, int64_t* faces) {
+  int r = need_bound(m);
+  if (r) return r;
+  unsigned long long t[2];
+  HIPCHECK(m, hipMemcpyAsync(t, m->dm.totals, sizeof t, hipMemcpyDeviceToHost, m->stream));
+  HIPCHECK(m, hipStreamSynchronize(m->stream));
+  if (cells) *cells = (int64_t)t[0];
+  if (faces) *faces = (int64_t)t[1];
+  return GVOF_OK;
+}
+
+int gvof_profile_enable(gvof_mesh* m, uint32_t mask) {
+  if (!m) return GVOF_E_ARG;
+  m->prof.mask = mask;
+  return GVOF_OK;
+}
+
+int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches) {
+  if (!m) return GVOF_E_ARG;
+  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(m, GVOF_E_ARG, "bad output arrays");
+  HIPCHECK(m, hipStreamSynchronize(m->stream));
+  for (int k = 0; k < n; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& rec : m->prof.recs) {
+    float t = 0.f;
+    HIPCHECK(m, hipEventElapsedTime(&t, rec.a, rec.b));
+    if (rec.k < n) {
+      ms[rec.k] += t;
+      launches[rec.k] += 1;
+    }
+  }
+  m->prof.clear();
+  return GVOF_OK;
+}
+
+const char* gvof_kernel_name(int32_t k) {
+  static const char* names[gvof::K_COUNT] = {"k_node_tag", "k_face_tag", "k_cell_tag", "k_recon",
+                                             "k_face_sweep", "k_flux", "k_update"};
+  return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";
+}
 
 }  // extern "C"

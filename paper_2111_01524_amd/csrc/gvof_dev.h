@@ -34,6 +34,7 @@ struct DevMesh {
   int* upwind;
   int *list_cells, *list_faces;
   int* counters;  // [0] tag-0 cells, [1] tag-0 faces, [2] geometry error flags, [3] refine cells
+  unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra (cumulative)
   double eps, beta, degen;
 };
 

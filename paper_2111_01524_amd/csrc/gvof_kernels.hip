@@ -19,13 +19,16 @@ __device__ inline int grid_stride_start() { return blockIdx.x * blockDim.x + thr
 __device__ inline int grid_stride() { return gridDim.x * blockDim.x; }
 
 // Wave-aggregated append of `item` when `pred`: one atomic per wave, slots in lane order.
-__device__ inline void wave_append(bool pred, int item, int* counter, int* list) {
+__device__ inline void wave_append(bool pred, int item, int* counter, int* list, unsigned long long* total = nullptr) {
   unsigned long long m = __ballot(pred);
   if (m == 0) return;
   int lane = __lane_id();
   int leader = __ffsll((long long)m) - 1;
   int base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  if (lane == leader) {
+    base = atomicAdd(counter, __popcll(m));
+    if (total) atomicAdd(total, (unsigned long long)__popcll(m));
+  }
   base = __shfl(base, leader);
   if (pred) {
     unsigned long long below = m & ((1ull << lane) - 1ull);
@@ -218,7 +221,7 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
         M.pC[c] = 0.0;
       }
     }
-    wave_append(inter, c, &M.counters[CNT_CELLS], M.list_cells);
+    wave_append(inter, c, &M.counters[CNT_CELLS], M.list_cells, &M.totals[0]);
   }
 }
 
@@ -396,7 +399,7 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
       else if (t == 1) M.VF[f] = vd;
       else geo = true;
     }
-    wave_append(geo, f, &M.counters[CNT_FACES], M.list_faces);
+    wave_append(geo, f, &M.counters[CNT_FACES], M.list_faces, &M.totals[1]);
   }
 }
 
@@ -836,21 +839,28 @@ hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s) {
+#define TIMED(k, launch)          \
+  do {                            \
+    if (prof) prof->before(k);    \
+    launch;                       \
+    if (prof) prof->after(k);     \
+  } while (0)
+
+hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s, Prof* prof) {
   k_zero<<<1, 64, 0, s>>>(M.counters + CNT_CELLS, 1);
-  k_node_tag<<<blocks_for(M.nv, 256), 256, 0, s>>>(M, F);
-  k_face_tag<<<blocks_for(M.nf, 256), 256, 0, s>>>(M);
-  k_cell_tag<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, F);
-  k_recon<<<blocks_for(M.nc, 128, 2048), 128, 0, s>>>(M, F);
+  TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, 256), 256, 0, s>>>(M, F)));
+  TIMED(K_FACE_TAG, (k_face_tag<<<blocks_for(M.nf, 256), 256, 0, s>>>(M)));
+  TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, F)));
+  TIMED(K_RECON, (k_recon<<<blocks_for(M.nc, 128, 2048), 128, 0, s>>>(M, F)));
   return hipGetLastError();
 }
 
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, hipStream_t s) {
+                         double* Fout, hipStream_t s, Prof* prof) {
   k_zero<<<1, 64, 0, s>>>(M.counters + CNT_FACES, 1);
-  k_face_sweep<<<blocks_for(M.nf, 256), 256, 0, s>>>(M, uf, dt);
-  k_flux<<<blocks_for(M.nf, 1, 4096), kFluxLanes, 0, s>>>(M, uv, dt);
-  k_update<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, Fin, Fout);
+  TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, 256), 256, 0, s>>>(M, uf, dt)));
+  TIMED(K_FLUX, (k_flux<<<blocks_for(M.nf, 1, 4096), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, Fin, Fout)));
   return hipGetLastError();
 }
 

@@ -5,10 +5,17 @@
 #include "gvof_dev.h"
 
 namespace gvof {
+enum KernelId { K_NODE_TAG = 0, K_FACE_TAG, K_CELL_TAG, K_RECON, K_FACE_SWEEP, K_FLUX, K_UPDATE, K_COUNT };
+// Optional per-kernel event bracketing: before(k)/after(k) are called around kernel k's launch.
+struct Prof {
+  virtual ~Prof() {}
+  virtual void before(int k) = 0;
+  virtual void after(int k) = 0;
+};
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
-hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s);
+hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s, Prof* prof = nullptr);
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, hipStream_t s);
+                         double* Fout, hipStream_t s, Prof* prof = nullptr);
 hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s);
 }  // namespace gvof

@@ -68,9 +68,15 @@ def lib() -> C.CDLL:
         L.gvof_status.argtypes = [_vp]
         L.gvof_last_error.argtypes = [_vp]
         L.gvof_last_error.restype = C.c_char_p
+        L.gvof_work_totals.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.gvof_profile_enable.argtypes = [_vp, C.c_uint32]
+        L.gvof_profile_read.argtypes = [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.gvof_kernel_name.argtypes = [C.c_int32]
+        L.gvof_kernel_name.restype = C.c_char_p
         for name in ("gvof_mesh_create", "gvof_mesh_workspace_bytes", "gvof_mesh_bind", "gvof_set_stream",
                      "gvof_mesh_sizes", "gvof_get_geometry", "gvof_init_fraction", "gvof_reconstruct",
-                     "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status"):
+                     "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status",
+                     "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -81,7 +87,7 @@ def exported_symbols():
     return ["gvof_params_default", "gvof_mesh_create", "gvof_mesh_workspace_bytes", "gvof_mesh_bind",
             "gvof_set_stream", "gvof_mesh_destroy", "gvof_mesh_sizes", "gvof_get_geometry", "gvof_init_fraction",
             "gvof_reconstruct", "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status",
-            "gvof_last_error"]
+            "gvof_last_error", "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_kernel_name"]
 
 
 def _check(code, handle=None):
@@ -187,6 +193,30 @@ def gvof_status(h):
     code = lib().gvof_status(h)
     _check(code, h)
     return code
+
+
+GVOF_NUM_KERNELS = 7
+
+
+def gvof_work_totals(h):
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().gvof_work_totals(h, C.byref(a), C.byref(b)), h)
+    return a.value, b.value
+
+
+def gvof_profile_enable(h, mask: int):
+    _check(lib().gvof_profile_enable(h, mask), h)
+
+
+def gvof_profile_read(h):
+    ms = (C.c_double * GVOF_NUM_KERNELS)()
+    n = (C.c_int64 * GVOF_NUM_KERNELS)()
+    _check(lib().gvof_profile_read(h, GVOF_NUM_KERNELS, ms, n), h)
+    return {gvof_kernel_name(k): (ms[k], n[k]) for k in range(GVOF_NUM_KERNELS)}
+
+
+def gvof_kernel_name(k: int) -> str:
+    return lib().gvof_kernel_name(k).decode()
 
 
 def gvof_last_error(h=None) -> str:
