@@ -27,10 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic FP64 operations per face that needs a flux polyhedron (FMFPA
-# construction + truncation) and per interfacial cell (LSGIR + plane
-# constant) on this workload, counted by the FLOP-counting build of the CPU
-# reference over a sample of the trajectory (oracle/count_flops.py).
+# construction + truncation, and the truncation alone, which k_flux_items
+# performs) and per interfacial cell (LSGIR + plane constant) on this
+# workload, counted by the FLOP-counting build of the CPU reference over a
+# sample of the trajectory (oracle/count_flops.py).
 FLOPS_PER_FLUX_FACE = 38766.0
+FLOPS_PER_FLUX_FACE_TRUNCATION = 37578.0
 FLOPS_PER_RECON_CELL = 53202.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -91,7 +93,7 @@ def main():
     torch.cuda.synchronize()
     g.status()
     c0, f0 = gvof.gvof_work_totals(g.h)
-    mask = (1 << 7) - 1 if args.profile_all else (1 << 5)  # k_flux
+    mask = (1 << gvof.GVOF_NUM_KERNELS) - 1 if args.profile_all else (1 << 5)  # k_flux_items_box
     gvof.gvof_profile_enable(g.h, mask)
     gvof.gvof_profile_read(g.h)  # clear
     stream = torch.cuda.current_stream(dev)
@@ -112,9 +114,9 @@ def main():
     ncells_work, nfaces_work = c1 - c0, f1 - f0
     K = args.steps
     value = mesh.nf * K / (ms_total / 1e3)
-    flux_ms, flux_n = prof["k_flux"]
+    flux_ms, flux_n = prof["k_flux_items_box"]
     flux_ms_avg = flux_ms / max(flux_n, 1)
-    flux_flops_per_launch = FLOPS_PER_FLUX_FACE * nfaces_work / max(flux_n, 1)
+    flux_flops_per_launch = FLOPS_PER_FLUX_FACE_TRUNCATION * nfaces_work / max(flux_n, 1)
     achieved_tflops = flux_flops_per_launch / (flux_ms_avg / 1e3) / 1e12 if flux_ms_avg > 0 else 0.0
     out = {
         "metric": "face·step flux updates/s",
@@ -140,14 +142,16 @@ def main():
         "wall_s": t_wall,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_flux",
+            "kernel": "k_flux_items_box",
             "achieved": achieved_tflops,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": None,
             "avg_launch_ms": flux_ms_avg,
-            "flops_per_flux_face": FLOPS_PER_FLUX_FACE,
+            "flops_per_unit": FLOPS_PER_FLUX_FACE_TRUNCATION,
+            "unit_of_work": "face needing a flux polyhedron (truncation FLOPs)",
+            "units_per_launch": nfaces_work / max(flux_n, 1),
         },
     }
     if args.profile_all:

@@ -46,7 +46,7 @@ def main():
     F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
     rng = np.random.default_rng(0)
     t = 0.0
-    face_flops, face_n, cell_flops, cell_n = 0, 0, 0, 0
+    face_flops, face_n, cell_flops, cell_n, poly_flops = 0, 0, 0, 0, 0
     t0 = time.time()
     for s in range(max(sample_steps) + 1):
         dts = sched[s] * inputs.enright_time_factor(t + 0.5 * sched[s], 3.0)
@@ -55,8 +55,12 @@ def main():
             faces = np.where(tf == 0)[0]
             sel = rng.choice(faces, min(args.faces, faces.size), replace=False)
             cm.flops_reset()
-            cm.face_flux(pl, tc, tf, uf, uv, dts, faces=sel)
+            Vd_s, VF_s, up_s, bad_s = cm.face_flux(pl, tc, tf, uf, uv, dts, faces=sel)
             face_flops += cm.flops(); face_n += sel.size
+            cm.flops_reset()
+            for f, vd in zip(sel, Vd_s):
+                cm.flux_polyhedron(int(f), uv, dts, float(vd))
+            poly_flops += cm.flops()
             cells = np.where(tc == 0)[0]
             csel = rng.choice(cells, min(args.cells, cells.size), replace=False)
             tsel = np.full(m.nc, -1, np.int8); tsel[csel] = 0
@@ -70,6 +74,8 @@ def main():
         t += sched[s]
     print(f"workload: {args.kind} {args.n}^3 Enright T=3 CFL 0.5, dt={dt:.6g}; sampled steps {sample_steps}")
     print(f"FLOPS_PER_FLUX_FACE {face_flops / face_n:.1f}  (sample {face_n} faces)")
+    print(f"  of which FMFPA polyhedron (with its signed-volume check) {poly_flops / face_n:.1f}, "
+          f"truncation {(face_flops - poly_flops) / face_n:.1f}")
     print(f"FLOPS_PER_RECON_CELL {cell_flops / cell_n:.1f}  (sample {cell_n} cells)")
     print(f"elapsed {time.time() - t0:.1f}s")
 

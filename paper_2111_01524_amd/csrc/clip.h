@@ -166,6 +166,138 @@ __host__ __device__ double clip_volume(const Tet& T, const Cont& C, const Leaf& 
   return acc;
 }
 
+// One split of a tetrahedron by an affine function with vertex values s
+// (kept side s >= 0), with its children generated on demand so that a chain
+// of splits stays in registers.
+struct Split {
+  d3 a, b, c, d;
+  double sa, sb, sc, sd;
+  int kind;  // 0 nothing kept, 1 kept whole, 2 one vertex kept, 3 three kept (prism), 4 two kept (wedge)
+  __host__ __device__ inline Split(const Tet& t, double s0, double s1, double s2, double s3) {
+    a = t.p0; b = t.p1; c = t.p2; d = t.p3;
+    sa = s0; sb = s1; sc = s2; sd = s3;
+    double mx = fmax(fmax(s0, s1), fmax(s2, s3)), mn = fmin(fmin(s0, s1), fmin(s2, s3));
+    if (mx <= 0.0) kind = 0;
+    else if (mn >= 0.0) kind = 1;
+    else {
+      cs_pt(sa, a, sb, b);
+      cs_pt(sc, c, sd, d);
+      cs_pt(sa, a, sc, c);
+      cs_pt(sb, b, sd, d);
+      cs_pt(sb, b, sc, c);
+      kind = (sb <= 0.0) ? 2 : ((sc >= 0.0) ? 3 : 4);
+    }
+  }
+  __host__ __device__ inline int count() const { return kind == 0 ? 0 : (kind <= 2 ? 1 : 3); }
+  __host__ __device__ inline Tet child(int i) const {
+    if (kind == 1) return Tet{a, b, c, d};
+    if (kind == 2) return Tet{a, cut_pt(a, sa, b, sb), cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd)};
+    if (kind == 3) {
+      d3 pa = cut_pt(a, sa, d, sd), pb = cut_pt(b, sb, d, sd);
+      if (i == 0) return Tet{a, b, c, pa};
+      if (i == 1) return Tet{b, c, pa, pb};
+      return Tet{c, pa, pb, cut_pt(c, sc, d, sd)};
+    }
+    d3 P1 = cut_pt(a, sa, c, sc), P4 = cut_pt(b, sb, d, sd);
+    if (i == 0) return Tet{a, P1, cut_pt(a, sa, d, sd), b};
+    if (i == 1) return Tet{P1, cut_pt(a, sa, d, sd), b, P4};
+    return Tet{P1, b, P4, cut_pt(b, sb, c, sc)};
+  }
+};
+
+// Clip by one or two planes given by index (planes known to cut the original
+// tetrahedron): registers only.
+template <class Cont>
+__host__ __device__ inline double clip1(const Tet& t, const Cont& C, int l, const Leaf& leaf) {
+  Split sp(t, C.dist(l, t.p0), C.dist(l, t.p1), C.dist(l, t.p2), C.dist(l, t.p3));
+  int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += leaf(sp.child(i));
+  return acc;
+}
+template <class Cont>
+__host__ __device__ inline double clip2(const Tet& t, const Cont& C, int l1, int l2, const Leaf& leaf) {
+  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
+  int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip1(sp.child(i), C, l2, leaf);
+  return acc;
+}
+template <class Cont>
+__host__ __device__ inline double clip3(const Tet& t, const Cont& C, int l1, int l2, int l3, const Leaf& leaf) {
+  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
+  int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip2(sp.child(i), C, l2, l3, leaf);
+  return acc;
+}
+template <class Cont>
+__host__ __device__ inline double clip4(const Tet& t, const Cont& C, int l1, int l2, int l3, int l4,
+                                         const Leaf& leaf) {
+  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
+  int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip3(sp.child(i), C, l2, l3, l4, leaf);
+  return acc;
+}
+
+// Cut mask of T against the container (bit l: plane l cuts T); returns false
+// when T lies entirely outside one plane.
+template <class Cont>
+__host__ __device__ inline bool cut_mask(const Tet& T, const Cont& C, unsigned& cut) {
+  cut = 0;
+  for (int l = 0; l < Cont::np; ++l) {
+    double s0 = C.dist(l, T.p0), s1 = C.dist(l, T.p1), s2 = C.dist(l, T.p2), s3 = C.dist(l, T.p3);
+    double mx = fmax(fmax(s0, s1), fmax(s2, s3)), mn = fmin(fmin(s0, s1), fmin(s2, s3));
+    if (mx <= 0.0) return false;
+    if (mn < 0.0) cut |= 1u << l;
+  }
+  return true;
+}
+
+// vol(T ∩ container ∩ leaf half-space) for a precomputed cut mask with at
+// most kMaxRegCuts cutting planes, in registers.  On the deformation workload
+// over 99.9% of box pairs are cut by at most two box planes; callers send the
+// rest to clip_volume (explicit stack) in a separate kernel.
+constexpr int kMaxRegCuts = 2;
+__host__ __device__ inline int cut_count(unsigned cut) {
+  int n = 0;
+  for (int l = 0; l < 6; ++l) n += (cut >> l) & 1u;
+  return n;
+}
+template <class Cont>
+__host__ __device__ inline double clip_masked(const Tet& T, const Cont& C, unsigned cut, const Leaf& leaf) {
+  if (cut == 0) return leaf(T);
+  int l1 = __builtin_ctz(cut);
+  unsigned rest = cut & (cut - 1u);
+  if (rest == 0) return clip1(T, C, l1, leaf);
+  return clip2(T, C, l1, (int)__builtin_ctz(rest), leaf);
+}
+
+// The same for a tetrahedron container: at most four cutting planes, all in
+// registers (MAXC limits the depth compiled in; deeper masks return -1).
+template <int MAXC = 4>
+__host__ __device__ inline double clip_masked_tet(const Tet& T, const TetCont& C, unsigned cut, const Leaf& leaf) {
+  int l[4] = {0, 0, 0, 0};
+  int n = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if ((cut >> q) & 1u) {
+      l[0] = n == 0 ? q : l[0];
+      l[1] = n == 1 ? q : l[1];
+      l[2] = n == 2 ? q : l[2];
+      l[3] = n == 3 ? q : l[3];
+      ++n;
+    }
+  }
+  if (n == 0) return leaf(T);
+  if (n == 1) return clip1(T, C, l[0], leaf);
+  if (n == 2) return clip2(T, C, l[0], l[1], leaf);
+  if (MAXC >= 3 && n == 3) return clip3(T, C, l[0], l[1], l[2], leaf);
+  if (MAXC >= 4) return clip4(T, C, l[0], l[1], l[2], l[3], leaf);
+  return -1.0;
+}
+
 // Volume of an axis-aligned box cut by {n.x >= s}: six Kuhn tetrahedra along
 // the lo-hi diagonal, each V/6, closed form per tetrahedron.  lev[i] = n.corner_i
 // with corner i = (i&1 ? hi.x : lo.x, i&2 ? hi.y : lo.y, i&4 ? hi.z : lo.z).

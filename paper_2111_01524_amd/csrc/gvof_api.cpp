@@ -304,8 +304,33 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.upwind = C.take<int>(nf);
   d.list_cells = C.take<int>(nc);
   d.list_faces = C.take<int>(nf);
+  {
+    int maxI = 3;
+    for (size_t f = 0; f < nf; ++f) maxI = std::max(maxI, m->fv_ptr[f + 1] - m->fv_ptr[f]);
+    d.pts_per_slot = 2 * maxI + 1;
+    d.poly_cap = (int)std::min<size_t>(nf, std::max<size_t>(65536, nf / 4));
+    d.item_cap = (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 4 * nf));
+    d.item_cap -= d.item_cap % gvof::kItemRegions;
+  }
+  d.poly = C.take<double>((size_t)d.poly_cap * d.pts_per_slot * 3);
+  d.item_off = C.take<int>(d.poly_cap);
+  d.item_cnt = C.take<int>(d.poly_cap);
+  d.item_slot = C.take<int>(d.item_cap);
+  d.item_cell = C.take<int>(d.item_cap);
+  d.item_tm = C.take<unsigned short>(d.item_cap);
+  d.item_vol = C.take<double>(d.item_cap);
+  d.list_over = C.take<int>(nf);
+  d.list_deep = C.take<int>(d.item_cap);
+  d.item_fill = C.take<int>(gvof::kItemRegions);
+  d.item_uoff = C.take<int>(d.item_cap);
+  d.item_ucnt = C.take<int>(d.item_cap);
+  d.unit_item = C.take<int>(d.item_cap);
+  d.unit_code = C.take<unsigned>(d.item_cap);
+  d.unit_vol = C.take<double>(d.item_cap);
+  d.unit_fill = C.take<int>(gvof::kItemRegions);
+  d.list_udeep = C.take<int>(d.item_cap);
   d.counters = C.take<int>(gvof::CNT_N);
-  d.totals = C.take<unsigned long long>(2);
+  d.totals = C.take<unsigned long long>(4);
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
@@ -354,7 +379,7 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
   if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
-  HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 4, s));
+  HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 8, s));
   HIPCHECK(m, gvof::launch_geometry(d, s));
   int cnt[gvof::CNT_N];
   HIPCHECK(m, hipMemcpyAsync(cnt, d.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
@@ -364,6 +389,12 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
     return fail(m, GVOF_E_MESH, "a cell is not closed or has non-positive volume");
   }
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
+  {
+    std::vector<int8_t> box(m->nc);
+    HIPCHECK(m, hipMemcpyAsync(box.data(), d.isbox, m->nc, hipMemcpyDeviceToHost, s));
+    HIPCHECK(m, hipStreamSynchronize(s));
+    d.all_box = std::all_of(box.begin(), box.end(), [](int8_t b) { return b != 0; }) ? 1 : 0;
+  }
   HIPCHECK(m, hipStreamSynchronize(s));
   m->bound = true;
   m->reconstructed = false;
@@ -530,7 +561,10 @@ int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches) {
 
 const char* gvof_kernel_name(int32_t k) {
   static const char* names[gvof::K_COUNT] = {"k_node_tag", "k_face_tag", "k_cell_tag", "k_recon",
-                                             "k_face_sweep", "k_flux", "k_update"};
+                                             "k_face_sweep", "k_flux_items_box", "k_update", "k_flux_prep",
+                                             "k_flux_sum", "k_flux_over", "k_flux_gen_filter",
+                                             "k_flux_deep", "k_flux_gen_units", "k_flux_gen_sum",
+                                             "k_flux_gen_units_deep"};
   return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";
 }
 

@@ -33,15 +33,35 @@ struct DevMesh {
   double *Vd, *VF;
   int* upwind;
   int *list_cells, *list_faces;
+  // flux work staging: polyhedron points per listed face, (face, cell, tet) pairs
+  double* poly;        // [slot][pts_per_slot][3]
+  int pts_per_slot, poly_cap;
+  int *item_off, *item_cnt;   // per slot (cnt = -1: face handled by the overflow kernel)
+  int *item_slot, *item_cell;  // per pair
+  unsigned short* item_tm;     // per pair: tet index (5 bits) | box cut mask << 5
+  double* item_vol;
+  int item_cap;
+  int* item_fill;              // fill counter of each of kItemRegions regions of the pair buffer
+  // general-cell pairs: surviving (pair, surface tetrahedron) units
+  int *item_uoff, *item_ucnt;  // per pair
+  int* unit_item;
+  unsigned* unit_code;         // surface tetrahedron index | cutting-plane mask << 16
+  double* unit_vol;
+  int* unit_fill;              // per region
+  int* list_udeep;             // units with four cutting planes
+  int* list_over;              // faces not staged (capacity exceeded)
+  int* list_deep;              // pairs cut by more planes than the register clip takes
   int* counters;  // [0] tag-0 cells, [1] tag-0 faces, [2] geometry error flags, [3] refine cells
-  unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra (cumulative)
+  unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
+  int all_box;  // every cell is an axis-aligned box (set at bind)
 };
 
-enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_N = 8 };
+enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_ITEMS = 4, CNT_OVER = 5, CNT_DEEP = 6, CNT_UDEEP = 7, CNT_N = 8 };
 enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16 };
 
 constexpr int kMaxFaceVerts = 8;
+constexpr int kItemRegions = 256;
 constexpr int kMaxNeighbours = 62;  // vertex-sharing neighbours of one cell
 constexpr int kMaxCellVerts = 30;   // distinct vertices of one cell
 constexpr int kMaxLevels = 40;      // sorted vertex levels used by the plane-constant search

@@ -440,98 +440,247 @@ __device__ inline void cell_piece(const DevMesh& M, int k, int m, d3& t0, d3& t1
   t0 = t1 = t2 = mk3(0.0, 0.0, 0.0);
 }
 
-__global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __restrict__ uv, double dt) {
-  __shared__ double px[kMaxPts], py[kMaxPts], pz[kMaxPts];
-  __shared__ double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
-  __shared__ double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
-  __shared__ int cand[kMaxCand];
-  __shared__ int cpre[kMaxCand + 1];
-  __shared__ unsigned queue[kQueue];
+// Flux tet t of the polyhedron (apex at the face centre c): for edge i,
+// kind 0 (x_{i+1}, x_i, b_{i+1}), kind 1 (x_i, b_i, b_{i+1}), kind 2 (a, b_{i+1}, b_i).
+__device__ inline void flux_tet_points(int t, int I, int& i1, int& i2, int& i3) {
+  int i = t / 3, kind = t - 3 * i;
+  int j = (i + 1 == I) ? 0 : i + 1;
+  i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
+  i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
+  i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
+}
 
+// LDS working set of one wavefront building one flux polyhedron.
+struct FluxLds {
+  double px[kMaxPts], py[kMaxPts], pz[kMaxPts];  // x_0..x_{I-1}, b_0..b_{I-1}, apex
+  double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
+  double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
+  int cand[kMaxCand];
+  int cpre[kMaxCand + 1];
+  double clox[kMaxCand], cloy[kMaxCand], cloz[kMaxCand], chix[kMaxCand], chiy[kMaxCand], chiz[kMaxCand];
+  double cpnx[kMaxCand], cpny[kMaxCand], cpnz[kMaxCand], cpc[kMaxCand];
+  double cccx[kMaxCand], cccy[kMaxCand], cccz[kMaxCand];
+  signed char ctag[kMaxCand], cbox[kMaxCand];
+  unsigned queue[kQueue];
+};
+
+// FMFPA polyhedron of face f into S.px/py/pz: lanes 0..I-1 build the
+// lateral-plane normals, line directions and back vertices; every lane then
+// places the apex (identical values).  Returns the face centre, area vector
+// and the polyhedron's bounding box.
+template <class Lds>
+__device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, int I,
+                                       const double* __restrict__ uv, double dt, d3& c, d3& Sv, d3& plo, d3& phi) {
   const int lane = threadIdx.x;
   const int nv = M.nv;
+  if (lane < I) {
+    int v = M.fv_idx[b0 + lane];
+    S.px[lane] = M.vx[v];
+    S.py[lane] = M.vy[v];
+    S.pz[lane] = M.vz[v];
+    S.ux[lane] = uv[v];
+    S.uy[lane] = uv[nv + v];
+    S.uz[lane] = uv[2 * nv + v];
+  }
+  __syncthreads();
+  if (lane < I) {
+    int j = (lane + 1 == I) ? 0 : lane + 1;
+    d3 ub = mk3(0.5 * (S.ux[lane] + S.ux[j]), 0.5 * (S.uy[lane] + S.uy[j]), 0.5 * (S.uz[lane] + S.uz[j]));
+    d3 e = mk3(S.px[j] - S.px[lane], S.py[j] - S.py[lane], S.pz[j] - S.pz[lane]);
+    d3 m = cross_x(e, ub);  // lateral plane through edge i, parallel to the edge-centre velocity
+    S.mx[lane] = m.x;
+    S.my[lane] = m.y;
+    S.mz[lane] = m.z;
+  }
+  __syncthreads();
+  if (lane < I) {
+    int i = lane, ip = (lane == 0) ? I - 1 : lane - 1;
+    d3 m0 = mk3(S.mx[ip], S.my[ip], S.mz[ip]), m1 = mk3(S.mx[i], S.my[i], S.mz[i]);
+    d3 d = cross_x(m0, m1);
+    double dd = dot_x(d, d), q0 = dot_x(m0, m0), q1 = dot_x(m1, m1);
+    bool fallback = (q0 == 0.0) || (q1 == 0.0) || (dd <= (M.degen * q0) * q1);
+    d3 x = mk3(S.px[i], S.py[i], S.pz[i]), u = mk3(S.ux[i], S.uy[i], S.uz[i]);
+    d3 bv;
+    if (fallback) bv = x - dt * u;  // back-trace along the streak line
+    else {
+      double t = dotf(u, d) / dd;  // projection of x - dt u on the line of the two lateral planes
+      bv = x - (dt * t) * d;
+    }
+    S.px[I + i] = bv.x;
+    S.py[I + i] = bv.y;
+    S.pz[I + i] = bv.z;
+  }
+  __syncthreads();
+  c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
+  Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+  {
+    // apex: back-vertex mean moved along S until the signed volume equals V_d
+    d3 g = mk3(0.0, 0.0, 0.0);
+    for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
+    double dI = (double)I;
+    g = mk3(g.x / dI, g.y / dI, g.z / dI);
+    double V0 = 0.0, W = 0.0;
+    for (int i = 0; i < I; ++i) {
+      int j = (i + 1 == I) ? 0 : i + 1;
+      d3 xi = mk3(S.px[i], S.py[i], S.pz[i]) - c, xj = mk3(S.px[j], S.py[j], S.pz[j]) - c;
+      d3 bi = mk3(S.px[I + i], S.py[I + i], S.pz[I + i]) - c, bj = mk3(S.px[I + j], S.py[I + j], S.pz[I + j]) - c;
+      V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
+      W += det3f(Sv, bj, bi);
+    }
+    V0 *= (1.0 / 6.0);
+    W *= (1.0 / 6.0);
+    double mu = 0.0;
+    if (fabs(W) <= 1e-12 * dotf(Sv, Sv)) {
+      if (lane == 0) atomicOr(&M.counters[CNT_ERR], ERR_APEX);
+    } else {
+      mu = (M.Vd[f] - V0) / W;
+    }
+    if (lane == 0) {
+      S.px[2 * I] = fma(mu, Sv.x, g.x);
+      S.py[2 * I] = fma(mu, Sv.y, g.y);
+      S.pz[2 * I] = fma(mu, Sv.z, g.z);
+    }
+  }
+  __syncthreads();
+  plo = c;
+  phi = c;
+  for (int i = 0; i <= 2 * I; ++i) {
+    d3 p = mk3(S.px[i], S.py[i], S.pz[i]);
+    plo = vmin(plo, p);
+    phi = vmax(phi, p);
+  }
+}
+
+// Candidate cells of face f (owner, neighbour and every cell sharing a vertex
+// with either) that hold fluid and whose boxes meet the polyhedron's box,
+// cached in LDS in a fixed order; cpre holds the prefix of pieces per
+// candidate (1 for a box, one per surface triangle otherwise).
+__device__ inline int flux_candidates(const DevMesh& M, FluxLds& S, int f, d3 plo, d3 phi) {
+  const int lane = threadIdx.x;
+  const int o = M.owner[f], nbr = M.neigh[f];
+  const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
+  const int nbb = nbr >= 0 ? M.nb_ptr[nbr] : 0, nbn = nbr >= 0 ? M.nb_ptr[nbr + 1] - nbb : 0;
+  const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
+  int ncand = 0;
+  for (int j0 = 0; j0 < L; j0 += kFluxLanes) {
+    int j = j0 + lane;
+    bool keep = false;
+    int k = -1;
+    int8_t tg = -1;
+    d3 klo = mk3(0, 0, 0), khi = klo;
+    if (j < L) {
+      bool second = j > on;
+      if (j == 0) k = o;
+      else if (j <= on) k = M.nb_idx[ob + j - 1];
+      else if (j == on + 1) k = nbr;
+      else k = M.nb_idx[nbb + j - on - 2];
+      tg = M.tag_cell[k];
+      keep = tg != -1;
+      if (keep && second) keep = !(k == o || sorted_contains(M.nb_idx + ob, on, k));
+      if (keep) {
+        klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
+        khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+        keep = box_overlap(plo, phi, klo, khi);
+      }
+    }
+    unsigned long long bm = __ballot(keep);
+    if (keep) {
+      int pos = ncand + __popcll(bm & ((1ull << lane) - 1ull));
+      S.cand[pos] = k;
+      S.clox[pos] = klo.x; S.cloy[pos] = klo.y; S.cloz[pos] = klo.z;
+      S.chix[pos] = khi.x; S.chiy[pos] = khi.y; S.chiz[pos] = khi.z;
+      S.ctag[pos] = tg;
+      S.cpnx[pos] = M.pnx[k]; S.cpny[pos] = M.pny[k]; S.cpnz[pos] = M.pnz[k]; S.cpc[pos] = M.pC[k];
+      S.cccx[pos] = M.ccx[k]; S.cccy[pos] = M.ccy[k]; S.cccz[pos] = M.ccz[k];
+      int box = M.isbox[k];
+      S.cbox[pos] = (signed char)box;
+      int np = 1;
+      if (!box) {
+        np = 0;
+        for (int q = M.cf_ptr[k]; q < M.cf_ptr[k + 1]; ++q) np += face_triangle_count(M, M.cf_idx[q]);
+      }
+      S.cpre[pos + 1] = np;
+    }
+    ncand += __popcll(bm);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    S.cpre[0] = 0;
+    for (int kc = 0; kc < ncand; ++kc) S.cpre[kc + 1] += S.cpre[kc];
+  }
+  __syncthreads();
+  return ncand;
+}
+
+// vol(cell k ∩ T [∩ PLIC half-space]) for a non-box cell: signed sum over the
+// cell's surface tetrahedra.  With DEEP false, a piece cut by more than
+// kMaxRegCuts planes makes the call return false (the caller defers the pair).
+template <bool DEEP>
+__device__ inline bool tet_cell_pieces_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf,
+                                              double& out) {
+  d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+  double acc = 0.0;
+  int fb = M.cf_ptr[k], fn = M.cf_ptr[k + 1] - fb;
+  for (int i = 0; i < fn; ++i) {
+    int e = M.cf_idx[fb + i];
+    int nt = face_triangle_count(M, e);
+    for (int q = 0; q < nt; ++q) {
+      d3 t0, t1, t2;
+      face_triangle(M, e, q, t0, t1, t2);
+      if (!box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)))) continue;
+      double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+      if (s6 == 0.0) continue;
+      TetCont TC = tet_container(cc, t0, t1, t2);
+      unsigned tm;
+      if (!cut_mask(T, TC, tm)) continue;
+      double v = clip_masked_tet(T, TC, tm, leaf);
+      acc += s6 > 0.0 ? v : -v;
+    }
+  }
+  out = acc;
+  return true;
+}
+
+// LDS of the staging kernel: the polyhedron and up to kPrepCand candidate cells.
+constexpr int kPrepCand = 64;
+struct PrepLds {
+  double px[kMaxPts], py[kMaxPts], pz[kMaxPts];
+  double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
+  double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
+  int cand[kPrepCand];
+  double clox[kPrepCand], cloy[kPrepCand], cloz[kPrepCand], chix[kPrepCand], chiy[kPrepCand], chiz[kPrepCand];
+  signed char cbox[kPrepCand];
+  int base;
+};
+
+// Stage the flux work of every listed face, one wavefront per face: build
+// its FMFPA polyhedron (stored per slot), gather the candidate cells that hold
+// fluid and whose boxes meet the polyhedron's box, then emit one
+// (face, cell, flux tet) pair for every flux tet whose box meets such a
+// cell's box (box cells: the tet is also not entirely outside one box plane,
+// and the pair carries the mask of the box planes that cut it).  Pairs of one
+// face are contiguous and in a fixed order.  Faces with more than kPrepCand
+// such cells or without room in the staging buffers go to the overflow kernel.
+__global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ uv, double dt) {
+  __shared__ PrepLds S;
+  const int lane = threadIdx.x;
   const int nfaces = M.counters[CNT_FACES];
   for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
     const int f = M.list_faces[it];
     const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
-    // ---- flux polyhedron: lanes 0..I-1 own face vertex i
-    if (lane < I) {
-      int v = M.fv_idx[b0 + lane];
-      px[lane] = M.vx[v];
-      py[lane] = M.vy[v];
-      pz[lane] = M.vz[v];
-      ux[lane] = uv[v];
-      uy[lane] = uv[nv + v];
-      uz[lane] = uv[2 * nv + v];
+    if (it >= M.poly_cap) {
+      if (lane == 0) M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
+      continue;
     }
-    __syncthreads();
-    if (lane < I) {
-      int j = (lane + 1 == I) ? 0 : lane + 1;
-      d3 ub = mk3(0.5 * (ux[lane] + ux[j]), 0.5 * (uy[lane] + uy[j]), 0.5 * (uz[lane] + uz[j]));
-      d3 e = mk3(px[j] - px[lane], py[j] - py[lane], pz[j] - pz[lane]);
-      d3 m = cross_x(e, ub);  // lateral plane through edge i, parallel to the edge-centre velocity
-      mx[lane] = m.x;
-      my[lane] = m.y;
-      mz[lane] = m.z;
+    d3 c, Sv, plo, phi;
+    flux_polyhedron(M, S, f, b0, I, uv, dt, c, Sv, plo, phi);
+    double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
+    if (lane <= 2 * I) {
+      P[3 * lane] = S.px[lane];
+      P[3 * lane + 1] = S.py[lane];
+      P[3 * lane + 2] = S.pz[lane];
     }
-    __syncthreads();
-    if (lane < I) {
-      int i = lane, ip = (lane == 0) ? I - 1 : lane - 1;
-      d3 m0 = mk3(mx[ip], my[ip], mz[ip]), m1 = mk3(mx[i], my[i], mz[i]);
-      d3 d = cross_x(m0, m1);
-      double dd = dot_x(d, d), q0 = dot_x(m0, m0), q1 = dot_x(m1, m1);
-      bool fallback = (q0 == 0.0) || (q1 == 0.0) || (dd <= (M.degen * q0) * q1);
-      d3 x = mk3(px[i], py[i], pz[i]), u = mk3(ux[i], uy[i], uz[i]);
-      d3 bv;
-      if (fallback) bv = x - dt * u;  // back-trace along the streak line
-      else {
-        double t = dotf(u, d) / dd;  // projection of x - dt u on the line of the two lateral planes
-        bv = x - (dt * t) * d;
-      }
-      px[I + i] = bv.x;
-      py[I + i] = bv.y;
-      pz[I + i] = bv.z;
-    }
-    __syncthreads();
-    const d3 c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
-    const d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-    {
-      // apex: back-vertex mean moved along S until the signed volume equals V_d (all lanes, same values)
-      d3 g = mk3(0.0, 0.0, 0.0);
-      for (int i = 0; i < I; ++i) g = g + mk3(px[I + i], py[I + i], pz[I + i]);
-      double dI = (double)I;
-      g = mk3(g.x / dI, g.y / dI, g.z / dI);
-      double V0 = 0.0, W = 0.0;
-      for (int i = 0; i < I; ++i) {
-        int j = (i + 1 == I) ? 0 : i + 1;
-        d3 xi = mk3(px[i], py[i], pz[i]) - c, xj = mk3(px[j], py[j], pz[j]) - c;
-        d3 bi = mk3(px[I + i], py[I + i], pz[I + i]) - c, bj = mk3(px[I + j], py[I + j], pz[I + j]) - c;
-        V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
-        W += det3f(S, bj, bi);
-      }
-      V0 *= (1.0 / 6.0);
-      W *= (1.0 / 6.0);
-      double mu = 0.0;
-      if (fabs(W) <= 1e-12 * dotf(S, S)) {
-        if (lane == 0) atomicOr(&M.counters[CNT_ERR], ERR_APEX);
-      } else {
-        mu = (M.Vd[f] - V0) / W;
-      }
-      if (lane == 0) {
-        px[2 * I] = fma(mu, S.x, g.x);
-        py[2 * I] = fma(mu, S.y, g.y);
-        pz[2 * I] = fma(mu, S.z, g.z);
-      }
-    }
-    __syncthreads();
-    // bounding box of the polyhedron
-    d3 plo = c, phi = c;
-    for (int i = 0; i <= 2 * I; ++i) {
-      d3 p = mk3(px[i], py[i], pz[i]);
-      plo = vmin(plo, p);
-      phi = vmax(phi, p);
-    }
-    // ---- candidate cells: owner, neighbour and their vertex-sharing cells, minus empty / far ones
+    // candidates
     const int o = M.owner[f], nbr = M.neigh[f];
     const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
     const int nbb = nbr >= 0 ? M.nb_ptr[nbr] : 0, nbn = nbr >= 0 ? M.nb_ptr[nbr + 1] - nbb : 0;
@@ -541,6 +690,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __
       int j = j0 + lane;
       bool keep = false;
       int k = -1;
+      d3 klo = mk3(0, 0, 0), khi = klo;
       if (j < L) {
         bool second = j > on;
         if (j == 0) k = o;
@@ -550,37 +700,371 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __
         keep = M.tag_cell[k] != -1;
         if (keep && second) keep = !(k == o || sorted_contains(M.nb_idx + ob, on, k));
         if (keep) {
-          d3 klo = mk3(M.lox[k], M.loy[k], M.loz[k]), khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+          klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
+          khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
           keep = box_overlap(plo, phi, klo, khi);
         }
       }
       unsigned long long bm = __ballot(keep);
-      if (keep) cand[ncand + __popcll(bm & ((1ull << lane) - 1ull))] = k;
+      if (keep) {
+        int pos = ncand + __popcll(bm & ((1ull << lane) - 1ull));
+        if (pos < kPrepCand) {
+          S.cand[pos] = k;
+          S.clox[pos] = klo.x; S.cloy[pos] = klo.y; S.cloz[pos] = klo.z;
+          S.chix[pos] = khi.x; S.chiy[pos] = khi.y; S.chiz[pos] = khi.z;
+          S.cbox[pos] = M.isbox[k];
+        }
+      }
       ncand += __popcll(bm);
     }
     __syncthreads();
-    // pieces per candidate: a box is one piece, any other cell one per surface tetrahedron
-    for (int kc = lane; kc < ncand; kc += kFluxLanes) {
-      int k = cand[kc];
-      int np = 1;
-      if (!M.isbox[k]) {
-        np = 0;
-        for (int i = M.cf_ptr[k]; i < M.cf_ptr[k + 1]; ++i) np += face_triangle_count(M, M.cf_idx[i]);
+    if (ncand > kPrepCand) {
+      if (lane == 0) {
+        M.item_cnt[it] = -1;
+        M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
       }
-      cpre[kc + 1] = np;
+      __syncthreads();
+      continue;
     }
-    __syncthreads();
-    if (lane == 0) {
-      cpre[0] = 0;
-      for (int kc = 0; kc < ncand; ++kc) cpre[kc + 1] += cpre[kc];
-    }
-    __syncthreads();
+    // pairs: pass 0 counts, pass 1 writes into the reserved range
     const int T3 = 3 * I;
-    const int total = cpre[ncand] * T3;
+    const int total = ncand * T3;
+    int count = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      int written = 0;
+      for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
+        int q = q0 + lane;
+        bool keep = false;
+        unsigned tm = 0;
+        int kc = 0;
+        if (q < total) {
+          int t = q % T3;
+          kc = q / T3;
+          int i1, i2, i3;
+          flux_tet_points(t, I, i1, i2, i3);
+          Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
+                mk3(S.px[i3], S.py[i3], S.pz[i3])};
+          d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+          BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
+          keep = box_overlap(tlo, thi, B.lo, B.hi);
+          unsigned mask = 0;
+          if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
+          tm = (unsigned)t | (mask << 5);
+        }
+        unsigned long long bm = __ballot(keep);
+        if (pass == 0) {
+          count += __popcll(bm);
+        } else if (keep) {
+          int i = S.base + written + __popcll(bm & ((1ull << lane) - 1ull));  // inside this block's region
+          M.item_slot[i] = it;
+          M.item_cell[i] = S.cand[kc];
+          M.item_tm[i] = (unsigned short)tm;
+        }
+        written += __popcll(bm);
+      }
+      if (pass == 0) {
+        if (lane == 0) {
+          // the pair buffer is split into kItemRegions regions with a fill counter
+          // each; a block reserves in region blockIdx % kItemRegions
+          int r = blockIdx.x % kItemRegions;
+          int rsize = M.item_cap / kItemRegions;
+          int base = atomicAdd(&M.item_fill[r], count);
+          if (base + count > rsize) {
+            M.item_cnt[it] = -1;
+            M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
+            base = -1;
+          } else {
+            base += r * rsize;
+            M.item_off[it] = base;
+            M.item_cnt[it] = count;
+          }
+          S.base = base;
+        }
+        __syncthreads();
+        if (S.base < 0) break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One lane per staged pair: signed fluid volume of (flux tet ∩ cell).  Two
+// instances, one for box cells and one for general cells, each skipping the
+// other kind, so each carries only its own registers.
+__device__ inline Tet staged_tet(const DevMesh& M, int slot, int t) {
+  int f = M.list_faces[slot];
+  int I = M.fv_ptr[f + 1] - M.fv_ptr[f];
+  const double* P = M.poly + (size_t)slot * M.pts_per_slot * 3;
+  int i1, i2, i3;
+  flux_tet_points(t, I, i1, i2, i3);
+  return Tet{mk3(M.fcx[f], M.fcy[f], M.fcz[f]), mk3(P[3 * i1], P[3 * i1 + 1], P[3 * i1 + 2]),
+             mk3(P[3 * i2], P[3 * i2 + 1], P[3 * i2 + 2]), mk3(P[3 * i3], P[3 * i3 + 1], P[3 * i3 + 2])};
+}
+
+// Pair buffer regions: block b serves region b % kItemRegions and strides over
+// that region's filled part with the other blocks of the same region.
+constexpr int kItemBlocksPerRegion = 16;
+
+// Box-cell pairs, one lane per pair.
+__global__ __launch_bounds__(256) void k_flux_items_box(DevMesh M) {
+  const int rsize = M.item_cap / kItemRegions;
+  const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
+  const int fill = min(M.item_fill[r], rsize);
+  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += kItemBlocksPerRegion * blockDim.x) {
+    const int i = r * rsize + li;
+    int k = M.item_cell[i];
+    if (!M.isbox[k]) continue;
+    unsigned tm = M.item_tm[i];
+    unsigned mask = tm >> 5;
+    if (cut_count(mask) > kMaxRegCuts) {  // more cutting planes than the register path takes: defer
+      M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
+      continue;
+    }
+    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+    double sT = tet6(T);
+    double v = 0.0;
+    if (sT != 0.0) {
+      Leaf leaf;
+      leaf.useH = M.tag_cell[k] == 0;
+      leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+      leaf.hd = M.pC[k];
+      BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
+      v = clip_masked(T, B, mask, leaf);
+      if (sT < 0.0) v = -v;
+    }
+    M.item_vol[i] = v;
+  }
+}
+
+// Surface tetrahedron p of cell k: (vertex mean, outward triangle), with its
+// orientation sign.
+__device__ inline void cell_sigma(const DevMesh& M, int k, int p, bool tri_only, d3& t0, d3& t1, d3& t2) {
+  if (tri_only) face_triangle(M, M.cf_idx[M.cf_ptr[k] + p], 0, t0, t1, t2);
+  else cell_piece(M, k, p, t0, t1, t2);
+}
+
+__device__ inline int cell_piece_count(const DevMesh& M, int k) {
+  int np = 0;
+  for (int e = M.cf_ptr[k]; e < M.cf_ptr[k + 1]; ++e) np += face_triangle_count(M, M.cf_idx[e]);
+  return np;
+}
+
+// Pairs with a general (non-box) cell, stage 1: one half-wavefront per pair,
+// lane j testing the cell's surface tetrahedra j, j+32, ...: boxes overlap and
+// no plane of the tetrahedron leaves the flux tet entirely outside.  The
+// survivors (pair, surface tetrahedron, mask of cutting planes) are written in
+// tetrahedron order into a range of the unit buffer reserved for the pair.
+__global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
+  const int rsize = M.item_cap / kItemRegions;
+  const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
+  const int fill = min(M.item_fill[r], rsize);
+  const int hl = threadIdx.x & 31, half = threadIdx.x >> 5;
+  const int halves = blockDim.x >> 5;
+  const unsigned long long hmask = 0xffffffffull << (threadIdx.x & 32);
+  for (int li = sub * halves + half; li < fill; li += kItemBlocksPerRegion * halves) {
+    const int i = r * rsize + li;
+    const int k = M.item_cell[i];
+    if (M.isbox[k]) continue;
+    unsigned tm = M.item_tm[i];
+    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+    const d3 cc = cell_centre(M, k);
+    d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+    const int np = cell_piece_count(M, k);
+    const bool tri_only = np == M.cf_ptr[k + 1] - M.cf_ptr[k];
+    const bool live = tet6(T) != 0.0;
+    int count = 0;
+    int base = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      int written = 0;
+      for (int p0 = 0; p0 < np; p0 += 32) {
+        int p = p0 + hl;
+        bool keep = false;
+        unsigned cm = 0;
+        if (live && p < np) {
+          d3 t0, t1, t2;
+          cell_sigma(M, k, p, tri_only, t0, t1, t2);
+          if (box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2))) &&
+              det3f(t0 - cc, t1 - cc, t2 - cc) != 0.0) {
+            TetCont TC = tet_container(cc, t0, t1, t2);
+            keep = cut_mask(T, TC, cm);
+          }
+        }
+        unsigned long long bm = __ballot(keep) & hmask;
+        int below = __popcll(bm & ((1ull << __lane_id()) - 1ull));
+        if (pass == 1 && keep) {
+          int u = base + written + below;
+          M.unit_item[u] = i;
+          M.unit_code[u] = (unsigned)p | (cm << 16);
+        }
+        written += __popcll(bm);
+      }
+      if (pass == 0) {
+        count = written;
+        int b = 0;
+        if (hl == 0) {
+          b = atomicAdd(&M.unit_fill[r], count);
+          if (b + count > rsize) b = -1;
+          else b += r * rsize;
+        }
+        base = __shfl(b, (threadIdx.x & 32), 64);
+        if (base < 0) {  // no room: the deferred kernel computes the whole pair
+          if (hl == 0) {
+            M.item_ucnt[i] = -1;
+            M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
+          }
+          break;
+        }
+        if (hl == 0) {
+          M.item_uoff[i] = base;
+          M.item_ucnt[i] = count;
+        }
+      }
+    }
+  }
+}
+
+// Stage 2: one lane per surviving (pair, surface tetrahedron): clip in
+// registers, up to three cutting planes; units with four (about 5% on the
+// distorted-grid workload) go to a list for k_flux_gen_units_deep.
+template <bool DEEP>
+__global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
+  const int rsize = M.item_cap / kItemRegions;
+  const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
+  const int fill = min(M.unit_fill[r], rsize);
+  for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += kItemBlocksPerRegion * blockDim.x) {
+    const int u = r * rsize + lu;
+    const int i = M.unit_item[u];
+    const unsigned code = M.unit_code[u];
+    const int p = code & 0xffff;
+    const unsigned cm = code >> 16;
+    const int k = M.item_cell[i];
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    const d3 cc = cell_centre(M, k);
+    const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
+    d3 t0, t1, t2;
+    cell_sigma(M, k, p, tri_only, t0, t1, t2);
+    double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+    TetCont TC = tet_container(cc, t0, t1, t2);
+    Leaf leaf;
+    leaf.useH = M.tag_cell[k] == 0;
+    leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+    leaf.hd = M.pC[k];
+    double v;
+    {
+      if (cut_count(cm) > 3) {  // four cutting planes: the deep instance takes it
+        M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;
+        continue;
+      }
+      v = clip_masked_tet<3>(T, TC, cm, leaf);
+    }
+    M.unit_vol[u] = s6 > 0.0 ? v : -v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
+  const int n = M.counters[CNT_UDEEP];
+  for (int j = grid_stride_start(); j < n; j += grid_stride()) {
+    const int u = M.list_udeep[j];
+    const int i = M.unit_item[u];
+    const unsigned code = M.unit_code[u];
+    const int k = M.item_cell[i];
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    const d3 cc = cell_centre(M, k);
+    const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
+    d3 t0, t1, t2;
+    cell_sigma(M, k, code & 0xffff, tri_only, t0, t1, t2);
+    double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+    TetCont TC = tet_container(cc, t0, t1, t2);
+    Leaf leaf;
+    leaf.useH = M.tag_cell[k] == 0;
+    leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+    leaf.hd = M.pC[k];
+    double v = clip_volume(T, TC, leaf);
+    if (v == -1.0) {
+      atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+      v = 0.0;
+    }
+    M.unit_vol[u] = s6 > 0.0 ? v : -v;
+  }
+}
+
+// Stage 3: per pair, the sum of its units in surface-tetrahedron order, signed by the flux tet.
+__global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
+  const int rsize = M.item_cap / kItemRegions;
+  const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
+  const int fill = min(M.item_fill[r], rsize);
+  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += kItemBlocksPerRegion * blockDim.x) {
+    const int i = r * rsize + li;
+    const int k = M.item_cell[i];
+    if (M.isbox[k]) continue;
+    const int cnt = M.item_ucnt[i];
+    if (cnt < 0) continue;  // deferred
+    const double* v = M.unit_vol + M.item_uoff[i];
+    double acc = 0.0;
+    for (int q = 0; q < cnt; ++q) acc += v[q];
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    M.item_vol[i] = tet6(T) < 0.0 ? -acc : acc;
+  }
+}
+
+// Deferred pairs: explicit-stack clipping, any number of cutting planes.
+__global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
+  int n = M.counters[CNT_DEEP];
+  for (int j = grid_stride_start(); j < n; j += grid_stride()) {
+    int i = M.list_deep[j];
+    int k = M.item_cell[i];
+    unsigned tm = M.item_tm[i];
+    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+    double sT = tet6(T);
+    Leaf leaf;
+    leaf.useH = M.tag_cell[k] == 0;
+    leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+    leaf.hd = M.pC[k];
+    double v;
+    if (M.isbox[k]) {
+      BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
+      v = clip_volume(T, B, leaf);
+      if (v == -1.0) {
+        atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+        v = 0.0;
+      }
+    } else {
+      tet_cell_pieces_volume<true>(M, k, cell_centre(M, k), T, leaf, v);
+    }
+    M.item_vol[i] = sT < 0.0 ? -v : v;
+  }
+}
+
+// Per staged face: V_F = sum of its pairs in their fixed order.
+__global__ void k_flux_sum(DevMesh M) {
+  int n = min(M.counters[CNT_FACES], M.poly_cap);
+  for (int it = grid_stride_start(); it < n; it += grid_stride()) {
+    int cnt = M.item_cnt[it];
+    if (cnt < 0) continue;
+    const double* v = M.item_vol + M.item_off[it];
+    double acc = 0.0;
+    for (int i = 0; i < cnt; ++i) acc += v[i];
+    M.VF[M.list_faces[it]] = acc;
+  }
+}
+
+// Faces that did not fit the staging buffers: one wavefront per face does the
+// whole computation with an LDS queue of (tet, piece) pairs.
+__global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const double* __restrict__ uv, double dt) {
+  __shared__ FluxLds S;
+  const int lane = threadIdx.x;
+  const int nfaces = M.counters[CNT_OVER];
+  for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
+    const int f = M.list_over[it];
+    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
+    d3 c, Sv, plo, phi;
+    flux_polyhedron(M, S, f, b0, I, uv, dt, c, Sv, plo, phi);
+    const int ncand = flux_candidates(M, S, f, plo, phi);
+    const int T3 = 3 * I;
+    const int total = S.cpre[ncand] * T3;
     double acc = 0.0;
     int qn = 0;
     for (int q0 = 0; q0 < total || qn > 0; q0 += kFluxLanes) {
-      // ---- enumerate (tet t, candidate kc, piece m), keep overlapping boxes
       if (q0 < total) {
         int q = q0 + lane;
         bool keep = false;
@@ -590,68 +1074,62 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __
           int lo = 0, hi = ncand;  // cpre[lo] <= r < cpre[lo+1]
           while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (cpre[mid] <= r) lo = mid;
+            if (S.cpre[mid] <= r) lo = mid;
             else hi = mid;
           }
-          int kc = lo, m = r - cpre[lo];
-          int i = t / 3, kind = t - 3 * i;
-          int j = (i + 1 == I) ? 0 : i + 1;
-          int i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
-          int i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
-          int i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
-          d3 p1 = mk3(px[i1], py[i1], pz[i1]), p2 = mk3(px[i2], py[i2], pz[i2]), p3 = mk3(px[i3], py[i3], pz[i3]);
-          d3 tlo = vmin(vmin(c, p1), vmin(p2, p3)), thi = vmax(vmax(c, p1), vmax(p2, p3));
-          int k = cand[kc];
-          d3 klo, khi;
-          if (M.isbox[k]) {
-            klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
-            khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+          int kc = lo, m = r - S.cpre[lo];
+          int i1, i2, i3;
+          flux_tet_points(t, I, i1, i2, i3);
+          Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
+                mk3(S.px[i3], S.py[i3], S.pz[i3])};
+          d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+          unsigned mask = 0;
+          if (S.cbox[kc]) {
+            BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
+            keep = box_overlap(tlo, thi, B.lo, B.hi) && cut_mask(T, B, mask);
           } else {
             d3 t0, t1, t2;
-            cell_piece(M, k, m, t0, t1, t2);
-            d3 cc = cell_centre(M, k);
-            klo = vmin(vmin(cc, t0), vmin(t1, t2));
-            khi = vmax(vmax(cc, t0), vmax(t1, t2));
+            cell_piece(M, S.cand[kc], m, t0, t1, t2);
+            d3 cc = mk3(S.cccx[kc], S.cccy[kc], S.cccz[kc]);
+            keep = box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)));
           }
-          keep = box_overlap(tlo, thi, klo, khi);
-          code = ((unsigned)m << 12) | ((unsigned)kc << 5) | (unsigned)t;
+          code = ((unsigned)m << 18) | (mask << 12) | ((unsigned)kc << 5) | (unsigned)t;
         }
         unsigned long long bm = __ballot(keep);
-        if (keep) queue[qn + __popcll(bm & ((1ull << lane) - 1ull))] = code;
+        if (keep) S.queue[qn + __popcll(bm & ((1ull << lane) - 1ull))] = code;
         qn += __popcll(bm);
       }
       __syncthreads();
       bool flush = (q0 + kFluxLanes >= total) || (qn + kFluxLanes > kQueue);
       if (!flush) continue;
-      // ---- clip the queued pairs
       for (int qi = lane; qi < qn; qi += kFluxLanes) {
-        unsigned code = queue[qi];
-        int t = code & 31, kc = (code >> 5) & 127, m = (int)(code >> 12);
-        int i = t / 3, kind = t - 3 * i;
-        int j = (i + 1 == I) ? 0 : i + 1;
-        int i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
-        int i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
-        int i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
-        Tet T{c, mk3(px[i1], py[i1], pz[i1]), mk3(px[i2], py[i2], pz[i2]), mk3(px[i3], py[i3], pz[i3])};
+        unsigned code = S.queue[qi];
+        int t = code & 31, kc = (code >> 5) & 127, m = (int)(code >> 18);
+        unsigned mask = (code >> 12) & 63u;
+        int i1, i2, i3;
+        flux_tet_points(t, I, i1, i2, i3);
+        Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
+              mk3(S.px[i3], S.py[i3], S.pz[i3])};
         double sT = tet6(T);
         if (sT == 0.0) continue;
-        int k = cand[kc];
         Leaf leaf;
-        leaf.useH = M.tag_cell[k] == 0;
-        leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
-        leaf.hd = M.pC[k];
+        leaf.useH = S.ctag[kc] == 0;
+        leaf.hn = mk3(S.cpnx[kc], S.cpny[kc], S.cpnz[kc]);
+        leaf.hd = S.cpc[kc];
         double v;
-        if (M.isbox[k]) {
-          BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-          v = clip_volume(T, B, leaf);
+        if (S.cbox[kc]) {
+          BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
+          v = cut_count(mask) <= kMaxRegCuts ? clip_masked(T, B, mask, leaf) : clip_volume(T, B, leaf);
         } else {
           d3 t0, t1, t2;
-          cell_piece(M, k, m, t0, t1, t2);
-          d3 cc = cell_centre(M, k);
+          cell_piece(M, S.cand[kc], m, t0, t1, t2);
+          d3 cc = mk3(S.cccx[kc], S.cccy[kc], S.cccz[kc]);
           double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
           if (s6 == 0.0) continue;
           TetCont TC = tet_container(cc, t0, t1, t2);
-          v = clip_volume(T, TC, leaf);
+          unsigned tmk;
+          v = !cut_mask(T, TC, tmk) ? 0.0
+              : (cut_count(tmk) <= kMaxRegCuts ? clip_masked(T, TC, tmk, leaf) : clip_volume(T, TC, leaf));
           if (v == -1.0) {
             atomicOr(&M.counters[CNT_ERR], ERR_STACK);
             v = 0.0;
@@ -667,11 +1145,21 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux(DevMesh M, const double* __
       qn = 0;
       __syncthreads();
     }
-    // ---- fixed-order wave reduction
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) M.VF[f] = acc;
     __syncthreads();
   }
+}
+
+__global__ void k_reset_advect(int* counters, int* item_fill) {
+  if (threadIdx.x == 0) {
+    counters[CNT_FACES] = 0;
+    counters[CNT_ITEMS] = 0;
+    counters[CNT_OVER] = 0;
+    counters[CNT_DEEP] = 0;
+    counters[CNT_UDEEP] = 0;
+  }
+  for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) item_fill[r] = 0;
 }
 
 // ============================================================== update
@@ -857,9 +1345,20 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s, Prof* 
 
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
                          double* Fout, hipStream_t s, Prof* prof) {
-  k_zero<<<1, 64, 0, s>>>(M.counters + CNT_FACES, 1);
+  k_reset_advect<<<1, 256, 0, s>>>(M.counters, M.item_fill);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, 256), 256, 0, s>>>(M, uf, dt)));
-  TIMED(K_FLUX, (k_flux<<<blocks_for(M.nf, 1, 4096), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, 16384), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX, (k_flux_items_box<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+  if (!M.all_box) {
+    k_zero<<<1, 256, 0, s>>>(M.unit_fill, kItemRegions);
+    TIMED(K_FLUX_GEN, (k_flux_gen_filter<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<false><<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_UDEEP, (k_flux_gen_units_deep<<<1024, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+  }
+  TIMED(K_FLUX_DEEP, (k_flux_deep<<<blocks_for(M.item_cap, 64, 1024), 64, 0, s>>>(M)));
+  TIMED(K_FLUX_SUM, (k_flux_sum<<<blocks_for(M.poly_cap, 256, 1024), 256, 0, s>>>(M)));
+  TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 2048), kFluxLanes, 0, s>>>(M, uv, dt)));
   TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, Fin, Fout)));
   return hipGetLastError();
 }

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgvof.so")
+LIB_PATH = os.environ.get("GVOF_LIB_PATH") or os.path.join(HERE, "libgvof.so")
 
 GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
@@ -195,7 +195,7 @@ def gvof_status(h):
     return code
 
 
-GVOF_NUM_KERNELS = 7
+GVOF_NUM_KERNELS = 15
 
 
 def gvof_work_totals(h):

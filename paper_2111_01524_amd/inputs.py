@@ -281,7 +281,7 @@ def velocity_enright(mesh: Mesh, solenoidal_projection: bool | None = None):
         nrm = 0.5 * np.cross((x1 - x0).T, (x2 - x0).T).T
         flux = (uf * nrm).sum(0)
         uf = uf + ((Q - flux) / (nrm * nrm).sum(0)) * nrm
-    return uf, uv
+    return np.ascontiguousarray(uf), np.ascontiguousarray(uv)
 
 
 def enright_time_factor(t: float, period: float) -> float:
