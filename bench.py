@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also run the batched workload with this many problems (256 = the full batch)")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--single-steps", type=int, default=2, help="timed steps per problem of the one-by-one baseline")
     return ap.parse_args()
 
 
@@ -56,6 +61,14 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    batch_problems = None
+    if args.batch > 0:
+        # host-side inputs first, in spawned workers, before anything touches the GPU
+        from paper_2111_01524_amd import batch_inputs, inputs as _inputs
+        t0 = time.perf_counter()
+        batch_problems = batch_inputs.generate(_inputs.batch_problem_specs(args.batch))
+        batch_gen_s = time.perf_counter() - t0
+        print(f"# batch inputs: {args.batch} problems in {batch_gen_s:.1f} s", file=sys.stderr, flush=True)
     import torch
 
     from paper_2111_01524_amd import gvof, inputs
@@ -156,9 +169,81 @@ def main():
     }
     if args.profile_all:
         out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    if batch_problems is not None:
+        del g, bufs, ufd, uvd
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(args, batch_problems, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(args, problems, dev):
+    """The batched workload (independent problems of uneven sizes and grid
+    kinds, each with its own sphere, period and time step) advanced together:
+    one captured step per graph launch, launch shapes autotuned, against the
+    same problems advanced one after another through the single-problem calls."""
+    import torch
+
+    from paper_2111_01524_amd import gvof
+    from paper_2111_01524_amd.runtime import BatchRun
+
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    R = BatchRun(problems, dev, st)
+    setup_s = time.perf_counter() - t0
+    print(f"# batch bound: nf={R.B.nf} nc={R.B.nc} setup {setup_s:.1f} s tuned {R.tuned}", file=sys.stderr, flush=True)
+    W, K = args.batch_warmup, args.batch_steps
+    for _ in range(W):
+        R.step()
+    st.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(K):
+        R.step()
+    e1.record(st)
+    st.synchronize()
+    R.status()
+    ms = e0.elapsed_time(e1)
+    fs = R.face_steps(W, W + K)
+    res = {
+        "workload": f"{R.nprob} problems, sides 16..48, Cartesian or distorted (+-0.25h), sphere r~U[0.1,0.2], "
+                    f"centre~U[0.3,0.7]^3, Enright period T~U[1,3], CFL 0.5; steps {W}..{W + K - 1}",
+        "faces": int(R.B.nf), "cells": int(R.B.nc),
+        "value": fs / (ms / 1e3), "unit": "face·steps/s", "ms_per_step": ms / K, "steps": K, "warmup": W,
+        "launch_config": R.tuned[0] if R.tuned else None, "autotune_ms_per_step": R.tuned[1] if R.tuned else None,
+        "setup_s": setup_s,
+    }
+    R.close()
+    del R
+    torch.cuda.empty_cache()
+    # the same problems one after another, each on its own handle, single-problem calls
+    Ks = args.single_steps
+    tot_ms, tot_fs = 0.0, 0
+    with torch.cuda.stream(st):
+        for qi, p in enumerate(problems):
+            if qi % 32 == 0:
+                print(f"# one-by-one: problem {qi}/{len(problems)}", file=sys.stderr, flush=True)
+            g = gvof.GvofMesh(p["mesh"], dev, stream=st)
+            ufd, uvd = torch.from_numpy(p["uf"]).to(dev), torch.from_numpy(p["uv"]).to(dev)
+            F = g.init_fraction(p["shape"][0], p["shape"][1], 10)
+            g.reconstruct(F)
+            g.advect_step(ufd, uvd, p["dt_eff"][0], F, F)
+            e0.record(st)
+            for s in range(1, 1 + Ks):
+                g.reconstruct(F)
+                g.advect_step(ufd, uvd, p["dt_eff"][min(s, p["nsteps"] - 1)], F, F)
+            e1.record(st)
+            st.synchronize()
+            tot_ms += e0.elapsed_time(e1)
+            tot_fs += p["mesh"].nf * Ks
+            g.status()
+            g.close()
+            del g, F, ufd, uvd
+    res["one_by_one"] = {"value": tot_fs / (tot_ms / 1e3), "unit": "face·steps/s",
+                         "sample": f"every problem alone, steps 1..{Ks} after one untimed step, sum of event times"}
+    res["speedup_vs_one_by_one"] = res["value"] / res["one_by_one"]["value"]
+    return res
 
 
 def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s):

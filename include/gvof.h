@@ -197,6 +197,98 @@ int gvof_profile_enable(gvof_mesh* m, uint32_t mask);
 int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches);
 const char* gvof_kernel_name(int32_t k);
 
+/*
+ * Batches of independent problems.  The method advances every problem on its
+ * own (Sec. "Problem statement"); a batch only lets one pass of each kernel
+ * serve many problems, over flat work lists that span all of them.
+ *
+ * gvof_batch_create makes a new, unbound handle whose mesh is the disjoint
+ * union of `nprob` handles made by gvof_mesh_create (bound or not; they are
+ * copied and may be destroyed afterwards).  Problem q owns the vertex, face
+ * and cell ranges reported by gvof_batch_offsets, in part order; each part's
+ * own numbering is kept within its range, so per-problem results are
+ * bit-identical to those of the part alone.  All parts must have the same
+ * gvof_params.  Indices must fit 32 bits (GVOF_E_LIMIT otherwise).  Every
+ * single-problem call works on a batch too, treating it as one problem.
+ */
+int gvof_batch_create(gvof_mesh** out, int32_t nprob, gvof_mesh* const* parts);
+
+/* Host arrays of nprob+1 entries each (any may be NULL): range starts of each problem, then the totals. */
+int gvof_batch_offsets(const gvof_mesh* m, int32_t* nprob, int32_t* vert_off, int32_t* face_off, int32_t* cell_off);
+
+/*
+ * gvof_init_fraction with one body per problem: shapes is a HOST array of
+ * nprob entries.  Synchronous.
+ */
+int gvof_batch_init_fraction(gvof_mesh* m, const gvof_shape* shapes, int32_t n_div, double* F_out);
+
+/*
+ * One step of every active problem: gvof_reconstruct followed by
+ * gvof_advect_step, in place on F (device, nc).  dt (device, nprob doubles)
+ * holds each problem's time step; active (device, nprob bytes) selects the
+ * problems that advance: the vertices, faces and cells of a problem with
+ * active[q] == 0 are neither read for work nor written, so its F stays as it
+ * is.  u_face (3 x nf) and u_vert (3 x nv) as in gvof_advect_step, over the
+ * batch's numbering.  dt and active are read on the device when the step
+ * runs, so a captured step (gvof_graph_capture) follows their current
+ * contents.
+ */
+int gvof_batch_step(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt,
+                    const uint8_t* active, double* F);
+
+/*
+ * Captures one gvof_batch_step with these device pointers into a HIP graph
+ * owned by the handle (replacing any previous one), and replays it on the
+ * handle's stream, which must not be the default stream.  The pointers are
+ * baked into the graph: the arrays must stay allocated while it is used.  The
+ * graph is dropped by gvof_set_launch_config, gvof_autotune and
+ * gvof_mesh_destroy.  The captured step contains kernels only (no memset or
+ * copy nodes).
+ */
+int gvof_graph_capture(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt,
+                       const uint8_t* active, double* F);
+int gvof_graph_launch(gvof_mesh* m);
+
+/*
+ * Launch shapes of the step's kernels.  None of them changes any result (every
+ * sum has a fixed order whatever the mapping); they change only the time.
+ *   sweep_threads           block size of the vertex / face / cell sweeps (multiple of 64, 64..1024)
+ *   recon_threads           block size of the reconstruction kernel (64 or 128)
+ *   prep_blocks             grid of the flux-polyhedron staging kernel, one wavefront per face (1..2^20)
+ *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256)
+ *   filter_lanes            lanes per (face, cell, flux tetrahedron) pair in the general-cell filter (16, 32, 64)
+ *   staged_faces            most faces whose flux work is staged per step (0: as many as the workspace
+ *                           holds); the others are computed whole by the overflow kernel, with the same
+ *                           values.  Not tuned by gvof_autotune.
+ *   staged_pairs            most (face, cell, flux tetrahedron) pairs, and most general-cell units, staged per
+ *                           step (0: as many as the workspace holds, else rounded down to a multiple of 256,
+ *                           at least 256); faces and pairs that do not fit are computed by the overflow and
+ *                           deferred kernels, with the same values.  Not tuned by gvof_autotune.
+ */
+typedef struct gvof_launch_config {
+  int32_t sweep_threads;
+  int32_t recon_threads;
+  int32_t prep_blocks;
+  int32_t pair_blocks_per_region;
+  int32_t filter_lanes;
+  int32_t staged_faces;
+  int32_t staged_pairs;
+} gvof_launch_config;
+int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c);
+int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c);
+
+/*
+ * Chooses the launch shapes for this mesh and these inputs by measurement:
+ * coordinate descent over the values of each field, every candidate timed
+ * with HIP events over `reps` batched steps (1..1000) from the same state.
+ * F (device, nc) is saved into F_save (device, nc, caller scratch) first and
+ * restored at the end, so F is unchanged on return.  Sets the handle's launch
+ * shapes to the best found and reports them and their time per step (either
+ * output may be NULL).  Synchronous.
+ */
+int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt, const uint8_t* active,
+                  double* F, double* F_save, int32_t reps, gvof_launch_config* best, double* best_ms);
+
 /* Synchronises the stream and returns GVOF_OK or the sticky GVOF_E_GEOM. */
 int gvof_status(gvof_mesh* m);
 

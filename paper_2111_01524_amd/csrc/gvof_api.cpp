@@ -62,6 +62,14 @@ struct gvof_mesh {
   std::vector<int> fv_ptr, fv_idx, owner, neigh;
   std::vector<int> cf_ptr, cf_idx, cv_ptr, cv_idx, vc_ptr, vc_idx, nb_ptr, nb_idx;
   int max_nb = 0;
+  // problem partition: problem q owns vertices [voff[q], voff[q+1]), faces
+  // [foff[q], foff[q+1]) and cells [coff[q], coff[q+1])
+  int nprob = 1;
+  std::vector<int> voff, foff, coff;
+  gvof::LaunchCfg cfg;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  gvof::Shape* shape_area = nullptr;  // per-problem bodies of a batched initialisation (workspace)
   // device
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -225,6 +233,9 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
     m->nb_ptr[c + 1] = (int)nb.size();
   }
   m->nb_idx.swap(nb);
+  m->voff = {0, nv};
+  m->foff = {0, nf};
+  m->coff = {0, nc};
   *out = m;
   return GVOF_OK;
 }
@@ -322,15 +333,25 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.list_over = C.take<int>(nf);
   d.list_deep = C.take<int>(d.item_cap);
   d.item_fill = C.take<int>(gvof::kItemRegions);
+  d.item_okend = C.take<int>(gvof::kItemRegions);
   d.item_uoff = C.take<int>(d.item_cap);
   d.item_ucnt = C.take<int>(d.item_cap);
   d.unit_item = C.take<int>(d.item_cap);
   d.unit_code = C.take<unsigned>(d.item_cap);
   d.unit_vol = C.take<double>(d.item_cap);
   d.unit_fill = C.take<int>(gvof::kItemRegions);
+  d.unit_okend = C.take<int>(gvof::kItemRegions);
   d.list_udeep = C.take<int>(d.item_cap);
   d.counters = C.take<int>(gvof::CNT_N);
   d.totals = C.take<unsigned long long>(4);
+  d.nprob = m->nprob;
+  if (m->nprob > 1) {
+    d.vert_pid = C.take<int>(nv);
+    d.face_pid = C.take<int>(nf);
+    d.cell_pid = C.take<int>(nc);
+  }
+  gvof::Shape* shp = C.take<gvof::Shape>(m->nprob);
+  if (dm) m->shape_area = shp;
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
@@ -378,6 +399,17 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, up(d.vc_idx, m->vc_idx.data(), m->vc_idx.size() * 4));
   HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
   if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
+  std::vector<int> pid[3];
+  if (m->nprob > 1) {
+    const std::vector<int>* offs[3] = {&m->voff, &m->foff, &m->coff};
+    int* dst[3] = {const_cast<int*>(d.vert_pid), const_cast<int*>(d.face_pid), const_cast<int*>(d.cell_pid)};
+    for (int a = 0; a < 3; ++a) {
+      const std::vector<int>& o = *offs[a];
+      pid[a].resize(o.back());
+      for (int q = 0; q < m->nprob; ++q) std::fill(pid[a].begin() + o[q], pid[a].begin() + o[q + 1], q);
+      HIPCHECK(m, up(dst[a], pid[a].data(), pid[a].size() * 4));
+    }
+  }
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
   HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 8, s));
   HIPCHECK(m, gvof::launch_geometry(d, s));
@@ -407,7 +439,18 @@ int gvof_set_stream(gvof_mesh* m, void* stream) {
   return GVOF_OK;
 }
 
-void gvof_mesh_destroy(gvof_mesh* m) { delete m; }
+static void drop_graph(gvof_mesh* m) {
+  if (m->gexec) hipGraphExecDestroy(m->gexec);
+  if (m->graph) hipGraphDestroy(m->graph);
+  m->gexec = nullptr;
+  m->graph = nullptr;
+}
+
+void gvof_mesh_destroy(gvof_mesh* m) {
+  if (!m) return;
+  drop_graph(m);
+  delete m;
+}
 
 int gvof_mesh_sizes(const gvof_mesh* m, int32_t* nv, int32_t* nf, int32_t* nc, int32_t* max_neigh) {
   if (!m) return GVOF_E_ARG;
@@ -462,7 +505,7 @@ int gvof_reconstruct(gvof_mesh* m, double* F, int8_t* cell_tag_out, double* plan
   if (r) return r;
   if (!F) return fail(m, GVOF_E_ARG, "F is NULL");
   m->prof.stream = m->stream;
-  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->stream, m->prof.mask ? &m->prof : nullptr));
+  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->cfg, m->stream, m->prof.mask ? &m->prof : nullptr));
   m->reconstructed = true;
   if ((r = d2d(m, cell_tag_out, m->dm.tag_cell, m->nc))) return r;
   return d2d(m, plane_out, m->dm.pnx, 4 * (size_t)m->nc * 8);
@@ -486,7 +529,7 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
   if (!u_face || !u_vert || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
   if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
   m->prof.stream = m->stream;
-  HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->stream,
+  HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->cfg, m->stream,
                                   m->prof.mask ? &m->prof : nullptr));
   if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
   if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;
@@ -556,6 +599,294 @@ int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches) {
     }
   }
   m->prof.clear();
+  return GVOF_OK;
+}
+
+// ------------------------------------------------------------------ batches
+int gvof_batch_create(gvof_mesh** out, int32_t nprob, gvof_mesh* const* parts) {
+  if (!out) return fail(nullptr, GVOF_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (nprob < 1 || !parts) return fail(nullptr, GVOF_E_ARG, "nprob=%d or parts NULL", nprob);
+  int64_t nv = 0, nf = 0, nc = 0, nfv = 0, ncf = 0, ncv = 0, nvc = 0, nnb = 0;
+  for (int q = 0; q < nprob; ++q) {
+    const gvof_mesh* a = parts[q];
+    if (!a) return fail(nullptr, GVOF_E_ARG, "part %d is NULL", q);
+    if (a->nprob != 1) return fail(nullptr, GVOF_E_ARG, "part %d is itself a batch", q);
+    const gvof_params& p0 = parts[0]->p;
+    if (a->p.eps != p0.eps || a->p.beta != p0.beta || a->p.fmfpa_degen != p0.fmfpa_degen || a->p.flags != p0.flags)
+      return fail(nullptr, GVOF_E_ARG, "part %d has parameters different from part 0", q);
+    nv += a->nv;
+    nf += a->nf;
+    nc += a->nc;
+    nfv += (int64_t)a->fv_idx.size();
+    ncf += (int64_t)a->cf_idx.size();
+    ncv += (int64_t)a->cv_idx.size();
+    nvc += (int64_t)a->vc_idx.size();
+    nnb += (int64_t)a->nb_idx.size();
+  }
+  const int64_t lim = INT32_MAX;
+  if (nv > lim || nf > lim || nc > lim || nfv > lim || ncf > lim || ncv > lim || nvc > lim || nnb > lim)
+    return fail(nullptr, GVOF_E_LIMIT, "batch exceeds 32-bit indexing (nv=%lld nf=%lld nc=%lld)", (long long)nv,
+                (long long)nf, (long long)nc);
+  gvof_mesh* m = new gvof_mesh;
+  m->p = parts[0]->p;
+  m->nv = (int)nv;
+  m->nf = (int)nf;
+  m->nc = (int)nc;
+  m->nprob = nprob;
+  m->voff.assign(1, 0);
+  m->foff.assign(1, 0);
+  m->coff.assign(1, 0);
+  for (auto* v : {&m->fv_ptr, &m->cf_ptr, &m->cv_ptr, &m->vc_ptr, &m->nb_ptr}) v->assign(1, 0);
+  m->vx.reserve(nv);
+  m->vy.reserve(nv);
+  m->vz.reserve(nv);
+  m->fv_idx.reserve(nfv);
+  m->owner.reserve(nf);
+  m->neigh.reserve(nf);
+  m->cf_idx.reserve(ncf);
+  m->cv_idx.reserve(ncv);
+  m->vc_idx.reserve(nvc);
+  m->nb_idx.reserve(nnb);
+  // a CSR pointer array continued by a part's (its entries shifted by `base`)
+  auto cat_ptr = [](std::vector<int>& dst, const std::vector<int>& src) {
+    int base = dst.back();
+    for (size_t i = 1; i < src.size(); ++i) dst.push_back(src[i] + base);
+  };
+  auto cat_idx = [](std::vector<int>& dst, const std::vector<int>& src, int shift) {
+    for (int x : src) dst.push_back(x + shift);
+  };
+  for (int q = 0; q < nprob; ++q) {
+    const gvof_mesh* a = parts[q];
+    const int vo = m->voff.back(), fo = m->foff.back(), co = m->coff.back();
+    m->vx.insert(m->vx.end(), a->vx.begin(), a->vx.end());
+    m->vy.insert(m->vy.end(), a->vy.begin(), a->vy.end());
+    m->vz.insert(m->vz.end(), a->vz.begin(), a->vz.end());
+    cat_ptr(m->fv_ptr, a->fv_ptr);
+    cat_idx(m->fv_idx, a->fv_idx, vo);
+    cat_idx(m->owner, a->owner, co);
+    for (int x : a->neigh) m->neigh.push_back(x >= 0 ? x + co : -1);
+    cat_ptr(m->cf_ptr, a->cf_ptr);
+    for (int e : a->cf_idx) m->cf_idx.push_back(e >= 0 ? e + fo : ~((~e) + fo));
+    cat_ptr(m->cv_ptr, a->cv_ptr);
+    cat_idx(m->cv_idx, a->cv_idx, vo);
+    cat_ptr(m->vc_ptr, a->vc_ptr);
+    cat_idx(m->vc_idx, a->vc_idx, co);
+    cat_ptr(m->nb_ptr, a->nb_ptr);
+    cat_idx(m->nb_idx, a->nb_idx, co);
+    m->max_nb = std::max(m->max_nb, a->max_nb);
+    m->voff.push_back(vo + a->nv);
+    m->foff.push_back(fo + a->nf);
+    m->coff.push_back(co + a->nc);
+  }
+  *out = m;
+  return GVOF_OK;
+}
+
+int gvof_batch_offsets(const gvof_mesh* m, int32_t* nprob, int32_t* vert_off, int32_t* face_off, int32_t* cell_off) {
+  if (!m) return GVOF_E_ARG;
+  if (nprob) *nprob = m->nprob;
+  for (int q = 0; q <= m->nprob; ++q) {
+    if (vert_off) vert_off[q] = m->voff[q];
+    if (face_off) face_off[q] = m->foff[q];
+    if (cell_off) cell_off[q] = m->coff[q];
+  }
+  return GVOF_OK;
+}
+
+int gvof_batch_init_fraction(gvof_mesh* m, const gvof_shape* shapes, int32_t n_div, double* F_out) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!shapes || !F_out) return fail(m, GVOF_E_ARG, "NULL shapes or F_out");
+  if (n_div < 1 || n_div > 64) return fail(m, GVOF_E_ARG, "n_div=%d outside 1..64", n_div);
+  std::vector<gvof::Shape> sh(m->nprob);
+  for (int q = 0; q < m->nprob; ++q) {
+    const gvof_shape& a = shapes[q];
+    if (a.kind != GVOF_SHAPE_SPHERE && a.kind != GVOF_SHAPE_PLANE)
+      return fail(m, GVOF_E_ARG, "problem %d: unknown shape kind %d", q, a.kind);
+    if (a.kind == GVOF_SHAPE_SPHERE && !(a.p[3] > 0.0)) return fail(m, GVOF_E_ARG, "problem %d: radius <= 0", q);
+    sh[q] = gvof::Shape{a.kind, a.p[0], a.p[1], a.p[2], a.p[3]};
+  }
+  HIPCHECK(m, hipMemcpyAsync(m->shape_area, sh.data(), sh.size() * sizeof(gvof::Shape), hipMemcpyHostToDevice,
+                             m->stream));
+  DevMesh d = m->dm;
+  d.prob_shape = m->shape_area;
+  const double unused[4] = {0.0, 0.0, 0.0, 1.0};
+  HIPCHECK(m, gvof::launch_init(d, GVOF_SHAPE_SPHERE, unused, n_div, F_out, m->stream));
+  HIPCHECK(m, hipStreamSynchronize(m->stream));  // the host shape array may go away after return
+  return GVOF_OK;
+}
+
+static int batch_launch(gvof_mesh* m, const double* uf, const double* uv, const double* dt, const uint8_t* active,
+                        double* F, gvof::Prof* prof) {
+  DevMesh d = m->dm;
+  d.prob_dt = dt;
+  d.prob_active = active;
+  HIPCHECK(m, gvof::launch_reconstruct(d, F, m->cfg, m->stream, prof));
+  HIPCHECK(m, gvof::launch_advect(d, uf, uv, 0.0, F, F, m->cfg, m->stream, prof));
+  return GVOF_OK;
+}
+
+static int batch_args(gvof_mesh* m, const double* uf, const double* uv, const double* dt, const uint8_t* active,
+                      double* F) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!uf || !uv || !dt || !active || !F) return fail(m, GVOF_E_ARG, "NULL array argument");
+  return GVOF_OK;
+}
+
+int gvof_batch_step(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt,
+                    const uint8_t* active, double* F) {
+  int r = batch_args(m, u_face, u_vert, dt, active, F);
+  if (r) return r;
+  m->prof.stream = m->stream;
+  if ((r = batch_launch(m, u_face, u_vert, dt, active, F, m->prof.mask ? &m->prof : nullptr))) return r;
+  m->reconstructed = true;
+  return GVOF_OK;
+}
+
+int gvof_graph_capture(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt,
+                       const uint8_t* active, double* F) {
+  int r = batch_args(m, u_face, u_vert, dt, active, F);
+  if (r) return r;
+  if (!m->stream) return fail(m, GVOF_E_ARG, "graph capture needs a stream other than the default stream");
+  drop_graph(m);
+  HIPCHECK(m, hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal));
+  r = batch_launch(m, u_face, u_vert, dt, active, F, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(m->stream, &g);
+  if (r) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(m, GVOF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  m->graph = g;
+  e = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(m);
+    return fail(m, GVOF_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return GVOF_OK;
+}
+
+int gvof_graph_launch(gvof_mesh* m) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!m->gexec) return fail(m, GVOF_E_ARG, "no captured step (gvof_graph_capture)");
+  HIPCHECK(m, hipGraphLaunch(m->gexec, m->stream));
+  m->reconstructed = true;
+  return GVOF_OK;
+}
+
+// ------------------------------------------------------------------ launch shapes
+static void cfg_out(const gvof::LaunchCfg& c, gvof_launch_config* o) {
+  o->sweep_threads = c.sweep_threads;
+  o->recon_threads = c.recon_threads;
+  o->prep_blocks = c.prep_blocks;
+  o->pair_blocks_per_region = c.pair_blocks_per_region;
+  o->filter_lanes = c.filter_lanes;
+  o->staged_faces = c.staged_faces;
+  o->staged_pairs = c.staged_pairs;
+}
+
+int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c) {
+  if (!m || !c) return GVOF_E_ARG;
+  cfg_out(m->cfg, c);
+  return GVOF_OK;
+}
+
+int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
+  if (!m || !c) return GVOF_E_ARG;
+  if (c->sweep_threads < 64 || c->sweep_threads > 1024 || c->sweep_threads % 64)
+    return fail(m, GVOF_E_ARG, "sweep_threads=%d (a multiple of 64 in 64..1024)", c->sweep_threads);
+  if (c->recon_threads != 64 && c->recon_threads != 128)
+    return fail(m, GVOF_E_ARG, "recon_threads=%d (64 or 128)", c->recon_threads);
+  if (c->prep_blocks < 1 || c->prep_blocks > (1 << 20))
+    return fail(m, GVOF_E_ARG, "prep_blocks=%d (1..2^20)", c->prep_blocks);
+  if (c->pair_blocks_per_region < 1 || c->pair_blocks_per_region > 256)
+    return fail(m, GVOF_E_ARG, "pair_blocks_per_region=%d (1..256)", c->pair_blocks_per_region);
+  if (c->filter_lanes != 16 && c->filter_lanes != 32 && c->filter_lanes != 64)
+    return fail(m, GVOF_E_ARG, "filter_lanes=%d (16, 32 or 64)", c->filter_lanes);
+  if (c->staged_faces < 0) return fail(m, GVOF_E_ARG, "staged_faces=%d (>= 0)", c->staged_faces);
+  if (c->staged_pairs < 0) return fail(m, GVOF_E_ARG, "staged_pairs=%d (>= 0)", c->staged_pairs);
+  m->cfg.sweep_threads = c->sweep_threads;
+  m->cfg.recon_threads = c->recon_threads;
+  m->cfg.prep_blocks = c->prep_blocks;
+  m->cfg.pair_blocks_per_region = c->pair_blocks_per_region;
+  m->cfg.filter_lanes = c->filter_lanes;
+  m->cfg.staged_faces = c->staged_faces;
+  m->cfg.staged_pairs = c->staged_pairs;
+  drop_graph(m);
+  return GVOF_OK;
+}
+
+int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, const double* dt, const uint8_t* active,
+                  double* F, double* F_save, int32_t reps, gvof_launch_config* best, double* best_ms) {
+  int r = batch_args(m, u_face, u_vert, dt, active, F);
+  if (r) return r;
+  if (!F_save) return fail(m, GVOF_E_ARG, "F_save is NULL");
+  if (reps < 1 || reps > 1000) return fail(m, GVOF_E_ARG, "reps=%d outside 1..1000", reps);
+  drop_graph(m);
+  const size_t fb = (size_t)m->nc * sizeof(double);
+  hipStream_t s = m->stream;
+  HIPCHECK(m, hipMemcpyAsync(F_save, F, fb, hipMemcpyDeviceToDevice, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(m, hipEventCreate(&e0));
+  HIPCHECK(m, hipEventCreate(&e1));
+  // time per step of `reps` steps from the saved state (after one untimed step)
+  auto timed = [&](const gvof::LaunchCfg& c, double& ms) -> int {
+    gvof::LaunchCfg keep = m->cfg;
+    m->cfg = c;
+    int rr = GVOF_OK;
+    HIPCHECK(m, hipMemcpyAsync(F, F_save, fb, hipMemcpyDeviceToDevice, s));
+    if ((rr = batch_launch(m, u_face, u_vert, dt, active, F, nullptr))) return rr;
+    HIPCHECK(m, hipMemcpyAsync(F, F_save, fb, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(m, hipEventRecord(e0, s));
+    for (int i = 0; i < reps && !rr; ++i) rr = batch_launch(m, u_face, u_vert, dt, active, F, nullptr);
+    HIPCHECK(m, hipEventRecord(e1, s));
+    HIPCHECK(m, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHECK(m, hipEventElapsedTime(&t, e0, e1));
+    ms = t / reps;
+    m->cfg = keep;
+    return rr;
+  };
+  gvof::LaunchCfg cur = m->cfg;
+  double cur_ms = 0.0;
+  if ((r = timed(cur, cur_ms))) return r;
+  // coordinate descent over the launch shapes, each with the others fixed
+  const int prep[] = {4096, 8192, 16384, 32768};
+  const int pbr[] = {4, 8, 16, 32, 64};
+  const int lanes[] = {16, 32, 64};
+  const int sweep[] = {128, 256, 512, 1024};
+  const int recon[] = {64, 128};
+  auto sweep_param = [&](int gvof::LaunchCfg::*field, const int* vals, int nvals) -> int {
+    for (int i = 0; i < nvals; ++i) {
+      if (cur.*field == vals[i]) continue;
+      gvof::LaunchCfg c = cur;
+      c.*field = vals[i];
+      double t = 0.0;
+      int rr = timed(c, t);
+      if (rr) return rr;
+      if (t < cur_ms) {
+        cur = c;
+        cur_ms = t;
+      }
+    }
+    return GVOF_OK;
+  };
+  if ((r = sweep_param(&gvof::LaunchCfg::prep_blocks, prep, 4))) return r;
+  if ((r = sweep_param(&gvof::LaunchCfg::pair_blocks_per_region, pbr, 5))) return r;
+  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 3))) return r;
+  if ((r = sweep_param(&gvof::LaunchCfg::sweep_threads, sweep, 4))) return r;
+  if ((r = sweep_param(&gvof::LaunchCfg::recon_threads, recon, 2))) return r;
+  m->cfg = cur;
+  HIPCHECK(m, hipMemcpyAsync(F, F_save, fb, hipMemcpyDeviceToDevice, s));
+  HIPCHECK(m, hipStreamSynchronize(s));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (best) cfg_out(cur, best);
+  if (best_ms) *best_ms = cur_ms;
   return GVOF_OK;
 }
 

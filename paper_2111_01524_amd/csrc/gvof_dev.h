@@ -42,12 +42,14 @@ struct DevMesh {
   double* item_vol;
   int item_cap;
   int* item_fill;              // fill counter of each of kItemRegions regions of the pair buffer
+  int* item_okend;             // per region: start of the first reservation that did not fit (INT_MAX: none)
   // general-cell pairs: surviving (pair, surface tetrahedron) units
   int *item_uoff, *item_ucnt;  // per pair
   int* unit_item;
   unsigned* unit_code;         // surface tetrahedron index | cutting-plane mask << 16
   double* unit_vol;
   int* unit_fill;              // per region
+  int* unit_okend;             // per region, as item_okend
   int* list_udeep;             // units with four cutting planes
   int* list_over;              // faces not staged (capacity exceeded)
   int* list_deep;              // pairs cut by more planes than the register clip takes
@@ -55,7 +57,38 @@ struct DevMesh {
   unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
   int all_box;  // every cell is an axis-aligned box (set at bind)
+  // problem partition of a batch (a disjoint union of independent meshes);
+  // with nprob == 1 the id arrays are not read
+  int nprob;
+  const int *vert_pid, *face_pid, *cell_pid;
+  // per-problem inputs of a batched step (NULL outside batched calls): time
+  // step, and whether the problem advances (inactive problems are left untouched)
+  const double* prob_dt;
+  const unsigned char* prob_active;
+  const struct Shape* prob_shape;  // per-problem body of a batched initialisation
 };
+
+// Body of the refinement initialisation: kind 0 sphere (centre a, b, c; radius
+// d), kind 1 half-space a x + b y + c z + d >= 0.
+struct Shape {
+  int kind;
+  double a, b, c, d;
+};
+
+__device__ inline int problem_of(const DevMesh& M, const int* pid, int i) { return M.nprob > 1 ? pid[i] : 0; }
+__device__ inline bool vert_live(const DevMesh& M, int v) {
+  return !M.prob_active || M.prob_active[problem_of(M, M.vert_pid, v)] != 0;
+}
+__device__ inline bool face_live(const DevMesh& M, int f) {
+  return !M.prob_active || M.prob_active[problem_of(M, M.face_pid, f)] != 0;
+}
+__device__ inline bool cell_live(const DevMesh& M, int c) {
+  return !M.prob_active || M.prob_active[problem_of(M, M.cell_pid, c)] != 0;
+}
+// time step of face f: the scalar argument, or its problem's entry in a batched step
+__device__ inline double face_dt(const DevMesh& M, int f, double dt) {
+  return M.prob_dt ? M.prob_dt[problem_of(M, M.face_pid, f)] : dt;
+}
 
 enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_ITEMS = 4, CNT_OVER = 5, CNT_DEEP = 6, CNT_UDEEP = 7, CNT_N = 8 };
 enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16 };

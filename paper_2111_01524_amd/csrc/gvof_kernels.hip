@@ -169,6 +169,7 @@ __global__ void k_cell_geom(DevMesh M) {
 __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
+    if (!vert_live(M, v)) continue;
     d3 x = vert(M, v);
     double num = 0.0, den = 0.0;
     for (int i = M.vc_ptr[v]; i < M.vc_ptr[v + 1]; ++i) {
@@ -187,6 +188,7 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
 
 __global__ void k_face_tag(DevMesh M) {
   for (int f = grid_stride_start(); f < M.nf; f += grid_stride()) {
+    if (!face_live(M, f)) continue;
     bool allm = true, allp = true;
     for (int i = M.fv_ptr[f]; i < M.fv_ptr[f + 1]; ++i) {
       int t = M.tag_node[M.fv_idx[i]];
@@ -207,7 +209,7 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
   for (int b = base0; b < n; b += stride) {
     int c = b + (threadIdx.x & 63);
     bool inter = false;
-    if (c < n) {
+    if (c < n && cell_live(M, c)) {
       double f = F[c];
       int8_t t = f < eps ? -1 : (f > one_m ? 1 : 0);
       M.tag_cell[c] = t;
@@ -386,10 +388,10 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
   for (int b = base0; b < n; b += stride) {
     int f = b + (threadIdx.x & 63);
     bool geo = false;
-    if (f < n) {
+    if (f < n && face_live(M, f)) {
       d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
       d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-      double vd = dt * dot_x(u, S);
+      double vd = face_dt(M, f, dt) * dot_x(u, S);
       int nb = M.neigh[f];
       M.Vd[f] = vd;
       M.upwind[f] = vd >= 0.0 ? M.owner[f] : nb;
@@ -407,7 +409,6 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
 constexpr int kFluxLanes = 64;
 constexpr int kMaxPts = 2 * kMaxFaceVerts + 1;
 constexpr int kMaxCand = 2 + 2 * kMaxNeighbours;
-constexpr int kQueue = 512;
 
 __device__ inline bool box_overlap(d3 alo, d3 ahi, d3 blo, d3 bhi) {
   return alo.x < bhi.x && blo.x < ahi.x && alo.y < bhi.y && blo.y < ahi.y && alo.z < bhi.z && blo.z < ahi.z;
@@ -461,7 +462,6 @@ struct FluxLds {
   double cpnx[kMaxCand], cpny[kMaxCand], cpnz[kMaxCand], cpc[kMaxCand];
   double cccx[kMaxCand], cccy[kMaxCand], cccz[kMaxCand];
   signed char ctag[kMaxCand], cbox[kMaxCand];
-  unsigned queue[kQueue];
 };
 
 // FMFPA polyhedron of face f into S.px/py/pz: lanes 0..I-1 build the
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       continue;
     }
     d3 c, Sv, plo, phi;
-    flux_polyhedron(M, S, f, b0, I, uv, dt, c, Sv, plo, phi);
+    flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
     if (lane <= 2 * I) {
       P[3 * lane] = S.px[lane];
@@ -765,11 +765,14 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       if (pass == 0) {
         if (lane == 0) {
           // the pair buffer is split into kItemRegions regions with a fill counter
-          // each; a block reserves in region blockIdx % kItemRegions
-          int r = blockIdx.x % kItemRegions;
+          // each; face slot it reserves in region it % kItemRegions
+          int r = it % kItemRegions;
           int rsize = M.item_cap / kItemRegions;
           int base = atomicAdd(&M.item_fill[r], count);
           if (base + count > rsize) {
+            // every reservation before this one in atomic order fitted and every
+            // later one fails: the region's written part is [0, smallest failed base)
+            atomicMin(&M.item_okend[r], base);
             M.item_cnt[it] = -1;
             M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
             base = -1;
@@ -802,15 +805,21 @@ __device__ inline Tet staged_tet(const DevMesh& M, int slot, int t) {
 }
 
 // Pair buffer regions: block b serves region b % kItemRegions and strides over
-// that region's filled part with the other blocks of the same region.
-constexpr int kItemBlocksPerRegion = 16;
+// that region's filled part with the other gridDim.x / kItemRegions blocks of
+// the same region (the grid is a multiple of kItemRegions).
+__device__ inline int region_blocks() { return gridDim.x / kItemRegions; }
+// Written pairs of region r: reservations that did not fit leave the fill
+// counter past what was written, so the count stops at the first of them.
+__device__ inline int region_items(const DevMesh& M, int r, int rsize) {
+  return min(min(M.item_fill[r], M.item_okend[r]), rsize);
+}
 
 // Box-cell pairs, one lane per pair.
 __global__ __launch_bounds__(256) void k_flux_items_box(DevMesh M) {
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
-  const int fill = min(M.item_fill[r], rsize);
-  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += kItemBlocksPerRegion * blockDim.x) {
+  const int fill = region_items(M, r, rsize);
+  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += region_blocks() * blockDim.x) {
     const int i = r * rsize + li;
     int k = M.item_cell[i];
     if (!M.isbox[k]) continue;
@@ -849,19 +858,23 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) {
   return np;
 }
 
-// Pairs with a general (non-box) cell, stage 1: one half-wavefront per pair,
-// lane j testing the cell's surface tetrahedra j, j+32, ...: boxes overlap and
+// Pairs with a general (non-box) cell, stage 1: a group of LPP lanes per pair
+// (16, 32 or 64; the lane-to-pair mapping is a launch choice), lane j of the
+// group testing the cell's surface tetrahedra j, j+LPP, ...: boxes overlap and
 // no plane of the tetrahedron leaves the flux tet entirely outside.  The
 // survivors (pair, surface tetrahedron, mask of cutting planes) are written in
-// tetrahedron order into a range of the unit buffer reserved for the pair.
+// tetrahedron order into a range of the unit buffer reserved for the pair, so
+// the result does not depend on LPP.
+template <int LPP>
 __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
-  const int fill = min(M.item_fill[r], rsize);
-  const int hl = threadIdx.x & 31, half = threadIdx.x >> 5;
-  const int halves = blockDim.x >> 5;
-  const unsigned long long hmask = 0xffffffffull << (threadIdx.x & 32);
-  for (int li = sub * halves + half; li < fill; li += kItemBlocksPerRegion * halves) {
+  const int fill = region_items(M, r, rsize);
+  const int hl = threadIdx.x & (LPP - 1), half = threadIdx.x / LPP;
+  const int halves = blockDim.x / LPP;
+  const int glead = threadIdx.x & 63 & ~(LPP - 1);  // first lane of the group within the wavefront
+  const unsigned long long hmask = (LPP == 64 ? ~0ull : ((1ull << LPP) - 1ull)) << glead;
+  for (int li = sub * halves + half; li < fill; li += region_blocks() * halves) {
     const int i = r * rsize + li;
     const int k = M.item_cell[i];
     if (M.isbox[k]) continue;
@@ -876,7 +889,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     int base = 0;
     for (int pass = 0; pass < 2; ++pass) {
       int written = 0;
-      for (int p0 = 0; p0 < np; p0 += 32) {
+      for (int p0 = 0; p0 < np; p0 += LPP) {
         int p = p0 + hl;
         bool keep = false;
         unsigned cm = 0;
@@ -903,10 +916,14 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
         int b = 0;
         if (hl == 0) {
           b = atomicAdd(&M.unit_fill[r], count);
-          if (b + count > rsize) b = -1;
-          else b += r * rsize;
+          if (b + count > rsize) {
+            atomicMin(&M.unit_okend[r], b);
+            b = -1;
+          } else {
+            b += r * rsize;
+          }
         }
-        base = __shfl(b, (threadIdx.x & 32), 64);
+        base = __shfl(b, glead, 64);
         if (base < 0) {  // no room: the deferred kernel computes the whole pair
           if (hl == 0) {
             M.item_ucnt[i] = -1;
@@ -925,13 +942,15 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 
 // Stage 2: one lane per surviving (pair, surface tetrahedron): clip in
 // registers, up to three cutting planes; units with four (about 5% on the
-// distorted-grid workload) go to a list for k_flux_gen_units_deep.
+// distorted-grid workload) go to a list for k_flux_gen_units_deep, which runs
+// the same register clip one level deeper (so every unit has one value
+// whichever kernel computes it).
 template <bool DEEP>
 __global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
-  const int fill = min(M.unit_fill[r], rsize);
-  for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += kItemBlocksPerRegion * blockDim.x) {
+  const int fill = min(min(M.unit_fill[r], M.unit_okend[r]), rsize);
+  for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += region_blocks() * blockDim.x) {
     const int u = r * rsize + lu;
     const int i = M.unit_item[u];
     const unsigned code = M.unit_code[u];
@@ -979,11 +998,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
     leaf.hd = M.pC[k];
-    double v = clip_volume(T, TC, leaf);
-    if (v == -1.0) {
-      atomicOr(&M.counters[CNT_ERR], ERR_STACK);
-      v = 0.0;
-    }
+    double v = clip_masked_tet<4>(T, TC, code >> 16, leaf);
     M.unit_vol[u] = s6 > 0.0 ? v : -v;
   }
 }
@@ -992,8 +1007,8 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
 __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
-  const int fill = min(M.item_fill[r], rsize);
-  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += kItemBlocksPerRegion * blockDim.x) {
+  const int fill = region_items(M, r, rsize);
+  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += region_blocks() * blockDim.x) {
     const int i = r * rsize + li;
     const int k = M.item_cell[i];
     if (M.isbox[k]) continue;
@@ -1007,7 +1022,34 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
   }
 }
 
-// Deferred pairs: explicit-stack clipping, any number of cutting planes.
+// Signed volume of one (flux tet, box cell) pair with cut mask `mask`: the
+// value every kernel gives the pair (register clip up to kMaxRegCuts cutting
+// planes, the explicit-stack clip beyond; a flat flux tet gives 0).
+__device__ inline double box_pair_volume(const DevMesh& M, const Tet& T, const BoxCont& B, unsigned mask,
+                                         const Leaf& leaf) {
+  double sT = tet6(T);
+  if (sT == 0.0) return 0.0;
+  double v = cut_count(mask) <= kMaxRegCuts ? clip_masked(T, B, mask, leaf) : clip_volume(T, B, leaf);
+  if (v == -1.0) {
+    atomicOr(&M.counters[CNT_ERR], ERR_STACK);
+    v = 0.0;
+  }
+  return sT < 0.0 ? -v : v;
+}
+
+// Signed volume of one (flux tet, general cell) pair: the cell's surface
+// tetrahedra in order, each clipped in registers (the same units and the same
+// order as the three-stage path).
+__device__ inline double general_pair_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf) {
+  double sT = tet6(T);
+  if (sT == 0.0) return 0.0;
+  double v;
+  tet_cell_pieces_volume<true>(M, k, cc, T, leaf, v);
+  return sT < 0.0 ? -v : v;
+}
+
+// Deferred pairs: box pairs with more cutting planes than the register clip
+// takes, and general pairs whose units did not fit the unit buffer.
 __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
   int n = M.counters[CNT_DEEP];
   for (int j = grid_stride_start(); j < n; j += grid_stride()) {
@@ -1015,7 +1057,6 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
     int k = M.item_cell[i];
     unsigned tm = M.item_tm[i];
     Tet T = staged_tet(M, M.item_slot[i], tm & 31);
-    double sT = tet6(T);
     Leaf leaf;
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
@@ -1023,15 +1064,11 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
     double v;
     if (M.isbox[k]) {
       BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-      v = clip_volume(T, B, leaf);
-      if (v == -1.0) {
-        atomicOr(&M.counters[CNT_ERR], ERR_STACK);
-        v = 0.0;
-      }
+      v = box_pair_volume(M, T, B, tm >> 5, leaf);
     } else {
-      tet_cell_pieces_volume<true>(M, k, cell_centre(M, k), T, leaf, v);
+      v = general_pair_volume(M, k, cell_centre(M, k), T, leaf);
     }
-    M.item_vol[i] = sT < 0.0 ? -v : v;
+    M.item_vol[i] = v;
   }
 }
 
@@ -1048,8 +1085,11 @@ __global__ void k_flux_sum(DevMesh M) {
   }
 }
 
-// Faces that did not fit the staging buffers: one wavefront per face does the
-// whole computation with an LDS queue of (tet, piece) pairs.
+// Faces that did not fit the staging buffers (or have more candidate cells
+// than the staging LDS holds): one wavefront per face, one lane per
+// (candidate, flux tet) pair computing the pair's volume with the same
+// functions as the staged path, summed in the same (candidate, tetrahedron)
+// order, so V_F does not depend on which path computed it.
 __global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const double* __restrict__ uv, double dt) {
   __shared__ FluxLds S;
   const int lane = threadIdx.x;
@@ -1058,114 +1098,68 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const doubl
     const int f = M.list_over[it];
     const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
     d3 c, Sv, plo, phi;
-    flux_polyhedron(M, S, f, b0, I, uv, dt, c, Sv, plo, phi);
+    flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
     const int ncand = flux_candidates(M, S, f, plo, phi);
     const int T3 = 3 * I;
-    const int total = S.cpre[ncand] * T3;
-    double acc = 0.0;
-    int qn = 0;
-    for (int q0 = 0; q0 < total || qn > 0; q0 += kFluxLanes) {
-      if (q0 < total) {
-        int q = q0 + lane;
-        bool keep = false;
-        unsigned code = 0;
-        if (q < total) {
-          int t = q % T3, r = q / T3;
-          int lo = 0, hi = ncand;  // cpre[lo] <= r < cpre[lo+1]
-          while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (S.cpre[mid] <= r) lo = mid;
-            else hi = mid;
-          }
-          int kc = lo, m = r - S.cpre[lo];
-          int i1, i2, i3;
-          flux_tet_points(t, I, i1, i2, i3);
-          Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
-                mk3(S.px[i3], S.py[i3], S.pz[i3])};
-          d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
-          unsigned mask = 0;
-          if (S.cbox[kc]) {
-            BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
-            keep = box_overlap(tlo, thi, B.lo, B.hi) && cut_mask(T, B, mask);
-          } else {
-            d3 t0, t1, t2;
-            cell_piece(M, S.cand[kc], m, t0, t1, t2);
-            d3 cc = mk3(S.cccx[kc], S.cccy[kc], S.cccz[kc]);
-            keep = box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)));
-          }
-          code = ((unsigned)m << 18) | (mask << 12) | ((unsigned)kc << 5) | (unsigned)t;
-        }
-        unsigned long long bm = __ballot(keep);
-        if (keep) S.queue[qn + __popcll(bm & ((1ull << lane) - 1ull))] = code;
-        qn += __popcll(bm);
-      }
-      __syncthreads();
-      bool flush = (q0 + kFluxLanes >= total) || (qn + kFluxLanes > kQueue);
-      if (!flush) continue;
-      for (int qi = lane; qi < qn; qi += kFluxLanes) {
-        unsigned code = S.queue[qi];
-        int t = code & 31, kc = (code >> 5) & 127, m = (int)(code >> 18);
-        unsigned mask = (code >> 12) & 63u;
+    const int total = ncand * T3;
+    double acc = 0.0;  // identical in every lane
+    for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
+      const int q = q0 + lane;
+      int keep = 0;
+      double v = 0.0;
+      if (q < total) {
+        const int t = q % T3, kc = q / T3;
         int i1, i2, i3;
         flux_tet_points(t, I, i1, i2, i3);
         Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
               mk3(S.px[i3], S.py[i3], S.pz[i3])};
-        double sT = tet6(T);
-        if (sT == 0.0) continue;
+        d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+        BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
+        keep = box_overlap(tlo, thi, B.lo, B.hi) ? 1 : 0;
         Leaf leaf;
         leaf.useH = S.ctag[kc] == 0;
         leaf.hn = mk3(S.cpnx[kc], S.cpny[kc], S.cpnz[kc]);
         leaf.hd = S.cpc[kc];
-        double v;
-        if (S.cbox[kc]) {
-          BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
-          v = cut_count(mask) <= kMaxRegCuts ? clip_masked(T, B, mask, leaf) : clip_volume(T, B, leaf);
-        } else {
-          d3 t0, t1, t2;
-          cell_piece(M, S.cand[kc], m, t0, t1, t2);
-          d3 cc = mk3(S.cccx[kc], S.cccy[kc], S.cccz[kc]);
-          double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-          if (s6 == 0.0) continue;
-          TetCont TC = tet_container(cc, t0, t1, t2);
-          unsigned tmk;
-          v = !cut_mask(T, TC, tmk) ? 0.0
-              : (cut_count(tmk) <= kMaxRegCuts ? clip_masked(T, TC, tmk, leaf) : clip_volume(T, TC, leaf));
-          if (v == -1.0) {
-            atomicOr(&M.counters[CNT_ERR], ERR_STACK);
-            v = 0.0;
-          }
-          if (s6 < 0.0) v = -v;
+        if (keep && S.cbox[kc]) {
+          unsigned mask = 0;
+          keep = cut_mask(T, B, mask) ? 1 : 0;
+          if (keep) v = box_pair_volume(M, T, B, mask, leaf);
+        } else if (keep) {
+          v = general_pair_volume(M, S.cand[kc], mk3(S.cccx[kc], S.cccy[kc], S.cccz[kc]), T, leaf);
         }
-        if (v == -1.0) {
-          atomicOr(&M.counters[CNT_ERR], ERR_STACK);
-          v = 0.0;
-        }
-        acc += sT > 0.0 ? v : -v;
       }
-      qn = 0;
-      __syncthreads();
+      const int nq = min(kFluxLanes, total - q0);
+      for (int j = 0; j < nq; ++j) {
+        double vj = __shfl(v, j);
+        if (__shfl(keep, j)) acc += vj;
+      }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) M.VF[f] = acc;
     __syncthreads();
   }
 }
 
-__global__ void k_reset_advect(int* counters, int* item_fill) {
+__global__ void k_reset_advect(DevMesh M) {
   if (threadIdx.x == 0) {
-    counters[CNT_FACES] = 0;
-    counters[CNT_ITEMS] = 0;
-    counters[CNT_OVER] = 0;
-    counters[CNT_DEEP] = 0;
-    counters[CNT_UDEEP] = 0;
+    M.counters[CNT_FACES] = 0;
+    M.counters[CNT_ITEMS] = 0;
+    M.counters[CNT_OVER] = 0;
+    M.counters[CNT_DEEP] = 0;
+    M.counters[CNT_UDEEP] = 0;
   }
-  for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) item_fill[r] = 0;
+  for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) {
+    M.item_fill[r] = 0;
+    M.unit_fill[r] = 0;
+    M.item_okend[r] = INT_MAX;
+    M.unit_okend[r] = INT_MAX;
+  }
 }
 
 // ============================================================== update
 // Eq. (fnext) with face sums in ascending face order, then the clamp.
 __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __restrict__ Fout) {
   for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
+    if (!cell_live(M, c)) continue;
     double VdT = 0.0, VFT = 0.0;
     for (int i = M.cf_ptr[c]; i < M.cf_ptr[c + 1]; ++i) {
       int e = M.cf_idx[i];
@@ -1185,11 +1179,6 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
 }
 
 // ============================================================== refinement initialisation
-struct Shape {
-  int kind;
-  double a, b, c, d;
-};
-
 __device__ inline bool shape_inside(const Shape& s, d3 p) {
   if (s.kind == 0) {
     d3 q = p - mk3(s.a, s.b, s.c);
@@ -1198,7 +1187,11 @@ __device__ inline bool shape_inside(const Shape& s, d3 p) {
   return dot_x(mk3(s.a, s.b, s.c), p) + s.d >= 0.0;
 }
 
-__global__ void k_init_classify(DevMesh M, Shape sh, double* __restrict__ F) {
+__device__ inline Shape cell_shape(const DevMesh& M, int c, const Shape& sh) {
+  return M.prob_shape ? M.prob_shape[problem_of(M, M.cell_pid, c)] : sh;
+}
+
+__global__ void k_init_classify(DevMesh M, Shape sh0, double* __restrict__ F) {
   int n = M.nc;
   int stride = grid_stride();
   int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
@@ -1206,6 +1199,7 @@ __global__ void k_init_classify(DevMesh M, Shape sh, double* __restrict__ F) {
     int c = b + (threadIdx.x & 63);
     bool refine = false;
     if (c < n) {
+      const Shape sh = cell_shape(M, c, sh0);
       bool allin = true, allout = true;
       for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1]; ++i) {
         if (shape_inside(sh, vert(M, M.cv_idx[i]))) allout = false;
@@ -1261,11 +1255,12 @@ __device__ inline double cell_subbox_volume(const DevMesh& M, int c, d3 a, d3 b,
   return acc;
 }
 
-__global__ __launch_bounds__(64) void k_init_refine(DevMesh M, Shape sh, int ndiv, double* __restrict__ F) {
+__global__ __launch_bounds__(64) void k_init_refine(DevMesh M, Shape sh0, int ndiv, double* __restrict__ F) {
   int ncell = M.counters[CNT_REFINE];
   const int lane = threadIdx.x;
   for (int it = blockIdx.x; it < ncell; it += gridDim.x) {
     int c = M.list_cells[it];
+    const Shape sh = cell_shape(M, c, sh0);
     d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
     double nd = (double)ndiv;
     d3 hs = mk3((hi.x - lo.x) / nd, (hi.y - lo.y) / nd, (hi.z - lo.z) / nd);
@@ -1334,32 +1329,40 @@ hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
     if (prof) prof->after(k);     \
   } while (0)
 
-hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s, Prof* prof) {
+hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof) {
+  const int st = L.sweep_threads;
   k_zero<<<1, 64, 0, s>>>(M.counters + CNT_CELLS, 1);
-  TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, 256), 256, 0, s>>>(M, F)));
-  TIMED(K_FACE_TAG, (k_face_tag<<<blocks_for(M.nf, 256), 256, 0, s>>>(M)));
-  TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, F)));
-  TIMED(K_RECON, (k_recon<<<blocks_for(M.nc, 128, 2048), 128, 0, s>>>(M, F)));
+  TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
+  TIMED(K_FACE_TAG, (k_face_tag<<<blocks_for(M.nf, st), st, 0, s>>>(M)));
+  TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
+  TIMED(K_RECON, (k_recon<<<blocks_for(M.nc, L.recon_threads, 2048), L.recon_threads, 0, s>>>(M, F)));
   return hipGetLastError();
 }
 
-hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, hipStream_t s, Prof* prof) {
-  k_reset_advect<<<1, 256, 0, s>>>(M.counters, M.item_fill);
-  TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, 256), 256, 0, s>>>(M, uf, dt)));
-  TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, 16384), kFluxLanes, 0, s>>>(M, uv, dt)));
-  TIMED(K_FLUX, (k_flux_items_box<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, double dt, const double* Fin,
+                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof) {
+  DevMesh M = M0;
+  if (L.staged_faces > 0 && L.staged_faces < M.poly_cap) M.poly_cap = L.staged_faces;
+  if (L.staged_pairs > 0 && L.staged_pairs < M.item_cap)
+    M.item_cap = max(kItemRegions, L.staged_pairs - L.staged_pairs % kItemRegions);
+  const int st = L.sweep_threads;
+  const int pair_grid = kItemRegions * L.pair_blocks_per_region;
+  k_reset_advect<<<1, 256, 0, s>>>(M);
+  TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
+  TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
   if (!M.all_box) {
-    k_zero<<<1, 256, 0, s>>>(M.unit_fill, kItemRegions);
-    TIMED(K_FLUX_GEN, (k_flux_gen_filter<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
-    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<false><<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+    if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
+    else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));
+    else TIMED(K_FLUX_GEN, (k_flux_gen_filter<32><<<pair_grid, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<false><<<pair_grid, 256, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_UDEEP, (k_flux_gen_units_deep<<<1024, 256, 0, s>>>(M)));
-    TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<kItemRegions * kItemBlocksPerRegion, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }
   TIMED(K_FLUX_DEEP, (k_flux_deep<<<blocks_for(M.item_cap, 64, 1024), 64, 0, s>>>(M)));
   TIMED(K_FLUX_SUM, (k_flux_sum<<<blocks_for(M.poly_cap, 256, 1024), 256, 0, s>>>(M)));
   TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 2048), kFluxLanes, 0, s>>>(M, uv, dt)));
-  TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, Fin, Fout)));
+  TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, st), st, 0, s>>>(M, Fin, Fout)));
   return hipGetLastError();
 }
 

@@ -12,10 +12,26 @@ struct Prof {
   virtual void before(int k) = 0;
   virtual void after(int k) = 0;
 };
+// Launch shapes (none changes any result): block size of the vertex / face /
+// cell sweeps, block size of the reconstruction, grid of the staging kernel
+// (one wavefront per face), blocks per pair-buffer region of the pair and unit
+// kernels, lanes per pair of the general-cell filter, and the most faces and
+// (face, cell, flux tet) pairs staged per step (0: as many as the workspace
+// holds; what does not fit goes to the overflow and deferred kernels, which
+// give the same values).
+struct LaunchCfg {
+  int sweep_threads = 256;
+  int recon_threads = 128;
+  int prep_blocks = 16384;
+  int pair_blocks_per_region = 16;
+  int filter_lanes = 32;
+  int staged_faces = 0;
+  int staged_pairs = 0;
+};
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
-hipError_t launch_reconstruct(const DevMesh& M, double* F, hipStream_t s, Prof* prof = nullptr);
+hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, hipStream_t s, Prof* prof = nullptr);
+                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
 hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s);
 }  // namespace gvof

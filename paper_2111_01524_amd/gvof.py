@@ -34,6 +34,15 @@ class gvof_shape(C.Structure):
     _fields_ = [("kind", C.c_int32), ("p", C.c_double * 4)]
 
 
+class gvof_launch_config(C.Structure):
+    _fields_ = [("sweep_threads", C.c_int32), ("recon_threads", C.c_int32), ("prep_blocks", C.c_int32),
+                ("pair_blocks_per_region", C.c_int32), ("filter_lanes", C.c_int32), ("staged_faces", C.c_int32),
+                ("staged_pairs", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = C.c_void_p
 
@@ -73,10 +82,21 @@ def lib() -> C.CDLL:
         L.gvof_profile_read.argtypes = [_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.gvof_kernel_name.argtypes = [C.c_int32]
         L.gvof_kernel_name.restype = C.c_char_p
+        L.gvof_batch_create.argtypes = [C.POINTER(_vp), C.c_int32, C.POINTER(_vp)]
+        L.gvof_batch_offsets.argtypes = [_vp, C.POINTER(C.c_int32), _vp, _vp, _vp]
+        L.gvof_batch_init_fraction.argtypes = [_vp, C.POINTER(gvof_shape), C.c_int32, _vp]
+        L.gvof_batch_step.argtypes = [_vp] * 6
+        L.gvof_graph_capture.argtypes = [_vp] * 6
+        L.gvof_graph_launch.argtypes = [_vp]
+        L.gvof_get_launch_config.argtypes = [_vp, C.POINTER(gvof_launch_config)]
+        L.gvof_set_launch_config.argtypes = [_vp, C.POINTER(gvof_launch_config)]
+        L.gvof_autotune.argtypes = [_vp] * 7 + [C.c_int32, C.POINTER(gvof_launch_config), C.POINTER(C.c_double)]
         for name in ("gvof_mesh_create", "gvof_mesh_workspace_bytes", "gvof_mesh_bind", "gvof_set_stream",
                      "gvof_mesh_sizes", "gvof_get_geometry", "gvof_init_fraction", "gvof_reconstruct",
                      "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status",
-                     "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read"):
+                     "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_batch_create",
+                     "gvof_batch_offsets", "gvof_batch_init_fraction", "gvof_batch_step", "gvof_graph_capture",
+                     "gvof_graph_launch", "gvof_get_launch_config", "gvof_set_launch_config", "gvof_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -87,7 +107,10 @@ def exported_symbols():
     return ["gvof_params_default", "gvof_mesh_create", "gvof_mesh_workspace_bytes", "gvof_mesh_bind",
             "gvof_set_stream", "gvof_mesh_destroy", "gvof_mesh_sizes", "gvof_get_geometry", "gvof_init_fraction",
             "gvof_reconstruct", "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status",
-            "gvof_last_error", "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_kernel_name"]
+            "gvof_last_error", "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_kernel_name",
+            "gvof_batch_create", "gvof_batch_offsets", "gvof_batch_init_fraction", "gvof_batch_step",
+            "gvof_graph_capture", "gvof_graph_launch", "gvof_get_launch_config", "gvof_set_launch_config",
+            "gvof_autotune"]
 
 
 def _check(code, handle=None):
@@ -219,6 +242,61 @@ def gvof_kernel_name(k: int) -> str:
     return lib().gvof_kernel_name(k).decode()
 
 
+def gvof_batch_create(parts):
+    arr = (_vp * len(parts))(*[p.value if isinstance(p, _vp) else p for p in parts])
+    h = _vp()
+    _check(lib().gvof_batch_create(C.byref(h), len(parts), arr), None)
+    return h
+
+
+def gvof_batch_offsets(h):
+    n = C.c_int32()
+    _check(lib().gvof_batch_offsets(h, C.byref(n), None, None, None), h)
+    vo, fo, co = (np.zeros(n.value + 1, np.int32) for _ in range(3))
+    _check(lib().gvof_batch_offsets(h, C.byref(n), vo.ctypes.data, fo.ctypes.data, co.ctypes.data), h)
+    return vo, fo, co
+
+
+def gvof_batch_init_fraction(h, shapes, n_div: int, F_out):
+    """shapes: list of (kind, (p0, p1, p2, p3)), one per problem."""
+    arr = (gvof_shape * len(shapes))()
+    for i, (kind, prm) in enumerate(shapes):
+        arr[i].kind = kind
+        for j in range(4):
+            arr[i].p[j] = float(prm[j])
+    _check(lib().gvof_batch_init_fraction(h, arr, int(n_div), _ptr(F_out)), h)
+
+
+def gvof_batch_step(h, u_face, u_vert, dt, active, F):
+    _check(lib().gvof_batch_step(h, _ptr(u_face), _ptr(u_vert), _ptr(dt), _ptr(active), _ptr(F)), h)
+
+
+def gvof_graph_capture(h, u_face, u_vert, dt, active, F):
+    _check(lib().gvof_graph_capture(h, _ptr(u_face), _ptr(u_vert), _ptr(dt), _ptr(active), _ptr(F)), h)
+
+
+def gvof_graph_launch(h):
+    _check(lib().gvof_graph_launch(h), h)
+
+
+def gvof_get_launch_config(h) -> gvof_launch_config:
+    c = gvof_launch_config()
+    _check(lib().gvof_get_launch_config(h, C.byref(c)), h)
+    return c
+
+
+def gvof_set_launch_config(h, cfg: gvof_launch_config):
+    _check(lib().gvof_set_launch_config(h, C.byref(cfg)), h)
+
+
+def gvof_autotune(h, u_face, u_vert, dt, active, F, F_save, reps: int):
+    c = gvof_launch_config()
+    ms = C.c_double()
+    _check(lib().gvof_autotune(h, _ptr(u_face), _ptr(u_vert), _ptr(dt), _ptr(active), _ptr(F), _ptr(F_save),
+                               int(reps), C.byref(c), C.byref(ms)), h)
+    return c, ms.value
+
+
 def gvof_last_error(h=None) -> str:
     m = lib().gvof_last_error(h)
     return m.decode() if m else ""
@@ -228,14 +306,16 @@ def gvof_last_error(h=None) -> str:
 class GvofMesh:
     """A mesh handle bound to a torch-allocated device workspace."""
 
-    def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None):
+    def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.mesh = mesh
-        self.nv, self.nf, self.nc = mesh.nv, mesh.nf, mesh.nc
-        self.h = gvof_mesh_create(mesh.vx, mesh.vy, mesh.vz, mesh.fv_ptr, mesh.fv_idx, mesh.owner, mesh.neigh,
-                                  mesh.nc, params)
+        if handle is None:
+            handle = gvof_mesh_create(mesh.vx, mesh.vy, mesh.vz, mesh.fv_ptr, mesh.fv_idx, mesh.owner, mesh.neigh,
+                                      mesh.nc, params)
+        self.h = handle
+        self.nv, self.nf, self.nc, _ = gvof_mesh_sizes(self.h)
         self.ws_bytes = gvof_mesh_workspace_bytes(self.h)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
@@ -300,3 +380,45 @@ class GvofMesh:
 
     def status(self):
         return gvof_status(self.h)
+
+
+class GvofBatch(GvofMesh):
+    """Independent problems advanced together: the handle of their disjoint
+    union (gvof_batch_create), bound to one torch-allocated workspace.
+    `offsets` gives each problem's vertex / face / cell ranges."""
+
+    def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None):
+        parts = []
+        try:
+            for m in meshes:
+                parts.append(gvof_mesh_create(m.vx, m.vy, m.vz, m.fv_ptr, m.fv_idx, m.owner, m.neigh, m.nc, params))
+            h = gvof_batch_create(parts)
+        finally:
+            for p in parts:
+                gvof_mesh_destroy(p)
+        super().__init__(None, device, params, stream, handle=h)
+        self.nprob = len(meshes)
+        self.vert_off, self.face_off, self.cell_off = gvof_batch_offsets(self.h)
+
+    def init_fraction_each(self, shapes, n_div: int = 10, F_out=None):
+        """shapes: one ("sphere" | "plane", params) per problem."""
+        F = F_out if F_out is not None else self.dzeros(self.nc)
+        kinds = {"sphere": GVOF_SHAPE_SPHERE, "plane": GVOF_SHAPE_PLANE}
+        gvof_batch_init_fraction(self.h, [(kinds[k], p) for k, p in shapes], n_div, F)
+        return F
+
+    def step(self, u_face, u_vert, dt, active, F):
+        gvof_batch_step(self.h, u_face, u_vert, dt, active, F)
+
+    def capture(self, u_face, u_vert, dt, active, F):
+        gvof_graph_capture(self.h, u_face, u_vert, dt, active, F)
+
+    def replay(self):
+        gvof_graph_launch(self.h)
+
+    def autotune(self, u_face, u_vert, dt, active, F, reps: int = 3):
+        scratch = self.torch.empty_like(F)
+        return gvof_autotune(self.h, u_face, u_vert, dt, active, F, scratch, reps)
+
+    def cells(self, q):
+        return slice(int(self.cell_off[q]), int(self.cell_off[q + 1]))

@@ -357,3 +357,30 @@ def served_job_specs(duration_s: float = 60.0, rate: float = 20.0, seed: int = 3
             steps=steps[0] + min(int(U[p, 8] * (steps[1] - steps[0] + 1)), steps[1] - steps[0]),
             jitter_seed=5000 + p))
     return jobs
+
+
+def problem_inputs(spec: dict, cfl: float = 0.5, steps: int | None = None) -> dict:
+    """Inputs of one batched or served problem: its grid, the Enright field
+    u0 at faces and vertices, the body, and the effective time step of every
+    step, dt_s * cos(pi t_{s+1/2} / T) (the field's time factor folded into dt).
+    The problem runs to its own period T, or for `steps` steps (served jobs,
+    spec["steps"]) of the CFL time step."""
+    n = int(spec["side"])
+    mesh = cartesian_mesh(n) if spec["kind"] == "cartesian" else jittered_mesh(n, seed=int(spec["jitter_seed"]))
+    uf, uv = velocity_enright(mesh)
+    dt = cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
+    T = float(spec["period"])
+    nsteps = steps if steps is not None else spec.get("steps")
+    sched = step_schedule(T, dt) if nsteps is None else [dt] * int(nsteps)
+    t, eff = 0.0, []
+    for d in sched:
+        eff.append(d * enright_time_factor(t + 0.5 * d, T))
+        t += d
+    c = spec["center"]
+    return dict(mesh=mesh, uf=uf, uv=uv, dt=dt, dt_eff=np.array(eff), nsteps=len(eff),
+                shape=("sphere", [float(c[0]), float(c[1]), float(c[2]), float(spec["radius"])]))
+
+
+def concat_soa(arrays):
+    """Batch layout of per-problem SoA arrays (3 x n_q each): 3 x sum n_q, problems in order."""
+    return np.ascontiguousarray(np.concatenate(arrays, axis=1))

@@ -84,3 +84,85 @@ def test_calls_before_bind_fail_cleanly():
         assert code == gvof.GVOF_E_ARG
     finally:
         gvof.gvof_mesh_destroy(h)
+
+
+def _concat(meshes):
+    """Disjoint union of meshes in the batch numbering (test-side reference)."""
+    vo = np.cumsum([0] + [m.nv for m in meshes])
+    co = np.cumsum([0] + [m.nc for m in meshes])
+    fvo = np.cumsum([0] + [m.fv_idx.size for m in meshes])
+    vx = np.concatenate([m.vx for m in meshes]); vy = np.concatenate([m.vy for m in meshes])
+    vz = np.concatenate([m.vz for m in meshes])
+    fv_ptr = np.concatenate([[0]] + [m.fv_ptr[1:] + fvo[q] for q, m in enumerate(meshes)])
+    fv_idx = np.concatenate([m.fv_idx + vo[q] for q, m in enumerate(meshes)])
+    owner = np.concatenate([m.owner + co[q] for q, m in enumerate(meshes)])
+    neigh = np.concatenate([np.where(m.neigh >= 0, m.neigh + co[q], -1) for q, m in enumerate(meshes)])
+    return vx, vy, vz, fv_ptr, fv_idx, owner, neigh, int(co[-1])
+
+
+def test_batch_create_is_the_disjoint_union():
+    ms = [inputs.cartesian_mesh(3), inputs.jittered_mesh(2, seed=1), inputs.cartesian_mesh(2)]
+    parts = [gvof.gvof_mesh_create(*m.arrays(), m.nc) for m in ms]
+    try:
+        h = gvof.gvof_batch_create(parts)
+    finally:
+        for p in parts:
+            gvof.gvof_mesh_destroy(p)
+    try:
+        vo, fo, co = gvof.gvof_batch_offsets(h)
+        assert list(vo) == list(np.cumsum([0] + [m.nv for m in ms]))
+        assert list(fo) == list(np.cumsum([0] + [m.nf for m in ms]))
+        assert list(co) == list(np.cumsum([0] + [m.nc for m in ms]))
+        u = gvof.gvof_mesh_create(*_concat(ms))
+        try:
+            assert gvof.gvof_mesh_sizes(h) == gvof.gvof_mesh_sizes(u)
+            # the batch carries three problem-id arrays and a shape table on top of the union's workspace
+            extra = gvof.gvof_mesh_workspace_bytes(h) - gvof.gvof_mesh_workspace_bytes(u)
+            assert 4 * (vo[-1] + fo[-1] + co[-1]) <= extra <= 4 * (vo[-1] + fo[-1] + co[-1]) + 8 * 256
+        finally:
+            gvof.gvof_mesh_destroy(u)
+        with pytest.raises(gvof.GvofError):  # a batch is not a part
+            gvof.gvof_batch_create([h])
+    finally:
+        gvof.gvof_mesh_destroy(h)
+
+
+def test_batch_create_rejects_mixed_parameters():
+    m = inputs.cartesian_mesh(2)
+    p2 = gvof.gvof_params_default()
+    p2.beta = 2.0
+    a = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+    b = gvof.gvof_mesh_create(*m.arrays(), m.nc, p2)
+    try:
+        with pytest.raises(gvof.GvofError):
+            gvof.gvof_batch_create([a, b])
+        with pytest.raises(gvof.GvofError):
+            gvof.gvof_batch_create([])
+    finally:
+        gvof.gvof_mesh_destroy(a)
+        gvof.gvof_mesh_destroy(b)
+
+
+def test_launch_config_validation_without_gpu():
+    m = inputs.cartesian_mesh(2)
+    h = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+    try:
+        c = gvof.gvof_get_launch_config(h)
+        assert c.as_dict() == dict(sweep_threads=256, recon_threads=128, prep_blocks=16384,
+                                   pair_blocks_per_region=16, filter_lanes=32, staged_faces=0,
+                                   staged_pairs=0)
+        for bad in (dict(sweep_threads=96), dict(recon_threads=256), dict(prep_blocks=0),
+                    dict(pair_blocks_per_region=300), dict(filter_lanes=8), dict(staged_faces=-1),
+                    dict(staged_pairs=-1)):
+            d = c.as_dict()
+            d.update(bad)
+            with pytest.raises(gvof.GvofError):
+                gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
+        d = c.as_dict()
+        d.update(sweep_threads=512, filter_lanes=64)
+        gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
+        assert gvof.gvof_get_launch_config(h).as_dict() == d
+        with pytest.raises(gvof.GvofError):  # not bound
+            gvof.gvof_graph_launch(h)
+    finally:
+        gvof.gvof_mesh_destroy(h)
