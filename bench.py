@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--single-steps", type=int, default=2, help="timed steps per problem of the one-by-one baseline")
+    ap.add_argument("--served", type=int, default=0,
+                    help="also serve this many jobs of the served workload (Poisson arrivals at 20/s)")
+    ap.add_argument("--served-budget-gb", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -69,6 +72,13 @@ def main():
         batch_problems = batch_inputs.generate(_inputs.batch_problem_specs(args.batch))
         batch_gen_s = time.perf_counter() - t0
         print(f"# batch inputs: {args.batch} problems in {batch_gen_s:.1f} s", file=sys.stderr, flush=True)
+    served = None
+    if args.served > 0:
+        from paper_2111_01524_amd import batch_inputs, inputs as _inputs
+        t0 = time.perf_counter()
+        sspecs = _inputs.served_job_specs()[: args.served]
+        served = (sspecs, batch_inputs.generate(sspecs))
+        print(f"# served inputs: {args.served} jobs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     import torch
 
     from paper_2111_01524_amd import gvof, inputs
@@ -173,9 +183,34 @@ def main():
         del g, bufs, ufd, uvd
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args, batch_problems, dev)
+    if served is not None:
+        torch.cuda.empty_cache()
+        out["served"] = served_leg(args, served, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def served_leg(args, served, dev):
+    """The served workload: the first jobs of the seeded Poisson arrival
+    stream (20 jobs/s, sides 32..128, both grid kinds, 50..500 steps), each
+    arriving at its own time with its inputs in host memory; admitted under
+    the HBM budget into cohorts that run concurrently; latency from arrival to
+    the job's fractions in host memory."""
+    from paper_2111_01524_amd import serve
+
+    specs, problems = served
+    jobs = serve.jobs_from_specs(specs, problems)
+    ex = serve.GpuExecutor(dev)
+    srv = serve.Server(ex, budget_bytes=int(args.served_budget_gb * 1e9), max_cohorts=4, depth=4)
+    rep = srv.run(jobs)
+    window = max(s["arrival"] for s in specs)
+    S = rep.summary(arrival_window=window)
+    S["unit"] = "face·steps/s"
+    S["workload"] = (f"first {len(specs)} jobs of the Poisson stream (20/s, seed 3), arrivals over {window:.2f} s, "
+                     f"sides {sorted(set(s['side'] for s in specs))}, budget {args.served_budget_gb:g} GB")
+    S["latency_includes_queueing"] = True
+    return S
 
 
 def batched_leg(args, problems, dev):

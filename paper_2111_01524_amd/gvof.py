@@ -387,10 +387,12 @@ class GvofBatch(GvofMesh):
     union (gvof_batch_create), bound to one torch-allocated workspace.
     `offsets` gives each problem's vertex / face / cell ranges."""
 
-    def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None):
-        parts = []
+    def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None, parts=None):
+        """parts: optional handles already made by gvof_mesh_create for these
+        meshes (taken over and destroyed here)."""
+        parts = list(parts) if parts is not None else []
         try:
-            for m in meshes:
+            for m in meshes[len(parts):]:
                 parts.append(gvof_mesh_create(m.vx, m.vy, m.vz, m.fv_ptr, m.fv_idx, m.owner, m.neigh, m.nc, params))
             h = gvof_batch_create(parts)
         finally:

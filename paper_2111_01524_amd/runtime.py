@@ -17,7 +17,7 @@ from . import gvof, inputs
 
 class BatchRun:
     def __init__(self, problems, device, stream, n_div: int = 10, autotune: bool = True, graph: bool = True,
-                 tune_reps: int = 2, launch_config: dict | None = None):
+                 tune_reps: int = 2, launch_config: dict | None = None, parts=None):
         import torch
         self.torch = torch
         self.stream = stream
@@ -26,7 +26,7 @@ class BatchRun:
         self.nsteps = np.array([p["nsteps"] for p in problems], np.int64)
         self.max_steps = int(self.nsteps.max())
         with torch.cuda.stream(stream):
-            self.B = gvof.GvofBatch([p["mesh"] for p in problems], device, stream=stream)
+            self.B = gvof.GvofBatch([p["mesh"] for p in problems], device, stream=stream, parts=parts)
             self.nf_q = np.diff(self.B.face_off).astype(np.int64)
             self.nc_q = np.diff(self.B.cell_off).astype(np.int64)
             self.uf = torch.from_numpy(inputs.concat_soa([p["uf"] for p in problems])).to(device)
