@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--served", type=int, default=0,
                     help="also serve this many jobs of the served workload (Poisson arrivals at 20/s)")
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB, 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -64,6 +66,9 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     batch_problems = None
     if args.batch > 0:
         # host-side inputs first, in spawned workers, before anything touches the GPU
@@ -189,6 +194,19 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def copy_probe(mib: int):
+    """A plain copy of mib MiB (FP64), five launches: reads and writes mib MiB each."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 5}), flush=True)
 
 
 def served_leg(args, served, dev):

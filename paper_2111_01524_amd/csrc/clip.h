@@ -12,27 +12,46 @@
 
 namespace gvof {
 
+// A plane as the affine function n.x + d (kept side >= 0).
+struct Plane {
+  d3 n;
+  double d;
+  __host__ __device__ inline double dist(d3 p) const { return dotf(n, p) + d; }
+};
+
+// Plane l of a container is picked with 0/1 weights, not with a chain of
+// selects (which the compiler turns into a dynamically indexed private array,
+// i.e. scratch memory).  With one weight 1 and the others 0 every sum below
+// is exact, so the distances are those of the plain formulas bit for bit:
+// for the box, x_a - lo_a and hi_a - x_a.
 struct BoxCont {
   d3 lo, hi;
   static constexpr int np = 6;
   // plane l: axis l/2, l even -> x_a - lo_a >= 0, l odd -> hi_a - x_a >= 0
-  __host__ __device__ inline double dist(int l, d3 p) const {
-    int a = l >> 1;
-    double v = a == 0 ? p.x : (a == 1 ? p.y : p.z);
-    double b = (l & 1) ? (a == 0 ? hi.x : (a == 1 ? hi.y : hi.z)) : (a == 0 ? lo.x : (a == 1 ? lo.y : lo.z));
-    return (l & 1) ? b - v : v - b;
+  __host__ __device__ inline Plane plane(int l) const {
+    const int a = l >> 1;
+    const bool up = (l & 1) != 0;
+    const double ex = a == 0 ? 1.0 : 0.0, ey = a == 1 ? 1.0 : 0.0, ez = a == 2 ? 1.0 : 0.0;
+    const double sg = up ? -1.0 : 1.0;
+    const double blo = fma(ez, lo.z, fma(ey, lo.y, ex * lo.x)), bhi = fma(ez, hi.z, fma(ey, hi.y, ex * hi.x));
+    return Plane{mk3(sg * ex, sg * ey, sg * ez), up ? bhi : -blo};
   }
+  __host__ __device__ inline double dist(int l, d3 p) const { return plane(l).dist(p); }
 };
 
 struct TetCont {
   d3 n0, n1, n2, n3;
   double d0, d1, d2, d3_;
   static constexpr int np = 4;
-  __host__ __device__ inline double dist(int l, d3 p) const {
-    d3 n = l == 0 ? n0 : (l == 1 ? n1 : (l == 2 ? n2 : n3));
-    double d = l == 0 ? d0 : (l == 1 ? d1 : (l == 2 ? d2 : d3_));
-    return dotf(n, p) + d;
+  __host__ __device__ inline Plane plane(int l) const {
+    const double w0 = l == 0 ? 1.0 : 0.0, w1 = l == 1 ? 1.0 : 0.0, w2 = l == 2 ? 1.0 : 0.0, w3 = l == 3 ? 1.0 : 0.0;
+    d3 n = mk3(fma(w3, n3.x, fma(w2, n2.x, fma(w1, n1.x, w0 * n0.x))),
+               fma(w3, n3.y, fma(w2, n2.y, fma(w1, n1.y, w0 * n0.y))),
+               fma(w3, n3.z, fma(w2, n2.z, fma(w1, n1.z, w0 * n0.z))));
+    double d = fma(w3, d3_, fma(w2, d2, fma(w1, d1, w0 * d0)));
+    return Plane{n, d};
   }
+  __host__ __device__ inline double dist(int l, d3 p) const { return plane(l).dist(p); }
 };
 
 // Inward half-spaces of the tetrahedron (a, b, c, d) as a point set.
@@ -65,14 +84,27 @@ __host__ __device__ inline d3 cut_pt(d3 pin, double sin_, d3 pout, double sout) 
   return axpy(t, pout - pin, pin);
 }
 
+// v unchanged, as a value the compiler cannot trace back to a load: a select
+// between two such values stays a register select (a select between two
+// loads is otherwise rewritten as a load from a selected address, which keeps
+// the operands in scratch memory).
+__host__ __device__ inline double opaque(double v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#endif
+  return v;
+}
+
+// Orders (sa, pa), (sb, pb) so that sa >= sb (a swap: the values are unchanged).
 __host__ __device__ inline void cs_pt(double& sa, d3& pa, double& sb, d3& pb) {
-  bool sw = sb > sa;
-  double ts = sw ? sb : sa;
-  sb = sw ? sa : sb;
-  sa = ts;
-  d3 tp = sw ? pb : pa;
-  pb = sw ? pa : pb;
-  pa = tp;
+  const double s0 = opaque(sa), s1 = opaque(sb);
+  const bool sw = s1 > s0;
+  sa = sw ? s1 : s0;
+  sb = sw ? s0 : s1;
+  const double ax = opaque(pa.x), ay = opaque(pa.y), az = opaque(pa.z);
+  const double bx = opaque(pb.x), by = opaque(pb.y), bz = opaque(pb.z);
+  pa = mk3(sw ? bx : ax, sw ? by : ay, sw ? bz : az);
+  pb = mk3(sw ? ax : bx, sw ? ay : by, sw ? az : bz);
 }
 
 struct Leaf {
@@ -189,55 +221,86 @@ struct Split {
     }
   }
   __host__ __device__ inline int count() const { return kind == 0 ? 0 : (kind <= 2 ? 1 : 3); }
-  __host__ __device__ inline Tet child(int i) const {
+  // children by constant index (a runtime index makes the compiler keep the
+  // three children in an indexed private array)
+  __host__ __device__ inline Tet child0() const {
     if (kind == 1) return Tet{a, b, c, d};
     if (kind == 2) return Tet{a, cut_pt(a, sa, b, sb), cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd)};
-    if (kind == 3) {
-      d3 pa = cut_pt(a, sa, d, sd), pb = cut_pt(b, sb, d, sd);
-      if (i == 0) return Tet{a, b, c, pa};
-      if (i == 1) return Tet{b, c, pa, pb};
-      return Tet{c, pa, pb, cut_pt(c, sc, d, sd)};
-    }
-    d3 P1 = cut_pt(a, sa, c, sc), P4 = cut_pt(b, sb, d, sd);
-    if (i == 0) return Tet{a, P1, cut_pt(a, sa, d, sd), b};
-    if (i == 1) return Tet{P1, cut_pt(a, sa, d, sd), b, P4};
-    return Tet{P1, b, P4, cut_pt(b, sb, c, sc)};
+    if (kind == 3) return Tet{a, b, c, cut_pt(a, sa, d, sd)};
+    return Tet{a, cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd), b};
   }
+  __host__ __device__ inline Tet child1() const {
+    if (kind == 3) return Tet{b, c, cut_pt(a, sa, d, sd), cut_pt(b, sb, d, sd)};
+    return Tet{cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd), b, cut_pt(b, sb, d, sd)};
+  }
+  __host__ __device__ inline Tet child2() const {
+    if (kind == 3) return Tet{c, cut_pt(a, sa, d, sd), cut_pt(b, sb, d, sd), cut_pt(c, sc, d, sd)};
+    return Tet{cut_pt(a, sa, c, sc), b, cut_pt(b, sb, d, sd), cut_pt(b, sb, c, sc)};
+  }
+  __host__ __device__ inline Tet child(int i) const { return i == 0 ? child0() : (i == 1 ? child1() : child2()); }
 };
 
-// Clip by one or two planes given by index (planes known to cut the original
-// tetrahedron): registers only.
-template <class Cont>
-__host__ __device__ inline double clip1(const Tet& t, const Cont& C, int l, const Leaf& leaf) {
-  Split sp(t, C.dist(l, t.p0), C.dist(l, t.p1), C.dist(l, t.p2), C.dist(l, t.p3));
-  int n = sp.count();
+// Clip by one to four planes known to cut the original tetrahedron, in
+// registers: the children of each split are visited in order 0, 1, 2 and
+// summed in that order.
+__host__ __device__ inline Split split_by(const Tet& t, const Plane& P) {
+  return Split(t, P.dist(t.p0), P.dist(t.p1), P.dist(t.p2), P.dist(t.p3));
+}
+__host__ __device__ inline double clip1(const Tet& t, const Plane& P, const Leaf& leaf) {
+  Split sp = split_by(t, P);
+  const int n = sp.count();
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += leaf(sp.child(i));
+  if (n > 0) acc += leaf(sp.child0());
+  if (n > 1) acc += leaf(sp.child1());
+  if (n > 2) acc += leaf(sp.child2());
   return acc;
 }
-template <class Cont>
-__host__ __device__ inline double clip2(const Tet& t, const Cont& C, int l1, int l2, const Leaf& leaf) {
-  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
-  int n = sp.count();
+__host__ __device__ inline double clip2(const Tet& t, const Plane& P1, const Plane& P2, const Leaf& leaf) {
+  Split sp = split_by(t, P1);
+  const int n = sp.count();
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += clip1(sp.child(i), C, l2, leaf);
+  if (n > 0) acc += clip1(sp.child0(), P2, leaf);
+  if (n > 1) acc += clip1(sp.child1(), P2, leaf);
+  if (n > 2) acc += clip1(sp.child2(), P2, leaf);
   return acc;
 }
-template <class Cont>
-__host__ __device__ inline double clip3(const Tet& t, const Cont& C, int l1, int l2, int l3, const Leaf& leaf) {
-  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
-  int n = sp.count();
-  double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += clip2(sp.child(i), C, l2, l3, leaf);
-  return acc;
-}
-template <class Cont>
-__host__ __device__ inline double clip4(const Tet& t, const Cont& C, int l1, int l2, int l3, int l4,
+__host__ __device__ inline double clip3(const Tet& t, const Plane& P1, const Plane& P2, const Plane& P3,
                                          const Leaf& leaf) {
-  Split sp(t, C.dist(l1, t.p0), C.dist(l1, t.p1), C.dist(l1, t.p2), C.dist(l1, t.p3));
-  int n = sp.count();
+  Split sp = split_by(t, P1);
+  const int n = sp.count();
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += clip3(sp.child(i), C, l2, l3, l4, leaf);
+  if (n > 0) acc += clip2(sp.child0(), P2, P3, leaf);
+  if (n > 1) acc += clip2(sp.child1(), P2, P3, leaf);
+  if (n > 2) acc += clip2(sp.child2(), P2, P3, leaf);
+  return acc;
+}
+// Compact forms for the rarely run deferred kernels: each level loops over
+// the children instead of expanding them, which keeps those kernels small.
+// The values and the order of the sums are those of the expanded forms.
+__host__ __device__ __attribute__((always_inline)) inline double clip2c(const Tet& t, const Plane& P1,
+                                                                        const Plane& P2, const Leaf& leaf) {
+  Split sp = split_by(t, P1);
+  const int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip1(sp.child(i), P2, leaf);
+  return acc;
+}
+__host__ __device__ __attribute__((always_inline)) inline double clip3c(const Tet& t, const Plane& P1,
+                                                                        const Plane& P2, const Plane& P3,
+                                                                        const Leaf& leaf) {
+  Split sp = split_by(t, P1);
+  const int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip2c(sp.child(i), P2, P3, leaf);
+  return acc;
+}
+__host__ __device__ __attribute__((always_inline)) inline double clip4c(const Tet& t, const Plane& P1,
+                                                                        const Plane& P2, const Plane& P3,
+                                                                        const Plane& P4, const Leaf& leaf) {
+  Split sp = split_by(t, P1);
+  const int n = sp.count();
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += clip3c(sp.child(i), P2, P3, P4, leaf);
   return acc;
 }
 
@@ -266,18 +329,22 @@ __host__ __device__ inline int cut_count(unsigned cut) {
   return n;
 }
 template <class Cont>
-__host__ __device__ inline double clip_masked(const Tet& T, const Cont& C, unsigned cut, const Leaf& leaf) {
+__host__ __device__ __attribute__((always_inline)) inline double clip_masked(const Tet& T, const Cont& C, unsigned cut,
+                                                                             const Leaf& leaf) {
   if (cut == 0) return leaf(T);
   int l1 = __builtin_ctz(cut);
   unsigned rest = cut & (cut - 1u);
-  if (rest == 0) return clip1(T, C, l1, leaf);
-  return clip2(T, C, l1, (int)__builtin_ctz(rest), leaf);
+  if (rest == 0) return clip1(T, C.plane(l1), leaf);
+  return clip2(T, C.plane(l1), C.plane((int)__builtin_ctz(rest)), leaf);
 }
 
 // The same for a tetrahedron container: at most four cutting planes, all in
 // registers (MAXC limits the depth compiled in; deeper masks return -1).
-template <int MAXC = 4>
-__host__ __device__ inline double clip_masked_tet(const Tet& T, const TetCont& C, unsigned cut, const Leaf& leaf) {
+// COMPACT selects the looping forms (same values; small code for the rarely
+// run deferred kernels).
+template <int MAXC = 4, bool COMPACT = true>
+__host__ __device__ __attribute__((always_inline)) inline double clip_masked_tet(const Tet& T, const TetCont& C,
+                                                                                 unsigned cut, const Leaf& leaf) {
   int l[4] = {0, 0, 0, 0};
   int n = 0;
 #pragma unroll
@@ -291,10 +358,13 @@ __host__ __device__ inline double clip_masked_tet(const Tet& T, const TetCont& C
     }
   }
   if (n == 0) return leaf(T);
-  if (n == 1) return clip1(T, C, l[0], leaf);
-  if (n == 2) return clip2(T, C, l[0], l[1], leaf);
-  if (MAXC >= 3 && n == 3) return clip3(T, C, l[0], l[1], l[2], leaf);
-  if (MAXC >= 4) return clip4(T, C, l[0], l[1], l[2], l[3], leaf);
+  if (n == 1) return clip1(T, C.plane(l[0]), leaf);
+  if (n == 2)
+    return COMPACT ? clip2c(T, C.plane(l[0]), C.plane(l[1]), leaf) : clip2(T, C.plane(l[0]), C.plane(l[1]), leaf);
+  if (MAXC >= 3 && n == 3)
+    return COMPACT ? clip3c(T, C.plane(l[0]), C.plane(l[1]), C.plane(l[2]), leaf)
+                   : clip3(T, C.plane(l[0]), C.plane(l[1]), C.plane(l[2]), leaf);
+  if (MAXC >= 4) return clip4c(T, C.plane(l[0]), C.plane(l[1]), C.plane(l[2]), C.plane(l[3]), leaf);
   return -1.0;
 }
 

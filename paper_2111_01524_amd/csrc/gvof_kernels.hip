@@ -616,7 +616,7 @@ __device__ inline int flux_candidates(const DevMesh& M, FluxLds& S, int f, d3 pl
 // cell's surface tetrahedra.  With DEEP false, a piece cut by more than
 // kMaxRegCuts planes makes the call return false (the caller defers the pair).
 template <bool DEEP>
-__device__ inline bool tet_cell_pieces_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf,
+__device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf,
                                               double& out) {
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   double acc = 0.0;
@@ -974,7 +974,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
         M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;
         continue;
       }
-      v = clip_masked_tet<3>(T, TC, cm, leaf);
+      v = clip_masked_tet<3, false>(T, TC, cm, leaf);
     }
     M.unit_vol[u] = s6 > 0.0 ? v : -v;
   }
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
 // Signed volume of one (flux tet, box cell) pair with cut mask `mask`: the
 // value every kernel gives the pair (register clip up to kMaxRegCuts cutting
 // planes, the explicit-stack clip beyond; a flat flux tet gives 0).
-__device__ inline double box_pair_volume(const DevMesh& M, const Tet& T, const BoxCont& B, unsigned mask,
+__device__ __attribute__((always_inline)) inline double box_pair_volume(const DevMesh& M, const Tet& T, const BoxCont& B, unsigned mask,
                                          const Leaf& leaf) {
   double sT = tet6(T);
   if (sT == 0.0) return 0.0;
@@ -1040,7 +1040,7 @@ __device__ inline double box_pair_volume(const DevMesh& M, const Tet& T, const B
 // Signed volume of one (flux tet, general cell) pair: the cell's surface
 // tetrahedra in order, each clipped in registers (the same units and the same
 // order as the three-stage path).
-__device__ inline double general_pair_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf) {
+__device__ __attribute__((always_inline)) inline double general_pair_volume(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf) {
   double sT = tet6(T);
   if (sT == 0.0) return 0.0;
   double v;
