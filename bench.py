@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many problems (256 = the full batch)")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -100,6 +101,13 @@ def main():
     ufd = torch.from_numpy(uf).to(dev)
     uvd = torch.from_numpy(uv).to(dev)
     F0 = g.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
+    tuned = None
+    if not args.no_autotune:
+        # launch shapes measured on the first step of the trajectory (F0 is left as it is)
+        dt0 = torch.tensor([dteff[0]], dtype=torch.float64, device=dev)
+        act0 = torch.ones(1, dtype=torch.uint8, device=dev)
+        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dt0, act0, F0, torch.empty_like(F0), 3)
+        tuned = cfg.as_dict()
     torch.cuda.synchronize()
     state = {"s": 0}
 
@@ -165,6 +173,8 @@ def main():
             "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
         },
         "cells_per_s": mesh.nc * K / (ms_total / 1e3),
+        "launch_config": tuned if tuned is not None else gvof.gvof_get_launch_config(g.h).as_dict(),
+        "launch_config_autotuned": tuned is not None,
         "interfacial_faces_per_step": nfaces_work / K,
         "interfacial_cells_per_step": ncells_work / K,
         "wall_s": t_wall,

@@ -256,7 +256,7 @@ int gvof_graph_launch(gvof_mesh* m);
  *   recon_threads           block size of the reconstruction kernel (64 or 128)
  *   prep_blocks             grid of the flux-polyhedron staging kernel, one wavefront per face (1..2^20)
  *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256)
- *   filter_lanes            lanes per (face, cell, flux tetrahedron) pair in the general-cell filter (16, 32, 64)
+ *   filter_lanes            lanes per (face, cell, flux tetrahedron) pair in the general-cell filter (8, 16, 32, 64)
  *   staged_faces            most faces whose flux work is staged per step (0: as many as the workspace
  *                           holds); the others are computed whole by the overflow kernel, with the same
  *                           values.  Not tuned by gvof_autotune.

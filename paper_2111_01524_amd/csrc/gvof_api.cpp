@@ -61,6 +61,7 @@ struct gvof_mesh {
   std::vector<double> vx, vy, vz;
   std::vector<int> fv_ptr, fv_idx, owner, neigh;
   std::vector<int> cf_ptr, cf_idx, cv_ptr, cv_idx, vc_ptr, vc_idx, nb_ptr, nb_idx;
+  std::vector<short> cell_np;  // surface triangles per cell
   int max_nb = 0;
   // problem partition: problem q owns vertices [voff[q], voff[q+1]), faces
   // [foff[q], foff[q+1]) and cells [coff[q], coff[q+1])
@@ -279,6 +280,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.vc_idx = C.take<int>(m->vc_idx.size());
   d.nb_ptr = C.take<int>(nc + 1);
   d.nb_idx = C.take<int>(std::max<size_t>(m->nb_idx.size(), 1));
+  d.cell_np = C.take<short>(nc);
   double* S = C.take<double>(3 * nf);
   double* fc = C.take<double>(3 * nf);
   d.Sx = S;
@@ -399,6 +401,20 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, up(d.vc_idx, m->vc_idx.data(), m->vc_idx.size() * 4));
   HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
   if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
+  {
+    // surface triangles per cell: a triangle counts once, a polygon of k vertices k times (fanned)
+    m->cell_np.assign(m->nc, 0);
+    for (int c = 0; c < m->nc; ++c) {
+      int np = 0;
+      for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+        int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
+        int k = m->fv_ptr[f + 1] - m->fv_ptr[f];
+        np += k == 3 ? 1 : k;
+      }
+      m->cell_np[c] = (short)np;
+    }
+    HIPCHECK(m, up(d.cell_np, m->cell_np.data(), m->cell_np.size() * sizeof(short)));
+  }
   std::vector<int> pid[3];
   if (m->nprob > 1) {
     const std::vector<int>* offs[3] = {&m->voff, &m->foff, &m->coff};
@@ -805,8 +821,8 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
     return fail(m, GVOF_E_ARG, "prep_blocks=%d (1..2^20)", c->prep_blocks);
   if (c->pair_blocks_per_region < 1 || c->pair_blocks_per_region > 256)
     return fail(m, GVOF_E_ARG, "pair_blocks_per_region=%d (1..256)", c->pair_blocks_per_region);
-  if (c->filter_lanes != 16 && c->filter_lanes != 32 && c->filter_lanes != 64)
-    return fail(m, GVOF_E_ARG, "filter_lanes=%d (16, 32 or 64)", c->filter_lanes);
+  if (c->filter_lanes != 8 && c->filter_lanes != 16 && c->filter_lanes != 32 && c->filter_lanes != 64)
+    return fail(m, GVOF_E_ARG, "filter_lanes=%d (8, 16, 32 or 64)", c->filter_lanes);
   if (c->staged_faces < 0) return fail(m, GVOF_E_ARG, "staged_faces=%d (>= 0)", c->staged_faces);
   if (c->staged_pairs < 0) return fail(m, GVOF_E_ARG, "staged_pairs=%d (>= 0)", c->staged_pairs);
   m->cfg.sweep_threads = c->sweep_threads;
@@ -857,7 +873,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   // coordinate descent over the launch shapes, each with the others fixed
   const int prep[] = {4096, 8192, 16384, 32768};
   const int pbr[] = {4, 8, 16, 32, 64};
-  const int lanes[] = {16, 32, 64};
+  const int lanes[] = {8, 16, 32, 64};
   const int sweep[] = {128, 256, 512, 1024};
   const int recon[] = {64, 128};
   auto sweep_param = [&](int gvof::LaunchCfg::*field, const int* vals, int nvals) -> int {
@@ -877,7 +893,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   };
   if ((r = sweep_param(&gvof::LaunchCfg::prep_blocks, prep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::pair_blocks_per_region, pbr, 5))) return r;
-  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 3))) return r;
+  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::sweep_threads, sweep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::recon_threads, recon, 2))) return r;
   m->cfg = cur;

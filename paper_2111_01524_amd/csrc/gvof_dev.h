@@ -22,6 +22,7 @@ struct DevMesh {
   const int *cv_ptr, *cv_idx;  // cell -> distinct vertices ascending
   const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
   const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
+  const short* cell_np;        // surface triangles of each cell (triangles as they are, polygons fanned)
   // geometry (computed on the device at bind)
   double *Sx, *Sy, *Sz, *fcx, *fcy, *fcz;
   double *V, *ccx, *ccy, *ccz, *lox, *loy, *loz, *hix, *hiy, *hiz;

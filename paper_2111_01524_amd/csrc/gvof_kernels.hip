@@ -852,14 +852,10 @@ __device__ inline void cell_sigma(const DevMesh& M, int k, int p, bool tri_only,
   else cell_piece(M, k, p, t0, t1, t2);
 }
 
-__device__ inline int cell_piece_count(const DevMesh& M, int k) {
-  int np = 0;
-  for (int e = M.cf_ptr[k]; e < M.cf_ptr[k + 1]; ++e) np += face_triangle_count(M, M.cf_idx[e]);
-  return np;
-}
+__device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_np[k]; }
 
 // Pairs with a general (non-box) cell, stage 1: a group of LPP lanes per pair
-// (16, 32 or 64; the lane-to-pair mapping is a launch choice), lane j of the
+// (8, 16, 32 or 64; the lane-to-pair mapping is a launch choice), lane j of the
 // group testing the cell's surface tetrahedra j, j+LPP, ...: boxes overlap and
 // no plane of the tetrahedron leaves the flux tet entirely outside.  The
 // survivors (pair, surface tetrahedron, mask of cutting planes) are written in
@@ -867,6 +863,7 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) {
 // the result does not depend on LPP.
 template <int LPP>
 __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
+  static_assert(LPP == 8 || LPP == 16 || LPP == 32 || LPP == 64, "lanes per pair");
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
   const int fill = region_items(M, r, rsize);
@@ -1352,7 +1349,8 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
   TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
   if (!M.all_box) {
-    if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
+    if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
+    else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));
     else TIMED(K_FLUX_GEN, (k_flux_gen_filter<32><<<pair_grid, 256, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<false><<<pair_grid, 256, 0, s>>>(M)));

@@ -152,7 +152,7 @@ def test_launch_config_validation_without_gpu():
                                    pair_blocks_per_region=16, filter_lanes=32, staged_faces=0,
                                    staged_pairs=0)
         for bad in (dict(sweep_threads=96), dict(recon_threads=256), dict(prep_blocks=0),
-                    dict(pair_blocks_per_region=300), dict(filter_lanes=8), dict(staged_faces=-1),
+                    dict(pair_blocks_per_region=300), dict(filter_lanes=12), dict(staged_faces=-1),
                     dict(staged_pairs=-1)):
             d = c.as_dict()
             d.update(bad)

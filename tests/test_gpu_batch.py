@@ -154,7 +154,7 @@ def test_launch_shapes_do_not_change_results(gv):
                 dict(sweep_threads=1024, recon_threads=128, prep_blocks=100, pair_blocks_per_region=64,
                      filter_lanes=64, staged_faces=7, staged_pairs=0),
                 dict(sweep_threads=256, recon_threads=128, prep_blocks=16384, pair_blocks_per_region=16,
-                     filter_lanes=32, staged_faces=0, staged_pairs=256 * 20),
+                     filter_lanes=8, staged_faces=0, staged_pairs=256 * 20),
                 dict(sweep_threads=512, recon_threads=64, prep_blocks=4096, pair_blocks_per_region=8,
                      filter_lanes=16, staged_faces=0, staged_pairs=256 * 60)):
         gv.gvof_set_launch_config(B.h, gv.gvof_launch_config(**odd))
