@@ -36,6 +36,21 @@ FLOPS_PER_FLUX_FACE_TRUNCATION = 37578.0
 FLOPS_PER_RECON_CELL = 53202.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of k_flux_items_box on this workload (FETCH_SIZE and
+# WRITE_SIZE counters, scaled by the same counters on a plain copy kernel of
+# known size; profiles/hbm_traffic_cartesian64_enright.md), valid for the
+# kernel sources whose digest is recorded beside it.
+ITEMS_BOX_TRAFFIC_BYTES = 1.99976e7
+ITEMS_BOX_TRAFFIC_SOURCES = "cfde570666bd0193"
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gvof_kernels.hip", "clip.h", "gvof_dev.h"):
+        with open(os.path.join(ROOT, "paper_2111_01524_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -185,7 +200,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": ITEMS_BOX_TRAFFIC_BYTES if kernel_sources_digest() == ITEMS_BOX_TRAFFIC_SOURCES else None,
+            "traffic_unit": "bytes per launch (HBM, counters)",
             "avg_launch_ms": flux_ms_avg,
             "flops_per_unit": FLOPS_PER_FLUX_FACE_TRUNCATION,
             "unit_of_work": "face needing a flux polyhedron (truncation FLOPs)",
