@@ -304,6 +304,36 @@ __host__ __device__ __attribute__((always_inline)) inline double clip4c(const Te
   return acc;
 }
 
+// Up to four cutting planes of any container with the looping forms (-1
+// beyond): the deferred kernels' clip.
+template <class Cont>
+__host__ __device__ __attribute__((always_inline)) inline double clip_masked_compact(const Tet& T, const Cont& C,
+                                                                                     unsigned cut,
+                                                                                     const Leaf& leaf) {
+  Plane P[4] = {};
+  int n = 0;
+  unsigned rest = cut;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (rest) {
+      int l = __builtin_ctz(rest);
+      rest &= rest - 1u;
+      const Plane pl = C.plane(l);
+      P[0] = q == 0 ? pl : P[0];
+      P[1] = q == 1 ? pl : P[1];
+      P[2] = q == 2 ? pl : P[2];
+      P[3] = q == 3 ? pl : P[3];
+      ++n;
+    }
+  }
+  if (rest) return -1.0;
+  if (n == 0) return leaf(T);
+  if (n == 1) return clip1(T, P[0], leaf);
+  if (n == 2) return clip2c(T, P[0], P[1], leaf);
+  if (n == 3) return clip3c(T, P[0], P[1], P[2], leaf);
+  return clip4c(T, P[0], P[1], P[2], P[3], leaf);
+}
+
 // Cut mask of T against the container (bit l: plane l cuts T); returns false
 // when T lies entirely outside one plane.
 template <class Cont>

@@ -36,6 +36,33 @@ __device__ inline void wave_append(bool pred, int item, int* counter, int* list,
   }
 }
 
+// Block-aggregated append of `item` when `pred`: one atomic per block (a
+// counter shared by every wave of the grid is the bottleneck of a sweep
+// otherwise), slots in (wave, lane) order within the block.  Every thread of
+// the block must make the same number of calls: it holds block barriers.
+constexpr int kMaxBlockWaves = 16;
+__device__ inline void block_append(bool pred, int item, int* counter, int* list, unsigned long long* total) {
+  __shared__ int s_off[kMaxBlockWaves];
+  __shared__ int s_base;
+  const int lane = __lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long m = __ballot(pred);
+  if (lane == 0) s_off[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < nw; ++i) {
+      int c = s_off[i];
+      s_off[i] = t;
+      t += c;
+    }
+    s_base = t ? atomicAdd(counter, t) : 0;
+    if (total && t) atomicAdd(total, (unsigned long long)t);
+  }
+  __syncthreads();
+  if (pred) list[s_base + s_off[w] + __popcll(m & ((1ull << lane) - 1ull))] = item;
+  __syncthreads();  // s_off and s_base are reused by the next call
+}
+
 __global__ void k_zero(int* p, int n) {
   int i = grid_stride_start();
   if (i < n) p[i] = 0;
@@ -204,10 +231,9 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
   int n = M.nc;
   int stride = grid_stride();
-  // every lane of a wave runs the same number of iterations (wave_append needs all lanes)
-  int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-  for (int b = base0; b < n; b += stride) {
-    int c = b + (threadIdx.x & 63);
+  // every thread of a block runs the same number of iterations (block_append holds barriers)
+  for (int b = blockIdx.x * blockDim.x; b < n; b += stride) {
+    int c = b + threadIdx.x;
     bool inter = false;
     if (c < n && cell_live(M, c)) {
       double f = F[c];
@@ -223,31 +249,9 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
         M.pC[c] = 0.0;
       }
     }
-    wave_append(inter, c, &M.counters[CNT_CELLS], M.list_cells, &M.totals[0]);
+    block_append(inter, c, &M.counters[CNT_CELLS], M.list_cells, &M.totals[0]);
   }
 }
-
-// ============================================================== LSGIR + plane constant
-struct CellLevels {
-  // general cell: volume of {n.x >= s} as signed tetrahedra from the vertex mean
-  __device__ static double general(const DevMesh& M, int c, d3 n, d3 cen, double s) {
-    double lc = dotf(n, cen) - s;
-    double acc = 0.0;
-    int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
-    for (int i = 0; i < fn; ++i) {
-      int e = M.cf_idx[fb + i];
-      int nt = face_triangle_count(M, e);
-      for (int t = 0; t < nt; ++t) {
-        d3 t0, t1, t2;
-        face_triangle(M, e, t, t0, t1, t2);
-        double v6 = det3f(t0 - cen, t1 - cen, t2 - cen);
-        double fr = halfspace_fraction(lc, dotf(n, t0) - s, dotf(n, t1) - s, dotf(n, t2) - s);
-        acc = fma(v6, fr, acc);
-      }
-    }
-    return acc * (1.0 / 6.0);
-  }
-};
 
 __device__ inline void insert_sorted(double* a, int& n, double v) {
   int i = n++;
@@ -287,106 +291,15 @@ __device__ inline double cubic_root(double s0, double w, double y0, double y1, d
   return fma(u, w * (1.0 / 3.0), s0);
 }
 
-__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F) {
-  int ncell = M.counters[CNT_CELLS];
-  const double beta = M.beta;
-  const bool beta15 = beta == 1.5;
-  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
-    int c = M.list_cells[it];
-    d3 xc = cell_centre(M, c);
-    double Fc = F[c];
-    // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta
-    double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, r0 = 0, r1 = 0, r2 = 0;
-    for (int i = M.nb_ptr[c]; i < M.nb_ptr[c + 1]; ++i) {
-      int k = M.nb_idx[i];
-      d3 d = cell_centre(M, k) - xc;
-      double d2 = dotf(d, d);
-      double w2 = beta15 ? 1.0 / (d2 * sqrt(d2)) : pow(d2, -beta);
-      double df = (F[k] - Fc) * w2;
-      a00 = fma(w2 * d.x, d.x, a00);
-      a01 = fma(w2 * d.x, d.y, a01);
-      a02 = fma(w2 * d.x, d.z, a02);
-      a11 = fma(w2 * d.y, d.y, a11);
-      a12 = fma(w2 * d.y, d.z, a12);
-      a22 = fma(w2 * d.z, d.z, a22);
-      r0 = fma(df, d.x, r0);
-      r1 = fma(df, d.y, r1);
-      r2 = fma(df, d.z, r2);
-    }
-    // adjugate solve (A symmetric positive definite): g ~ adj(A) r
-    double c00 = fma(a11, a22, -a12 * a12), c01 = fma(a02, a12, -a01 * a22), c02 = fma(a01, a12, -a02 * a11);
-    double c11 = fma(a00, a22, -a02 * a02), c12 = fma(a01, a02, -a00 * a12), c22 = fma(a00, a11, -a01 * a01);
-    double det = fma(a00, c00, fma(a01, c01, a02 * c02));
-    d3 g = mk3(fma(c00, r0, fma(c01, r1, c02 * r2)), fma(c01, r0, fma(c11, r1, c12 * r2)),
-               fma(c02, r0, fma(c12, r1, c22 * r2)));
-    if (det < 0.0) g = mk3(-g.x, -g.y, -g.z);
-    double gg = dotf(g, g);
-    d3 n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
-    // ---- plane constant: g(s) = vol(cell ∩ {n.x >= s}) = F V
-    double Vc = M.V[c];
-    double T = Fc * Vc;
-    double lev[kMaxLevels];
-    int nl = 0;
-    bool box = M.isbox[c] != 0;
-    double blev[8];
-    d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
-    if (box) {
-      for (int q = 0; q < 8; ++q) {
-        d3 p = mk3((q & 1) ? hi.x : lo.x, (q & 2) ? hi.y : lo.y, (q & 4) ? hi.z : lo.z);
-        blev[q] = dotf(n, p);
-        insert_sorted(lev, nl, blev[q]);
-      }
-    } else {
-      insert_sorted(lev, nl, dotf(n, xc));
-      for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i) insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
-      int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
-      for (int i = 0; i < fn && nl < kMaxLevels; ++i) {
-        int e = M.cf_idx[fb + i];
-        int f = e >= 0 ? e : ~e;
-        if (M.fv_ptr[f + 1] - M.fv_ptr[f] > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
-      }
-      if (M.cv_ptr[c + 1] - M.cv_ptr[c] + 1 > kMaxLevels) atomicOr(&M.counters[CNT_ERR], ERR_LEVELS);
-    }
-    auto G = [&](double s) -> double {
-      return box ? box_level_volume(blev, Vc, s) : CellLevels::general(M, c, n, xc, s);
-    };
-    int lo_i = 0, hi_i = nl - 1;
-    double glo = G(lev[0]), ghi = 0.0;
-    while (hi_i - lo_i > 1) {
-      int mid = (lo_i + hi_i) >> 1;
-      double gm = G(lev[mid]);
-      if (gm >= T) {
-        lo_i = mid;
-        glo = gm;
-      } else {
-        hi_i = mid;
-        ghi = gm;
-      }
-    }
-    double s0 = lev[lo_i], w = lev[hi_i] - s0;
-    double s;
-    if (!(w > 0.0)) {
-      s = s0;
-    } else {
-      double y1 = G(fma(w, 1.0 / 3.0, s0)), y2 = G(fma(w, 2.0 / 3.0, s0));
-      s = cubic_root(s0, w, glo, y1, y2, ghi, T);
-    }
-    M.pnx[c] = n.x;
-    M.pny[c] = n.y;
-    M.pnz[c] = n.z;
-    M.pC[c] = -s;
-  }
-}
-
 // ============================================================== face sweep
 // V_d = dt u.S, upwind cell, the flux of faces that need no geometry, and the
 // list of faces that need a flux polyhedron.
 __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt) {
   int n = M.nf;
   int stride = grid_stride();
-  int base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-  for (int b = base0; b < n; b += stride) {
-    int f = b + (threadIdx.x & 63);
+  // every thread of a block runs the same number of iterations (block_append holds barriers)
+  for (int b = blockIdx.x * blockDim.x; b < n; b += stride) {
+    int f = b + threadIdx.x;
     bool geo = false;
     if (f < n && face_live(M, f)) {
       d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
@@ -401,7 +314,7 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
       else if (t == 1) M.VF[f] = vd;
       else geo = true;
     }
-    wave_append(geo, f, &M.counters[CNT_FACES], M.list_faces, &M.totals[1]);
+    block_append(geo, f, &M.counters[CNT_FACES], M.list_faces, &M.totals[1]);
   }
 }
 
@@ -1020,13 +933,16 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
 }
 
 // Signed volume of one (flux tet, box cell) pair with cut mask `mask`: the
-// value every kernel gives the pair (register clip up to kMaxRegCuts cutting
-// planes, the explicit-stack clip beyond; a flat flux tet gives 0).
+// value every kernel gives the pair (the looping form of the register clip up
+// to four cutting planes, equal bit for bit to the expanded form the pair
+// kernel runs up to kMaxRegCuts; the explicit-stack clip beyond; a flat flux
+// tet gives 0).
 __device__ __attribute__((always_inline)) inline double box_pair_volume(const DevMesh& M, const Tet& T, const BoxCont& B, unsigned mask,
                                          const Leaf& leaf) {
   double sT = tet6(T);
   if (sT == 0.0) return 0.0;
-  double v = cut_count(mask) <= kMaxRegCuts ? clip_masked(T, B, mask, leaf) : clip_volume(T, B, leaf);
+  const int nc = cut_count(mask);
+  double v = nc <= 4 ? clip_masked_compact(T, B, mask, leaf) : clip_volume(T, B, leaf);
   if (v == -1.0) {
     atomicOr(&M.counters[CNT_ERR], ERR_STACK);
     v = 0.0;
@@ -1149,6 +1065,172 @@ __global__ void k_reset_advect(DevMesh M) {
     M.unit_fill[r] = 0;
     M.item_okend[r] = INT_MAX;
     M.unit_okend[r] = INT_MAX;
+  }
+}
+
+// ============================================================== LSGIR + plane constant
+// A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
+// the GPU nearly idle: a few thousand cells, each a long dependent chain).
+constexpr int kReconLanes = 8;
+
+// Sum over the lanes of a group.  Each butterfly level adds a lane's value
+// and its partner's, which gives the same bits on both lanes, so every lane
+// of the group ends with the same sum, in a fixed order.
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < kReconLanes; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// vol(cell ∩ {n.x >= s}) for a general cell: signed surface tetrahedra from
+// the vertex mean, split over the group's lanes.
+__device__ inline double general_level_volume(const DevMesh& M, int c, d3 n, d3 cen, double s, int sub, int np,
+                                              bool tri_only) {
+  const double lc = dotf(n, cen) - s;
+  double acc = 0.0;
+  for (int p = sub; p < np; p += kReconLanes) {
+    d3 t0, t1, t2;
+    cell_sigma(M, c, p, tri_only, t0, t1, t2);
+    double v6 = det3f(t0 - cen, t1 - cen, t2 - cen);
+    double fr = halfspace_fraction(lc, dotf(n, t0) - s, dotf(n, t1) - s, dotf(n, t2) - s);
+    acc = fma(v6, fr, acc);
+  }
+  return group_sum(acc) * (1.0 / 6.0);
+}
+
+__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F) {
+  const int ncell = M.counters[CNT_CELLS];
+  const double beta = M.beta;
+  const bool beta15 = beta == 1.5;
+  const int sub = threadIdx.x & (kReconLanes - 1);
+  const int gbase = __lane_id() & ~(kReconLanes - 1);  // first lane of the group in the wavefront
+  const int ngroups = (gridDim.x * blockDim.x) / kReconLanes;
+  // the trip count is the same for every lane of a group (the shuffles below need all of them)
+  for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kReconLanes; it < ncell; it += ngroups) {
+    const int c = M.list_cells[it];
+    const d3 xc = cell_centre(M, c);
+    const double Fc = F[c];
+    // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta.
+    // The lanes gather the neighbours' terms, a round of kReconLanes at a time,
+    // and every lane accumulates all terms in neighbour order: the sums keep the
+    // order of a serial loop (which decides the normal where the gradient
+    // vanishes to rounding, e.g. a lone filled cell).
+    double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, r0 = 0, r1 = 0, r2 = 0;
+    const int nb0 = M.nb_ptr[c], nnb = M.nb_ptr[c + 1] - nb0;
+    for (int r = 0; r < nnb; r += kReconLanes) {
+      d3 d = mk3(0.0, 0.0, 0.0);
+      double w2 = 0.0, df = 0.0;
+      if (r + sub < nnb) {
+        int k = M.nb_idx[nb0 + r + sub];
+        d = cell_centre(M, k) - xc;
+        double d2 = dotf(d, d);
+        w2 = beta15 ? 1.0 / (d2 * sqrt(d2)) : pow(d2, -beta);
+        df = (F[k] - Fc) * w2;
+      }
+      const int nq = min(kReconLanes, nnb - r);
+      for (int j = 0; j < nq; ++j) {
+        const double dx = __shfl(d.x, gbase + j), dy = __shfl(d.y, gbase + j), dz = __shfl(d.z, gbase + j);
+        const double wj = __shfl(w2, gbase + j), fj = __shfl(df, gbase + j);
+        a00 = fma(wj * dx, dx, a00);
+        a01 = fma(wj * dx, dy, a01);
+        a02 = fma(wj * dx, dz, a02);
+        a11 = fma(wj * dy, dy, a11);
+        a12 = fma(wj * dy, dz, a12);
+        a22 = fma(wj * dz, dz, a22);
+        r0 = fma(fj, dx, r0);
+        r1 = fma(fj, dy, r1);
+        r2 = fma(fj, dz, r2);
+      }
+    }
+    // adjugate solve (A symmetric positive definite): g ~ adj(A) r
+    double c00 = fma(a11, a22, -a12 * a12), c01 = fma(a02, a12, -a01 * a22), c02 = fma(a01, a12, -a02 * a11);
+    double c11 = fma(a00, a22, -a02 * a02), c12 = fma(a01, a02, -a00 * a12), c22 = fma(a00, a11, -a01 * a01);
+    double det = fma(a00, c00, fma(a01, c01, a02 * c02));
+    d3 g = mk3(fma(c00, r0, fma(c01, r1, c02 * r2)), fma(c01, r0, fma(c11, r1, c12 * r2)),
+               fma(c02, r0, fma(c12, r1, c22 * r2)));
+    if (det < 0.0) g = mk3(-g.x, -g.y, -g.z);
+    double gg = dotf(g, g);
+    d3 n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
+    // ---- plane constant: G(s) = vol(cell ∩ {n.x >= s}) = F V, G decreasing from V to 0
+    // over the sorted vertex levels
+    const double Vc = M.V[c];
+    const double T = Fc * Vc;
+    double s0, w, glo, ghi;
+    double lev[kMaxLevels];
+    int nl = 0;
+    if (M.isbox[c] != 0) {
+      double blev[8];
+      d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+      for (int q = 0; q < 8; ++q) {
+        d3 p = mk3((q & 1) ? hi.x : lo.x, (q & 2) ? hi.y : lo.y, (q & 4) ? hi.z : lo.z);
+        blev[q] = dotf(n, p);
+        insert_sorted(lev, nl, blev[q]);
+      }
+      // G at the eight levels, one per lane; the bracket is the last level with G >= T and the next
+      const double gj = box_level_volume(blev, Vc, lev[sub]);
+      int lo_i = 0;
+      glo = __shfl(gj, gbase);
+      for (int q = 1; q < 8; ++q) {
+        double gq = __shfl(gj, gbase + q);
+        if (gq >= T) {
+          lo_i = q;
+          glo = gq;
+        }
+      }
+      const int hi_i = lo_i < 7 ? lo_i + 1 : 7;
+      const double gh = __shfl(gj, gbase + hi_i);
+      ghi = hi_i == 7 ? 0.0 : gh;
+      s0 = lev[lo_i];
+      w = lev[hi_i] - s0;
+      if (w > 0.0) {
+        // the two interior points of the bracket's cubic, on lanes 0 and 1
+        const double sq = fma(w, (sub & 1) ? 2.0 / 3.0 : 1.0 / 3.0, s0);
+        const double yq = box_level_volume(blev, Vc, sq);
+        const double y1 = __shfl(yq, gbase), y2 = __shfl(yq, gbase + 1);
+        s0 = cubic_root(s0, w, glo, y1, y2, ghi, T);
+      }
+    } else {
+      insert_sorted(lev, nl, dotf(n, xc));
+      for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i)
+        insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
+      int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+      for (int i = 0; i < fn && nl < kMaxLevels; ++i) {
+        int e = M.cf_idx[fb + i];
+        int f = e >= 0 ? e : ~e;
+        if (M.fv_ptr[f + 1] - M.fv_ptr[f] > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
+      }
+      if (sub == 0 && M.cv_ptr[c + 1] - M.cv_ptr[c] + 1 > kMaxLevels) atomicOr(&M.counters[CNT_ERR], ERR_LEVELS);
+      const int np = cell_piece_count(M, c);
+      const bool tri_only = np == fn;
+      // bisection over the levels; every evaluation is spread over the group
+      int lo_i = 0, hi_i = nl - 1;
+      glo = general_level_volume(M, c, n, xc, lev[0], sub, np, tri_only);
+      ghi = 0.0;
+      while (hi_i - lo_i > 1) {
+        int mid = (lo_i + hi_i) >> 1;
+        double gm = general_level_volume(M, c, n, xc, lev[mid], sub, np, tri_only);
+        if (gm >= T) {
+          lo_i = mid;
+          glo = gm;
+        } else {
+          hi_i = mid;
+          ghi = gm;
+        }
+      }
+      s0 = lev[lo_i];
+      w = lev[hi_i] - s0;
+      if (w > 0.0) {
+        double y1 = general_level_volume(M, c, n, xc, fma(w, 1.0 / 3.0, s0), sub, np, tri_only);
+        double y2 = general_level_volume(M, c, n, xc, fma(w, 2.0 / 3.0, s0), sub, np, tri_only);
+        s0 = cubic_root(s0, w, glo, y1, y2, ghi, T);
+      }
+    }
+    if (sub == 0) {
+      M.pnx[c] = n.x;
+      M.pny[c] = n.y;
+      M.pnz[c] = n.z;
+      M.pC[c] = -s0;
+    }
   }
 }
 
@@ -1332,7 +1414,7 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
   TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
   TIMED(K_FACE_TAG, (k_face_tag<<<blocks_for(M.nf, st), st, 0, s>>>(M)));
   TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
-  TIMED(K_RECON, (k_recon<<<blocks_for(M.nc, L.recon_threads, 2048), L.recon_threads, 0, s>>>(M, F)));
+  TIMED(K_RECON, (k_recon<<<blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096), L.recon_threads, 0, s>>>(M, F)));
   return hipGetLastError();
 }
 
