@@ -62,6 +62,7 @@ struct gvof_mesh {
   std::vector<int> fv_ptr, fv_idx, owner, neigh;
   std::vector<int> cf_ptr, cf_idx, cv_ptr, cv_idx, vc_ptr, vc_idx, nb_ptr, nb_idx;
   std::vector<short> cell_np;  // surface triangles per cell
+  std::vector<int> tri_off;    // surface-triangle cache offsets (cells bounded by triangles only)
   int max_nb = 0;
   // problem partition: problem q owns vertices [voff[q], voff[q+1]), faces
   // [foff[q], foff[q+1]) and cells [coff[q], coff[q+1])
@@ -99,6 +100,8 @@ static int fail(gvof_mesh* m, int code, const char* fmt, ...) {
     hipError_t e_ = (call);                                                               \
     if (e_ != hipSuccess) return fail(m, GVOF_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
+
+static void cell_counts(gvof_mesh* m);
 
 extern "C" {
 
@@ -237,11 +240,33 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
   m->voff = {0, nv};
   m->foff = {0, nf};
   m->coff = {0, nc};
+  cell_counts(m);
   *out = m;
   return GVOF_OK;
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ derived per-cell counts
+// Surface triangles per cell (a triangle counts once, a polygon of k vertices
+// k times, fanned) and the offsets of the surface-triangle cache, which holds
+// the cells bounded by triangles only.
+static void cell_counts(gvof_mesh* m) {
+  m->cell_np.assign(m->nc, 0);
+  m->tri_off.assign(m->nc + 1, 0);
+  for (int c = 0; c < m->nc; ++c) {
+    int np = 0;
+    bool tri_only = true;
+    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+      int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
+      int k = m->fv_ptr[f + 1] - m->fv_ptr[f];
+      np += k == 3 ? 1 : k;
+      tri_only = tri_only && k == 3;
+    }
+    m->cell_np[c] = (short)np;
+    m->tri_off[c + 1] = m->tri_off[c] + (tri_only ? np : 0);
+  }
+}
 
 // ------------------------------------------------------------------ workspace layout
 namespace {
@@ -281,6 +306,8 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.nb_ptr = C.take<int>(nc + 1);
   d.nb_idx = C.take<int>(std::max<size_t>(m->nb_idx.size(), 1));
   d.cell_np = C.take<short>(nc);
+  d.tri_off = C.take<int>(nc + 1);
+  d.tri_xyz = C.take<double>(9 * std::max<size_t>(m->tri_off.empty() ? 0 : m->tri_off.back(), 1));
   double* S = C.take<double>(3 * nf);
   double* fc = C.take<double>(3 * nf);
   d.Sx = S;
@@ -401,20 +428,8 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, up(d.vc_idx, m->vc_idx.data(), m->vc_idx.size() * 4));
   HIPCHECK(m, up(d.nb_ptr, m->nb_ptr.data(), m->nb_ptr.size() * 4));
   if (!m->nb_idx.empty()) HIPCHECK(m, up(d.nb_idx, m->nb_idx.data(), m->nb_idx.size() * 4));
-  {
-    // surface triangles per cell: a triangle counts once, a polygon of k vertices k times (fanned)
-    m->cell_np.assign(m->nc, 0);
-    for (int c = 0; c < m->nc; ++c) {
-      int np = 0;
-      for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
-        int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
-        int k = m->fv_ptr[f + 1] - m->fv_ptr[f];
-        np += k == 3 ? 1 : k;
-      }
-      m->cell_np[c] = (short)np;
-    }
-    HIPCHECK(m, up(d.cell_np, m->cell_np.data(), m->cell_np.size() * sizeof(short)));
-  }
+  HIPCHECK(m, up(d.cell_np, m->cell_np.data(), m->cell_np.size() * sizeof(short)));
+  HIPCHECK(m, up(d.tri_off, m->tri_off.data(), m->tri_off.size() * sizeof(int)));
   std::vector<int> pid[3];
   if (m->nprob > 1) {
     const std::vector<int>* offs[3] = {&m->voff, &m->foff, &m->coff};
@@ -429,6 +444,7 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
   HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 8, s));
   HIPCHECK(m, gvof::launch_geometry(d, s));
+  HIPCHECK(m, gvof::launch_tri_cache(d, s));
   int cnt[gvof::CNT_N];
   HIPCHECK(m, hipMemcpyAsync(cnt, d.counters, sizeof cnt, hipMemcpyDeviceToHost, s));
   HIPCHECK(m, hipStreamSynchronize(s));
@@ -533,7 +549,10 @@ int gvof_get_tags(gvof_mesh* m, double* node_value, int8_t* node_tag, int8_t* fa
   if (!m->reconstructed) return fail(m, GVOF_E_ARG, "no reconstruction yet");
   if ((r = d2d(m, node_value, m->dm.Fstar, (size_t)m->nv * 8))) return r;
   if ((r = d2d(m, node_tag, m->dm.tag_node, m->nv))) return r;
-  if ((r = d2d(m, face_tag, m->dm.tag_face, m->nf))) return r;
+  if (face_tag) {
+    HIPCHECK(m, gvof::launch_face_tags(m->dm, m->stream));
+    if ((r = d2d(m, face_tag, m->dm.tag_face, m->nf))) return r;
+  }
   return d2d(m, cell_tag, m->dm.tag_cell, m->nc);
 }
 
@@ -695,6 +714,7 @@ int gvof_batch_create(gvof_mesh** out, int32_t nprob, gvof_mesh* const* parts) {
     m->foff.push_back(fo + a->nf);
     m->coff.push_back(co + a->nc);
   }
+  cell_counts(m);
   *out = m;
   return GVOF_OK;
 }

@@ -23,6 +23,11 @@ struct DevMesh {
   const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
   const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
   const short* cell_np;        // surface triangles of each cell (triangles as they are, polygons fanned)
+  // surface triangles of the cells bounded by triangles only, in the order and
+  // orientation face_triangle gives them: cell c's are triangles
+  // tri_off[c] .. tri_off[c+1]-1 of tri_xyz (9 doubles each); other cells have none
+  const int* tri_off;
+  double* tri_xyz;
   // geometry (computed on the device at bind)
   double *Sx, *Sy, *Sz, *fcx, *fcy, *fcz;
   double *V, *ccx, *ccy, *ccz, *lox, *loy, *loz, *hix, *hiy, *hiz;

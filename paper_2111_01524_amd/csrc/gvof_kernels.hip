@@ -195,6 +195,8 @@ __global__ void k_cell_geom(DevMesh M) {
 // cell id), w = 1/|x_v - x_c|^2; node tag in {-1, 0, 1}.
 __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
+  // the interfacial-cell counter of this reconstruction (first incremented by k_cell_tag, which runs after)
+  if (blockIdx.x == 0 && threadIdx.x == 0) M.counters[CNT_CELLS] = 0;
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
     if (!vert_live(M, v)) continue;
     d3 x = vert(M, v);
@@ -213,16 +215,23 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   }
 }
 
+// Face tag from its node tags: -1 (all -1), 1 (all 1), else 0.  The step
+// derives it where it is used (k_face_sweep); k_face_tag stores it for
+// gvof_get_tags.
+__device__ inline int8_t face_tag_of(const DevMesh& M, int f) {
+  bool allm = true, allp = true;
+  for (int i = M.fv_ptr[f]; i < M.fv_ptr[f + 1]; ++i) {
+    int t = M.tag_node[M.fv_idx[i]];
+    allm = allm && t == -1;
+    allp = allp && t == 1;
+  }
+  return allm ? -1 : (allp ? 1 : 0);
+}
+
 __global__ void k_face_tag(DevMesh M) {
   for (int f = grid_stride_start(); f < M.nf; f += grid_stride()) {
     if (!face_live(M, f)) continue;
-    bool allm = true, allp = true;
-    for (int i = M.fv_ptr[f]; i < M.fv_ptr[f + 1]; ++i) {
-      int t = M.tag_node[M.fv_idx[i]];
-      allm = allm && t == -1;
-      allp = allp && t == 1;
-    }
-    M.tag_face[f] = allm ? -1 : (allp ? 1 : 0);
+    M.tag_face[f] = face_tag_of(M, f);
   }
 }
 
@@ -308,7 +317,7 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
       int nb = M.neigh[f];
       M.Vd[f] = vd;
       M.upwind[f] = vd >= 0.0 ? M.owner[f] : nb;
-      int8_t t = M.tag_face[f];
+      int8_t t = face_tag_of(M, f);
       if (nb < 0 && vd < 0.0) M.VF[f] = 0.0;
       else if (t == -1) M.VF[f] = 0.0;
       else if (t == 1) M.VF[f] = vd;
@@ -761,8 +770,34 @@ __global__ __launch_bounds__(256) void k_flux_items_box(DevMesh M) {
 // Surface tetrahedron p of cell k: (vertex mean, outward triangle), with its
 // orientation sign.
 __device__ inline void cell_sigma(const DevMesh& M, int k, int p, bool tri_only, d3& t0, d3& t1, d3& t2) {
-  if (tri_only) face_triangle(M, M.cf_idx[M.cf_ptr[k] + p], 0, t0, t1, t2);
-  else cell_piece(M, k, p, t0, t1, t2);
+  if (tri_only) {
+    const int o = M.tri_off[k];
+    if (M.tri_off[k + 1] > o) {  // cached at bind: one contiguous read instead of a chain of gathers
+      const double* q = M.tri_xyz + 9 * (size_t)(o + p);
+      t0 = mk3(q[0], q[1], q[2]);
+      t1 = mk3(q[3], q[4], q[5]);
+      t2 = mk3(q[6], q[7], q[8]);
+    } else {
+      face_triangle(M, M.cf_idx[M.cf_ptr[k] + p], 0, t0, t1, t2);
+    }
+  } else {
+    cell_piece(M, k, p, t0, t1, t2);
+  }
+}
+
+// Fills the surface-triangle cache (bind time).
+__global__ void k_tri_cache(DevMesh M) {
+  for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
+    const int o = M.tri_off[c], n = M.tri_off[c + 1] - o;
+    for (int p = 0; p < n; ++p) {
+      d3 t0, t1, t2;
+      face_triangle(M, M.cf_idx[M.cf_ptr[c] + p], 0, t0, t1, t2);
+      double* q = M.tri_xyz + 9 * (size_t)(o + p);
+      q[0] = t0.x; q[1] = t0.y; q[2] = t0.z;
+      q[3] = t1.x; q[4] = t1.y; q[5] = t1.z;
+      q[6] = t2.x; q[7] = t2.y; q[8] = t2.z;
+    }
+  }
 }
 
 __device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_np[k]; }
@@ -1410,9 +1445,7 @@ hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
 
 hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof) {
   const int st = L.sweep_threads;
-  k_zero<<<1, 64, 0, s>>>(M.counters + CNT_CELLS, 1);
   TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
-  TIMED(K_FACE_TAG, (k_face_tag<<<blocks_for(M.nf, st), st, 0, s>>>(M)));
   TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
   TIMED(K_RECON, (k_recon<<<blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096), L.recon_threads, 0, s>>>(M, F)));
   return hipGetLastError();
@@ -1441,8 +1474,18 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   }
   TIMED(K_FLUX_DEEP, (k_flux_deep<<<blocks_for(M.item_cap, 64, 1024), 64, 0, s>>>(M)));
   TIMED(K_FLUX_SUM, (k_flux_sum<<<blocks_for(M.poly_cap, 256, 1024), 256, 0, s>>>(M)));
-  TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 2048), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 512), kFluxLanes, 0, s>>>(M, uv, dt)));
   TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, st), st, 0, s>>>(M, Fin, Fout)));
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_cache(const DevMesh& M, hipStream_t s) {
+  k_tri_cache<<<blocks_for(M.nc, 256), 256, 0, s>>>(M);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_tags(const DevMesh& M, hipStream_t s) {
+  k_face_tag<<<blocks_for(M.nf, 256), 256, 0, s>>>(M);
   return hipGetLastError();
 }
 

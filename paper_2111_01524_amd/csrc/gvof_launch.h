@@ -33,5 +33,7 @@ hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
 hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
                          double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
+hipError_t launch_face_tags(const DevMesh& M, hipStream_t s);
+hipError_t launch_tri_cache(const DevMesh& M, hipStream_t s);
 hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s);
 }  // namespace gvof
