@@ -151,13 +151,14 @@ def cartesian_mesh(n: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Mesh:
                 nei.astype(np.int32), n ** 3, "cartesian", n)
 
 
-def jittered_mesh(n: int, seed: int = 1, amp: float = 0.25) -> Mesh:
+def jittered_mesh(n: int, seed: int = 1, amp: float = 0.25, split: bool = True) -> Mesh:
     """Non-convex hexahedral grid on the unit cube.
 
     Interior lattice vertices are moved by (2U-1)*amp*h per axis, U drawn from
     splitmix64(seed) in lexicographic vertex order (x, y, z draws per vertex).
     Every quadrilateral is then split into 4 triangles through the mean of its
-    four corners, which becomes a new mesh vertex.
+    four corners, which becomes a new mesh vertex.  With split=False the
+    (non-planar) quadrilaterals are kept as faces.
     """
     h = 1.0 / n
     X, Y, Z = _lattice(n)
@@ -170,6 +171,10 @@ def jittered_mesh(n: int, seed: int = 1, amp: float = 0.25) -> Mesh:
     Y[interior] += (2.0 * U[:, 1] - 1.0) * amp * h
     Z[interior] += (2.0 * U[:, 2] - 1.0) * amp * h
     quads, own, nei = _structured_quads(n)
+    if not split:
+        fv_ptr = (np.arange(quads.shape[0] + 1) * 4).astype(np.int32)
+        return Mesh(X, Y, Z, fv_ptr, quads.ravel().astype(np.int32), own.astype(np.int32), nei.astype(np.int32),
+                    n ** 3, "jittered-quad", n)
     nq = quads.shape[0]
     nv0 = X.shape[0]
     cx = (X[quads[:, 0]] + X[quads[:, 1]] + X[quads[:, 2]] + X[quads[:, 3]]) / 4.0
@@ -315,7 +320,7 @@ def cfl_dt(mesh: Mesh, u_face_max: np.ndarray, cfl: float) -> float:
 
 def step_schedule(t_end: float, dt: float):
     """Constant dt, with the last step shortened to land on t_end."""
-    n = int(math.ceil(t_end / dt - 1e-12))
+    n = max(1, int(math.ceil(t_end / dt - 1e-12)))
     dts = [dt] * n
     dts[-1] = t_end - dt * (n - 1)
     return dts

@@ -461,3 +461,27 @@ def test_clipper_rounding_level_contact(oracle_mod):
     ref = float(XR.clip_volume(Tq, pq))
     got = oracle_mod.tet_clip_volume(T, planes)
     assert abs(got - ref) <= 1e-13 * abs(ref), (got, ref)
+
+
+def test_zero_step_and_empty_field_invariants(oracle_mod):
+    """A zero time step moves no fluid: every V_d is 0 exactly, V_F is 0 to
+    rounding (the collapsed polyhedra have rounding-level volumes) and F after
+    the step is F after the cut-off to rounding.  An empty field has no
+    interfacial cell or face and stays exactly empty."""
+    m = inputs.jittered_mesh(3, seed=2)
+    om = oracle_mod.OracleMesh(m)
+    uf, uv = inputs.velocity_enright(m)
+    F0 = om.init_fraction("sphere", [0.5, 0.45, 0.55, 0.3], 4)
+    Fc, Fs, tn, tf, tc, pl = om.reconstruct(F0)
+    assert (tc == 0).any() and (tf == 0).any()
+    F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, 0.0, Fc)
+    V = om.geometry()["V"]
+    assert bad == 0 and not Vd.any()
+    assert np.abs(VF).max() <= 1e-15 * V.min()
+    assert np.abs(F1 - Fc).max() <= 1e-14
+    Z = np.zeros(m.nc)
+    Zc, Zs, zn, zf, zc, zp = om.reconstruct(Z)
+    assert (zc == -1).all() and (zf == -1).all()
+    dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
+    Z1, *_ = om.advect(zp, zc, zf, uf, uv, dt, Zc)
+    assert not Z1.any()
