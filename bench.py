@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--served", type=int, default=0,
                     help="also serve this many jobs of the served workload (Poisson arrivals at 20/s)")
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
+    ap.add_argument("--served-cohort-jobs", type=int, default=2, help="most jobs per admitted cohort (0: no limit)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB, 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -246,13 +247,15 @@ def served_leg(args, served, dev):
     specs, problems = served
     jobs = serve.jobs_from_specs(specs, problems)
     ex = serve.GpuExecutor(dev)
-    srv = serve.Server(ex, budget_bytes=int(args.served_budget_gb * 1e9), max_cohorts=4, depth=4)
+    srv = serve.Server(ex, budget_bytes=int(args.served_budget_gb * 1e9), max_cohorts=4, depth=4,
+                       max_jobs_per_cohort=args.served_cohort_jobs or None)
     rep = srv.run(jobs)
     window = max(s["arrival"] for s in specs)
     S = rep.summary(arrival_window=window)
     S["unit"] = "face·steps/s"
     S["workload"] = (f"first {len(specs)} jobs of the Poisson stream (20/s, seed 3), arrivals over {window:.2f} s, "
-                     f"sides {sorted(set(s['side'] for s in specs))}, budget {args.served_budget_gb:g} GB")
+                     f"sides {sorted(set(s['side'] for s in specs))}, budget {args.served_budget_gb:g} GB, "
+                     f"at most 4 cohorts of {args.served_cohort_jobs or 'any number of'} jobs")
     S["latency_includes_queueing"] = True
     return S
 

@@ -31,7 +31,7 @@ def test_served_results_equal_alone():
     ex.estimate(probe)
     ex.reject(probe)
     budget = int(2.5 * probe.bytes)  # about two jobs at a time
-    rep = serve.Server(ex, budget_bytes=budget, max_cohorts=2, depth=2).run(jobs)
+    rep = serve.Server(ex, budget_bytes=budget, max_cohorts=2, depth=2, max_jobs_per_cohort=2).run(jobs)
     S = rep.summary()
     log(f"served: {S}")
     assert S["completed"] == len(jobs) and S["rejected"] == 0

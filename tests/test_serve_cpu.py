@@ -14,38 +14,58 @@ from paper_2111_01524_amd.serve import Job, Server
 
 
 class FakeExecutor:
-    def __init__(self, sec_per_face_step=1e-8, setup_s=0.01, arrivals=()):
+    """Sizing is immediate; a cohort becomes ready setup_s after its admission
+    (the loop does not wait for it); the device runs enqueued steps in order."""
+
+    def __init__(self, sec_per_face_step=1e-8, setup_s=0.01, arrivals=(), size_delay=None):
         self.t = 0.0
         self.arrivals = sorted(arrivals)
         self.ends_all = []
         self.device_free = 0.0
         self.k = sec_per_face_step
         self.setup_s = setup_s
+        self.size_delay = size_delay or (lambda job: 0.0)
         self.log = []          # (time, event, job ids)
-        self.live = 0          # bytes of running cohorts
+        self.live = 0          # bytes of cohorts admitted and not released
         self.max_live = 0
 
     def now(self):
         return self.t
 
     def idle(self, dt):
-        # jump to the next event (a step ending or a job arriving) instead of ticking
+        # jump to the next event (a step ending, a cohort or a size becoming ready, a job arriving)
         nxt = [e for e in self.ends_all if e > self.t] + [a for a in self.arrivals if a > self.t]
         self.t = max(self.t + max(dt, 1e-9), min(nxt)) if nxt else self.t + max(dt, 1e-6)
 
-    def estimate(self, job):
+    def shutdown(self):
+        pass
+
+    def submit_estimate(self, job):
         job.bytes = job.faces * 100
+        job._ready = self.t + self.size_delay(job)
+        self.ends_all.append(job._ready)
+
+    def estimate_ready(self, job):
+        return self.t >= job._ready
 
     def reject(self, job):
         self.log.append((self.t, "reject", [job.id]))
 
-    def start(self, jobs):
-        self.t += self.setup_s
+    def submit_start(self, jobs):
         nbytes = sum(j.bytes for j in jobs)
         self.live += nbytes
         self.max_live = max(self.max_live, self.live)
         self.log.append((self.t, "start", [j.id for j in jobs]))
-        return dict(jobs=jobs, s=0, max=max(j.nsteps for j in jobs), ends=[], fin={}, done=set(), bytes=nbytes), nbytes
+        ready = self.t + self.setup_s
+        self.ends_all.append(ready)
+        return dict(jobs=jobs, s=0, max=max(j.nsteps for j in jobs), ends=[], fin={}, done=set(), bytes=nbytes,
+                    ready=ready)
+
+    def start_ready(self, c):
+        return self.t >= c["ready"]
+
+    def cohort_bytes(self, c):
+        return c["bytes"]
 
     def finished_enqueue(self, c):
         return c["s"] >= c["max"]
@@ -154,3 +174,16 @@ def test_latency_matches_single_job_service_time_when_idle():
     service = 0.02 + 100 * 1e-9 * 10 ** 6
     assert math.isclose(j.t_done - j.arrival, service, rel_tol=1e-6, abs_tol=5e-4)
     assert rep.summary()["p50_latency_s"] == pytest.approx(j.t_done - j.arrival)
+
+
+def test_cohort_size_cap_and_arrival_order_with_slow_sizing():
+    # sizing takes longer for larger jobs, so sizes complete out of arrival order;
+    # admission must still follow arrival order, at most two jobs per cohort
+    jobs = make_jobs(20)
+    ex = FakeExecutor(arrivals=[j.arrival for j in jobs], size_delay=lambda j: j.faces * 2e-8)
+    rep = Server(ex, budget_bytes=10 ** 12, max_cohorts=3, depth=2, max_jobs_per_cohort=2).run(jobs)
+    starts = [ids for t, ev, ids in ex.log if ev == "start"]
+    assert all(len(ids) <= 2 for ids in starts)
+    order = sorted(range(len(jobs)), key=lambda i: (jobs[i].arrival, i))
+    assert [i for ids in starts for i in ids] == order
+    assert rep.summary()["completed"] == len(jobs)
