@@ -458,6 +458,7 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
     HIPCHECK(m, hipMemcpyAsync(box.data(), d.isbox, m->nc, hipMemcpyDeviceToHost, s));
     HIPCHECK(m, hipStreamSynchronize(s));
     d.all_box = std::all_of(box.begin(), box.end(), [](int8_t b) { return b != 0; }) ? 1 : 0;
+    d.any_box = std::any_of(box.begin(), box.end(), [](int8_t b) { return b != 0; }) ? 1 : 0;
   }
   HIPCHECK(m, hipStreamSynchronize(s));
   m->bound = true;

@@ -63,6 +63,7 @@ struct DevMesh {
   unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
   int all_box;  // every cell is an axis-aligned box (set at bind)
+  int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);
   // with nprob == 1 the id arrays are not read
   int nprob;

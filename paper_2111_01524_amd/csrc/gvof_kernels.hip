@@ -386,35 +386,30 @@ struct FluxLds {
   signed char ctag[kMaxCand], cbox[kMaxCand];
 };
 
-// FMFPA polyhedron of face f into S.px/py/pz: lanes 0..I-1 build the
-// lateral-plane normals, line directions and back vertices; every lane then
-// places the apex (identical values).  Returns the face centre, area vector
-// and the polyhedron's bounding box.
+// FMFPA polyhedron of face f into S.px/py/pz, in phases over the lanes of
+// one wavefront (the caller puts x_i, u_i of the face's vertices in
+// S.px/py/pz[i], S.ux/uy/uz[i] first, and synchronises between phases).
+// Lateral planes: lanes 0..I-1 take the plane through edge i parallel to the
+// edge-centre velocity.
 template <class Lds>
-__device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, int I,
-                                       const double* __restrict__ uv, double dt, d3& c, d3& Sv, d3& plo, d3& phi) {
+__device__ inline void poly_lateral(Lds& S, int I) {
   const int lane = threadIdx.x;
-  const int nv = M.nv;
-  if (lane < I) {
-    int v = M.fv_idx[b0 + lane];
-    S.px[lane] = M.vx[v];
-    S.py[lane] = M.vy[v];
-    S.pz[lane] = M.vz[v];
-    S.ux[lane] = uv[v];
-    S.uy[lane] = uv[nv + v];
-    S.uz[lane] = uv[2 * nv + v];
-  }
-  __syncthreads();
   if (lane < I) {
     int j = (lane + 1 == I) ? 0 : lane + 1;
     d3 ub = mk3(0.5 * (S.ux[lane] + S.ux[j]), 0.5 * (S.uy[lane] + S.uy[j]), 0.5 * (S.uz[lane] + S.uz[j]));
     d3 e = mk3(S.px[j] - S.px[lane], S.py[j] - S.py[lane], S.pz[j] - S.pz[lane]);
-    d3 m = cross_x(e, ub);  // lateral plane through edge i, parallel to the edge-centre velocity
+    d3 m = cross_x(e, ub);
     S.mx[lane] = m.x;
     S.my[lane] = m.y;
     S.mz[lane] = m.z;
   }
-  __syncthreads();
+}
+
+// Back vertices: lanes 0..I-1 move x_i back along the line where the two
+// lateral planes through x_i meet (or along u_i where they are parallel).
+template <class Lds>
+__device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt) {
+  const int lane = threadIdx.x;
   if (lane < I) {
     int i = lane, ip = (lane == 0) ? I - 1 : lane - 1;
     d3 m0 = mk3(S.mx[ip], S.my[ip], S.mz[ip]), m1 = mk3(S.mx[i], S.my[i], S.mz[i]);
@@ -432,38 +427,43 @@ __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, 
     S.py[I + i] = bv.y;
     S.pz[I + i] = bv.z;
   }
-  __syncthreads();
-  c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
-  Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-  {
-    // apex: back-vertex mean moved along S until the signed volume equals V_d
-    d3 g = mk3(0.0, 0.0, 0.0);
-    for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
-    double dI = (double)I;
-    g = mk3(g.x / dI, g.y / dI, g.z / dI);
-    double V0 = 0.0, W = 0.0;
-    for (int i = 0; i < I; ++i) {
-      int j = (i + 1 == I) ? 0 : i + 1;
-      d3 xi = mk3(S.px[i], S.py[i], S.pz[i]) - c, xj = mk3(S.px[j], S.py[j], S.pz[j]) - c;
-      d3 bi = mk3(S.px[I + i], S.py[I + i], S.pz[I + i]) - c, bj = mk3(S.px[I + j], S.py[I + j], S.pz[I + j]) - c;
-      V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
-      W += det3f(Sv, bj, bi);
-    }
-    V0 *= (1.0 / 6.0);
-    W *= (1.0 / 6.0);
-    double mu = 0.0;
-    if (fabs(W) <= 1e-12 * dotf(Sv, Sv)) {
-      if (lane == 0) atomicOr(&M.counters[CNT_ERR], ERR_APEX);
-    } else {
-      mu = (M.Vd[f] - V0) / W;
-    }
-    if (lane == 0) {
-      S.px[2 * I] = fma(mu, Sv.x, g.x);
-      S.py[2 * I] = fma(mu, Sv.y, g.y);
-      S.pz[2 * I] = fma(mu, Sv.z, g.z);
-    }
+}
+
+// Apex: the back-vertex mean moved along S until the polyhedron's signed
+// volume equals V_d (every lane computes the same values; lane 0 stores).
+template <class Lds>
+__device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, double vd) {
+  const int lane = threadIdx.x;
+  d3 g = mk3(0.0, 0.0, 0.0);
+  for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
+  double dI = (double)I;
+  g = mk3(g.x / dI, g.y / dI, g.z / dI);
+  double V0 = 0.0, W = 0.0;
+  for (int i = 0; i < I; ++i) {
+    int j = (i + 1 == I) ? 0 : i + 1;
+    d3 xi = mk3(S.px[i], S.py[i], S.pz[i]) - c, xj = mk3(S.px[j], S.py[j], S.pz[j]) - c;
+    d3 bi = mk3(S.px[I + i], S.py[I + i], S.pz[I + i]) - c, bj = mk3(S.px[I + j], S.py[I + j], S.pz[I + j]) - c;
+    V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
+    W += det3f(Sv, bj, bi);
   }
-  __syncthreads();
+  V0 *= (1.0 / 6.0);
+  W *= (1.0 / 6.0);
+  double mu = 0.0;
+  if (fabs(W) <= 1e-12 * dotf(Sv, Sv)) {
+    if (lane == 0) atomicOr(&M.counters[CNT_ERR], ERR_APEX);
+  } else {
+    mu = (vd - V0) / W;
+  }
+  if (lane == 0) {
+    S.px[2 * I] = fma(mu, Sv.x, g.x);
+    S.py[2 * I] = fma(mu, Sv.y, g.y);
+    S.pz[2 * I] = fma(mu, Sv.z, g.z);
+  }
+}
+
+// Bounding box of the polyhedron (the face centre included).
+template <class Lds>
+__device__ inline void poly_box(const Lds& S, int I, d3 c, d3& plo, d3& phi) {
   plo = c;
   phi = c;
   for (int i = 0; i <= 2 * I; ++i) {
@@ -471,6 +471,34 @@ __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, 
     plo = vmin(plo, p);
     phi = vmax(phi, p);
   }
+}
+
+// The whole polyhedron of face f with block barriers between the phases.
+// Returns the face centre, area vector and the polyhedron's bounding box.
+template <class Lds>
+__device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, int I,
+                                       const double* __restrict__ uv, double dt, d3& c, d3& Sv, d3& plo, d3& phi) {
+  const int lane = threadIdx.x;
+  const int nv = M.nv;
+  if (lane < I) {
+    int v = M.fv_idx[b0 + lane];
+    S.px[lane] = M.vx[v];
+    S.py[lane] = M.vy[v];
+    S.pz[lane] = M.vz[v];
+    S.ux[lane] = uv[v];
+    S.uy[lane] = uv[nv + v];
+    S.uz[lane] = uv[2 * nv + v];
+  }
+  __syncthreads();
+  poly_lateral(S, I);
+  __syncthreads();
+  poly_back(M, S, I, dt);
+  __syncthreads();
+  c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
+  Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+  poly_apex(M, S, I, c, Sv, M.Vd[f]);
+  __syncthreads();
+  poly_box(S, I, c, plo, phi);
 }
 
 // Candidate cells of face f (owner, neighbour and every cell sharing a vertex
@@ -563,17 +591,79 @@ __device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(con
   return true;
 }
 
-// LDS of the staging kernel: the polyhedron and up to kPrepCand candidate cells.
+// LDS of the staging kernel: the polyhedron, the owner's neighbour list and up
+// to kPrepCand candidate cells.
 constexpr int kPrepCand = 64;
 struct PrepLds {
   double px[kMaxPts], py[kMaxPts], pz[kMaxPts];
   double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
   double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
+  int onb[kMaxNeighbours];
   int cand[kPrepCand];
   double clox[kPrepCand], cloy[kPrepCand], cloz[kPrepCand], chix[kPrepCand], chiy[kPrepCand], chiz[kPrepCand];
   signed char cbox[kPrepCand];
-  int base;
 };
+
+// Hands LDS data between the lanes of a block that is one wavefront: the
+// wavefront's LDS operations complete in order, so waiting for its own is
+// enough; its global loads stay in flight, and the compiler moves no memory
+// access across the wait.
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Candidate j of face f: the owner, the owner's neighbours, the neighbour,
+// then the neighbour's neighbours.
+__device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int on, int nbr, int nbb) {
+  if (j == 0) return o;
+  if (j <= on) return M.nb_idx[ob + j - 1];
+  if (j == on + 1) return nbr;
+  return M.nb_idx[nbb + j - on - 2];
+}
+
+// Test of candidate kc of the staged candidates against flux tet t: the tet's
+// box meets the cell's box and, for a box cell, the tet is not entirely
+// outside one box plane.  tm packs t and the mask of the box planes that cut
+// the tet.
+__device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, unsigned& tm, int& kc) {
+  const int t = q % T3;
+  kc = q / T3;
+  int i1, i2, i3;
+  flux_tet_points(t, I, i1, i2, i3);
+  Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]), mk3(S.px[i3], S.py[i3], S.pz[i3])};
+  d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+  BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
+  bool keep = box_overlap(tlo, thi, B.lo, B.hi);
+  unsigned mask = 0;
+  if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
+  tm = (unsigned)t | (mask << 5);
+  return keep;
+}
+
+// Reserves count pairs for face slot it in region it % kItemRegions of the
+// pair buffer (lane 0).  Returns the first index, or -1 when the region is
+// full: the face then goes to the overflow kernel.
+__device__ inline int reserve_pairs(const DevMesh& M, int it, int f, int count) {
+  const int r = it % kItemRegions;
+  const int rsize = M.item_cap / kItemRegions;
+  int base = atomicAdd(&M.item_fill[r], count);
+  if (base + count > rsize) {
+    // every reservation before this one in atomic order fitted and every
+    // later one fails: the region's written part is [0, smallest failed base)
+    atomicMin(&M.item_okend[r], base);
+    M.item_cnt[it] = -1;
+    M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
+    return -1;
+  }
+  base += r * rsize;
+  M.item_off[it] = base;
+  M.item_cnt[it] = count;
+  return base;
+}
+
+__device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, unsigned tm) {
+  M.item_slot[i] = it;
+  M.item_cell[i] = cell;
+  M.item_tm[i] = (unsigned short)tm;
+}
 
 // Stage the flux work of every listed face, one wavefront per face: build
 // its FMFPA polyhedron (stored per slot), gather the candidate cells that hold
@@ -583,133 +673,148 @@ struct PrepLds {
 // and the pair carries the mask of the box planes that cut it).  Pairs of one
 // face are contiguous and in a fixed order.  Faces with more than kPrepCand
 // such cells or without room in the staging buffers go to the overflow kernel.
+// The loads of the face's vertices and of its candidate cells form two
+// independent chains; they are issued interleaved so that their latencies
+// overlap.
 __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ uv, double dt) {
   __shared__ PrepLds S;
   const int lane = threadIdx.x;
   const int nfaces = M.counters[CNT_FACES];
+  const int nv = M.nv;
   for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
     const int f = M.list_faces[it];
-    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
     if (it >= M.poly_cap) {
       if (lane == 0) M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
       continue;
     }
-    d3 c, Sv, plo, phi;
-    flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
+    // Loads first, straight-line with clamped indices (every lane reads valid
+    // memory), so both chains are in flight together.
+    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
+    const int o = M.owner[f], nbr = M.neigh[f];
+    const d3 c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
+    const d3 Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+    const double vd = M.Vd[f];
+    const int nbs = nbr >= 0 ? nbr : o;
+    const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
+    const int nbb0 = M.nb_ptr[nbs], nbn0 = M.nb_ptr[nbs + 1] - nbb0;
+    const int nbb = nbr >= 0 ? nbb0 : 0, nbn = nbr >= 0 ? nbn0 : 0;
+    const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
+    // first round of candidates, j = lane (it holds the owner's whole list);
+    // lanes past the list read the owner
+    const bool in_list = lane < L;
+    const bool listed = in_list & (lane != 0) & (lane != on + 1);
+    int idx = lane <= on ? ob + lane - 1 : nbb + lane - on - 2;
+    idx = listed ? idx : 0;
+    const int kl = M.nb_idx[idx];
+    const int v = M.fv_idx[b0 + min(lane, I - 1)];
+    int k = listed ? kl : o;
+    k = (in_list & (lane == on + 1)) ? nbr : k;
+    const d3 x = vert(M, v);
+    const d3 u = mk3(uv[v], uv[nv + v], uv[2 * nv + v]);
+    const int8_t tg = M.tag_cell[k];
+    d3 klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
+    d3 khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+    signed char kbox = M.isbox[k];
+    // then the LDS hand-offs and the polyhedron's phases
+    if (lane >= 1 && lane <= on) S.onb[lane - 1] = k;
+    if (lane < I) {
+      S.px[lane] = x.x; S.py[lane] = x.y; S.pz[lane] = x.z;
+      S.ux[lane] = u.x; S.uy[lane] = u.y; S.uz[lane] = u.z;
+    }
+    wave_lds_sync();
+    poly_lateral(S, I);
+    // a cell of the neighbour's list that is the owner or on the owner's list is already listed
+    bool keep = in_list & (tg != -1);
+    if (keep && lane > on) keep = !(k == o || sorted_contains(S.onb, on, k));
+    const double fdt = face_dt(M, f, dt);
+    wave_lds_sync();
+    poly_back(M, S, I, fdt);
+    wave_lds_sync();
+    poly_apex(M, S, I, c, Sv, vd);
+    wave_lds_sync();
+    d3 plo, phi;
+    poly_box(S, I, c, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
     if (lane <= 2 * I) {
       P[3 * lane] = S.px[lane];
       P[3 * lane + 1] = S.py[lane];
       P[3 * lane + 2] = S.pz[lane];
     }
-    // candidates
-    const int o = M.owner[f], nbr = M.neigh[f];
-    const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
-    const int nbb = nbr >= 0 ? M.nb_ptr[nbr] : 0, nbn = nbr >= 0 ? M.nb_ptr[nbr + 1] - nbb : 0;
-    const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
+    // candidates: keep the cells whose boxes meet the polyhedron's
     int ncand = 0;
     for (int j0 = 0; j0 < L; j0 += kFluxLanes) {
-      int j = j0 + lane;
-      bool keep = false;
-      int k = -1;
-      d3 klo = mk3(0, 0, 0), khi = klo;
-      if (j < L) {
-        bool second = j > on;
-        if (j == 0) k = o;
-        else if (j <= on) k = M.nb_idx[ob + j - 1];
-        else if (j == on + 1) k = nbr;
-        else k = M.nb_idx[nbb + j - on - 2];
-        keep = M.tag_cell[k] != -1;
-        if (keep && second) keep = !(k == o || sorted_contains(M.nb_idx + ob, on, k));
-        if (keep) {
-          klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
-          khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
-          keep = box_overlap(plo, phi, klo, khi);
+      int kj = k;
+      if (j0 > 0) {  // later rounds (more than kFluxLanes cells listed)
+        const int j = j0 + lane;
+        keep = false;
+        if (j < L) {
+          kj = candidate_cell(M, j, o, ob, on, nbr, nbb);
+          keep = M.tag_cell[kj] != -1 && !(kj == o || sorted_contains(S.onb, on, kj));
+          if (keep) {
+            klo = mk3(M.lox[kj], M.loy[kj], M.loz[kj]);
+            khi = mk3(M.hix[kj], M.hiy[kj], M.hiz[kj]);
+            kbox = M.isbox[kj];
+          }
         }
       }
+      keep = keep && box_overlap(plo, phi, klo, khi);
       unsigned long long bm = __ballot(keep);
       if (keep) {
         int pos = ncand + __popcll(bm & ((1ull << lane) - 1ull));
         if (pos < kPrepCand) {
-          S.cand[pos] = k;
+          S.cand[pos] = kj;
           S.clox[pos] = klo.x; S.cloy[pos] = klo.y; S.cloz[pos] = klo.z;
           S.chix[pos] = khi.x; S.chiy[pos] = khi.y; S.chiz[pos] = khi.z;
-          S.cbox[pos] = M.isbox[k];
+          S.cbox[pos] = kbox;
         }
       }
       ncand += __popcll(bm);
     }
-    __syncthreads();
+    wave_lds_sync();
     if (ncand > kPrepCand) {
       if (lane == 0) {
         M.item_cnt[it] = -1;
         M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
       }
-      __syncthreads();
       continue;
     }
-    // pairs: pass 0 counts, pass 1 writes into the reserved range
     const int T3 = 3 * I;
     const int total = ncand * T3;
-    int count = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-      int written = 0;
+    if (total <= kFluxLanes) {
+      // one round: the tests stay in registers between counting and writing
+      unsigned tm = 0;
+      int kc = 0;
+      const bool kp = lane < total && pair_test(S, c, I, T3, lane, tm, kc);
+      const unsigned long long bm = __ballot(kp);
+      int base = 0;
+      if (lane == 0) base = reserve_pairs(M, it, f, __popcll(bm));
+      base = __shfl(base, 0);
+      if (base >= 0 && kp) write_pair(M, base + __popcll(bm & ((1ull << lane) - 1ull)), it, S.cand[kc], tm);
+    } else {
+      // pass 0 counts, pass 1 writes into the reserved range
+      int count = 0;
       for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
-        int q = q0 + lane;
-        bool keep = false;
-        unsigned tm = 0;
-        int kc = 0;
-        if (q < total) {
-          int t = q % T3;
-          kc = q / T3;
-          int i1, i2, i3;
-          flux_tet_points(t, I, i1, i2, i3);
-          Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
-                mk3(S.px[i3], S.py[i3], S.pz[i3])};
-          d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
-          BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
-          keep = box_overlap(tlo, thi, B.lo, B.hi);
-          unsigned mask = 0;
-          if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
-          tm = (unsigned)t | (mask << 5);
-        }
-        unsigned long long bm = __ballot(keep);
-        if (pass == 0) {
-          count += __popcll(bm);
-        } else if (keep) {
-          int i = S.base + written + __popcll(bm & ((1ull << lane) - 1ull));  // inside this block's region
-          M.item_slot[i] = it;
-          M.item_cell[i] = S.cand[kc];
-          M.item_tm[i] = (unsigned short)tm;
-        }
-        written += __popcll(bm);
+        unsigned tm;
+        int kc;
+        const bool kp = q0 + lane < total && pair_test(S, c, I, T3, q0 + lane, tm, kc);
+        count += __popcll(__ballot(kp));
       }
-      if (pass == 0) {
-        if (lane == 0) {
-          // the pair buffer is split into kItemRegions regions with a fill counter
-          // each; face slot it reserves in region it % kItemRegions
-          int r = it % kItemRegions;
-          int rsize = M.item_cap / kItemRegions;
-          int base = atomicAdd(&M.item_fill[r], count);
-          if (base + count > rsize) {
-            // every reservation before this one in atomic order fitted and every
-            // later one fails: the region's written part is [0, smallest failed base)
-            atomicMin(&M.item_okend[r], base);
-            M.item_cnt[it] = -1;
-            M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
-            base = -1;
-          } else {
-            base += r * rsize;
-            M.item_off[it] = base;
-            M.item_cnt[it] = count;
-          }
-          S.base = base;
+      int base = 0;
+      if (lane == 0) base = reserve_pairs(M, it, f, count);
+      base = __shfl(base, 0);
+      if (base >= 0) {
+        int written = 0;
+        for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
+          unsigned tm = 0;
+          int kc = 0;
+          const bool kp = q0 + lane < total && pair_test(S, c, I, T3, q0 + lane, tm, kc);
+          const unsigned long long bm = __ballot(kp);
+          if (kp) write_pair(M, base + written + __popcll(bm & ((1ull << lane) - 1ull)), it, S.cand[kc], tm);
+          written += __popcll(bm);
         }
-        __syncthreads();
-        if (S.base < 0) break;
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 }
 
@@ -1106,7 +1211,7 @@ __global__ void k_reset_advect(DevMesh M) {
 // ============================================================== LSGIR + plane constant
 // A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
 // the GPU nearly idle: a few thousand cells, each a long dependent chain).
-constexpr int kReconLanes = 8;
+constexpr int kReconLanes = 32;
 
 // Sum over the lanes of a group.  Each butterfly level adds a lane's value
 // and its partner's, which gives the same bits on both lanes, so every lane
@@ -1133,6 +1238,10 @@ __device__ inline double general_level_volume(const DevMesh& M, int c, d3 n, d3 
   return group_sum(acc) * (1.0 / 6.0);
 }
 
+// Two instances: BOX handles the axis-aligned box cells, whose plane constant
+// needs only the eight corner levels (held one per lane of the group, so the
+// instance keeps no per-lane arrays), and !BOX the general cells.
+template <bool BOX>
 __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F) {
   const int ncell = M.counters[CNT_CELLS];
   const double beta = M.beta;
@@ -1143,6 +1252,7 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
   // the trip count is the same for every lane of a group (the shuffles below need all of them)
   for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kReconLanes; it < ncell; it += ngroups) {
     const int c = M.list_cells[it];
+    if ((M.isbox[c] != 0) != BOX) continue;  // uniform over the group
     const d3 xc = cell_centre(M, c);
     const double Fc = F[c];
     // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta.
@@ -1191,18 +1301,26 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
     const double Vc = M.V[c];
     const double T = Fc * Vc;
     double s0, w, glo, ghi;
-    double lev[kMaxLevels];
-    int nl = 0;
-    if (M.isbox[c] != 0) {
-      double blev[8];
+    if constexpr (BOX) {
+      // lane sub holds the level of corner sub; every lane gathers all eight
       d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+      const d3 p = mk3((sub & 1) ? hi.x : lo.x, (sub & 2) ? hi.y : lo.y, (sub & 4) ? hi.z : lo.z);
+      const double bl = dotf(n, p);
+      double blev[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) blev[q] = __shfl(bl, gbase + q);
+      // rank of this lane's level in ascending order (ties by corner index),
+      // then the level of rank sub: the sorted levels, one per lane
+      int rank = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rank += (blev[q] < bl || (blev[q] == bl && q < sub)) ? 1 : 0;
+      double lev = 0.0;
+#pragma unroll
       for (int q = 0; q < 8; ++q) {
-        d3 p = mk3((q & 1) ? hi.x : lo.x, (q & 2) ? hi.y : lo.y, (q & 4) ? hi.z : lo.z);
-        blev[q] = dotf(n, p);
-        insert_sorted(lev, nl, blev[q]);
+        if (__shfl(rank, gbase + q) == sub) lev = blev[q];
       }
       // G at the eight levels, one per lane; the bracket is the last level with G >= T and the next
-      const double gj = box_level_volume(blev, Vc, lev[sub]);
+      const double gj = box_level_volume(blev, Vc, lev);
       int lo_i = 0;
       glo = __shfl(gj, gbase);
       for (int q = 1; q < 8; ++q) {
@@ -1215,8 +1333,8 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
       const int hi_i = lo_i < 7 ? lo_i + 1 : 7;
       const double gh = __shfl(gj, gbase + hi_i);
       ghi = hi_i == 7 ? 0.0 : gh;
-      s0 = lev[lo_i];
-      w = lev[hi_i] - s0;
+      s0 = __shfl(lev, gbase + lo_i);
+      w = __shfl(lev, gbase + hi_i) - s0;
       if (w > 0.0) {
         // the two interior points of the bracket's cubic, on lanes 0 and 1
         const double sq = fma(w, (sub & 1) ? 2.0 / 3.0 : 1.0 / 3.0, s0);
@@ -1225,6 +1343,8 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
         s0 = cubic_root(s0, w, glo, y1, y2, ghi, T);
       }
     } else {
+      double lev[kMaxLevels];
+      int nl = 0;
       insert_sorted(lev, nl, dotf(n, xc));
       for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i)
         insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
@@ -1447,7 +1567,9 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
   const int st = L.sweep_threads;
   TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
   TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
-  TIMED(K_RECON, (k_recon<<<blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096), L.recon_threads, 0, s>>>(M, F)));
+  const int rb = blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096);
+  if (M.any_box) TIMED(K_RECON, (k_recon<true><<<rb, L.recon_threads, 0, s>>>(M, F)));
+  if (!M.all_box) TIMED(K_RECON, (k_recon<false><<<rb, L.recon_threads, 0, s>>>(M, F)));
   return hipGetLastError();
 }
 
@@ -1462,7 +1584,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   k_reset_advect<<<1, 256, 0, s>>>(M);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
   TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
-  TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
+  if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
   if (!M.all_box) {
     if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
