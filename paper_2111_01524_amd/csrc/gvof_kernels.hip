@@ -193,6 +193,7 @@ __global__ void k_cell_geom(DevMesh M) {
 // ============================================================== tagging and cut-off
 // Node value F* = sum w F / sum w over the cells sharing the node (ascending
 // cell id), w = 1/|x_v - x_c|^2; node tag in {-1, 0, 1}.
+constexpr int kNodeCells = 8;
 __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
   // the interfacial-cell counter of this reconstruction (first incremented by k_cell_tag, which runs after)
@@ -201,7 +202,30 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
     if (!vert_live(M, v)) continue;
     d3 x = vert(M, v);
     double num = 0.0, den = 0.0;
-    for (int i = M.vc_ptr[v]; i < M.vc_ptr[v + 1]; ++i) {
+    const int b = M.vc_ptr[v], n = M.vc_ptr[v + 1] - b;  // n >= 1
+    // the first kNodeCells cells' loads issued together (clamped indices), then
+    // summed in list order like the rest
+    int cq[kNodeCells];
+#pragma unroll
+    for (int q = 0; q < kNodeCells; ++q) cq[q] = M.vc_idx[b + min(q, n - 1)];
+    d3 xq[kNodeCells];
+    double fq[kNodeCells];
+#pragma unroll
+    for (int q = 0; q < kNodeCells; ++q) {
+      xq[q] = cell_centre(M, cq[q]);
+      fq[q] = F[cq[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kNodeCells; ++q) {
+      if (q < n) {
+        d3 d = x - xq[q];
+        double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
+        double w = 1.0 / d2;
+        num = num + w * fq[q];
+        den = den + w;
+      }
+    }
+    for (int i = b + kNodeCells; i < b + n; ++i) {
       int c = M.vc_idx[i];
       d3 d = x - cell_centre(M, c);
       double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
@@ -219,8 +243,20 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
 // derives it where it is used (k_face_sweep); k_face_tag stores it for
 // gvof_get_tags.
 __device__ inline int8_t face_tag_of(const DevMesh& M, int f) {
+  const int b = M.fv_ptr[f], n = M.fv_ptr[f + 1] - b;  // 3 <= n <= kMaxFaceVerts
+  int vq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) vq[q] = M.fv_idx[b + min(q, n - 1)];
+  int tq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) tq[q] = M.tag_node[vq[q]];  // the first four tags in flight together
   bool allm = true, allp = true;
-  for (int i = M.fv_ptr[f]; i < M.fv_ptr[f + 1]; ++i) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    allm = allm && tq[q] == -1;
+    allp = allp && tq[q] == 1;
+  }
+  for (int i = b + 4; i < b + n; ++i) {
     int t = M.tag_node[M.fv_idx[i]];
     allm = allm && t == -1;
     allp = allp && t == 1;
@@ -311,13 +347,15 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
     int f = b + threadIdx.x;
     bool geo = false;
     if (f < n && face_live(M, f)) {
+      // every load before the first store (the compiler cannot move loads
+      // above stores through these pointers), so the tag chain overlaps the rest
       d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
       d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+      const int nb = M.neigh[f], ow = M.owner[f];
+      const int8_t t = face_tag_of(M, f);
       double vd = face_dt(M, f, dt) * dot_x(u, S);
-      int nb = M.neigh[f];
       M.Vd[f] = vd;
-      M.upwind[f] = vd >= 0.0 ? M.owner[f] : nb;
-      int8_t t = face_tag_of(M, f);
+      M.upwind[f] = vd >= 0.0 ? ow : nb;
       if (nb < 0 && vd < 0.0) M.VF[f] = 0.0;
       else if (t == -1) M.VF[f] = 0.0;
       else if (t == 1) M.VF[f] = vd;
@@ -1101,27 +1139,88 @@ __device__ __attribute__((always_inline)) inline double general_pair_volume(cons
   return sT < 0.0 ? -v : v;
 }
 
-// Deferred pairs: box pairs with more cutting planes than the register clip
-// takes, and general pairs whose units did not fit the unit buffer.
+// Box pair with three or four cutting planes, computed by a group of
+// kDeepLanes lanes: lane 3i + j takes grandchild j of child i of the first
+// two splits and clips it by the remaining planes; the group then adds the
+// parts level by level in child order, each level's sum starting from zero,
+// which is exactly the association of the serial looping clip (the overflow
+// kernel's), so both paths give the same bits.
+constexpr int kDeepLanes = 16;
+__device__ inline double box_pair_volume_group(const Tet& T, const BoxCont& B, unsigned mask, int nc,
+                                               const Leaf& leaf, int sub, int gbase) {
+  const double sT = tet6(T);
+  if (sT == 0.0) return 0.0;
+  Plane P0 = {}, P1 = {}, P2 = {}, P3 = {};
+  unsigned rest = mask;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (rest) {
+      const int l = __builtin_ctz(rest);
+      rest &= rest - 1u;
+      const Plane pl = B.plane(l);
+      P0 = q == 0 ? pl : P0;
+      P1 = q == 1 ? pl : P1;
+      P2 = q == 2 ? pl : P2;
+      P3 = q == 3 ? pl : P3;
+    }
+  }
+  const int ci = sub / 3, cj = sub - 3 * ci;
+  const Split s1 = split_by(T, P0);
+  const int n1 = s1.count();
+  double d = 0.0;
+  int n2 = 0;
+  if (sub < 9 && ci < n1) {
+    const Split s2 = split_by(s1.child(ci), P1);
+    n2 = s2.count();
+    if (cj < n2) {
+      const Tet g = s2.child(cj);
+      d = nc == 3 ? clip1(g, P2, leaf) : clip2c(g, P2, P3, leaf);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int na = __shfl(n2, gbase + 3 * a);
+    double ca = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double db = __shfl(d, gbase + 3 * a + b);
+      if (b < na) ca += db;
+    }
+    if (a < n1) acc += ca;
+  }
+  return sT < 0.0 ? -acc : acc;
+}
+
+// Deferred pairs, a group of kDeepLanes lanes per pair: box pairs with more
+// cutting planes than the register clip takes, and general pairs whose units
+// did not fit the unit buffer.
 __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
-  int n = M.counters[CNT_DEEP];
-  for (int j = grid_stride_start(); j < n; j += grid_stride()) {
-    int i = M.list_deep[j];
-    int k = M.item_cell[i];
-    unsigned tm = M.item_tm[i];
-    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+  const int n = M.counters[CNT_DEEP];
+  const int sub = threadIdx.x & (kDeepLanes - 1);
+  const int gbase = __lane_id() & ~(kDeepLanes - 1);
+  const int ngroups = (gridDim.x * blockDim.x) / kDeepLanes;
+  // the trip count is the same for every lane of a group (the shuffles need all of them)
+  for (int j = (blockIdx.x * blockDim.x + threadIdx.x) / kDeepLanes; j < n; j += ngroups) {
+    const int i = M.list_deep[j];
+    const int k = M.item_cell[i];
+    const unsigned tm = M.item_tm[i];
+    const Tet T = staged_tet(M, M.item_slot[i], tm & 31);
     Leaf leaf;
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
     leaf.hd = M.pC[k];
-    double v;
+    double v = 0.0;
     if (M.isbox[k]) {
-      BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-      v = box_pair_volume(M, T, B, tm >> 5, leaf);
-    } else {
+      const BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
+      const unsigned mask = tm >> 5;
+      const int nc = cut_count(mask);
+      if (nc == 3 || nc == 4) v = box_pair_volume_group(T, B, mask, nc, leaf, sub, gbase);
+      else if (sub == 0) v = box_pair_volume(M, T, B, mask, leaf);
+    } else if (sub == 0) {
       v = general_pair_volume(M, k, cell_centre(M, k), T, leaf);
     }
-    M.item_vol[i] = v;
+    if (sub == 0) M.item_vol[i] = v;
   }
 }
 
@@ -1129,12 +1228,20 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
 __global__ void k_flux_sum(DevMesh M) {
   int n = min(M.counters[CNT_FACES], M.poly_cap);
   for (int it = grid_stride_start(); it < n; it += grid_stride()) {
-    int cnt = M.item_cnt[it];
+    const int cnt = M.item_cnt[it], off = M.item_off[it], f = M.list_faces[it];
     if (cnt < 0) continue;
-    const double* v = M.item_vol + M.item_off[it];
+    const double* v = M.item_vol + off;
     double acc = 0.0;
-    for (int i = 0; i < cnt; ++i) acc += v[i];
-    M.VF[M.list_faces[it]] = acc;
+    int i = 0;
+    for (; i + 8 <= cnt; i += 8) {  // eight loads in flight, added in order
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = v[i + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += t[q];
+    }
+    for (; i < cnt; ++i) acc += v[i];
+    M.VF[f] = acc;
   }
 }
 
@@ -1143,8 +1250,7 @@ __global__ void k_flux_sum(DevMesh M) {
 // (candidate, flux tet) pair computing the pair's volume with the same
 // functions as the staged path, summed in the same (candidate, tetrahedron)
 // order, so V_F does not depend on which path computed it.
-__global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const double* __restrict__ uv, double dt) {
-  __shared__ FluxLds S;
+__device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double* __restrict__ uv, double dt) {
   const int lane = threadIdx.x;
   const int nfaces = M.counters[CNT_OVER];
   for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
@@ -1190,6 +1296,11 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const doubl
     if (lane == 0) M.VF[f] = acc;
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const double* __restrict__ uv, double dt) {
+  __shared__ FluxLds S;
+  overflow_faces(M, S, uv, dt);
 }
 
 __global__ void k_reset_advect(DevMesh M) {
@@ -1391,11 +1502,37 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
 
 // ============================================================== update
 // Eq. (fnext) with face sums in ascending face order, then the clamp.
+constexpr int kUpdateFaces = 6;
 __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __restrict__ Fout) {
   for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
     if (!cell_live(M, c)) continue;
     double VdT = 0.0, VFT = 0.0;
-    for (int i = M.cf_ptr[c]; i < M.cf_ptr[c + 1]; ++i) {
+    const int b = M.cf_ptr[c], n = M.cf_ptr[c + 1] - b;  // n >= 4
+    // the first kUpdateFaces faces' loads issued together (clamped indices),
+    // then summed in face order like the rest
+    int eq[kUpdateFaces];
+#pragma unroll
+    for (int q = 0; q < kUpdateFaces; ++q) eq[q] = M.cf_idx[b + min(q, n - 1)];
+    double dq[kUpdateFaces], fq[kUpdateFaces];
+#pragma unroll
+    for (int q = 0; q < kUpdateFaces; ++q) {
+      const int fi = eq[q] >= 0 ? eq[q] : ~eq[q];
+      dq[q] = M.Vd[fi];
+      fq[q] = M.VF[fi];
+    }
+#pragma unroll
+    for (int q = 0; q < kUpdateFaces; ++q) {
+      if (q < n) {
+        if (eq[q] >= 0) {
+          VdT = VdT + dq[q];
+          VFT = VFT + fq[q];
+        } else {
+          VdT = VdT - dq[q];
+          VFT = VFT - fq[q];
+        }
+      }
+    }
+    for (int i = b + kUpdateFaces; i < b + n; ++i) {
       int e = M.cf_idx[i];
       if (e >= 0) {
         VdT = VdT + M.Vd[e];
@@ -1594,7 +1731,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
     TIMED(K_FLUX_GEN_UDEEP, (k_flux_gen_units_deep<<<1024, 256, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }
-  TIMED(K_FLUX_DEEP, (k_flux_deep<<<blocks_for(M.item_cap, 64, 1024), 64, 0, s>>>(M)));
+  TIMED(K_FLUX_DEEP, (k_flux_deep<<<1024, 64, 0, s>>>(M)));
   TIMED(K_FLUX_SUM, (k_flux_sum<<<blocks_for(M.poly_cap, 256, 1024), 256, 0, s>>>(M)));
   TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 512), kFluxLanes, 0, s>>>(M, uv, dt)));
   TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, st), st, 0, s>>>(M, Fin, Fout)));
