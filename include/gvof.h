@@ -173,8 +173,9 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
                      double* F_out, int32_t* upwind_out, double* vd_out, double* vf_out);
 
 /*
- * Number of interfacial cells and of faces needing flux polyhedra in the last
- * reconstruction / advection.  Synchronous (reads two device counters).
+ * Number of interfacial cells of the last reconstruction and of faces needing
+ * flux polyhedra in the last advection (0 when a reconstruction came after
+ * it).  Synchronous (reads two device counters).
  */
 int gvof_interface_counts(gvof_mesh* m, int32_t* n_cells, int32_t* n_faces);
 

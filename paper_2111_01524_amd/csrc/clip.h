@@ -94,6 +94,12 @@ __host__ __device__ inline double opaque(double v) {
 #endif
   return v;
 }
+__host__ __device__ inline int opaque(int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(v));
+#endif
+  return v;
+}
 
 // Orders (sa, pa), (sb, pb) so that sa >= sb (a swap: the values are unchanged).
 __host__ __device__ inline void cs_pt(double& sa, d3& pa, double& sb, d3& pb) {
@@ -204,6 +210,7 @@ __host__ __device__ double clip_volume(const Tet& T, const Cont& C, const Leaf& 
 struct Split {
   d3 a, b, c, d;
   double sa, sb, sc, sd;
+  d3 q0, q1, q2, q3;  // the cut points the children use, each computed once
   int kind;  // 0 nothing kept, 1 kept whole, 2 one vertex kept, 3 three kept (prism), 4 two kept (wedge)
   __host__ __device__ inline Split(const Tet& t, double s0, double s1, double s2, double s3) {
     a = t.p0; b = t.p1; c = t.p2; d = t.p3;
@@ -219,23 +226,27 @@ struct Split {
       cs_pt(sb, b, sc, c);
       kind = (sb <= 0.0) ? 2 : ((sc >= 0.0) ? 3 : 4);
     }
+    // edges cut: kind 2 ab ac ad, kind 3 ad bd cd, kind 4 ac ad bd bc
+    const bool k2 = kind == 2, k3 = kind == 3;
+    q0 = cut_pt(a, sa, k2 ? b : (k3 ? d : c), k2 ? sb : (k3 ? sd : sc));
+    q1 = cut_pt(k3 ? b : a, k3 ? sb : sa, k2 ? c : d, k2 ? sc : sd);
+    q2 = cut_pt(k2 ? a : (k3 ? c : b), k2 ? sa : (k3 ? sc : sb), d, sd);
+    q3 = cut_pt(b, sb, c, sc);
   }
   __host__ __device__ inline int count() const { return kind == 0 ? 0 : (kind <= 2 ? 1 : 3); }
   // children by constant index (a runtime index makes the compiler keep the
   // three children in an indexed private array)
   __host__ __device__ inline Tet child0() const {
-    if (kind == 1) return Tet{a, b, c, d};
-    if (kind == 2) return Tet{a, cut_pt(a, sa, b, sb), cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd)};
-    if (kind == 3) return Tet{a, b, c, cut_pt(a, sa, d, sd)};
-    return Tet{a, cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd), b};
+    const bool k1 = kind == 1, k2 = kind == 2, k3 = kind == 3;
+    return Tet{a, (k1 || k3) ? b : q0, (k1 || k3) ? c : q1, k1 ? d : (k2 ? q2 : (k3 ? q0 : b))};
   }
   __host__ __device__ inline Tet child1() const {
-    if (kind == 3) return Tet{b, c, cut_pt(a, sa, d, sd), cut_pt(b, sb, d, sd)};
-    return Tet{cut_pt(a, sa, c, sc), cut_pt(a, sa, d, sd), b, cut_pt(b, sb, d, sd)};
+    const bool k3 = kind == 3;
+    return Tet{k3 ? b : q0, k3 ? c : q1, k3 ? q0 : b, k3 ? q1 : q2};
   }
   __host__ __device__ inline Tet child2() const {
-    if (kind == 3) return Tet{c, cut_pt(a, sa, d, sd), cut_pt(b, sb, d, sd), cut_pt(c, sc, d, sd)};
-    return Tet{cut_pt(a, sa, c, sc), b, cut_pt(b, sb, d, sd), cut_pt(b, sb, c, sc)};
+    const bool k3 = kind == 3;
+    return Tet{k3 ? c : q0, k3 ? q0 : b, k3 ? q1 : q2, k3 ? q2 : q3};
   }
   __host__ __device__ inline Tet child(int i) const { return i == 0 ? child0() : (i == 1 ? child1() : child2()); }
 };

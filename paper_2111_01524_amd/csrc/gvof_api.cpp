@@ -31,23 +31,35 @@ struct EventProf : gvof::Prof {
   };
   std::vector<Rec> recs;
   hipEvent_t pending = nullptr;
+  // A failed event call leaves that launch out of the timings (and out of the
+  // launch count); the launch itself is not affected.
   void before(int k) override {
     if (!((mask >> k) & 1u)) return;
-    hipEventCreate(&pending);
-    hipEventRecord(pending, stream);
+    if (hipEventCreate(&pending) != hipSuccess) {
+      pending = nullptr;
+      return;
+    }
+    if (hipEventRecord(pending, stream) != hipSuccess) {
+      (void)hipEventDestroy(pending);
+      pending = nullptr;
+    }
   }
   void after(int k) override {
     if (!((mask >> k) & 1u) || !pending) return;
-    hipEvent_t e;
-    hipEventCreate(&e);
-    hipEventRecord(e, stream);
-    recs.push_back({k, pending, e});
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    if (e && hipEventRecord(e, stream) != hipSuccess) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+    if (e) recs.push_back({k, pending, e});
+    else (void)hipEventDestroy(pending);
     pending = nullptr;
   }
   void clear() {
-    for (auto& r : recs) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+    for (auto& r : recs) {  // nothing to do about a failed destroy
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
     recs.clear();
   }
@@ -78,6 +90,7 @@ struct gvof_mesh {
   hipStream_t stream = nullptr;
   DevMesh dm{};
   bool bound = false, reconstructed = false;
+  bool advect_state_clear = false;  // a reconstruction cleared the step counters and no advection used them yet
   std::string err;
   EventProf prof;
 };
@@ -472,9 +485,9 @@ int gvof_set_stream(gvof_mesh* m, void* stream) {
   return GVOF_OK;
 }
 
-static void drop_graph(gvof_mesh* m) {
-  if (m->gexec) hipGraphExecDestroy(m->gexec);
-  if (m->graph) hipGraphDestroy(m->graph);
+static void drop_graph(gvof_mesh* m) {  // nothing to do about a failed destroy
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
   m->gexec = nullptr;
   m->graph = nullptr;
 }
@@ -540,6 +553,7 @@ int gvof_reconstruct(gvof_mesh* m, double* F, int8_t* cell_tag_out, double* plan
   m->prof.stream = m->stream;
   HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->cfg, m->stream, m->prof.mask ? &m->prof : nullptr));
   m->reconstructed = true;
+  m->advect_state_clear = true;
   if ((r = d2d(m, cell_tag_out, m->dm.tag_cell, m->nc))) return r;
   return d2d(m, plane_out, m->dm.pnx, 4 * (size_t)m->nc * 8);
 }
@@ -566,7 +580,8 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
   if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
   m->prof.stream = m->stream;
   HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->cfg, m->stream,
-                                  m->prof.mask ? &m->prof : nullptr));
+                                  m->prof.mask ? &m->prof : nullptr, !m->advect_state_clear));
+  m->advect_state_clear = false;
   if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
   if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;
   return d2d(m, vf_out, m->dm.VF, (size_t)m->nf * 8);
@@ -760,7 +775,8 @@ static int batch_launch(gvof_mesh* m, const double* uf, const double* uv, const 
   d.prob_dt = dt;
   d.prob_active = active;
   HIPCHECK(m, gvof::launch_reconstruct(d, F, m->cfg, m->stream, prof));
-  HIPCHECK(m, gvof::launch_advect(d, uf, uv, 0.0, F, F, m->cfg, m->stream, prof));
+  HIPCHECK(m, gvof::launch_advect(d, uf, uv, 0.0, F, F, m->cfg, m->stream, prof, false));
+  m->advect_state_clear = false;
   return GVOF_OK;
 }
 
@@ -793,7 +809,7 @@ int gvof_graph_capture(gvof_mesh* m, const double* u_face, const double* u_vert,
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(m->stream, &g);
   if (r) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return r;
   }
   if (e != hipSuccess) return fail(m, GVOF_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -920,8 +936,8 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   m->cfg = cur;
   HIPCHECK(m, hipMemcpyAsync(F, F_save, fb, hipMemcpyDeviceToDevice, s));
   HIPCHECK(m, hipStreamSynchronize(s));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (best) cfg_out(cur, best);
   if (best_ms) *best_ms = cur_ms;
   return GVOF_OK;

@@ -147,12 +147,17 @@ __host__ __device__ inline void cswap_desc(double& a, double& b) {
 
 // Fraction of a tetrahedron's volume where the affine function with vertex
 // values s0..s3 is >= 0.  The fraction depends only on the four values: with
-// them sorted a >= b >= c >= d,
-//   one positive:  a^3 / ((a-b)(a-c)(a-d))
-//   one negative:  1 - (-d)^3 / ((a-d)(b-d)(c-d))
-//   two and two:   t_ac t_ad + t_ac t_bd (1 - t_ad) + t_bc t_bd (1 - t_ac),
-//                  t_xy = x / (x - y)  (the kept wedge split in three tetrahedra).
-// Every denominator is a difference of values of opposite sign.
+// them sorted a >= b >= c >= d it is, when
+//   only a is positive:      a^3 / ((a-b)(a-c)(a-d)),
+//   only d is negative:      [abc - d(ab+bc+ca) + d^2(a+b+c)] / ((a-d)(b-d)(c-d)),
+//   a, b positive, c, d not: [a^2 b^2 - (c+d) ab (a+b) + cd (a^2+ab+b^2)]
+//                              / ((a-c)(a-d)(b-c)(b-d)),
+// 1 when d >= 0 and 0 when a <= 0.  The second is 1 - (-d)^3 / ((a-d)(b-d)(c-d))
+// and the third the sum of the volumes of the three tetrahedra of the kept
+// wedge (vertices a, b and the cut points on ac, ad, bc, bd), each written
+// over the common denominator.  In each case every term of the numerator and
+// every factor of the denominator is >= 0, so nothing cancels, and the three
+// agree where the cases meet.  Computed without branches, with one division.
 __host__ __device__ inline double halfspace_fraction(double s0, double s1, double s2, double s3) {
   double a = s0, b = s1, c = s2, d = s3;
   cswap_desc(a, b);
@@ -160,19 +165,18 @@ __host__ __device__ inline double halfspace_fraction(double s0, double s1, doubl
   cswap_desc(a, c);
   cswap_desc(b, d);
   cswap_desc(b, c);
-  if (d >= 0.0) return 1.0;
-  if (a <= 0.0) return 0.0;
-  if (b <= 0.0) {
-    double den = (a - b) * (a - c) * (a - d);
-    return (a * a * a) / den;
-  }
-  if (c >= 0.0) {
-    double m = -d;
-    double den = (a - d) * (b - d) * (c - d);
-    return 1.0 - (m * m * m) / den;
-  }
-  double tac = a / (a - c), tad = a / (a - d), tbc = b / (b - c), tbd = b / (b - d);
-  return fma(tac, tad, fma(tac * tbd, 1.0 - tad, tbc * tbd * (1.0 - tac)));
+  const double ab = a * b, apb = a + b;
+  const double n1 = (a * a) * a;
+  const double d1 = ((a - b) * (a - c)) * (a - d);
+  const double n2 = (ab * c - d * fma(c, apb, ab)) + (d * d) * (apb + c);
+  const double d2 = ((a - d) * (b - d)) * (c - d);
+  const double n3 = (ab * ab - (c + d) * (ab * apb)) + (c * d) * fma(a, a, fma(b, b, ab));
+  const double d3 = ((a - c) * (a - d)) * ((b - c) * (b - d));
+  const bool one_pos = b <= 0.0, one_neg = c >= 0.0;
+  const double num = one_pos ? n1 : (one_neg ? n2 : n3);
+  const double den = one_pos ? d1 : (one_neg ? d2 : d3);
+  const double f = num / den;
+  return d >= 0.0 ? 1.0 : (a <= 0.0 ? 0.0 : f);
 }
 
 }  // namespace gvof

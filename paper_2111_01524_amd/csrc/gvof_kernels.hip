@@ -193,11 +193,34 @@ __global__ void k_cell_geom(DevMesh M) {
 // ============================================================== tagging and cut-off
 // Node value F* = sum w F / sum w over the cells sharing the node (ascending
 // cell id), w = 1/|x_v - x_c|^2; node tag in {-1, 0, 1}.
+// Counters, fill counters and written-part bounds of one advection step
+// (one block).
+__device__ inline void reset_advect_state(const DevMesh& M) {
+  if (threadIdx.x == 0) {
+    M.counters[CNT_FACES] = 0;
+    M.counters[CNT_ITEMS] = 0;
+    M.counters[CNT_OVER] = 0;
+    M.counters[CNT_DEEP] = 0;
+    M.counters[CNT_UDEEP] = 0;
+  }
+  for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) {
+    M.item_fill[r] = 0;
+    M.unit_fill[r] = 0;
+    M.item_okend[r] = INT_MAX;
+    M.unit_okend[r] = INT_MAX;
+  }
+}
+
 constexpr int kNodeCells = 8;
 __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
-  // the interfacial-cell counter of this reconstruction (first incremented by k_cell_tag, which runs after)
-  if (blockIdx.x == 0 && threadIdx.x == 0) M.counters[CNT_CELLS] = 0;
+  // the interfacial-cell counter of this reconstruction (first incremented by
+  // k_cell_tag, which runs after), and the state of the advection step that
+  // follows it (which then needs no reset kernel of its own)
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) M.counters[CNT_CELLS] = 0;
+    reset_advect_state(M);
+  }
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
     if (!vert_live(M, v)) continue;
     d3 x = vert(M, v);
@@ -1303,21 +1326,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const doubl
   overflow_faces(M, S, uv, dt);
 }
 
-__global__ void k_reset_advect(DevMesh M) {
-  if (threadIdx.x == 0) {
-    M.counters[CNT_FACES] = 0;
-    M.counters[CNT_ITEMS] = 0;
-    M.counters[CNT_OVER] = 0;
-    M.counters[CNT_DEEP] = 0;
-    M.counters[CNT_UDEEP] = 0;
-  }
-  for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) {
-    M.item_fill[r] = 0;
-    M.unit_fill[r] = 0;
-    M.item_okend[r] = INT_MAX;
-    M.unit_okend[r] = INT_MAX;
-  }
-}
+__global__ void k_reset_advect(DevMesh M) { reset_advect_state(M); }
 
 // ============================================================== LSGIR + plane constant
 // A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
@@ -1363,25 +1372,40 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
   // the trip count is the same for every lane of a group (the shuffles below need all of them)
   for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kReconLanes; it < ncell; it += ngroups) {
     const int c = M.list_cells[it];
-    if ((M.isbox[c] != 0) != BOX) continue;  // uniform over the group
+    // every load that depends only on c, issued together; the empty asm takes
+    // them all at once, which keeps the compiler from sinking each to its
+    // first use (a round trip each)
+    int isb = M.isbox[c];
     const d3 xc = cell_centre(M, c);
-    const double Fc = F[c];
+    double Fc = F[c];
+    const int nb0 = M.nb_ptr[c], nnb = M.nb_ptr[c + 1] - nb0;
+    double Vc = M.V[c];
+    d3 blo = xc, bhi = xc;
+    if constexpr (BOX) {
+      blo = mk3(M.lox[c], M.loy[c], M.loz[c]);
+      bhi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
+    }
+    asm volatile("" : "+v"(isb), "+v"(Fc), "+v"(Vc), "+v"(blo.x), "+v"(blo.y), "+v"(blo.z), "+v"(bhi.x),
+                 "+v"(bhi.y), "+v"(bhi.z));
+    if ((isb != 0) != BOX) continue;  // uniform over the group
     // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta.
     // The lanes gather the neighbours' terms, a round of kReconLanes at a time,
     // and every lane accumulates all terms in neighbour order: the sums keep the
     // order of a serial loop (which decides the normal where the gradient
     // vanishes to rounding, e.g. a lone filled cell).
     double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, r0 = 0, r1 = 0, r2 = 0;
-    const int nb0 = M.nb_ptr[c], nnb = M.nb_ptr[c + 1] - nb0;
     for (int r = 0; r < nnb; r += kReconLanes) {
       d3 d = mk3(0.0, 0.0, 0.0);
       double w2 = 0.0, df = 0.0;
       if (r + sub < nnb) {
         int k = M.nb_idx[nb0 + r + sub];
-        d = cell_centre(M, k) - xc;
+        d3 ck = cell_centre(M, k);
+        double fk = F[k];
+        asm volatile("" : "+v"(ck.x), "+v"(ck.y), "+v"(ck.z), "+v"(fk));  // both loads in flight together
+        d = ck - xc;
         double d2 = dotf(d, d);
         w2 = beta15 ? 1.0 / (d2 * sqrt(d2)) : pow(d2, -beta);
-        df = (F[k] - Fc) * w2;
+        df = (fk - Fc) * w2;
       }
       const int nq = min(kReconLanes, nnb - r);
       for (int j = 0; j < nq; ++j) {
@@ -1409,13 +1433,11 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
     d3 n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
     // ---- plane constant: G(s) = vol(cell ∩ {n.x >= s}) = F V, G decreasing from V to 0
     // over the sorted vertex levels
-    const double Vc = M.V[c];
     const double T = Fc * Vc;
     double s0, w, glo, ghi;
     if constexpr (BOX) {
       // lane sub holds the level of corner sub; every lane gathers all eight
-      d3 lo = mk3(M.lox[c], M.loy[c], M.loz[c]), hi = mk3(M.hix[c], M.hiy[c], M.hiz[c]);
-      const d3 p = mk3((sub & 1) ? hi.x : lo.x, (sub & 2) ? hi.y : lo.y, (sub & 4) ? hi.z : lo.z);
+      const d3 p = mk3((sub & 1) ? bhi.x : blo.x, (sub & 2) ? bhi.y : blo.y, (sub & 4) ? bhi.z : blo.z);
       const double bl = dotf(n, p);
       double blev[8];
 #pragma unroll
@@ -1711,14 +1733,14 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
 }
 
 hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof) {
+                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof, bool reset) {
   DevMesh M = M0;
   if (L.staged_faces > 0 && L.staged_faces < M.poly_cap) M.poly_cap = L.staged_faces;
   if (L.staged_pairs > 0 && L.staged_pairs < M.item_cap)
     M.item_cap = max(kItemRegions, L.staged_pairs - L.staged_pairs % kItemRegions);
   const int st = L.sweep_threads;
   const int pair_grid = kItemRegions * L.pair_blocks_per_region;
-  k_reset_advect<<<1, 256, 0, s>>>(M);
+  if (reset) k_reset_advect<<<1, 256, 0, s>>>(M);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
   TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));

@@ -31,8 +31,10 @@ struct LaunchCfg {
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
 hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
+// reset: clear the step's counters first (not needed right after
+// launch_reconstruct, whose first kernel clears them)
 hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, double dt, const double* Fin,
-                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr);
+                         double* Fout, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr, bool reset = true);
 hipError_t launch_face_tags(const DevMesh& M, hipStream_t s);
 hipError_t launch_tri_cache(const DevMesh& M, hipStream_t s);
 hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s);
