@@ -996,55 +996,84 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     const int np = cell_piece_count(M, k);
     const bool tri_only = np == M.cf_ptr[k + 1] - M.cf_ptr[k];
     const bool live = tet6(T) != 0.0;
-    int count = 0;
-    int base = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-      int written = 0;
-      for (int p0 = 0; p0 < np; p0 += LPP) {
-        int p = p0 + hl;
-        bool keep = false;
-        unsigned cm = 0;
-        if (live && p < np) {
-          d3 t0, t1, t2;
-          cell_sigma(M, k, p, tri_only, t0, t1, t2);
-          if (box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2))) &&
-              det3f(t0 - cc, t1 - cc, t2 - cc) != 0.0) {
-            TetCont TC = tet_container(cc, t0, t1, t2);
-            keep = cut_mask(T, TC, cm);
-          }
+    // test of surface tetrahedron p against T: keep, and the mask of its planes that cut T
+    auto test = [&](int p, unsigned& cm) -> bool {
+      cm = 0;
+      if (!live || p >= np) return false;
+      d3 t0, t1, t2;
+      cell_sigma(M, k, p, tri_only, t0, t1, t2);
+      if (!box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2))) ||
+          det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0)
+        return false;
+      TetCont TC = tet_container(cc, t0, t1, t2);
+      return cut_mask(T, TC, cm);
+    };
+    // reserves count units (lane 0 of the group); -1 when the region is full
+    auto reserve = [&](int count) -> int {
+      int b = 0;
+      if (hl == 0) {
+        b = atomicAdd(&M.unit_fill[r], count);
+        if (b + count > rsize) {
+          atomicMin(&M.unit_okend[r], b);
+          b = -1;
+        } else {
+          b += r * rsize;
         }
-        unsigned long long bm = __ballot(keep) & hmask;
-        int below = __popcll(bm & ((1ull << __lane_id()) - 1ull));
-        if (pass == 1 && keep) {
-          int u = base + written + below;
-          M.unit_item[u] = i;
-          M.unit_code[u] = (unsigned)p | (cm << 16);
-        }
-        written += __popcll(bm);
       }
-      if (pass == 0) {
-        count = written;
-        int b = 0;
-        if (hl == 0) {
-          b = atomicAdd(&M.unit_fill[r], count);
-          if (b + count > rsize) {
-            atomicMin(&M.unit_okend[r], b);
-            b = -1;
-          } else {
-            b += r * rsize;
-          }
-        }
-        base = __shfl(b, glead, 64);
+      const int base = __shfl(b, glead, 64);
+      if (hl == 0) {
         if (base < 0) {  // no room: the deferred kernel computes the whole pair
-          if (hl == 0) {
-            M.item_ucnt[i] = -1;
-            M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
-          }
-          break;
-        }
-        if (hl == 0) {
+          M.item_ucnt[i] = -1;
+          M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
+        } else {
           M.item_uoff[i] = base;
           M.item_ucnt[i] = count;
+        }
+      }
+      return base;
+    };
+    auto write_unit = [&](int u, int p, unsigned cm) {
+      M.unit_item[u] = i;
+      M.unit_code[u] = (unsigned)p | (cm << 16);
+    };
+    const unsigned long long below_mask = (1ull << __lane_id()) - 1ull;
+    if (np <= 4 * LPP) {
+      // up to four rounds: the tests stay in registers between counting and writing
+      bool kq[4];
+      unsigned cq[4];
+      unsigned long long bq[4];
+      int count = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        kq[q] = test(q * LPP + hl, cq[q]);
+        bq[q] = __ballot(kq[q]) & hmask;
+        count += __popcll(bq[q]);
+      }
+      const int base = reserve(count);
+      if (base >= 0) {
+        int written = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (kq[q]) write_unit(base + written + __popcll(bq[q] & below_mask), q * LPP + hl, cq[q]);
+          written += __popcll(bq[q]);
+        }
+      }
+    } else {
+      // pass 0 counts, pass 1 writes into the reserved range
+      int count = 0;
+      for (int p0 = 0; p0 < np; p0 += LPP) {
+        unsigned cm;
+        count += __popcll(__ballot(test(p0 + hl, cm)) & hmask);
+      }
+      const int base = reserve(count);
+      if (base >= 0) {
+        int written = 0;
+        for (int p0 = 0; p0 < np; p0 += LPP) {
+          unsigned cm;
+          const bool keep = test(p0 + hl, cm);
+          const unsigned long long bm = __ballot(keep) & hmask;
+          if (keep) write_unit(base + written + __popcll(bm & below_mask), p0 + hl, cm);
+          written += __popcll(bm);
         }
       }
     }
