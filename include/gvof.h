@@ -255,7 +255,7 @@ int gvof_graph_launch(gvof_mesh* m);
  * sum has a fixed order whatever the mapping); they change only the time.
  *   sweep_threads           block size of the vertex / face / cell sweeps (multiple of 64, 64..1024)
  *   recon_threads           block size of the reconstruction kernel (64 or 128)
- *   prep_blocks             grid of the flux-polyhedron staging kernel, one wavefront per face (1..2^20)
+ *   prep_blocks             grid of the flux-polyhedron staging kernel, blocks of one wavefront (1..2^20)
  *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256)
  *   filter_lanes            lanes per (face, cell, flux tetrahedron) pair in the general-cell filter (8, 16, 32, 64)
  *   staged_faces            most faces whose flux work is staged per step (0: as many as the workspace
@@ -265,6 +265,7 @@ int gvof_graph_launch(gvof_mesh* m);
  *                           step (0: as many as the workspace holds, else rounded down to a multiple of 256,
  *                           at least 256); faces and pairs that do not fit are computed by the overflow and
  *                           deferred kernels, with the same values.  Not tuned by gvof_autotune.
+ *   prep_lanes              lanes per face in the staging kernel (64: one face per wavefront, 32: two)
  */
 typedef struct gvof_launch_config {
   int32_t sweep_threads;
@@ -274,6 +275,7 @@ typedef struct gvof_launch_config {
   int32_t filter_lanes;
   int32_t staged_faces;
   int32_t staged_pairs;
+  int32_t prep_lanes;
 } gvof_launch_config;
 int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c);
 int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c);

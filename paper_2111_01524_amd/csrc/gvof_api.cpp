@@ -840,6 +840,7 @@ static void cfg_out(const gvof::LaunchCfg& c, gvof_launch_config* o) {
   o->filter_lanes = c.filter_lanes;
   o->staged_faces = c.staged_faces;
   o->staged_pairs = c.staged_pairs;
+  o->prep_lanes = c.prep_lanes;
 }
 
 int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c) {
@@ -862,6 +863,8 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
     return fail(m, GVOF_E_ARG, "filter_lanes=%d (8, 16, 32 or 64)", c->filter_lanes);
   if (c->staged_faces < 0) return fail(m, GVOF_E_ARG, "staged_faces=%d (>= 0)", c->staged_faces);
   if (c->staged_pairs < 0) return fail(m, GVOF_E_ARG, "staged_pairs=%d (>= 0)", c->staged_pairs);
+  if (c->prep_lanes != 32 && c->prep_lanes != 64)
+    return fail(m, GVOF_E_ARG, "prep_lanes=%d (32 or 64)", c->prep_lanes);
   m->cfg.sweep_threads = c->sweep_threads;
   m->cfg.recon_threads = c->recon_threads;
   m->cfg.prep_blocks = c->prep_blocks;
@@ -869,6 +872,7 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
   m->cfg.filter_lanes = c->filter_lanes;
   m->cfg.staged_faces = c->staged_faces;
   m->cfg.staged_pairs = c->staged_pairs;
+  m->cfg.prep_lanes = c->prep_lanes;
   drop_graph(m);
   return GVOF_OK;
 }
@@ -913,6 +917,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   const int lanes[] = {8, 16, 32, 64};
   const int sweep[] = {128, 256, 512, 1024};
   const int recon[] = {64, 128};
+  const int plan[] = {64, 32};
   auto sweep_param = [&](int gvof::LaunchCfg::*field, const int* vals, int nvals) -> int {
     for (int i = 0; i < nvals; ++i) {
       if (cur.*field == vals[i]) continue;
@@ -928,6 +933,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
     }
     return GVOF_OK;
   };
+  if ((r = sweep_param(&gvof::LaunchCfg::prep_lanes, plan, 2))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::prep_blocks, prep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::pair_blocks_per_region, pbr, 5))) return r;
   if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 4))) return r;

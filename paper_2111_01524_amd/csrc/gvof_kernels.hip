@@ -448,13 +448,13 @@ struct FluxLds {
 };
 
 // FMFPA polyhedron of face f into S.px/py/pz, in phases over the lanes of
-// one wavefront (the caller puts x_i, u_i of the face's vertices in
-// S.px/py/pz[i], S.ux/uy/uz[i] first, and synchronises between phases).
+// the face's group (lane = index within the group; the caller puts x_i, u_i
+// of the face's vertices in S.px/py/pz[i], S.ux/uy/uz[i] first, and
+// synchronises between phases).
 // Lateral planes: lanes 0..I-1 take the plane through edge i parallel to the
 // edge-centre velocity.
 template <class Lds>
-__device__ inline void poly_lateral(Lds& S, int I) {
-  const int lane = threadIdx.x;
+__device__ inline void poly_lateral(Lds& S, int I, int lane) {
   if (lane < I) {
     int j = (lane + 1 == I) ? 0 : lane + 1;
     d3 ub = mk3(0.5 * (S.ux[lane] + S.ux[j]), 0.5 * (S.uy[lane] + S.uy[j]), 0.5 * (S.uz[lane] + S.uz[j]));
@@ -469,8 +469,7 @@ __device__ inline void poly_lateral(Lds& S, int I) {
 // Back vertices: lanes 0..I-1 move x_i back along the line where the two
 // lateral planes through x_i meet (or along u_i where they are parallel).
 template <class Lds>
-__device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt) {
-  const int lane = threadIdx.x;
+__device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt, int lane) {
   if (lane < I) {
     int i = lane, ip = (lane == 0) ? I - 1 : lane - 1;
     d3 m0 = mk3(S.mx[ip], S.my[ip], S.mz[ip]), m1 = mk3(S.mx[i], S.my[i], S.mz[i]);
@@ -493,8 +492,7 @@ __device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt) {
 // Apex: the back-vertex mean moved along S until the polyhedron's signed
 // volume equals V_d (every lane computes the same values; lane 0 stores).
 template <class Lds>
-__device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, double vd) {
-  const int lane = threadIdx.x;
+__device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, double vd, int lane) {
   d3 g = mk3(0.0, 0.0, 0.0);
   for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
   double dI = (double)I;
@@ -551,13 +549,13 @@ __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, 
     S.uz[lane] = uv[2 * nv + v];
   }
   __syncthreads();
-  poly_lateral(S, I);
+  poly_lateral(S, I, lane);
   __syncthreads();
-  poly_back(M, S, I, dt);
+  poly_back(M, S, I, dt, lane);
   __syncthreads();
   c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
   Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-  poly_apex(M, S, I, c, Sv, M.Vd[f]);
+  poly_apex(M, S, I, c, Sv, M.Vd[f], lane);
   __syncthreads();
   poly_box(S, I, c, plo, phi);
 }
@@ -652,8 +650,9 @@ __device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(con
   return true;
 }
 
-// LDS of the staging kernel: the polyhedron, the owner's neighbour list and up
-// to kPrepCand candidate cells.
+// LDS of the staging kernel, per face: the polyhedron, the owner's neighbour
+// list and up to kPrepCand candidate cells (first staged as listed, then
+// compacted in place to those that survive the tests).
 constexpr int kPrepCand = 64;
 struct PrepLds {
   double px[kMaxPts], py[kMaxPts], pz[kMaxPts];
@@ -662,16 +661,16 @@ struct PrepLds {
   int onb[kMaxNeighbours];
   int cand[kPrepCand];
   double clox[kPrepCand], cloy[kPrepCand], cloz[kPrepCand], chix[kPrepCand], chiy[kPrepCand], chiz[kPrepCand];
-  signed char cbox[kPrepCand];
+  signed char cbox[kPrepCand], ctag[kPrepCand];
 };
 
-// Hands LDS data between the lanes of a block that is one wavefront: the
-// wavefront's LDS operations complete in order, so waiting for its own is
-// enough; its global loads stay in flight, and the compiler moves no memory
-// access across the wait.
+// Hands LDS data between the lanes of a wavefront: the wavefront's LDS
+// operations complete in order, so waiting for its own is enough; its global
+// loads stay in flight, and the compiler moves no memory access across the
+// wait.  (Blocks of the staging kernels are one wavefront.)
 __device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// Candidate j of face f: the owner, the owner's neighbours, the neighbour,
+// Candidate j of a face: the owner, the owner's neighbours, the neighbour,
 // then the neighbour's neighbours.
 __device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int on, int nbr, int nbb) {
   if (j == 0) return o;
@@ -680,10 +679,9 @@ __device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int
   return M.nb_idx[nbb + j - on - 2];
 }
 
-// Test of candidate kc of the staged candidates against flux tet t: the tet's
-// box meets the cell's box and, for a box cell, the tet is not entirely
-// outside one box plane.  tm packs t and the mask of the box planes that cut
-// the tet.
+// Test of staged candidate kc against flux tet t: the tet's box meets the
+// cell's box and, for a box cell, the tet is not entirely outside one box
+// plane.  tm packs t and the mask of the box planes that cut the tet.
 __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, unsigned& tm, int& kc) {
   const int t = q % T3;
   kc = q / T3;
@@ -700,8 +698,8 @@ __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, u
 }
 
 // Reserves count pairs for face slot it in region it % kItemRegions of the
-// pair buffer (lane 0).  Returns the first index, or -1 when the region is
-// full: the face then goes to the overflow kernel.
+// pair buffer.  Returns the first index, or -1 when the region is full: the
+// face then goes to the overflow kernel.
 __device__ inline int reserve_pairs(const DevMesh& M, int it, int f, int count) {
   const int r = it % kItemRegions;
   const int rsize = M.item_cap / kItemRegions;
@@ -726,26 +724,35 @@ __device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, uns
   M.item_tm[i] = (unsigned short)tm;
 }
 
-// Stage the flux work of every listed face, one wavefront per face: build
-// its FMFPA polyhedron (stored per slot), gather the candidate cells that hold
-// fluid and whose boxes meet the polyhedron's box, then emit one
-// (face, cell, flux tet) pair for every flux tet whose box meets such a
-// cell's box (box cells: the tet is also not entirely outside one box plane,
-// and the pair carries the mask of the box planes that cut it).  Pairs of one
-// face are contiguous and in a fixed order.  Faces with more than kPrepCand
-// such cells or without room in the staging buffers go to the overflow kernel.
-// The loads of the face's vertices and of its candidate cells form two
-// independent chains; they are issued interleaved so that their latencies
-// overlap.
+// Stage the flux work of every listed face, a group of G lanes per face
+// (64 / G faces per wavefront): build its FMFPA polyhedron (stored per slot),
+// gather the candidate cells that hold fluid and whose boxes meet the
+// polyhedron's box, then emit one (face, cell, flux tet) pair for every flux
+// tet whose box meets such a cell's box (box cells: the tet is also not
+// entirely outside one box plane, and the pair carries the mask of the box
+// planes that cut it).  Pairs of one face are contiguous and in a fixed
+// order.  Faces with more than kPrepCand such cells or without room in the
+// staging buffers go to the overflow kernel.
+// The loads of the face's vertices and of its first 64 listed cells form two
+// independent chains; they are issued together, straight-line with clamped
+// indices, and the cells' data go to LDS as soon as they arrive.
+template <int G>
 __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ uv, double dt) {
-  __shared__ PrepLds S;
+  static_assert(G == 32 || G == 64, "lanes per face");
+  constexpr int NG = kFluxLanes / G;  // faces per wavefront
+  constexpr int NR = kFluxLanes / G;  // rounds of G lanes over the first 64 listed cells
+  __shared__ PrepLds SS[NG];
   const int lane = threadIdx.x;
+  const int grp = lane / G, sub = lane - grp * G, gbase = grp * G;
+  PrepLds& S = SS[grp];
+  const unsigned long long gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+  const unsigned long long lbelow = ((1ull << lane) - 1ull) & gmask;
   const int nfaces = M.counters[CNT_FACES];
   const int nv = M.nv;
-  for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
+  for (int it = blockIdx.x * NG + grp; it < nfaces; it += gridDim.x * NG) {
     const int f = M.list_faces[it];
     if (it >= M.poly_cap) {
-      if (lane == 0) M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
+      if (sub == 0) M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
       continue;
     }
     // Loads first, straight-line with clamped indices (every lane reads valid
@@ -760,80 +767,120 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     const int nbb0 = M.nb_ptr[nbs], nbn0 = M.nb_ptr[nbs + 1] - nbb0;
     const int nbb = nbr >= 0 ? nbb0 : 0, nbn = nbr >= 0 ? nbn0 : 0;
     const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
-    // first round of candidates, j = lane (it holds the owner's whole list);
-    // lanes past the list read the owner
-    const bool in_list = lane < L;
-    const bool listed = in_list & (lane != 0) & (lane != on + 1);
-    int idx = lane <= on ? ob + lane - 1 : nbb + lane - on - 2;
-    idx = listed ? idx : 0;
-    const int kl = M.nb_idx[idx];
-    const int v = M.fv_idx[b0 + min(lane, I - 1)];
-    int k = listed ? kl : o;
-    k = (in_list & (lane == on + 1)) ? nbr : k;
+    // listed cells j = sub + G r (r < NR); lanes past the list read the owner
+    int kq[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = sub + G * r;
+      const bool in_list = j < L;
+      const bool listed = in_list & (j != 0) & (j != on + 1);
+      int idx = j <= on ? ob + j - 1 : nbb + j - on - 2;
+      idx = listed ? idx : 0;
+      const int kl = M.nb_idx[idx];
+      int k = listed ? kl : o;
+      kq[r] = (in_list & (j == on + 1)) ? nbr : k;
+    }
+    const int v = M.fv_idx[b0 + min(sub, I - 1)];
     const d3 x = vert(M, v);
     const d3 u = mk3(uv[v], uv[nv + v], uv[2 * nv + v]);
-    const int8_t tg = M.tag_cell[k];
-    d3 klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
-    d3 khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
-    signed char kbox = M.isbox[k];
-    // then the LDS hand-offs and the polyhedron's phases
-    if (lane >= 1 && lane <= on) S.onb[lane - 1] = k;
-    if (lane < I) {
-      S.px[lane] = x.x; S.py[lane] = x.y; S.pz[lane] = x.z;
-      S.ux[lane] = u.x; S.uy[lane] = u.y; S.uz[lane] = u.z;
+    int8_t tq[NR];
+    signed char bq[NR];
+    d3 loq[NR], hiq[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int k = kq[r];
+      tq[r] = M.tag_cell[k];
+      loq[r] = mk3(M.lox[k], M.loy[k], M.loz[k]);
+      hiq[r] = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+      bq[r] = M.isbox[k];
+    }
+    // then the LDS hand-offs: the face's vertices, the owner's list and the listed cells
+    if (sub < I) {
+      S.px[sub] = x.x; S.py[sub] = x.y; S.pz[sub] = x.z;
+      S.ux[sub] = u.x; S.uy[sub] = u.y; S.uz[sub] = u.z;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = sub + G * r;
+      if (j >= 1 && j <= on) S.onb[j - 1] = kq[r];
+      S.cand[j] = kq[r];
+      S.ctag[j] = tq[r];
+      S.clox[j] = loq[r].x; S.cloy[j] = loq[r].y; S.cloz[j] = loq[r].z;
+      S.chix[j] = hiq[r].x; S.chiy[j] = hiq[r].y; S.chiz[j] = hiq[r].z;
+      S.cbox[j] = bq[r];
     }
     wave_lds_sync();
-    poly_lateral(S, I);
-    // a cell of the neighbour's list that is the owner or on the owner's list is already listed
-    bool keep = in_list & (tg != -1);
-    if (keep && lane > on) keep = !(k == o || sorted_contains(S.onb, on, k));
+    poly_lateral(S, I, sub);
     const double fdt = face_dt(M, f, dt);
     wave_lds_sync();
-    poly_back(M, S, I, fdt);
+    poly_back(M, S, I, fdt, sub);
     wave_lds_sync();
-    poly_apex(M, S, I, c, Sv, vd);
+    poly_apex(M, S, I, c, Sv, vd, sub);
     wave_lds_sync();
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
-    if (lane <= 2 * I) {
-      P[3 * lane] = S.px[lane];
-      P[3 * lane + 1] = S.py[lane];
-      P[3 * lane + 2] = S.pz[lane];
+    if (sub <= 2 * I) {
+      P[3 * sub] = S.px[sub];
+      P[3 * sub + 1] = S.py[sub];
+      P[3 * sub + 2] = S.pz[sub];
     }
-    // candidates: keep the cells whose boxes meet the polyhedron's
+    // candidates: cells that hold fluid, not listed before (a cell of the
+    // neighbour's list that is the owner or on the owner's list) and whose
+    // boxes meet the polyhedron's; compacted in place (a cell moves only to
+    // a slot already read)
     int ncand = 0;
-    for (int j0 = 0; j0 < L; j0 += kFluxLanes) {
-      int kj = k;
-      if (j0 > 0) {  // later rounds (more than kFluxLanes cells listed)
-        const int j = j0 + lane;
-        keep = false;
-        if (j < L) {
-          kj = candidate_cell(M, j, o, ob, on, nbr, nbb);
-          keep = M.tag_cell[kj] != -1 && !(kj == o || sorted_contains(S.onb, on, kj));
-          if (keep) {
-            klo = mk3(M.lox[kj], M.loy[kj], M.loz[kj]);
-            khi = mk3(M.hix[kj], M.hiy[kj], M.hiz[kj]);
-            kbox = M.isbox[kj];
-          }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = sub + G * r;
+      const int k = S.cand[j];
+      const d3 klo = mk3(S.clox[j], S.cloy[j], S.cloz[j]), khi = mk3(S.chix[j], S.chiy[j], S.chiz[j]);
+      const signed char kb = S.cbox[j];
+      bool keep = j < L && S.ctag[j] != -1;
+      if (keep && j > on) keep = !(k == o || sorted_contains(S.onb, on, k));
+      keep = keep && box_overlap(plo, phi, klo, khi);
+      const unsigned long long bm = __ballot(keep) & gmask;
+      wave_lds_sync();  // every lane has read its slot before any slot is rewritten
+      if (keep) {
+        const int pos = ncand + __popcll(bm & lbelow);
+        S.cand[pos] = k;
+        S.clox[pos] = klo.x; S.cloy[pos] = klo.y; S.cloz[pos] = klo.z;
+        S.chix[pos] = khi.x; S.chiy[pos] = khi.y; S.chiz[pos] = khi.z;
+        S.cbox[pos] = kb;
+      }
+      ncand += __popcll(bm);
+    }
+    for (int j0 = kFluxLanes; j0 < L; j0 += G) {  // more than 64 cells listed (general meshes only)
+      const int j = j0 + sub;
+      bool keep = false;
+      int k = o;
+      d3 klo = mk3(0.0, 0.0, 0.0), khi = klo;
+      signed char kb = 0;
+      if (j < L) {
+        k = candidate_cell(M, j, o, ob, on, nbr, nbb);
+        keep = M.tag_cell[k] != -1 && !(k == o || sorted_contains(S.onb, on, k));
+        if (keep) {
+          klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
+          khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+          kb = M.isbox[k];
+          keep = box_overlap(plo, phi, klo, khi);
         }
       }
-      keep = keep && box_overlap(plo, phi, klo, khi);
-      unsigned long long bm = __ballot(keep);
+      const unsigned long long bm = __ballot(keep) & gmask;
       if (keep) {
-        int pos = ncand + __popcll(bm & ((1ull << lane) - 1ull));
+        const int pos = ncand + __popcll(bm & lbelow);
         if (pos < kPrepCand) {
-          S.cand[pos] = kj;
+          S.cand[pos] = k;
           S.clox[pos] = klo.x; S.cloy[pos] = klo.y; S.cloz[pos] = klo.z;
           S.chix[pos] = khi.x; S.chiy[pos] = khi.y; S.chiz[pos] = khi.z;
-          S.cbox[pos] = kbox;
+          S.cbox[pos] = kb;
         }
       }
       ncand += __popcll(bm);
     }
     wave_lds_sync();
     if (ncand > kPrepCand) {
-      if (lane == 0) {
+      if (sub == 0) {
         M.item_cnt[it] = -1;
         M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
       }
@@ -842,35 +889,52 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     const int T3 = 3 * I;
     const int total = ncand * T3;
     if (total <= kFluxLanes) {
-      // one round: the tests stay in registers between counting and writing
-      unsigned tm = 0;
-      int kc = 0;
-      const bool kp = lane < total && pair_test(S, c, I, T3, lane, tm, kc);
-      const unsigned long long bm = __ballot(kp);
+      // up to NR rounds: the tests stay in registers between counting and writing
+      bool kp[NR];
+      unsigned tmq[NR];
+      int kcq[NR];
+      unsigned long long bmq[NR];
+      int count = 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int q = sub + G * r;
+        tmq[r] = 0;
+        kcq[r] = 0;
+        kp[r] = q < total && pair_test(S, c, I, T3, q, tmq[r], kcq[r]);
+        bmq[r] = __ballot(kp[r]) & gmask;
+        count += __popcll(bmq[r]);
+      }
       int base = 0;
-      if (lane == 0) base = reserve_pairs(M, it, f, __popcll(bm));
-      base = __shfl(base, 0);
-      if (base >= 0 && kp) write_pair(M, base + __popcll(bm & ((1ull << lane) - 1ull)), it, S.cand[kc], tm);
+      if (sub == 0) base = reserve_pairs(M, it, f, count);
+      base = __shfl(base, gbase);
+      if (base >= 0) {
+        int written = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (kp[r]) write_pair(M, base + written + __popcll(bmq[r] & lbelow), it, S.cand[kcq[r]], tmq[r]);
+          written += __popcll(bmq[r]);
+        }
+      }
     } else {
       // pass 0 counts, pass 1 writes into the reserved range
       int count = 0;
-      for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
+      for (int q0 = 0; q0 < total; q0 += G) {
         unsigned tm;
         int kc;
-        const bool kp = q0 + lane < total && pair_test(S, c, I, T3, q0 + lane, tm, kc);
-        count += __popcll(__ballot(kp));
+        const bool kp = q0 + sub < total && pair_test(S, c, I, T3, q0 + sub, tm, kc);
+        count += __popcll(__ballot(kp) & gmask);
       }
       int base = 0;
-      if (lane == 0) base = reserve_pairs(M, it, f, count);
-      base = __shfl(base, 0);
+      if (sub == 0) base = reserve_pairs(M, it, f, count);
+      base = __shfl(base, gbase);
       if (base >= 0) {
         int written = 0;
-        for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
+        for (int q0 = 0; q0 < total; q0 += G) {
           unsigned tm = 0;
           int kc = 0;
-          const bool kp = q0 + lane < total && pair_test(S, c, I, T3, q0 + lane, tm, kc);
-          const unsigned long long bm = __ballot(kp);
-          if (kp) write_pair(M, base + written + __popcll(bm & ((1ull << lane) - 1ull)), it, S.cand[kc], tm);
+          const bool kp = q0 + sub < total && pair_test(S, c, I, T3, q0 + sub, tm, kc);
+          const unsigned long long bm = __ballot(kp) & gmask;
+          if (kp) write_pair(M, base + written + __popcll(bm & lbelow), it, S.cand[kc], tm);
           written += __popcll(bm);
         }
       }
@@ -1771,7 +1835,8 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   const int pair_grid = kItemRegions * L.pair_blocks_per_region;
   if (reset) k_reset_advect<<<1, 256, 0, s>>>(M);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
-  TIMED(K_FLUX_PREP, (k_flux_prep<<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
+  if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
+  else TIMED(K_FLUX_PREP, (k_flux_prep<64><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
   if (!M.all_box) {
     if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));

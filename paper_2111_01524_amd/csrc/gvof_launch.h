@@ -14,11 +14,11 @@ struct Prof {
 };
 // Launch shapes (none changes any result): block size of the vertex / face /
 // cell sweeps, block size of the reconstruction, grid of the staging kernel
-// (one wavefront per face), blocks per pair-buffer region of the pair and unit
-// kernels, lanes per pair of the general-cell filter, and the most faces and
+// (one wavefront per block), blocks per pair-buffer region of the pair and unit
+// kernels, lanes per pair of the general-cell filter, the most faces and
 // (face, cell, flux tet) pairs staged per step (0: as many as the workspace
 // holds; what does not fit goes to the overflow and deferred kernels, which
-// give the same values).
+// give the same values), and lanes per face of the staging kernel.
 struct LaunchCfg {
   int sweep_threads = 256;
   int recon_threads = 128;
@@ -27,6 +27,7 @@ struct LaunchCfg {
   int filter_lanes = 32;
   int staged_faces = 0;
   int staged_pairs = 0;
+  int prep_lanes = 64;
 };
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
