@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
+    ap.add_argument("--launch-config", default=None,
+                    help="JSON object of launch-shape fields to set instead of autotuning (others keep their defaults)")
     ap.add_argument("--batch", type=int, default=0,
                     help="also run the batched workload with this many problems (256 = the full batch)")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -118,7 +120,11 @@ def main():
     uvd = torch.from_numpy(uv).to(dev)
     F0 = g.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
     tuned = None
-    if not args.no_autotune:
+    if args.launch_config:
+        d = gvof.gvof_get_launch_config(g.h).as_dict()
+        d.update(json.loads(args.launch_config))
+        gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**d))
+    elif not args.no_autotune:
         # launch shapes measured on the first step of the trajectory (F0 is left as it is)
         dt0 = torch.tensor([dteff[0]], dtype=torch.float64, device=dev)
         act0 = torch.ones(1, dtype=torch.uint8, device=dev)
