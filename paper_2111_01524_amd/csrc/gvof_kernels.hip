@@ -966,34 +966,81 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
   return min(min(M.item_fill[r], M.item_okend[r]), rsize);
 }
 
-// Box-cell pairs, one lane per pair.
-__global__ __launch_bounds__(256) void k_flux_items_box(DevMesh M) {
+// Box-cell pairs, one lane per pair.  A pair's work grows with the number of
+// box planes cutting its tetrahedron (up to 9 leaves for two), and a
+// wavefront runs as long as its slowest lane, so each block first ranks its
+// 256 pairs by that number in LDS (a counting sort: two cuts, then one, then
+// none) and each thread then clips the pair at its rank: most wavefronts see
+// pairs of one kind.  Each pair's volume goes to its own slot, so the order
+// changes no result.
+constexpr int kItemsBlock = 256;
+__global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
+  __shared__ int s_list[kItemsBlock];
+  __shared__ int s_off[kItemsBlock / 64][kMaxRegCuts + 1];
+  __shared__ int s_n;
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
   const int fill = region_items(M, r, rsize);
-  for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += region_blocks() * blockDim.x) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // every thread of a block makes the same number of passes (block barriers)
+  for (int b = sub * kItemsBlock; b < fill; b += region_blocks() * kItemsBlock) {
+    const int li = b + threadIdx.x;
+    int cls = -1;  // cutting planes, or -1: nothing for the register clip
     const int i = r * rsize + li;
-    int k = M.item_cell[i];
-    if (!M.isbox[k]) continue;
-    unsigned tm = M.item_tm[i];
-    unsigned mask = tm >> 5;
-    if (cut_count(mask) > kMaxRegCuts) {  // more cutting planes than the register path takes: defer
-      M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
-      continue;
+    if (li < fill) {
+      const int k = M.item_cell[i];
+      if (M.isbox[k]) {
+        const int nc = cut_count((unsigned)M.item_tm[i] >> 5);
+        if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
+        else cls = nc;
+      }
     }
-    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
-    double sT = tet6(T);
-    double v = 0.0;
-    if (sT != 0.0) {
-      Leaf leaf;
-      leaf.useH = M.tag_cell[k] == 0;
-      leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
-      leaf.hd = M.pC[k];
-      BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-      v = clip_masked(T, B, mask, leaf);
-      if (sT < 0.0) v = -v;
+    unsigned long long bm[kMaxRegCuts + 1];
+#pragma unroll
+    for (int c = 0; c <= kMaxRegCuts; ++c) bm[c] = __ballot(cls == c);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c <= kMaxRegCuts; ++c) s_off[w][c] = __popcll(bm[c]);
     }
-    M.item_vol[i] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int c = kMaxRegCuts; c >= 0; --c)
+        for (int v = 0; v < kItemsBlock / 64; ++v) {
+          const int n = s_off[v][c];
+          s_off[v][c] = t;
+          t += n;
+        }
+      s_n = t;
+    }
+    __syncthreads();
+    if (cls >= 0) {
+      unsigned long long m = bm[0];
+#pragma unroll
+      for (int c = 1; c <= kMaxRegCuts; ++c) m = cls == c ? bm[c] : m;
+      s_list[s_off[w][cls] + __popcll(m & below)] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x < s_n) {
+      const int ip = s_list[threadIdx.x];
+      const int k = M.item_cell[ip];
+      const unsigned tm = M.item_tm[ip];
+      const Tet T = staged_tet(M, M.item_slot[ip], tm & 31);
+      const double sT = tet6(T);
+      double v = 0.0;
+      if (sT != 0.0) {
+        Leaf leaf;
+        leaf.useH = M.tag_cell[k] == 0;
+        leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+        leaf.hd = M.pC[k];
+        BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
+        v = clip_masked(T, B, tm >> 5, leaf);
+        if (sT < 0.0) v = -v;
+      }
+      M.item_vol[ip] = v;
+    }
+    __syncthreads();  // s_list and s_off are reused by the next pass
   }
 }
 
@@ -1837,7 +1884,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
   if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
   else TIMED(K_FLUX_PREP, (k_flux_prep<64><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
-  if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, 256, 0, s>>>(M)));
+  if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, kItemsBlock, 0, s>>>(M)));
   if (!M.all_box) {
     if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
