@@ -679,9 +679,14 @@ __device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int
   return M.nb_idx[nbb + j - on - 2];
 }
 
+// Pair word tm: bits 0-4 the flux tet, 5-10 the mask of the box planes that
+// cut it, bit 11 set when the first of those cuts keeps three tetrahedra.
+constexpr int kTmWideBit = 11;
+__device__ inline unsigned tm_mask(unsigned tm) { return (tm >> 5) & 63u; }
+
 // Test of staged candidate kc against flux tet t: the tet's box meets the
 // cell's box and, for a box cell, the tet is not entirely outside one box
-// plane.  tm packs t and the mask of the box planes that cut the tet.
+// plane.
 __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, unsigned& tm, int& kc) {
   const int t = q % T3;
   kc = q / T3;
@@ -694,6 +699,13 @@ __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, u
   unsigned mask = 0;
   if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
   tm = (unsigned)t | (mask << 5);
+  if (mask) {
+    // the first cut keeps three tetrahedra (two or more vertices inside) or one:
+    // a hint for grouping pairs of like work in the truncation kernel
+    const Plane P = B.plane(__builtin_ctz(mask));
+    const int inside = (P.dist(T.p0) > 0.0) + (P.dist(T.p1) > 0.0) + (P.dist(T.p2) > 0.0) + (P.dist(T.p3) > 0.0);
+    tm |= (inside >= 2 ? 1u : 0u) << kTmWideBit;
+  }
   return keep;
 }
 
@@ -967,16 +979,17 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
 }
 
 // Box-cell pairs, one lane per pair.  A pair's work grows with the number of
-// box planes cutting its tetrahedron (up to 9 leaves for two), and a
-// wavefront runs as long as its slowest lane, so each block first ranks its
-// 256 pairs by that number in LDS (a counting sort: two cuts, then one, then
-// none) and each thread then clips the pair at its rank: most wavefronts see
-// pairs of one kind.  Each pair's volume goes to its own slot, so the order
-// changes no result.
+// box planes cutting its tetrahedron (up to 9 leaves for two) and with the
+// children of the first cut (one or three), and a wavefront runs as long as
+// its slowest lane, so each block first ranks its 256 pairs by that work in
+// LDS (a counting sort, most work first) and each thread then clips the pair
+// at its rank: most wavefronts see pairs of one kind.  Each pair's volume
+// goes to its own slot, so the order changes no result.
 constexpr int kItemsBlock = 256;
 __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
   __shared__ int s_list[kItemsBlock];
-  __shared__ int s_off[kItemsBlock / 64][kMaxRegCuts + 1];
+  constexpr int NCLS = 2 * kMaxRegCuts + 1;  // none; then per cut count, first cut keeping one or three
+  __shared__ int s_off[kItemsBlock / 64][NCLS];
   __shared__ int s_n;
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
@@ -986,27 +999,28 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
   // every thread of a block makes the same number of passes (block barriers)
   for (int b = sub * kItemsBlock; b < fill; b += region_blocks() * kItemsBlock) {
     const int li = b + threadIdx.x;
-    int cls = -1;  // cutting planes, or -1: nothing for the register clip
+    int cls = -1;  // work class (more work, higher), or -1: nothing for the register clip
     const int i = r * rsize + li;
     if (li < fill) {
       const int k = M.item_cell[i];
       if (M.isbox[k]) {
-        const int nc = cut_count((unsigned)M.item_tm[i] >> 5);
+        const unsigned tm = M.item_tm[i];
+        const int nc = cut_count(tm_mask(tm));
         if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
-        else cls = nc;
+        else cls = nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u);
       }
     }
-    unsigned long long bm[kMaxRegCuts + 1];
+    unsigned long long bm[NCLS];
 #pragma unroll
-    for (int c = 0; c <= kMaxRegCuts; ++c) bm[c] = __ballot(cls == c);
+    for (int c = 0; c < NCLS; ++c) bm[c] = __ballot(cls == c);
     if (lane == 0) {
 #pragma unroll
-      for (int c = 0; c <= kMaxRegCuts; ++c) s_off[w][c] = __popcll(bm[c]);
+      for (int c = 0; c < NCLS; ++c) s_off[w][c] = __popcll(bm[c]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int t = 0;
-      for (int c = kMaxRegCuts; c >= 0; --c)
+      for (int c = NCLS - 1; c >= 0; --c)
         for (int v = 0; v < kItemsBlock / 64; ++v) {
           const int n = s_off[v][c];
           s_off[v][c] = t;
@@ -1018,7 +1032,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
     if (cls >= 0) {
       unsigned long long m = bm[0];
 #pragma unroll
-      for (int c = 1; c <= kMaxRegCuts; ++c) m = cls == c ? bm[c] : m;
+      for (int c = 1; c < NCLS; ++c) m = cls == c ? bm[c] : m;
       s_list[s_off[w][cls] + __popcll(m & below)] = i;
     }
     __syncthreads();
@@ -1035,7 +1049,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
         leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
         leaf.hd = M.pC[k];
         BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-        v = clip_masked(T, B, tm >> 5, leaf);
+        v = clip_masked(T, B, tm_mask(tm), leaf);
         if (sT < 0.0) v = -v;
       }
       M.item_vol[ip] = v;
@@ -1376,7 +1390,7 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
     double v = 0.0;
     if (M.isbox[k]) {
       const BoxCont B{mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k])};
-      const unsigned mask = tm >> 5;
+      const unsigned mask = tm_mask(tm);
       const int nc = cut_count(mask);
       if (nc == 3 || nc == 4) v = box_pair_volume_group(T, B, mask, nc, leaf, sub, gbase);
       else if (sub == 0) v = box_pair_volume(M, T, B, mask, leaf);
