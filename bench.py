@@ -131,7 +131,7 @@ def main():
         # launch shapes measured on the first step of the trajectory (F0 is left as it is)
         dt0 = torch.tensor([dteff[0]], dtype=torch.float64, device=dev)
         act0 = torch.ones(1, dtype=torch.uint8, device=dev)
-        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dt0, act0, F0, torch.empty_like(F0), 3)
+        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dt0, act0, F0, torch.empty_like(F0), 20)
         tuned = cfg.as_dict()
     torch.cuda.synchronize()
     state = {"s": 0}

@@ -952,7 +952,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
 const char* gvof_kernel_name(int32_t k) {
   static const char* names[gvof::K_COUNT] = {"k_node_tag", "k_face_tag", "k_cell_tag", "k_recon",
                                              "k_face_sweep", "k_flux_items_box", "k_update", "k_flux_prep",
-                                             "k_flux_sum", "k_flux_over", "k_flux_gen_filter",
+                                             "k_flux_sum", "(unused)", "k_flux_gen_filter",
                                              "k_flux_deep", "k_flux_gen_units", "k_flux_gen_sum",
                                              "k_flux_gen_units_deep"};
   return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";

@@ -1401,8 +1401,8 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
   }
 }
 
-// Per staged face: V_F = sum of its pairs in their fixed order.
-__global__ void k_flux_sum(DevMesh M) {
+// Per staged face: V_F = sum of its pairs in their fixed order (grid-strided).
+__device__ inline void staged_face_sums(const DevMesh& M) {
   int n = min(M.counters[CNT_FACES], M.poly_cap);
   for (int it = grid_stride_start(); it < n; it += grid_stride()) {
     const int cnt = M.item_cnt[it], off = M.item_off[it], f = M.list_faces[it];
@@ -1475,8 +1475,13 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
   }
 }
 
-__global__ __launch_bounds__(kFluxLanes) void k_flux_over(DevMesh M, const double* __restrict__ uv, double dt) {
+// The end of the flux stage in one launch of kFluxLanes-thread blocks: V_F of
+// the staged faces (grid-strided, a thread per face), then of the faces that
+// went to the overflow path (a block per face).  Neither reads what the other
+// writes.
+__global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double* __restrict__ uv, double dt) {
   __shared__ FluxLds S;
+  staged_face_sums(M);
   overflow_faces(M, S, uv, dt);
 }
 
@@ -1909,8 +1914,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
     TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }
   TIMED(K_FLUX_DEEP, (k_flux_deep<<<1024, 64, 0, s>>>(M)));
-  TIMED(K_FLUX_SUM, (k_flux_sum<<<blocks_for(M.poly_cap, 256, 1024), 256, 0, s>>>(M)));
-  TIMED(K_FLUX_OVER, (k_flux_over<<<blocks_for(M.nf, 1, 512), kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX_SUM, (k_flux_sum<<<1024, kFluxLanes, 0, s>>>(M, uv, dt)));
   TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, st), st, 0, s>>>(M, Fin, Fout)));
   return hipGetLastError();
 }
