@@ -128,11 +128,19 @@ def main():
         d.update(json.loads(args.launch_config))
         gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**d))
     elif not args.no_autotune:
-        # launch shapes measured on the first step of the trajectory (F0 is left as it is)
-        dt0 = torch.tensor([dteff[0]], dtype=torch.float64, device=dev)
+        # launch shapes measured at the middle of the trajectory, where the
+        # interface is most stretched (the timed steps restart from F0)
+        s_mid = len(sched) // 2
+        Fm, Fn = F0.clone(), torch.empty_like(F0)
+        for s in range(s_mid):
+            g.reconstruct(Fm)
+            g.advect_step(ufd, uvd, dteff[s], Fm, Fn)
+            Fm, Fn = Fn, Fm
+        dtm = torch.tensor([dteff[s_mid]], dtype=torch.float64, device=dev)
         act0 = torch.ones(1, dtype=torch.uint8, device=dev)
-        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dt0, act0, F0, torch.empty_like(F0), 20)
+        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dtm, act0, Fm, Fn, 20)
         tuned = cfg.as_dict()
+        del Fm, Fn
     torch.cuda.synchronize()
     state = {"s": 0}
 

@@ -283,7 +283,8 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c);
 /*
  * Chooses the launch shapes for this mesh and these inputs by measurement:
  * coordinate descent over the values of each field, every candidate timed
- * with HIP events over `reps` batched steps (1..1000) from the same state.
+ * twice with HIP events over `reps` batched steps (1..1000) from the same
+ * state, the smaller time counting (after one untimed warm-up timing).
  * F (device, nc) is saved into F_save (device, nc, caller scratch) first and
  * restored at the end, so F is unchanged on return.  Sets the handle's launch
  * shapes to the best found and reports them and their time per step (either

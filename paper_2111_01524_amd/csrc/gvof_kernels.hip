@@ -979,16 +979,21 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
 }
 
 // Box-cell pairs, one lane per pair.  A pair's work grows with the number of
-// box planes cutting its tetrahedron (up to 9 leaves for two) and with the
-// children of the first cut (one or three), and a wavefront runs as long as
-// its slowest lane, so each block first ranks its 256 pairs by that work in
-// LDS (a counting sort, most work first) and each thread then clips the pair
-// at its rank: most wavefronts see pairs of one kind.  Each pair's volume
-// goes to its own slot, so the order changes no result.
+// box planes cutting its tetrahedron (up to 9 leaves for two), with the
+// children of the first cut (one or three) and with whether the cell's
+// interface cuts the leaves, and a wavefront runs as long as its slowest
+// lane (and runs every path one of its lanes takes), so each block first
+// ranks its 256 pairs by that work in LDS (a counting sort, most work first)
+// and each thread then clips the pair at its rank: most wavefronts see pairs
+// of one kind.  Each pair's volume goes to its own slot, so the order changes
+// no result.
 constexpr int kItemsBlock = 256;
 __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
   __shared__ int s_list[kItemsBlock];
-  constexpr int NCLS = 2 * kMaxRegCuts + 1;  // none; then per cut count, first cut keeping one or three
+  // classes: 2 x (none; then per cut count, first cut keeping one or three),
+  // the factor 2 for cells cut by their interface (the leaves then take the
+  // half-space fraction) or not
+  constexpr int NCLS = 2 * (2 * kMaxRegCuts + 1);
   __shared__ int s_off[kItemsBlock / 64][NCLS];
   __shared__ int s_n;
   const int rsize = M.item_cap / kItemRegions;
@@ -1003,11 +1008,12 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
     const int i = r * rsize + li;
     if (li < fill) {
       const int k = M.item_cell[i];
+      const int8_t tg = M.tag_cell[k];
       if (M.isbox[k]) {
         const unsigned tm = M.item_tm[i];
         const int nc = cut_count(tm_mask(tm));
         if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
-        else cls = nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u);
+        else cls = 2 * (nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u)) + (tg == 0 ? 1 : 0);
       }
     }
     unsigned long long bm[NCLS];
