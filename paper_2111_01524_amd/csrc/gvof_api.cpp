@@ -360,7 +360,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   {
     int maxI = 3;
     for (size_t f = 0; f < nf; ++f) maxI = std::max(maxI, m->fv_ptr[f + 1] - m->fv_ptr[f]);
-    d.pts_per_slot = 2 * maxI + 1;
+    d.pts_per_slot = 2 * maxI + 2;  // polyhedron points, then the face centre
     d.poly_cap = (int)std::min<size_t>(nf, std::max<size_t>(65536, nf / 4));
     d.item_cap = (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 4 * nf));
     d.item_cap -= d.item_cap % gvof::kItemRegions;

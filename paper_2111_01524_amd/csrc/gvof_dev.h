@@ -40,7 +40,7 @@ struct DevMesh {
   int* upwind;
   int *list_cells, *list_faces;
   // flux work staging: polyhedron points per listed face, (face, cell, tet) pairs
-  double* poly;        // [slot][pts_per_slot][3]
+  double* poly;        // [slot][pts_per_slot][3]: x_0..x_{I-1}, b_0..b_{I-1}, apex, face centre
   int pts_per_slot, poly_cap;
   int *item_off, *item_cnt;   // per slot (cnt = -1: face handled by the overflow kernel)
   int *item_slot, *item_cell;  // per pair

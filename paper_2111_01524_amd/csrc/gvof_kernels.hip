@@ -680,9 +680,11 @@ __device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int
 }
 
 // Pair word tm: bits 0-4 the flux tet, 5-10 the mask of the box planes that
-// cut it, bit 11 set when the first of those cuts keeps three tetrahedra.
+// cut it, bit 11 set when the first of those cuts keeps three tetrahedra,
+// 12-15 the face's vertex count.
 constexpr int kTmWideBit = 11;
 __device__ inline unsigned tm_mask(unsigned tm) { return (tm >> 5) & 63u; }
+__device__ inline int tm_verts(unsigned tm) { return (int)((tm >> 12) & 15u); }
 
 // Test of staged candidate kc against flux tet t: the tet's box meets the
 // cell's box and, for a box cell, the tet is not entirely outside one box
@@ -698,7 +700,7 @@ __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, u
   bool keep = box_overlap(tlo, thi, B.lo, B.hi);
   unsigned mask = 0;
   if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
-  tm = (unsigned)t | (mask << 5);
+  tm = (unsigned)t | (mask << 5) | ((unsigned)I << 12);
   if (mask) {
     // the first cut keeps three tetrahedra (two or more vertices inside) or one:
     // a hint for grouping pairs of like work in the truncation kernel
@@ -832,10 +834,14 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
-    if (sub <= 2 * I) {
+    if (sub <= 2 * I) {  // the points, then the face centre (the flux tets' common vertex)
       P[3 * sub] = S.px[sub];
       P[3 * sub + 1] = S.py[sub];
       P[3 * sub + 2] = S.pz[sub];
+    } else if (sub == 2 * I + 1) {
+      P[3 * sub] = c.x;
+      P[3 * sub + 1] = c.y;
+      P[3 * sub + 2] = c.z;
     }
     // candidates: cells that hold fluid, not listed before (a cell of the
     // neighbour's list that is the owner or on the owner's list) and whose
@@ -958,13 +964,15 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
 // One lane per staged pair: signed fluid volume of (flux tet ∩ cell).  Two
 // instances, one for box cells and one for general cells, each skipping the
 // other kind, so each carries only its own registers.
-__device__ inline Tet staged_tet(const DevMesh& M, int slot, int t) {
-  int f = M.list_faces[slot];
-  int I = M.fv_ptr[f + 1] - M.fv_ptr[f];
+// Flux tet of a staged pair from its pair word alone: the tet and the face's
+// vertex count are in the word, the points and the face centre in the slot.
+__device__ inline Tet staged_tet(const DevMesh& M, int slot, unsigned tm) {
+  const int t = tm & 31, I = tm_verts(tm);
   const double* P = M.poly + (size_t)slot * M.pts_per_slot * 3;
   int i1, i2, i3;
   flux_tet_points(t, I, i1, i2, i3);
-  return Tet{mk3(M.fcx[f], M.fcy[f], M.fcz[f]), mk3(P[3 * i1], P[3 * i1 + 1], P[3 * i1 + 2]),
+  const int ic = 2 * I + 1;
+  return Tet{mk3(P[3 * ic], P[3 * ic + 1], P[3 * ic + 2]), mk3(P[3 * i1], P[3 * i1 + 1], P[3 * i1 + 2]),
              mk3(P[3 * i2], P[3 * i2 + 1], P[3 * i2 + 2]), mk3(P[3 * i3], P[3 * i3 + 1], P[3 * i3 + 2])};
 }
 
@@ -989,7 +997,8 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
 // no result.
 constexpr int kItemsBlock = 256;
 __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
-  __shared__ int s_list[kItemsBlock];
+  __shared__ int s_list[kItemsBlock], s_cell[kItemsBlock], s_slot[kItemsBlock];
+  __shared__ unsigned short s_tm[kItemsBlock];
   // classes: 2 x (none; then per cut count, first cut keeping one or three),
   // the factor 2 for cells cut by their interface (the leaves then take the
   // half-space fraction) or not
@@ -1006,11 +1015,14 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
     const int li = b + threadIdx.x;
     int cls = -1;  // work class (more work, higher), or -1: nothing for the register clip
     const int i = r * rsize + li;
+    int k = 0, slot = 0;
+    unsigned tm = 0;
     if (li < fill) {
-      const int k = M.item_cell[i];
+      k = M.item_cell[i];
+      tm = M.item_tm[i];
+      slot = M.item_slot[i];
       const int8_t tg = M.tag_cell[k];
       if (M.isbox[k]) {
-        const unsigned tm = M.item_tm[i];
         const int nc = cut_count(tm_mask(tm));
         if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
         else cls = 2 * (nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u)) + (tg == 0 ? 1 : 0);
@@ -1039,14 +1051,18 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
       unsigned long long m = bm[0];
 #pragma unroll
       for (int c = 1; c < NCLS; ++c) m = cls == c ? bm[c] : m;
-      s_list[s_off[w][cls] + __popcll(m & below)] = i;
+      const int pos = s_off[w][cls] + __popcll(m & below);
+      s_list[pos] = i;  // the pair and what the clip needs of it first
+      s_cell[pos] = k;
+      s_slot[pos] = slot;
+      s_tm[pos] = (unsigned short)tm;
     }
     __syncthreads();
     if (threadIdx.x < s_n) {
       const int ip = s_list[threadIdx.x];
-      const int k = M.item_cell[ip];
-      const unsigned tm = M.item_tm[ip];
-      const Tet T = staged_tet(M, M.item_slot[ip], tm & 31);
+      const int k = s_cell[threadIdx.x];
+      const unsigned tm = s_tm[threadIdx.x];
+      const Tet T = staged_tet(M, s_slot[threadIdx.x], tm);
       const double sT = tet6(T);
       double v = 0.0;
       if (sT != 0.0) {
@@ -1121,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     const int k = M.item_cell[i];
     if (M.isbox[k]) continue;
     unsigned tm = M.item_tm[i];
-    Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+    Tet T = staged_tet(M, M.item_slot[i], tm);
     const d3 cc = cell_centre(M, k);
     d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
     const int np = cell_piece_count(M, k);
@@ -1228,7 +1244,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
     const int p = code & 0xffff;
     const unsigned cm = code >> 16;
     const int k = M.item_cell[i];
-    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
     const d3 cc = cell_centre(M, k);
     const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
     d3 t0, t1, t2;
@@ -1258,7 +1274,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
     const int i = M.unit_item[u];
     const unsigned code = M.unit_code[u];
     const int k = M.item_cell[i];
-    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
     const d3 cc = cell_centre(M, k);
     const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
     d3 t0, t1, t2;
@@ -1288,7 +1304,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
     const double* v = M.unit_vol + M.item_uoff[i];
     double acc = 0.0;
     for (int q = 0; q < cnt; ++q) acc += v[q];
-    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i] & 31);
+    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
     M.item_vol[i] = tet6(T) < 0.0 ? -acc : acc;
   }
 }
@@ -1388,7 +1404,7 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
     const int i = M.list_deep[j];
     const int k = M.item_cell[i];
     const unsigned tm = M.item_tm[i];
-    const Tet T = staged_tet(M, M.item_slot[i], tm & 31);
+    const Tet T = staged_tet(M, M.item_slot[i], tm);
     Leaf leaf;
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
