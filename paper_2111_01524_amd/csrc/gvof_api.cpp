@@ -374,15 +374,12 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.item_vol = C.take<double>(d.item_cap);
   d.list_over = C.take<int>(nf);
   d.list_deep = C.take<int>(d.item_cap);
-  d.item_fill = C.take<int>(gvof::kItemRegions);
-  d.item_okend = C.take<int>(gvof::kItemRegions);
+  d.regions = C.take<gvof::RegionCounters>(gvof::kItemRegions);
   d.item_uoff = C.take<int>(d.item_cap);
   d.item_ucnt = C.take<int>(d.item_cap);
   d.unit_item = C.take<int>(d.item_cap);
   d.unit_code = C.take<unsigned>(d.item_cap);
   d.unit_vol = C.take<double>(d.item_cap);
-  d.unit_fill = C.take<int>(gvof::kItemRegions);
-  d.unit_okend = C.take<int>(gvof::kItemRegions);
   d.list_udeep = C.take<int>(d.item_cap);
   d.counters = C.take<int>(gvof::CNT_N);
   d.totals = C.take<unsigned long long>(4);

@@ -13,6 +13,15 @@
 
 namespace gvof {
 
+// Counters of one region of the pair and unit buffers: fill counters and
+// the start of the first reservation that did not fit (INT_MAX: none).
+// Faces and pairs reserve their ranges with device-wide atomics on these;
+// one cache line per region keeps atomics of different regions apart
+// (atomics on one line are serialised).
+struct alignas(128) RegionCounters {
+  int item_fill, item_okend, unit_fill, unit_okend;
+};
+
 struct DevMesh {
   int nv, nf, nc;
   // vertices, faces, connectivity (uploaded once)
@@ -44,18 +53,15 @@ struct DevMesh {
   int pts_per_slot, poly_cap;
   int *item_off, *item_cnt;   // per slot (cnt = -1: face handled by the overflow kernel)
   int *item_slot, *item_cell;  // per pair
-  unsigned short* item_tm;     // per pair: tet index (5 bits) | box cut mask << 5
+  unsigned short* item_tm;     // per pair: tet index, box cut mask, first-cut width, face vertex count
   double* item_vol;
   int item_cap;
-  int* item_fill;              // fill counter of each of kItemRegions regions of the pair buffer
-  int* item_okend;             // per region: start of the first reservation that did not fit (INT_MAX: none)
+  struct RegionCounters* regions;  // kItemRegions, one cache line each
   // general-cell pairs: surviving (pair, surface tetrahedron) units
   int *item_uoff, *item_ucnt;  // per pair
   int* unit_item;
   unsigned* unit_code;         // surface tetrahedron index | cutting-plane mask << 16
   double* unit_vol;
-  int* unit_fill;              // per region
-  int* unit_okend;             // per region, as item_okend
   int* list_udeep;             // units with four cutting planes
   int* list_over;              // faces not staged (capacity exceeded)
   int* list_deep;              // pairs cut by more planes than the register clip takes

@@ -204,10 +204,10 @@ __device__ inline void reset_advect_state(const DevMesh& M) {
     M.counters[CNT_UDEEP] = 0;
   }
   for (int r = threadIdx.x; r < kItemRegions; r += blockDim.x) {
-    M.item_fill[r] = 0;
-    M.unit_fill[r] = 0;
-    M.item_okend[r] = INT_MAX;
-    M.unit_okend[r] = INT_MAX;
+    M.regions[r].item_fill = 0;
+    M.regions[r].unit_fill = 0;
+    M.regions[r].item_okend = INT_MAX;
+    M.regions[r].unit_okend = INT_MAX;
   }
 }
 
@@ -317,7 +317,7 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
         M.pC[c] = 0.0;
       }
     }
-    block_append(inter, c, &M.counters[CNT_CELLS], M.list_cells, &M.totals[0]);
+    block_append(inter, c, &M.counters[CNT_CELLS], M.list_cells, nullptr);  // counted once by k_recon
   }
 }
 
@@ -384,7 +384,7 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
       else if (t == 1) M.VF[f] = vd;
       else geo = true;
     }
-    block_append(geo, f, &M.counters[CNT_FACES], M.list_faces, &M.totals[1]);
+    block_append(geo, f, &M.counters[CNT_FACES], M.list_faces, nullptr);  // counted once per step by k_flux_sum
   }
 }
 
@@ -717,11 +717,11 @@ __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, u
 __device__ inline int reserve_pairs(const DevMesh& M, int it, int f, int count) {
   const int r = it % kItemRegions;
   const int rsize = M.item_cap / kItemRegions;
-  int base = atomicAdd(&M.item_fill[r], count);
+  int base = atomicAdd(&M.regions[r].item_fill, count);
   if (base + count > rsize) {
     // every reservation before this one in atomic order fitted and every
     // later one fails: the region's written part is [0, smallest failed base)
-    atomicMin(&M.item_okend[r], base);
+    atomicMin(&M.regions[r].item_okend, base);
     M.item_cnt[it] = -1;
     M.list_over[atomicAdd(&M.counters[CNT_OVER], 1)] = f;
     return -1;
@@ -983,7 +983,7 @@ __device__ inline int region_blocks() { return gridDim.x / kItemRegions; }
 // Written pairs of region r: reservations that did not fit leave the fill
 // counter past what was written, so the count stops at the first of them.
 __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
-  return min(min(M.item_fill[r], M.item_okend[r]), rsize);
+  return min(min(M.regions[r].item_fill, M.regions[r].item_okend), rsize);
 }
 
 // Box-cell pairs, one lane per pair.  A pair's work grows with the number of
@@ -1159,9 +1159,9 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     auto reserve = [&](int count) -> int {
       int b = 0;
       if (hl == 0) {
-        b = atomicAdd(&M.unit_fill[r], count);
+        b = atomicAdd(&M.regions[r].unit_fill, count);
         if (b + count > rsize) {
-          atomicMin(&M.unit_okend[r], b);
+          atomicMin(&M.regions[r].unit_okend, b);
           b = -1;
         } else {
           b += r * rsize;
@@ -1236,7 +1236,7 @@ template <bool DEEP>
 __global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
-  const int fill = min(min(M.unit_fill[r], M.unit_okend[r]), rsize);
+  const int fill = min(min(M.regions[r].unit_fill, M.regions[r].unit_okend), rsize);
   for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += region_blocks() * blockDim.x) {
     const int u = r * rsize + lu;
     const int i = M.unit_item[u];
@@ -1503,6 +1503,7 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
 // writes.
 __global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double* __restrict__ uv, double dt) {
   __shared__ FluxLds S;
+  if (blockIdx.x == 0 && threadIdx.x == 0) M.totals[1] += (unsigned long long)M.counters[CNT_FACES];
   staged_face_sums(M);
   overflow_faces(M, S, uv, dt);
 }
@@ -1543,8 +1544,9 @@ __device__ inline double general_level_volume(const DevMesh& M, int c, d3 n, d3 
 // needs only the eight corner levels (held one per lane of the group, so the
 // instance keeps no per-lane arrays), and !BOX the general cells.
 template <bool BOX>
-__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F) {
+__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F, int count_cells) {
   const int ncell = M.counters[CNT_CELLS];
+  if (count_cells && blockIdx.x == 0 && threadIdx.x == 0) M.totals[0] += (unsigned long long)ncell;
   const double beta = M.beta;
   const bool beta15 = beta == 1.5;
   const int sub = threadIdx.x & (kReconLanes - 1);
@@ -1908,8 +1910,9 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
   TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
   TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
   const int rb = blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096);
-  if (M.any_box) TIMED(K_RECON, (k_recon<true><<<rb, L.recon_threads, 0, s>>>(M, F)));
-  if (!M.all_box) TIMED(K_RECON, (k_recon<false><<<rb, L.recon_threads, 0, s>>>(M, F)));
+  // the first instance launched adds the interfacial cells to the running total
+  if (M.any_box) TIMED(K_RECON, (k_recon<true><<<rb, L.recon_threads, 0, s>>>(M, F, 1)));
+  if (!M.all_box) TIMED(K_RECON, (k_recon<false><<<rb, L.recon_threads, 0, s>>>(M, F, M.any_box ? 0 : 1)));
   return hipGetLastError();
 }
 
