@@ -75,6 +75,7 @@ struct gvof_mesh {
   std::vector<int> cf_ptr, cf_idx, cv_ptr, cv_idx, vc_ptr, vc_idx, nb_ptr, nb_idx;
   std::vector<short> cell_np;  // surface triangles per cell
   std::vector<int> tri_off;    // surface-triangle cache offsets (cells bounded by triangles only)
+  int64_t gen_faces = 0;       // faces of cells that are not axis-aligned boxes (the test of the geometry kernel)
   int max_nb = 0;
   // problem partition: problem q owns vertices [voff[q], voff[q+1]), faces
   // [foff[q], foff[q+1]) and cells [coff[q], coff[q+1])
@@ -279,6 +280,42 @@ static void cell_counts(gvof_mesh* m) {
     m->cell_np[c] = (short)np;
     m->tri_off[c + 1] = m->tri_off[c] + (tri_only ? np : 0);
   }
+  // faces of general cells (the box test of the geometry kernel: 8 vertices,
+  // 6 quadrilateral faces, every vertex a corner of the enclosing box)
+  m->gen_faces = 0;
+  for (int c = 0; c < m->nc; ++c) {
+    const int vb = m->cv_ptr[c], vn = m->cv_ptr[c + 1] - vb;
+    const int fb = m->cf_ptr[c], fn = m->cf_ptr[c + 1] - fb;
+    bool box = vn == 8 && fn == 6;
+    for (int i = fb; box && i < fb + fn; ++i) {
+      const int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
+      box = m->fv_ptr[f + 1] - m->fv_ptr[f] == 4;
+    }
+    if (box) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int i = vb; i < vb + vn; ++i) {
+        const int v = m->cv_idx[i];
+        const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], p[a]);
+          hi[a] = std::max(hi[a], p[a]);
+        }
+      }
+      int mask = 0;
+      for (int i = vb; box && i < vb + vn; ++i) {
+        const int v = m->cv_idx[i];
+        const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
+        int bit = 0;
+        for (int a = 0; a < 3; ++a) {
+          if (p[a] != lo[a] && p[a] != hi[a]) box = false;
+          bit |= (p[a] == hi[a] ? 1 : 0) << a;
+        }
+        mask |= 1 << bit;
+      }
+      box = box && mask == 255 && lo[0] < hi[0] && lo[1] < hi[1] && lo[2] < hi[2];
+    }
+    if (!box) m->gen_faces += fn;
+  }
 }
 
 // ------------------------------------------------------------------ workspace layout
@@ -364,6 +401,14 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
     d.poly_cap = (int)std::min<size_t>(nf, std::max<size_t>(65536, nf / 4));
     d.item_cap = (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 4 * nf));
     d.item_cap -= d.item_cap % gvof::kItemRegions;
+    // units: up to about 12 per face of the general cells (6 per cell-face
+    // incidence, each face counting for both of its cells) at the most stretched
+    // interface of the deformation workload (pairs that do not fit are
+    // computed whole by the deferred kernel)
+    d.unit_cap = m->gen_faces == 0
+                     ? gvof::kItemRegions
+                     : (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 6 * (size_t)m->gen_faces));
+    d.unit_cap -= d.unit_cap % gvof::kItemRegions;
   }
   d.poly = C.take<double>((size_t)d.poly_cap * d.pts_per_slot * 3);
   d.item_off = C.take<int>(d.poly_cap);
@@ -377,10 +422,10 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.regions = C.take<gvof::RegionCounters>(gvof::kItemRegions);
   d.item_uoff = C.take<int>(d.item_cap);
   d.item_ucnt = C.take<int>(d.item_cap);
-  d.unit_item = C.take<int>(d.item_cap);
-  d.unit_code = C.take<unsigned>(d.item_cap);
-  d.unit_vol = C.take<double>(d.item_cap);
-  d.list_udeep = C.take<int>(d.item_cap);
+  d.unit_item = C.take<int>(d.unit_cap);
+  d.unit_code = C.take<unsigned>(d.unit_cap);
+  d.unit_vol = C.take<double>(d.unit_cap);
+  d.list_udeep = C.take<int>(d.unit_cap);
   d.counters = C.take<int>(gvof::CNT_N);
   d.totals = C.take<unsigned long long>(4);
   d.nprob = m->nprob;

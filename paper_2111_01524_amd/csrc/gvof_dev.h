@@ -61,6 +61,7 @@ struct DevMesh {
   int *item_uoff, *item_ucnt;  // per pair
   int* unit_item;
   unsigned* unit_code;         // surface tetrahedron index | cutting-plane mask << 16
+  int unit_cap;                // units staged per step at most (kItemRegions regions)
   double* unit_vol;
   int* list_udeep;             // units with four cutting planes
   int* list_over;              // faces not staged (capacity exceeded)

@@ -1125,7 +1125,7 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_
 template <int LPP>
 __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
   static_assert(LPP == 8 || LPP == 16 || LPP == 32 || LPP == 64, "lanes per pair");
-  const int rsize = M.item_cap / kItemRegions;
+  const int rsize = M.item_cap / kItemRegions, ursize = M.unit_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
   const int fill = region_items(M, r, rsize);
   const int hl = threadIdx.x & (LPP - 1), half = threadIdx.x / LPP;
@@ -1160,11 +1160,11 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
       int b = 0;
       if (hl == 0) {
         b = atomicAdd(&M.regions[r].unit_fill, count);
-        if (b + count > rsize) {
+        if (b + count > ursize) {
           atomicMin(&M.regions[r].unit_okend, b);
           b = -1;
         } else {
-          b += r * rsize;
+          b += r * ursize;
         }
       }
       const int base = __shfl(b, glead, 64);
@@ -1234,7 +1234,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 // whichever kernel computes it).
 template <bool DEEP>
 __global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
-  const int rsize = M.item_cap / kItemRegions;
+  const int rsize = M.unit_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
   const int fill = min(min(M.regions[r].unit_fill, M.regions[r].unit_okend), rsize);
   for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += region_blocks() * blockDim.x) {
@@ -1391,6 +1391,47 @@ __device__ inline double box_pair_volume_group(const Tet& T, const BoxCont& B, u
   return sT < 0.0 ? -acc : acc;
 }
 
+// General pair computed by a group of kDeepLanes lanes: lane sub takes the
+// cell's surface pieces sub, sub + kDeepLanes, ...; each piece's signed volume
+// is computed as in the serial sum over the pieces, and the group adds the
+// kept pieces in piece order (the serial sum's order, so the same bits).
+__device__ inline double general_pair_volume_group(const DevMesh& M, int k, d3 cc, const Tet& T, const Leaf& leaf,
+                                                   int sub, int gbase) {
+  const double sT = tet6(T);
+  if (sT == 0.0) return 0.0;
+  const d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+  const int np = cell_piece_count(M, k);
+  const bool tri_only = np == M.cf_ptr[k + 1] - M.cf_ptr[k];
+  double acc = 0.0;
+  for (int p0 = 0; p0 < np; p0 += kDeepLanes) {
+    const int p = p0 + sub;
+    bool kept = false;
+    double val = 0.0;
+    if (p < np) {
+      d3 t0, t1, t2;
+      cell_sigma(M, k, p, tri_only, t0, t1, t2);
+      if (box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)))) {
+        const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+        if (s6 != 0.0) {
+          const TetCont TC = tet_container(cc, t0, t1, t2);
+          unsigned tm;
+          if (cut_mask(T, TC, tm)) {
+            const double v = clip_masked_tet(T, TC, tm, leaf);
+            val = s6 > 0.0 ? v : -v;
+            kept = true;
+          }
+        }
+      }
+    }
+    const int nq = min(kDeepLanes, np - p0);
+    for (int q = 0; q < nq; ++q) {
+      const double vq = __shfl(val, gbase + q);
+      if (__shfl((int)kept, gbase + q)) acc += vq;
+    }
+  }
+  return sT < 0.0 ? -acc : acc;
+}
+
 // Deferred pairs, a group of kDeepLanes lanes per pair: box pairs with more
 // cutting planes than the register clip takes, and general pairs whose units
 // did not fit the unit buffer.
@@ -1416,8 +1457,8 @@ __global__ __launch_bounds__(64) void k_flux_deep(DevMesh M) {
       const int nc = cut_count(mask);
       if (nc == 3 || nc == 4) v = box_pair_volume_group(T, B, mask, nc, leaf, sub, gbase);
       else if (sub == 0) v = box_pair_volume(M, T, B, mask, leaf);
-    } else if (sub == 0) {
-      v = general_pair_volume(M, k, cell_centre(M, k), T, leaf);
+    } else {
+      v = general_pair_volume_group(M, k, cell_centre(M, k), T, leaf, sub, gbase);
     }
     if (sub == 0) M.item_vol[i] = v;
   }
@@ -1922,6 +1963,8 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   if (L.staged_faces > 0 && L.staged_faces < M.poly_cap) M.poly_cap = L.staged_faces;
   if (L.staged_pairs > 0 && L.staged_pairs < M.item_cap)
     M.item_cap = max(kItemRegions, L.staged_pairs - L.staged_pairs % kItemRegions);
+  if (L.staged_pairs > 0 && L.staged_pairs < M.unit_cap)
+    M.unit_cap = max(kItemRegions, L.staged_pairs - L.staged_pairs % kItemRegions);
   const int st = L.sweep_threads;
   const int pair_grid = kItemRegions * L.pair_blocks_per_region;
   if (reset) k_reset_advect<<<1, 256, 0, s>>>(M);
