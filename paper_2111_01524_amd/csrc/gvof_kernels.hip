@@ -1232,38 +1232,84 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 // distorted-grid workload) go to a list for k_flux_gen_units_deep, which runs
 // the same register clip one level deeper (so every unit has one value
 // whichever kernel computes it).
-template <bool DEEP>
-__global__ __launch_bounds__(256) void k_flux_gen_units(DevMesh M) {
+__global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
+  // As in the box-pair kernel, each block ranks its units by their work (the
+  // number of cutting planes, 0..3, and whether the cell's interface cuts the
+  // leaves) before clipping, so that most wavefronts run one kind of unit.
+  constexpr int NCLS = 8;
+  __shared__ int s_unit[kItemsBlock], s_item[kItemsBlock];
+  __shared__ unsigned s_code[kItemsBlock];
+  __shared__ int s_off[kItemsBlock / 64][NCLS];
+  __shared__ int s_n;
   const int rsize = M.unit_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
   const int fill = min(min(M.regions[r].unit_fill, M.regions[r].unit_okend), rsize);
-  for (int lu = sub * blockDim.x + threadIdx.x; lu < fill; lu += region_blocks() * blockDim.x) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // every thread of a block makes the same number of passes (block barriers)
+  for (int b = sub * kItemsBlock; b < fill; b += region_blocks() * kItemsBlock) {
+    const int lu = b + threadIdx.x;
     const int u = r * rsize + lu;
-    const int i = M.unit_item[u];
-    const unsigned code = M.unit_code[u];
-    const int p = code & 0xffff;
-    const unsigned cm = code >> 16;
-    const int k = M.item_cell[i];
-    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
-    const d3 cc = cell_centre(M, k);
-    const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
-    d3 t0, t1, t2;
-    cell_sigma(M, k, p, tri_only, t0, t1, t2);
-    double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-    TetCont TC = tet_container(cc, t0, t1, t2);
-    Leaf leaf;
-    leaf.useH = M.tag_cell[k] == 0;
-    leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
-    leaf.hd = M.pC[k];
-    double v;
-    {
-      if (cut_count(cm) > 3) {  // four cutting planes: the deep instance takes it
-        M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;
-        continue;
-      }
-      v = clip_masked_tet<3, false>(T, TC, cm, leaf);
+    int cls = -1, i = 0;
+    unsigned code = 0;
+    if (lu < fill) {
+      i = M.unit_item[u];
+      code = M.unit_code[u];
+      const int nc = cut_count(code >> 16);
+      const int8_t tg = M.tag_cell[M.item_cell[i]];
+      if (nc > 3) M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;  // four cutting planes: the deep instance
+      else cls = 2 * nc + (tg == 0 ? 1 : 0);
     }
-    M.unit_vol[u] = s6 > 0.0 ? v : -v;
+    unsigned long long bm[NCLS];
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) bm[c] = __ballot(cls == c);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) s_off[w][c] = __popcll(bm[c]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int c = NCLS - 1; c >= 0; --c)
+        for (int v = 0; v < kItemsBlock / 64; ++v) {
+          const int n = s_off[v][c];
+          s_off[v][c] = t;
+          t += n;
+        }
+      s_n = t;
+    }
+    __syncthreads();
+    if (cls >= 0) {
+      unsigned long long m = bm[0];
+#pragma unroll
+      for (int c = 1; c < NCLS; ++c) m = cls == c ? bm[c] : m;
+      const int pos = s_off[w][cls] + __popcll(m & below);
+      s_unit[pos] = u;
+      s_item[pos] = i;
+      s_code[pos] = code;
+    }
+    __syncthreads();
+    if (threadIdx.x < s_n) {
+      const int uu = s_unit[threadIdx.x], ii = s_item[threadIdx.x];
+      const unsigned cd = s_code[threadIdx.x];
+      const int p = cd & 0xffff;
+      const unsigned cm = cd >> 16;
+      const int k = M.item_cell[ii];
+      const Tet T = staged_tet(M, M.item_slot[ii], M.item_tm[ii]);
+      const d3 cc = cell_centre(M, k);
+      const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
+      d3 t0, t1, t2;
+      cell_sigma(M, k, p, tri_only, t0, t1, t2);
+      const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+      const TetCont TC = tet_container(cc, t0, t1, t2);
+      Leaf leaf;
+      leaf.useH = M.tag_cell[k] == 0;
+      leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+      leaf.hd = M.pC[k];
+      const double v = clip_masked_tet<3, false>(T, TC, cm, leaf);
+      M.unit_vol[uu] = s6 > 0.0 ? v : -v;
+    }
+    __syncthreads();  // the lists are reused by the next pass
   }
 }
 
@@ -1977,7 +2023,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));
     else TIMED(K_FLUX_GEN, (k_flux_gen_filter<32><<<pair_grid, 256, 0, s>>>(M)));
-    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<false><<<pair_grid, 256, 0, s>>>(M)));
+    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<<<pair_grid, kItemsBlock, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_UDEEP, (k_flux_gen_units_deep<<<1024, 256, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }
