@@ -60,7 +60,7 @@ struct DevMesh {
   // general-cell pairs: surviving (pair, surface tetrahedron) units
   int *item_uoff, *item_ucnt;  // per pair
   int* unit_item;
-  unsigned* unit_code;         // surface tetrahedron index | cutting-plane mask << 16
+  unsigned* unit_code;         // surface tetrahedron index, cutting-plane mask << 16, first-cut width bit
   int unit_cap;                // units staged per step at most (kItemRegions regions)
   double* unit_vol;
   int* list_udeep;             // units with four cutting planes

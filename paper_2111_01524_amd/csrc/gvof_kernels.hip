@@ -1122,6 +1122,12 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_
 // survivors (pair, surface tetrahedron, mask of cutting planes) are written in
 // tetrahedron order into a range of the unit buffer reserved for the pair, so
 // the result does not depend on LPP.
+// Unit word: bits 0-15 the surface tetrahedron, 16-19 the mask of its
+// planes that cut the flux tet, bit 16 + kUnitWideBit set when the first of
+// those cuts keeps three tetrahedra.
+constexpr int kUnitWideBit = 4;
+__device__ inline unsigned unit_mask(unsigned code) { return (code >> 16) & 15u; }
+
 template <int LPP>
 __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
   static_assert(LPP == 8 || LPP == 16 || LPP == 32 || LPP == 64, "lanes per pair");
@@ -1153,7 +1159,14 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
           det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0)
         return false;
       TetCont TC = tet_container(cc, t0, t1, t2);
-      return cut_mask(T, TC, cm);
+      if (!cut_mask(T, TC, cm)) return false;
+      if (cm) {
+        // the first cut keeps three tetrahedra or one: a hint for grouping units of like work
+        const Plane P = TC.plane(__builtin_ctz(cm));
+        const int inside = (P.dist(T.p0) > 0.0) + (P.dist(T.p1) > 0.0) + (P.dist(T.p2) > 0.0) + (P.dist(T.p3) > 0.0);
+        cm |= (inside >= 2 ? 1u : 0u) << kUnitWideBit;
+      }
+      return true;
     };
     // reserves count units (lane 0 of the group); -1 when the region is full
     auto reserve = [&](int count) -> int {
@@ -1236,7 +1249,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   // As in the box-pair kernel, each block ranks its units by their work (the
   // number of cutting planes, 0..3, and whether the cell's interface cuts the
   // leaves) before clipping, so that most wavefronts run one kind of unit.
-  constexpr int NCLS = 8;
+  constexpr int NCLS = 14;  // none; then per cut count 1..3, first cut keeping one or three; x interface
   __shared__ int s_unit[kItemsBlock], s_item[kItemsBlock];
   __shared__ unsigned s_code[kItemsBlock];
   __shared__ int s_off[kItemsBlock / 64][NCLS];
@@ -1255,10 +1268,11 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
     if (lu < fill) {
       i = M.unit_item[u];
       code = M.unit_code[u];
-      const int nc = cut_count(code >> 16);
+      const int nc = cut_count(unit_mask(code));
       const int8_t tg = M.tag_cell[M.item_cell[i]];
+      const int wide = (int)((code >> (16 + kUnitWideBit)) & 1u);
       if (nc > 3) M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;  // four cutting planes: the deep instance
-      else cls = 2 * nc + (tg == 0 ? 1 : 0);
+      else cls = nc == 0 ? (tg == 0 ? 1 : 0) : 2 + 4 * (nc - 1) + 2 * wide + (tg == 0 ? 1 : 0);
     }
     unsigned long long bm[NCLS];
 #pragma unroll
@@ -1293,7 +1307,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       const int uu = s_unit[threadIdx.x], ii = s_item[threadIdx.x];
       const unsigned cd = s_code[threadIdx.x];
       const int p = cd & 0xffff;
-      const unsigned cm = cd >> 16;
+      const unsigned cm = unit_mask(cd);
       const int k = M.item_cell[ii];
       const Tet T = staged_tet(M, M.item_slot[ii], M.item_tm[ii]);
       const d3 cc = cell_centre(M, k);
@@ -1331,7 +1345,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
     leaf.hd = M.pC[k];
-    double v = clip_masked_tet<4>(T, TC, code >> 16, leaf);
+    double v = clip_masked_tet<4>(T, TC, unit_mask(code), leaf);
     M.unit_vol[u] = s6 > 0.0 ? v : -v;
   }
 }
