@@ -349,6 +349,16 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.neigh = C.take<int>(nf);
   d.cf_ptr = C.take<int>(nc + 1);
   d.cf_idx = C.take<int>(m->cf_idx.size());
+  // uniform counts become strides (the kernels then skip the offset loads)
+  auto stride_of = [](const std::vector<int>& ptr) {
+    const size_t n = ptr.size() - 1;
+    const int k = n ? ptr[1] - ptr[0] : 0;
+    for (size_t i = 0; i < n; ++i)
+      if (ptr[i + 1] - ptr[i] != k) return 0;
+    return k;
+  };
+  d.fv_stride = stride_of(m->fv_ptr);
+  d.cf_stride = stride_of(m->cf_ptr);
   d.cv_ptr = C.take<int>(nc + 1);
   d.cv_idx = C.take<int>(m->cv_idx.size());
   d.vc_ptr = C.take<int>(nv + 1);

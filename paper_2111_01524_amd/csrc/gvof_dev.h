@@ -28,6 +28,7 @@ struct DevMesh {
   const double *vx, *vy, *vz;
   const int *fv_ptr, *fv_idx, *owner, *neigh;
   const int *cf_ptr, *cf_idx;  // cell -> faces ascending; entry f (cell owns f) or ~f (cell is f's neighbour)
+  int fv_stride, cf_stride;    // vertices of every face / faces of every cell when all equal, else 0
   const int *cv_ptr, *cv_idx;  // cell -> distinct vertices ascending
   const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
   const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
@@ -137,6 +138,17 @@ __host__ __device__ inline d3 vmin(d3 a, d3 b) { return mk3(fmin(a.x, b.x), fmin
 __host__ __device__ inline d3 vmax(d3 a, d3 b) { return mk3(fmax(a.x, b.x), fmax(a.y, b.y), fmax(a.z, b.z)); }
 
 __device__ inline d3 vert(const DevMesh& M, int v) { return mk3(M.vx[v], M.vy[v], M.vz[v]); }
+
+// CSR ranges.  When every face has the same vertex count (every cell the same
+// face count) the count is kept as a stride and a range costs no load.
+__device__ inline int fv_begin(const DevMesh& M, int f) { return M.fv_stride ? f * M.fv_stride : M.fv_ptr[f]; }
+__device__ inline int fv_count(const DevMesh& M, int f) {
+  return M.fv_stride ? M.fv_stride : M.fv_ptr[f + 1] - M.fv_ptr[f];
+}
+__device__ inline int cf_begin(const DevMesh& M, int c) { return M.cf_stride ? c * M.cf_stride : M.cf_ptr[c]; }
+__device__ inline int cf_count(const DevMesh& M, int c) {
+  return M.cf_stride ? M.cf_stride : M.cf_ptr[c + 1] - M.cf_ptr[c];
+}
 __device__ inline d3 cell_centre(const DevMesh& M, int c) { return mk3(M.ccx[c], M.ccy[c], M.ccz[c]); }
 
 // ---------------------------------------------------------------- tetrahedra and half-spaces

@@ -73,7 +73,7 @@ __global__ void k_zero(int* p, int n) {
 // evaluated in vertex order with separate roundings (bitwise reproducible).
 __global__ void k_face_geom(DevMesh M) {
   for (int f = grid_stride_start(); f < M.nf; f += grid_stride()) {
-    int b = M.fv_ptr[f], k = M.fv_ptr[f + 1] - b;
+    int b = fv_begin(M, f), k = fv_count(M, f);
     d3 s = mk3(0.0, 0.0, 0.0);
     for (int i = 0; i < k; ++i) s = s + vert(M, M.fv_idx[b + i]);
     double dk = (double)k;
@@ -95,7 +95,7 @@ __global__ void k_face_geom(DevMesh M) {
 // i-th surface triangle of cell-face entry e (outward for the cell).
 __device__ inline void face_triangle(const DevMesh& M, int e, int i, d3& t0, d3& t1, d3& t2) {
   int f = e >= 0 ? e : ~e;
-  int b = M.fv_ptr[f], k = M.fv_ptr[f + 1] - b;
+  int b = fv_begin(M, f), k = fv_count(M, f);
   if (k == 3) {
     t0 = vert(M, M.fv_idx[b]);
     t1 = vert(M, M.fv_idx[b + 1]);
@@ -120,7 +120,7 @@ __device__ inline void face_triangle(const DevMesh& M, int e, int i, d3& t0, d3&
 
 __device__ inline int face_triangle_count(const DevMesh& M, int e) {
   int f = e >= 0 ? e : ~e;
-  int k = M.fv_ptr[f + 1] - M.fv_ptr[f];
+  int k = fv_count(M, f);
   return k == 3 ? 1 : k;
 }
 
@@ -140,7 +140,7 @@ __global__ void k_cell_geom(DevMesh M) {
     }
     double dn = (double)vn;
     d3 cen = mk3(s.x / dn, s.y / dn, s.z / dn);
-    int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+    int fb = cf_begin(M, c), fn = cf_count(M, c);
     bool box = vn == 8 && fn == 6;
     if (box) {
       int mask = 0;
@@ -155,7 +155,7 @@ __global__ void k_cell_geom(DevMesh M) {
       for (int i = 0; i < fn; ++i) {
         int e = M.cf_idx[fb + i];
         int f = e >= 0 ? e : ~e;
-        if (M.fv_ptr[f + 1] - M.fv_ptr[f] != 4) box = false;
+        if (fv_count(M, f) != 4) box = false;
       }
     }
     double vol = 0.0, amag = 0.0;
@@ -266,7 +266,7 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
 // derives it where it is used (k_face_sweep); k_face_tag stores it for
 // gvof_get_tags.
 __device__ inline int8_t face_tag_of(const DevMesh& M, int f) {
-  const int b = M.fv_ptr[f], n = M.fv_ptr[f + 1] - b;  // 3 <= n <= kMaxFaceVerts
+  const int b = fv_begin(M, f), n = fv_count(M, f);  // 3 <= n <= kMaxFaceVerts
   int vq[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) vq[q] = M.fv_idx[b + min(q, n - 1)];
@@ -411,7 +411,7 @@ __device__ inline bool sorted_contains(const int* a, int n, int key) {
 
 // surface triangle m of cell k (walks the face list when faces are polygons)
 __device__ inline void cell_piece(const DevMesh& M, int k, int m, d3& t0, d3& t1, d3& t2) {
-  int fb = M.cf_ptr[k], fn = M.cf_ptr[k + 1] - fb;
+  int fb = cf_begin(M, k), fn = cf_count(M, k);
   for (int i = 0; i < fn; ++i) {
     int e = M.cf_idx[fb + i];
     int nt = face_triangle_count(M, e);
@@ -606,7 +606,7 @@ __device__ inline int flux_candidates(const DevMesh& M, FluxLds& S, int f, d3 pl
       int np = 1;
       if (!box) {
         np = 0;
-        for (int q = M.cf_ptr[k]; q < M.cf_ptr[k + 1]; ++q) np += face_triangle_count(M, M.cf_idx[q]);
+        for (int q = cf_begin(M, k); q < cf_begin(M, k) + cf_count(M, k); ++q) np += face_triangle_count(M, M.cf_idx[q]);
       }
       S.cpre[pos + 1] = np;
     }
@@ -629,7 +629,7 @@ __device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(con
                                               double& out) {
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   double acc = 0.0;
-  int fb = M.cf_ptr[k], fn = M.cf_ptr[k + 1] - fb;
+  int fb = cf_begin(M, k), fn = cf_count(M, k);
   for (int i = 0; i < fn; ++i) {
     int e = M.cf_idx[fb + i];
     int nt = face_triangle_count(M, e);
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     }
     // Loads first, straight-line with clamped indices (every lane reads valid
     // memory), so both chains are in flight together.
-    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
+    const int b0 = fv_begin(M, f), I = fv_count(M, f);
     const int o = M.owner[f], nbr = M.neigh[f];
     const d3 c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
     const d3 Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
@@ -1091,7 +1091,7 @@ __device__ inline void cell_sigma(const DevMesh& M, int k, int p, bool tri_only,
       t1 = mk3(q[3], q[4], q[5]);
       t2 = mk3(q[6], q[7], q[8]);
     } else {
-      face_triangle(M, M.cf_idx[M.cf_ptr[k] + p], 0, t0, t1, t2);
+      face_triangle(M, M.cf_idx[cf_begin(M, k) + p], 0, t0, t1, t2);
     }
   } else {
     cell_piece(M, k, p, t0, t1, t2);
@@ -1104,7 +1104,7 @@ __global__ void k_tri_cache(DevMesh M) {
     const int o = M.tri_off[c], n = M.tri_off[c + 1] - o;
     for (int p = 0; p < n; ++p) {
       d3 t0, t1, t2;
-      face_triangle(M, M.cf_idx[M.cf_ptr[c] + p], 0, t0, t1, t2);
+      face_triangle(M, M.cf_idx[cf_begin(M, c) + p], 0, t0, t1, t2);
       double* q = M.tri_xyz + 9 * (size_t)(o + p);
       q[0] = t0.x; q[1] = t0.y; q[2] = t0.z;
       q[3] = t1.x; q[4] = t1.y; q[5] = t1.z;
@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     const d3 cc = cell_centre(M, k);
     d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
     const int np = cell_piece_count(M, k);
-    const bool tri_only = np == M.cf_ptr[k + 1] - M.cf_ptr[k];
+    const bool tri_only = np == cf_count(M, k);
     const bool live = tet6(T) != 0.0;
     // test of surface tetrahedron p against T: keep, and the mask of its planes that cut T
     auto test = [&](int p, unsigned& cm) -> bool {
@@ -1311,7 +1311,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       const int k = M.item_cell[ii];
       const Tet T = staged_tet(M, M.item_slot[ii], M.item_tm[ii]);
       const d3 cc = cell_centre(M, k);
-      const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
+      const bool tri_only = cf_count(M, k) == cell_piece_count(M, k);
       d3 t0, t1, t2;
       cell_sigma(M, k, p, tri_only, t0, t1, t2);
       const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
@@ -1336,7 +1336,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
     const int k = M.item_cell[i];
     Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
     const d3 cc = cell_centre(M, k);
-    const bool tri_only = (M.cf_ptr[k + 1] - M.cf_ptr[k]) == cell_piece_count(M, k);
+    const bool tri_only = cf_count(M, k) == cell_piece_count(M, k);
     d3 t0, t1, t2;
     cell_sigma(M, k, code & 0xffff, tri_only, t0, t1, t2);
     double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
@@ -1461,7 +1461,7 @@ __device__ inline double general_pair_volume_group(const DevMesh& M, int k, d3 c
   if (sT == 0.0) return 0.0;
   const d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   const int np = cell_piece_count(M, k);
-  const bool tri_only = np == M.cf_ptr[k + 1] - M.cf_ptr[k];
+  const bool tri_only = np == cf_count(M, k);
   double acc = 0.0;
   for (int p0 = 0; p0 < np; p0 += kDeepLanes) {
     const int p = p0 + sub;
@@ -1555,7 +1555,7 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
   const int nfaces = M.counters[CNT_OVER];
   for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
     const int f = M.list_over[it];
-    const int b0 = M.fv_ptr[f], I = M.fv_ptr[f + 1] - b0;
+    const int b0 = fv_begin(M, f), I = fv_count(M, f);
     d3 c, Sv, plo, phi;
     flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
     const int ncand = flux_candidates(M, S, f, plo, phi);
@@ -1765,11 +1765,11 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
       insert_sorted(lev, nl, dotf(n, xc));
       for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i)
         insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
-      int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+      int fb = cf_begin(M, c), fn = cf_count(M, c);
       for (int i = 0; i < fn && nl < kMaxLevels; ++i) {
         int e = M.cf_idx[fb + i];
         int f = e >= 0 ? e : ~e;
-        if (M.fv_ptr[f + 1] - M.fv_ptr[f] > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
+        if (fv_count(M, f) > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
       }
       if (sub == 0 && M.cv_ptr[c + 1] - M.cv_ptr[c] + 1 > kMaxLevels) atomicOr(&M.counters[CNT_ERR], ERR_LEVELS);
       const int np = cell_piece_count(M, c);
@@ -1813,7 +1813,7 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
   for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
     if (!cell_live(M, c)) continue;
     double VdT = 0.0, VFT = 0.0;
-    const int b = M.cf_ptr[c], n = M.cf_ptr[c + 1] - b;  // n >= 4
+    const int b = cf_begin(M, c), n = cf_count(M, c);  // n >= 4
     // the first kUpdateFaces faces' loads issued together (clamped indices),
     // then summed in face order like the rest
     int eq[kUpdateFaces];
@@ -1908,7 +1908,7 @@ __device__ inline double cell_subbox_volume(const DevMesh& M, int c, d3 a, d3 b,
   }
   double acc = 0.0;
   d3 cen = cell_centre(M, c);
-  int fb = M.cf_ptr[c], fn = M.cf_ptr[c + 1] - fb;
+  int fb = cf_begin(M, c), fn = cf_count(M, c);
   for (int i = 0; i < fn; ++i) {
     int e = M.cf_idx[fb + i];
     int nt = face_triangle_count(M, e);
