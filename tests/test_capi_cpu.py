@@ -166,3 +166,26 @@ def test_launch_config_validation_without_gpu():
             gvof.gvof_graph_launch(h)
     finally:
         gvof.gvof_mesh_destroy(h)
+
+
+def test_unit_buffer_only_for_meshes_with_general_cells():
+    """The general-cell unit buffer is sized on the host from the cells that
+    are not axis-aligned boxes (the device's box test, redone on the host):
+    none for a Cartesian grid, at least 4 Mi entries (16 B each, plus the
+    deep-unit list) once one interior vertex moves and its 8 cells become
+    general."""
+    def ws(m):
+        h = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+        try:
+            return gvof.gvof_mesh_workspace_bytes(h)
+        finally:
+            gvof.gvof_mesh_destroy(h)
+
+    m = inputs.cartesian_mesh(6)
+    base = ws(m)
+    v = (3 * 7 + 3) * 7 + 3  # an interior vertex of the 7^3 lattice
+    m.vx[v] += 0.01
+    moved = ws(m)
+    grown = ((4 << 20) - 256) * (16 + 4)  # all boxes: a minimal buffer of 256 entries
+    assert moved - base >= grown
+    assert ws(inputs.jittered_mesh(6, seed=2)) - base >= grown
