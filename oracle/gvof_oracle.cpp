@@ -8,7 +8,8 @@
 //   plic-eq), LSGIR normals (Sec. LSGIR, Eqs. lsgir1, lsgir2, lsgir-beta),
 //   the plane constant enforcing the cell's volume fraction, face flux
 //   volumes (Eq. a-donacion), FMFPA flux polyhedra (Sec. "Face-matched flux
-//   polyhedron"), their truncation by the PLIC half-spaces of the cells they
+//   polyhedron") or EMFPA ones (Sec. "Edge-matched flux polyhedron", chosen
+//   per mesh), their truncation by the PLIC half-spaces of the cells they
 //   overlap (Sec. "Fluid advected through cell faces") and the volume fraction
 //   update with clamp (Eq. fnext), plus the refinement initialisation (Sec.
 //   "Fluid volume fraction initialization").
@@ -216,6 +217,7 @@ struct OMesh {
   std::vector<real> V;
   std::vector<char> isbox;
   std::vector<std::vector<Tet>> tets;  // surface tets of every non-box cell
+  int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA
 };
 
 // Surface triangles of cell c: triangle faces as they are, polygons fanned
@@ -519,7 +521,7 @@ real plane_constant(const OMesh& M, int c, V3 n, double Fc) {
 // --------------------------------------------------------------------------
 struct FluxPoly {
   int I = 0;
-  std::vector<V3> x, b;
+  std::vector<V3> x, b, m;  // m: EMFPA lateral-face centres (empty for FMFPA)
   V3 a, c;
   bool degenerate = false;
   std::vector<std::array<V3, 4>> tets;
@@ -597,6 +599,95 @@ void fmfpa(const OMesh& M, int f, const double* uv, double dt_, real Vd, double 
   }
 }
 
+// --------------------------------------------------------------------------
+// EMFPA flux polyhedron (Sec. "Edge-matched flux polyhedron").
+//   first face = the cell face x_0..x_{I-1};
+//   back vertex b_i = x_i - dt u_i: vertex i moved back along its streak line,
+//   Eq. (streak-line2), so every face through a vertex shares its b_i;
+//   lateral face i, bounded by x_i, x_{i+1}, b_{i+1}, b_i, is replaced by four
+//   triangles about its vertex mean m_i (3I+1 vertices in all);
+//   back face triangulated about the mean g of the b_i moved along the face
+//   normal (along S) so that the signed volume equals V_d (5I+1 faces).
+// m_i sums the two edge ends and the two back vertices pairwise, an order
+// symmetric in i and i+1, so the faces on either side of an edge build the
+// same centre to the last bit.
+// Tets fanned from the face centre: for each edge i (j = i+1),
+//   (c; x_j, x_i, m_i), (c; x_i, b_i, m_i), (c; b_i, b_j, m_i), (c; b_j, x_j, m_i),
+//   (c; a, b_j, b_i)
+// (the lateral quad taken x_j, x_i, b_i, b_j: the orientation of the FMFPA
+// lateral face).
+// --------------------------------------------------------------------------
+void emfpa(const OMesh& M, int f, const double* uv, double dt_, real Vd, FluxPoly& P) {
+  int b0 = M.fptr[f], I = M.fptr[f + 1] - b0;
+  int nv = M.nv;
+  real dt = dt_;
+  P.I = I;
+  P.x.resize(I);
+  P.b.resize(I);
+  P.m.resize(I);
+  for (int i = 0; i < I; ++i) {
+    int v = M.fidx[b0 + i];
+    P.x[i] = M.X[v];
+    V3 u = mk(uv[v], uv[nv + v], uv[2 * nv + v]);
+    P.b[i] = P.x[i] - dt * u;
+  }
+  for (int i = 0; i < I; ++i) {
+    int j = (i + 1) % I;
+    V3 s = (P.x[i] + P.x[j]) + (P.b[i] + P.b[j]);
+    P.m[i] = mk(s.x / real(4.0), s.y / real(4.0), s.z / real(4.0));
+  }
+  P.c = M.fc[f];
+  V3 g = mk(0.0, 0.0, 0.0);
+  for (int i = 0; i < I; ++i) g = g + P.b[i];
+  real iI = real(double(I));
+  g = mk(g.x / iI, g.y / iI, g.z / iI);
+  V3 S = M.S[f], c = P.c;
+  // signed volume with the back-face vertex at g, and its slope along S
+  real V0 = 0.0, W = 0.0;
+  for (int i = 0; i < I; ++i) {
+    int j = (i + 1) % I;
+    V3 xi = P.x[i] - c, xj = P.x[j] - c, bi = P.b[i] - c, bj = P.b[j] - c, mi = P.m[i] - c;
+    V0 = V0 + det3(xj, xi, mi);
+    V0 = V0 + det3(xi, bi, mi);
+    V0 = V0 + det3(bi, bj, mi);
+    V0 = V0 + det3(bj, xj, mi);
+    V0 = V0 + det3(g - c, bj, bi);
+    W = W + det3(S, bj, bi);
+  }
+  V0 = V0 / real(6.0);
+  W = W / real(6.0);
+  real SS = dot(S, S);
+  real mu = 0.0;
+  if (fabs(W) <= real(1e-12) * SS) {
+    P.degenerate = true;
+  } else {
+    mu = (Vd - V0) / W;
+  }
+  P.a = g + mu * S;
+  P.tets.clear();
+  P.sgn.clear();
+  for (int i = 0; i < I; ++i) {
+    int j = (i + 1) % I;
+    std::array<V3, 4> t[5] = {{c, P.x[j], P.x[i], P.m[i]},
+                              {c, P.x[i], P.b[i], P.m[i]},
+                              {c, P.b[i], P.b[j], P.m[i]},
+                              {c, P.b[j], P.x[j], P.m[i]},
+                              {c, P.a, P.b[j], P.b[i]}};
+    for (auto& T : t) {
+      real d = det3(T[1] - c, T[2] - c, T[3] - c);
+      if (d == real(0.0)) continue;
+      P.tets.push_back(T);
+      P.sgn.push_back(d > real(0.0) ? real(1.0) : real(-1.0));
+    }
+  }
+}
+
+// The flux polyhedron of face f by the mesh's method.
+void flux_poly(const OMesh& M, int f, const double* uv, double dt, real Vd, double degen, FluxPoly& P) {
+  if (M.method == 1) emfpa(M, f, uv, dt, Vd, P);
+  else fmfpa(M, f, uv, dt, Vd, degen, P);
+}
+
 // Candidate cells of face f: the owner, the neighbour and every cell sharing
 // a vertex with either of them, ascending.
 void candidates(const OMesh& M, int f, std::vector<int>& out) {
@@ -654,7 +745,7 @@ FaceOut face_flux(const OMesh& M, int f, const double* planes, const int8_t* tce
   else if (tface[f] == 1) o.VF = o.Vd;
   else {
     FluxPoly P;
-    fmfpa(M, f, uv, dt, o.Vd, degen, P);
+    flux_poly(M, f, uv, dt, o.Vd, degen, P);
     o.degenerate = P.degenerate;
     o.VF = face_fluid_volume(M, f, P, planes, tcell);
   }
@@ -827,6 +918,14 @@ void* orc_mesh_new(int nv, const double* vx, const double* vy, const double* vz,
 
 void orc_mesh_free(void* h) { delete static_cast<OMesh*>(h); }
 
+// Flux polyhedra of the mesh: 0 FMFPA (default), 1 EMFPA.  Returns 0, or -1
+// for another value.
+int orc_mesh_set_method(void* h, int method) {
+  if (method != 0 && method != 1) return -1;
+  static_cast<OMesh*>(h)->method = method;
+  return 0;
+}
+
 void orc_geometry(void* h, double* S, double* fc, double* V, double* cc, double* bbmin, double* bbmax,
                   int8_t* isbox) {
   OMesh& M = *static_cast<OMesh*>(h);
@@ -956,15 +1055,21 @@ void orc_update(void* h, const double* Vd, const double* VF, const double* Fin, 
   for (int c = 0; c < M.nc; ++c) Fout[c] = to_double(update_cell(M, c, Vd, VF, Fin[c]));
 }
 
-// The FMFPA polyhedron of face f: points x_0..x_{I-1}, b_0..b_{I-1}, apex;
+// The flux polyhedron of face f by the mesh's method: points x_0..x_{I-1},
+// b_0..b_{I-1}, apex, then (EMFPA) the lateral-face centres m_0..m_{I-1};
 // returns I (or -I when the apex is degenerate).  pts holds 3*(2I+1) doubles
-// (xyz interleaved); vol_out gets the signed volume of the tet fan.
+// (3*(3I+1) for EMFPA, xyz interleaved); vol_out gets the signed volume of
+// the tet fan.
 int orc_flux_polyhedron(void* h, int f, const double* uv, double dt, double Vd, double degen, double* pts,
                         double* vol_out) {
   OMesh& M = *static_cast<OMesh*>(h);
   FluxPoly P;
-  fmfpa(M, f, uv, dt, Vd, degen, P);
+  flux_poly(M, f, uv, dt, Vd, degen, P);
   int I = P.I;
+  for (size_t i = 0; i < P.m.size(); ++i) {
+    double* q = pts + 3 * (2 * I + 1 + i);
+    q[0] = to_double(P.m[i].x); q[1] = to_double(P.m[i].y); q[2] = to_double(P.m[i].z);
+  }
   for (int i = 0; i < I; ++i) {
     pts[3 * i] = to_double(P.x[i].x); pts[3 * i + 1] = to_double(P.x[i].y); pts[3 * i + 2] = to_double(P.x[i].z);
     pts[3 * (I + i)] = to_double(P.b[i].x); pts[3 * (I + i) + 1] = to_double(P.b[i].y);

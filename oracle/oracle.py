@@ -29,6 +29,8 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_mesh_new.restype = C.c_void_p
         lib.orc_mesh_new.argtypes = [C.c_int, _d, _d, _d, C.c_int, _i, _i, _i, _i, C.c_int]
         lib.orc_mesh_free.argtypes = [C.c_void_p]
+        lib.orc_mesh_set_method.argtypes = [C.c_void_p, C.c_int]
+        lib.orc_mesh_set_method.restype = C.c_int
         lib.orc_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d, _d, _d, _b]
         lib.orc_neighbours.argtypes = [C.c_void_p, _i, _i]
         lib.orc_neighbours.restype = C.c_int
@@ -83,11 +85,20 @@ def set_threads(n: int = 0, counting: bool = False) -> int:
 
 
 class OracleMesh:
-    """The oracle's view of a mesh: topology and geometry built on the CPU."""
+    """The oracle's view of a mesh: topology and geometry built on the CPU.
 
-    def __init__(self, mesh, counting: bool = False):
+    method selects the flux polyhedra: "fmfpa" (Sec. "Face-matched flux
+    polyhedron") or "emfpa" (Sec. "Edge-matched flux polyhedron").
+    """
+
+    METHODS = {"fmfpa": 0, "emfpa": 1}
+
+    def __init__(self, mesh, counting: bool = False, method: str = "fmfpa"):
+        if method not in self.METHODS:
+            raise ValueError(f"unknown flux polyhedron method {method!r}")
         self.lib = _lib(counting)
         self.counting = counting
+        self.method = method
         self.mesh = mesh
         self.nv, self.nf, self.nc = mesh.nv, mesh.nf, mesh.nc
         self._keep = [_dbl(mesh.vx), _dbl(mesh.vy), _dbl(mesh.vz), _int(mesh.fv_ptr), _int(mesh.fv_idx),
@@ -95,6 +106,8 @@ class OracleMesh:
         vx, vy, vz, fp, fi, ow, ne = self._keep
         self.h = self.lib.orc_mesh_new(self.nv, _p(vx, _d), _p(vy, _d), _p(vz, _d), self.nf, _p(fp, _i),
                                        _p(fi, _i), _p(ow, _i), _p(ne, _i), self.nc)
+        if self.lib.orc_mesh_set_method(self.h, self.METHODS[method]) != 0:
+            raise RuntimeError("oracle rejected the flux polyhedron method")
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -176,12 +189,18 @@ class OracleMesh:
         return Fout
 
     def flux_polyhedron(self, face, u_vert, dt, Vd, degen=1e-12):
+        """(points, signed volume of the tet fan, apex degenerate).
+
+        Points: x_0..x_{I-1}, b_0..b_{I-1}, apex, then for EMFPA the
+        lateral-face centres m_0..m_{I-1}.
+        """
         uv = _dbl(u_vert)
-        pts = np.zeros(3 * 17); vol = np.zeros(1)
+        pts = np.zeros(3 * (3 * 8 + 1)); vol = np.zeros(1)
         I = self.lib.orc_flux_polyhedron(self.h, int(face), _p(uv, _d), float(dt), float(Vd), degen, _p(pts, _d),
                                          _p(vol, _d))
         k = abs(I)
-        return pts[: 3 * (2 * k + 1)].reshape(-1, 3), float(vol[0]), I < 0
+        npts = 3 * k + 1 if self.method == "emfpa" else 2 * k + 1
+        return pts[: 3 * npts].reshape(-1, 3), float(vol[0]), I < 0
 
     def tet_cell_volume(self, tet, c, plane=None):
         t = _dbl(tet).ravel()

@@ -3,8 +3,9 @@
 Given rational vertices, vertex/face velocities, dt and *unnormalised*
 rational PLIC planes, every quantity of the advection step is a rational
 function of the inputs: face area vectors, V_d, the FMFPA lateral-plane
-normals, line directions and back-vertex projections, the apex shift, every
-clip point and every volume.  This module recomputes them with Python
+normals, line directions and back-vertex projections, the EMFPA streak-line
+back vertices and lateral-face centres, the apex shift, every clip point and
+every volume.  This module recomputes them with Python
 Fractions, so its answers carry no rounding error at all.
 
 It is written independently of the oracle: volumes of intersections are done
@@ -244,7 +245,55 @@ class ExactMesh:
                     tets.append((t, 1 if d6 > 0 else -1))
         return tets, x, b, apex, degenerate
 
-    def face_flux(self, f, planes, tcell, tface, u_face, u_vert, dt):
+    def emfpa(self, f, u_vert, dt, Vd):
+        """Exact EMFPA polyhedron (Sec. "Edge-matched flux polyhedron").
+
+        Returns (tets with signs, x, b, lateral centres, apex, degenerate).
+        The polyhedron is described by its closed surface: the cell face, four
+        triangles per lateral face about the face's vertex mean, and the back
+        face fanned about the apex; its tets join each surface triangle to the
+        face centre.
+        """
+        vs = self.faces[f]
+        I = len(vs)
+        x = [self.X[v] for v in vs]
+        b = [sub(x[i], scl(dt, u_vert[v])) for i, v in enumerate(vs)]
+        cen = []
+        tris = []  # lateral triangles, outward with the back face as (apex, b_j, b_i)
+        for i in range(I):
+            j = (i + 1) % I
+            quad = [x[j], x[i], b[i], b[j]]
+            m = tuple(sum(p[a] for p in quad) / 4 for a in range(3))
+            cen.append(m)
+            for k in range(4):
+                tris.append((quad[k], quad[(k + 1) % 4], m))
+        g = tuple(sum(p[a] for p in b) / I for a in range(3))
+        c = self.fc[f]
+        S = self.S[f]
+
+        def vol6(apex):
+            tot = sum(det(sub(p, c), sub(q, c), sub(r, c)) for p, q, r in tris)
+            for i in range(I):
+                j = (i + 1) % I
+                tot += det(sub(apex, c), sub(b[j], c), sub(b[i], c))
+            return tot
+
+        # the volume is affine in the apex shift along S: solve V(g + mu S) = Vd
+        v0 = vol6(g) / 6
+        w = vol6(add(g, S)) / 6 - v0
+        degenerate = abs(w) <= Q(1, 10 ** 12) * dot(S, S)
+        mu = ZERO if degenerate else (Vd - v0) / w
+        apex = add(g, scl(mu, S))
+        back = [(apex, b[(i + 1) % I], b[i]) for i in range(I)]
+        tets = []
+        for (p, q, r) in tris + back:
+            t = (c, p, q, r)
+            d6 = tet_signed6(t)
+            if d6 != 0:
+                tets.append((t, 1 if d6 > 0 else -1))
+        return tets, x, b, cen, apex, degenerate
+
+    def face_flux(self, f, planes, tcell, tface, u_face, u_vert, dt, method="fmfpa"):
         """Exact (Vd, VF, upwind) of face f; planes[c] = ((nx,ny,nz), C) rational."""
         Vd = dt * dot(u_face[f], self.S[f])
         up = self.owner[f] if Vd >= 0 else self.neigh[f]
@@ -254,7 +303,10 @@ class ExactMesh:
             return Vd, ZERO, up
         if tface[f] == 1:
             return Vd, Vd, up
-        tets, *_ = self.fmfpa(f, u_vert, dt, Vd)
+        if method == "emfpa":
+            tets, *_ = self.emfpa(f, u_vert, dt, Vd)
+        else:
+            tets, *_ = self.fmfpa(f, u_vert, dt, Vd)
         acc = ZERO
         cands = self.candidates(f)
         for (T, sg) in tets:

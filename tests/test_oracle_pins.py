@@ -295,6 +295,140 @@ def test_fmfpa_uniform_velocity_is_swept_prism(oracle_mod, kind):
         assert abs(vol - Vd) <= 1e-14 * max(abs(Vd), 1e-6)
 
 
+# ----------------------------------------------------------------------------- EMFPA
+
+@pytest.mark.parametrize("kind", ["cartesian", "jittered"])
+def test_emfpa_uniform_velocity_is_swept_prism(oracle_mod, kind):
+    """Uniform u: the streak-line back vertices are x - dt u, every lateral face is a
+    planar parallelogram whose centre is its vertex mean, the back face is the
+    translated cell face, so the apex needs no shift and the volume is dt u.S."""
+    m = inputs.cartesian_mesh(4) if kind == "cartesian" else inputs.jittered_mesh(4, seed=5)
+    om = oracle_mod.OracleMesh(m, method="emfpa")
+    g = om.geometry()
+    u = np.array([0.7, -0.4, 0.3])
+    uv = np.tile(u[:, None], (1, m.nv))
+    dt = 0.05
+    for f in range(0, m.nf, 3):
+        Vd = dt * float(u @ g["S"][:, f])
+        pts, vol, bad = om.flux_polyhedron(f, uv, dt, Vd)
+        assert not bad
+        I = (pts.shape[0] - 1) // 3
+        assert pts.shape[0] == 3 * I + 1 and I == m.fv_ptr[f + 1] - m.fv_ptr[f]
+        x, b, a, mc = pts[:I], pts[I:2 * I], pts[2 * I], pts[2 * I + 1:]
+        assert np.abs(x - np.stack([m.vx, m.vy, m.vz], 1)[m.fv_idx[m.fv_ptr[f]:m.fv_ptr[f + 1]]]).max() == 0
+        assert np.abs(b - (x - dt * u)).max() < 1e-15
+        assert np.abs(mc - (0.5 * (x + np.roll(x, -1, 0)) - 0.5 * dt * u)).max() < 1e-15
+        assert np.abs(a - (g["fc"][:, f] - dt * u)).max() < 1e-14
+        assert abs(vol - Vd) <= 1e-14 * max(abs(Vd), 1e-6)
+
+
+def _emfpa_surface(pts, I):
+    """The closed surface of an EMFPA polyhedron as the section describes it: the
+    cell face, four triangles per lateral face about its vertex mean, the back
+    face fanned about the apex; oriented so the volume is positive for a
+    polyhedron behind the face (against the area vector)."""
+    x, b, a = pts[:I], pts[I:2 * I], pts[2 * I]
+    tris = [(x[0], x[k], x[k + 1]) for k in range(1, I - 1)]  # cell face, along the area vector
+    for i in range(I):
+        j = (i + 1) % I
+        quad = [x[j], x[i], b[i], b[j]]
+        mi = sum(quad) / 4.0
+        tris += [(quad[k], quad[(k + 1) % 4], mi) for k in range(4)]
+    tris += [(a, b[(i + 1) % I], b[i]) for i in range(I)]
+    return tris
+
+
+def _surface_volume(tris, origin):
+    return sum(float(np.dot(p - origin, np.cross(q - origin, r - origin))) for p, q, r in tris) / 6.0
+
+
+@pytest.mark.parametrize("kind", ["cartesian", "jittered"])
+def test_emfpa_closed_surface_volume_is_vd(oracle_mod, kind):
+    """Non-uniform vertex velocities: the divergence-theorem volume of the 5I+1-face
+    surface built here from the returned 3I+1 points equals V_d (the volume
+    constraint of the section), the returned lateral centres are the vertex
+    means, and the apex lies on the line through the back-vertex mean along S."""
+    m = inputs.cartesian_mesh(3) if kind == "cartesian" else inputs.jittered_mesh(3, seed=4)
+    om = oracle_mod.OracleMesh(m, method="emfpa")
+    g = om.geometry()
+    rng = np.random.default_rng(31)
+    uv = rng.uniform(-1, 1, (3, m.nv))
+    uf = rng.uniform(-1, 1, (3, m.nf))
+    dt = 0.08
+    checked = 0
+    for f in range(m.nf):
+        Vd = dt * float(uf[:, f] @ g["S"][:, f])
+        pts, vol, bad = om.flux_polyhedron(f, uv, dt, Vd)
+        if bad:
+            continue
+        I = (pts.shape[0] - 1) // 3
+        x, b, a, mc = pts[:I], pts[I:2 * I], pts[2 * I], pts[2 * I + 1:]
+        assert np.abs(mc - 0.25 * (x + np.roll(x, -1, 0) + b + np.roll(b, -1, 0))).max() < 1e-15
+        gb = b.mean(0)
+        Sf = g["S"][:, f]
+        assert np.linalg.norm(np.cross(a - gb, Sf)) <= 1e-12 * np.linalg.norm(Sf) * (np.linalg.norm(a - gb) + 1e-3)
+        scale = np.linalg.norm(Sf) * dt
+        for origin in (np.zeros(3), g["fc"][:, f], b[0]):
+            assert abs(_surface_volume(_emfpa_surface(pts, I), origin) - Vd) <= 1e-13 * scale
+        assert abs(vol - Vd) <= 1e-13 * scale
+        checked += 1
+    assert checked > m.nf // 2
+
+
+@pytest.mark.parametrize("kind", ["cartesian", "jittered"])
+def test_emfpa_edge_matched(oracle_mod, kind):
+    """Faces sharing a vertex share its back vertex, and faces sharing an edge share
+    the edge's lateral face, centre included, to the last bit; over the faces of
+    one cell the lateral faces therefore cancel, and the back faces close into
+    the back-traced cell of volume V(cell) - sum(sigma V_d)."""
+    m = inputs.cartesian_mesh(3) if kind == "cartesian" else inputs.jittered_mesh(3, seed=8)
+    om = oracle_mod.OracleMesh(m, method="emfpa")
+    g = om.geometry()
+    rng = np.random.default_rng(5)
+    uv = rng.uniform(-1, 1, (3, m.nv))
+    uf = rng.uniform(-1, 1, (3, m.nf))
+    dt = 0.05
+    back, lateral, polys = {}, {}, {}
+    for f in range(m.nf):
+        Vd = dt * float(uf[:, f] @ g["S"][:, f])
+        pts, vol, bad = om.flux_polyhedron(f, uv, dt, Vd)
+        assert not bad
+        vs = m.fv_idx[m.fv_ptr[f]:m.fv_ptr[f + 1]]
+        I = len(vs)
+        polys[f] = (pts, Vd)
+        for i, v in enumerate(vs):
+            key = bytes(pts[I + i].tobytes())
+            assert back.setdefault(int(v), key) == key
+            e = tuple(sorted((int(v), int(vs[(i + 1) % I]))))
+            key = bytes(pts[2 * I + 1 + i].tobytes())
+            assert lateral.setdefault(e, key) == key
+    cf = [[] for _ in range(m.nc)]
+    for f in range(m.nf):
+        cf[m.owner[f]].append((f, 1))
+        if m.neigh[f] >= 0:
+            cf[m.neigh[f]].append((f, -1))
+    for c in range(m.nc):
+        lat, backs, vds = [], [], 0.0
+        for f, sg in cf[c]:
+            pts, Vd = polys[f]
+            I = (pts.shape[0] - 1) // 3
+            x, b, a = pts[:I], pts[I:2 * I], pts[2 * I]
+            for i in range(I):
+                j = (i + 1) % I
+                mi = pts[2 * I + 1 + i]
+                quad = [x[j], x[i], b[i], b[j]]
+                tr = [(quad[k], quad[(k + 1) % 4], mi) for k in range(4)]
+                lat += tr if sg > 0 else [(p, r, q) for p, q, r in tr]
+                bt = (a, b[j], b[i])
+                backs.append(bt if sg > 0 else (bt[0], bt[2], bt[1]))
+            vds += sg * Vd
+        o = g["cc"][:, c]
+        assert abs(_surface_volume(lat, o)) <= 1e-15, c  # exact cancellation up to the final sum
+        # outward back-traced cell: back triangles point into the swept region
+        vback = -_surface_volume(backs, o)
+        assert abs(vback - (g["V"][c] - vds)) <= 1e-14 * g["V"][c], c
+
+
 def _rational_mesh(kind, n, seed):
     """A tiny mesh with exactly representable (dyadic) coordinates."""
     m = inputs.cartesian_mesh(n)
@@ -316,16 +450,18 @@ def _rational_mesh(kind, n, seed):
     return m
 
 
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
 @pytest.mark.parametrize("kind", ["cartesian", "jittered"])
-def test_advect_exact_rational(oracle_mod, kind):
-    """Whole advection step (V_d, FMFPA, signed truncation, update) against exact rationals.
+def test_advect_exact_rational(oracle_mod, kind, method):
+    """Whole advection step (V_d, FMFPA or EMFPA, signed truncation, update) against
+    exact rationals.
 
     Non-uniform, partly reversing vertex velocities make the lateral faces and
     back faces non-planar and self-intersecting; planes are arbitrary rational
     half-spaces (unnormalised); tags mix -1, 0 and 1.
     """
     m = _rational_mesh(kind, 2, seed=3)
-    om = oracle_mod.OracleMesh(m)
+    om = oracle_mod.OracleMesh(m, method=method)
     rng = np.random.default_rng(17 if kind == "cartesian" else 23)
     q = lambda x: Q(float(x))  # noqa: E731  all inputs are dyadic doubles
     uv = np.round(rng.uniform(-1, 1, (3, m.nv)) * 64) / 64
@@ -348,7 +484,7 @@ def test_advect_exact_rational(oracle_mod, kind):
     Vdx, VFx = {}, {}
     for f in range(m.nf):
         if f in faces:
-            vd, vf, upx = xm.face_flux(f, P, tcell, tface, Uf, U, q(dt))
+            vd, vf, upx = xm.face_flux(f, P, tcell, tface, Uf, U, q(dt), method=method)
             assert abs(Vd[f] - float(vd)) <= 1e-16 * scale
             assert abs(VF[f] - float(vf)) <= 2e-14 * scale, (f, VF[f], float(vf))
             assert up[f] == upx
@@ -359,7 +495,8 @@ def test_advect_exact_rational(oracle_mod, kind):
         assert abs(Fout[c] - float(ref)) <= 1e-14
 
 
-def test_step_translated_plane_exact(oracle_mod):
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+def test_step_translated_plane_exact(oracle_mod, method):
     """Uniform translation of a planar interface with exact planes reproduces the exact solution.
 
     F^0 = box ∩ {n.x >= s} (closed form); planes forced to that plane; after one
@@ -367,7 +504,7 @@ def test_step_translated_plane_exact(oracle_mod):
     prisms are exact and the interface is exactly planar.
     """
     m = inputs.cartesian_mesh(10)
-    om = oracle_mod.OracleMesh(m)
+    om = oracle_mod.OracleMesh(m, method=method)
     g = om.geometry()
     nrm = np.array([0.6, 0.48, 0.64])
     s0 = 1.27  # the fluid corner stays clear of the inflow walls x=0, y=0, z=0
@@ -412,13 +549,13 @@ def test_init_sphere_volume_converges(oracle_mod, kind):
 
 # ----------------------------------------------------------------------------- conservation
 
-@pytest.mark.parametrize("kind", ["cartesian", "jittered"])
-def test_enright_conserves_volume(oracle_mod, kind):
+@pytest.mark.parametrize("kind,method", [("cartesian", "fmfpa"), ("jittered", "fmfpa"), ("jittered", "emfpa")])
+def test_enright_conserves_volume(oracle_mod, kind, method):
     """Discretely solenoidal face fluxes: the update before the clamp changes the total
     fluid volume only by round-off; cut-off and clamp losses are itemised."""
     n = 12
     m = inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
-    om = oracle_mod.OracleMesh(m)
+    om = oracle_mod.OracleMesh(m, method=method)
     V = om.geometry()["V"]
     F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 6)
     uf, uv = inputs.velocity_enright(m)
@@ -444,6 +581,11 @@ def test_enright_conserves_volume(oracle_mod, kind):
         assert abs(cut) <= 1e-11 * vol0
         if kind == "cartesian":
             assert abs(clamp_loss) <= 1e-15 * vol0
+        elif method == "emfpa":
+            # edge-matched polyhedra of faces with a common vertex neither overlap nor
+            # leave gaps (Sec. "Edge-matched flux polyhedron"): no bounding error
+            assert abs(clamp_loss) <= 1e-14 * vol0, (step, clamp_loss)
+            assert Fu.min() >= -1e-14 and Fu.max() <= 1 + 1e-14
         else:  # vertex over/underlaps of face-matched polyhedra on a coarse distorted grid
             assert abs(clamp_loss) <= 1e-3 * vol0
         F = F1
