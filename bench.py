@@ -1,4 +1,4 @@
-"""Throughput of the LSGIR + FMFPA VOF step on one MI355X.
+"""Throughput of the LSGIR + FMFPA (or EMFPA) VOF step on one MI355X.
 
 Workload (default): 64^3 uniform hexahedra on the unit cube, sphere r=0.15 at
 (0.35, 0.35, 0.35) initialised by refinement (10 divisions), Enright 3D
@@ -26,13 +26,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face that needs a flux polyhedron (FMFPA
+# Algorithmic FP64 operations per face that needs a flux polyhedron (its
 # construction + truncation, and the truncation alone, which k_flux_items
-# performs) and per interfacial cell (LSGIR + plane constant) on this
-# workload, counted by the FLOP-counting build of the CPU reference over a
-# sample of the trajectory (oracle/count_flops.py).
-FLOPS_PER_FLUX_FACE = 38766.0
-FLOPS_PER_FLUX_FACE_TRUNCATION = 37578.0
+# performs), by flux polyhedron method, and per interfacial cell (LSGIR +
+# plane constant) on this workload, counted by the FLOP-counting build of the
+# CPU reference over a sample of the trajectory (oracle/count_flops.py).
+FLOPS_PER_FLUX_FACE = {"fmfpa": 38766.0, "emfpa": 49094.0}
+FLOPS_PER_FLUX_FACE_TRUNCATION = {"fmfpa": 37578.0, "emfpa": 47629.0}
 FLOPS_PER_RECON_CELL = 53202.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
+    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa"],
+                    help="flux polyhedra: face-matched (the default workload) or edge-matched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
@@ -113,7 +115,7 @@ def main():
     dev = torch.device("cuda:0")
     n, T_end, cfl = args.n, 3.0, 0.5
     mesh = inputs.cartesian_mesh(n) if args.kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
-    g = gvof.GvofMesh(mesh, dev)
+    g = gvof.GvofMesh(mesh, dev, method=args.method)
     uf, uv = inputs.velocity_enright(mesh)
     dt = inputs.cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
     sched = inputs.step_schedule(T_end, dt)
@@ -190,7 +192,8 @@ def main():
     value = mesh.nf * K / (ms_total / 1e3)
     flux_ms, flux_n = prof["k_flux_items_box"]
     flux_ms_avg = flux_ms / max(flux_n, 1)
-    flux_flops_per_launch = FLOPS_PER_FLUX_FACE_TRUNCATION * nfaces_work / K  # one launch per step
+    flops_per_face = FLOPS_PER_FLUX_FACE_TRUNCATION[args.method]
+    flux_flops_per_launch = flops_per_face * nfaces_work / K  # one launch per step
     achieved_tflops = flux_flops_per_launch / (flux_ms_avg / 1e3) / 1e12 if flux_ms_avg > 0 else 0.0
     out = {
         "metric": "face·step flux updates/s",
@@ -207,7 +210,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.kind} {n}^3 unit cube, sphere r=0.15 at 0.35, Enright deformation T=3, CFL 0.5, "
-                        f"LSGIR+FMFPA, {len(sched)} steps per trajectory",
+                        f"LSGIR+{args.method.upper()}, {len(sched)} steps per trajectory",
             "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
         },
         "cells_per_s": mesh.nc * K / (ms_total / 1e3),
@@ -223,10 +226,12 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": ITEMS_BOX_TRAFFIC_BYTES if kernel_sources_digest() == ITEMS_BOX_TRAFFIC_SOURCES else None,
+            "traffic": (ITEMS_BOX_TRAFFIC_BYTES
+                        if kernel_sources_digest() == ITEMS_BOX_TRAFFIC_SOURCES and args.method == "fmfpa"
+                        and args.kind == "cartesian" and n == 64 else None),
             "traffic_unit": "bytes per launch (HBM, counters)",
             "avg_launch_ms": flux_ms_avg,
-            "flops_per_unit": FLOPS_PER_FLUX_FACE_TRUNCATION,
+            "flops_per_unit": flops_per_face,
             "unit_of_work": "face needing a flux polyhedron (truncation FLOPs)",
             "units_per_launch": nfaces_work / K,
             "launches_timed": flux_n,
@@ -242,7 +247,7 @@ def main():
         torch.cuda.empty_cache()
         out["served"] = served_leg(args, served, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds, args.method)
     print(json.dumps(out), flush=True)
 
 
@@ -351,11 +356,11 @@ def batched_leg(args, problems, dev):
     return res
 
 
-def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s):
+def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s, method):
     """The CPU reference (as it stands) on the host cores: the first steps of the same trajectory."""
     from oracle import oracle as O
     threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
-    om = O.OracleMesh(mesh)
+    om = O.OracleMesh(mesh, method=method)
     F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
     t0 = time.perf_counter()
     done = 0

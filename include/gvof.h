@@ -1,6 +1,7 @@
 /*
  * gvof.h -- C interface of the MI355X library for unsplit geometric VOF
- * advection with LSGIR reconstruction and face-matched (FMFPA) flux polyhedra.
+ * advection with LSGIR reconstruction and face-matched (FMFPA) or
+ * edge-matched (EMFPA) flux polyhedra.
  *
  * Method: J. Lopez and J. Hernandez, "gVOF: An open-source package for
  * unsplit geometric volume of fluid methods on arbitrary grids",
@@ -46,8 +47,15 @@ enum {
   GVOF_E_LIMIT = -6    /* a mesh entity exceeds a compiled-in capacity */
 };
 
-/* Flags for gvof_params.flags */
+/* Flags for gvof_params.flags (any other bit: GVOF_E_ARG from gvof_mesh_create) */
 #define GVOF_FLAG_NONE 0u
+/* Flux polyhedra by EMFPA (Sec. "Edge-matched flux polyhedron": vertices moved
+ * back along their streak lines, Eq. streak-line2; each lateral face as four
+ * triangles about its vertex mean; 3I+1 vertices, 5I+1 faces) instead of
+ * FMFPA (Sec. "Face-matched flux polyhedron").  Edge-matched polyhedra of
+ * faces with a common vertex share their back vertex and lateral faces to the
+ * last bit.  fmfpa_degen is not used with this flag. */
+#define GVOF_FLAG_EMFPA 1u
 
 typedef struct gvof_params {
   double eps;         /* volume-fraction tolerance (Sec. "Interface reconstruction"); 1e-12 as in all tests */

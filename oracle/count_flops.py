@@ -7,7 +7,7 @@ the sampled steps the counting build evaluates the flux of a random sample of
 faces that need flux polyhedra and the reconstruction of a random sample of
 interfacial cells, and reports operations per face and per cell.
 
-    python oracle/count_flops.py [--n 64] [--steps 0,60,120] [--faces 300] [--cells 300]
+    python oracle/count_flops.py [--n 64] [--steps 0,60,120] [--faces 300] [--cells 300] [--method emfpa]
 """
 from __future__ import annotations
 
@@ -33,11 +33,12 @@ def main():
     ap.add_argument("--faces", type=int, default=300)
     ap.add_argument("--cells", type=int, default=300)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa"])
     args = ap.parse_args()
     O.set_threads(args.threads)
     m = inputs.cartesian_mesh(args.n) if args.kind == "cartesian" else inputs.jittered_mesh(args.n, seed=1)
-    om = O.OracleMesh(m)
-    cm = O.OracleMesh(m, counting=True)
+    om = O.OracleMesh(m, method=args.method)
+    cm = O.OracleMesh(m, counting=True, method=args.method)
     O.set_threads(1, counting=True)
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
@@ -72,9 +73,10 @@ def main():
                   f"running flops/face {face_flops / face_n:.0f}, flops/cell {cell_flops / cell_n:.0f}", flush=True)
         F, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dts, Fc)
         t += sched[s]
-    print(f"workload: {args.kind} {args.n}^3 Enright T=3 CFL 0.5, dt={dt:.6g}; sampled steps {sample_steps}")
+    print(f"workload: {args.kind} {args.n}^3 Enright T=3 CFL 0.5, dt={dt:.6g}, {args.method}; "
+          f"sampled steps {sample_steps}")
     print(f"FLOPS_PER_FLUX_FACE {face_flops / face_n:.1f}  (sample {face_n} faces)")
-    print(f"  of which FMFPA polyhedron (with its signed-volume check) {poly_flops / face_n:.1f}, "
+    print(f"  of which the polyhedron (with its signed-volume check) {poly_flops / face_n:.1f}, "
           f"truncation {(face_flops - poly_flops) / face_n:.1f}")
     print(f"FLOPS_PER_RECON_CELL {cell_flops / cell_n:.1f}  (sample {cell_n} cells)")
     print(f"elapsed {time.time() - t0:.1f}s")

@@ -150,6 +150,9 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
     if (!std::isfinite(vx[v]) || !std::isfinite(vy[v]) || !std::isfinite(vz[v]))
       return fail(nullptr, GVOF_E_MESH, "vertex %d not finite", v);
 
+  if (params && (params->flags & ~GVOF_FLAG_EMFPA))
+    return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~GVOF_FLAG_EMFPA));
+
   gvof_mesh* m = new gvof_mesh;
   m->nv = nv;
   m->nf = nf;
@@ -407,9 +410,13 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   {
     int maxI = 3;
     for (size_t f = 0; f < nf; ++f) maxI = std::max(maxI, m->fv_ptr[f + 1] - m->fv_ptr[f]);
-    d.pts_per_slot = 2 * maxI + 2;  // polyhedron points, then the face centre
+    const bool em = (m->p.flags & GVOF_FLAG_EMFPA) != 0;
+    // polyhedron points, the face centre, then the EMFPA lateral centres
+    d.pts_per_slot = (em ? 3 : 2) * maxI + 2;
     d.poly_cap = (int)std::min<size_t>(nf, std::max<size_t>(65536, nf / 4));
-    d.item_cap = (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 4 * nf));
+    // EMFPA faces carry 5I flux tets against 3I
+    const size_t per_face = em ? 7 : 4, floor_pairs = em ? (size_t(7) << 20) : (size_t(1) << 22);
+    d.item_cap = (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(floor_pairs, per_face * nf));
     d.item_cap -= d.item_cap % gvof::kItemRegions;
     // units: up to about 12 per face of the general cells (6 per cell-face
     // incidence, each face counting for both of its cells) at the most stretched
@@ -449,6 +456,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
+  d.emfpa = (m->p.flags & GVOF_FLAG_EMFPA) ? 1 : 0;
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
 }

@@ -50,11 +50,11 @@ struct DevMesh {
   int* upwind;
   int *list_cells, *list_faces;
   // flux work staging: polyhedron points per listed face, (face, cell, tet) pairs
-  double* poly;        // [slot][pts_per_slot][3]: x_0..x_{I-1}, b_0..b_{I-1}, apex, face centre
+  double* poly;        // [slot][pts_per_slot][3]: x_0..x_{I-1}, b_0..b_{I-1}, apex, face centre, then (EMFPA) m_0..m_{I-1}
   int pts_per_slot, poly_cap;
   int *item_off, *item_cnt;   // per slot (cnt = -1: face handled by the overflow kernel)
   int *item_slot, *item_cell;  // per pair
-  unsigned short* item_tm;     // per pair: tet index, box cut mask, first-cut width, face vertex count
+  unsigned short* item_tm;     // per pair: flux tet, box cut mask, first-cut width, face vertex count
   double* item_vol;
   int item_cap;
   struct RegionCounters* regions;  // kItemRegions, one cache line each
@@ -70,6 +70,7 @@ struct DevMesh {
   int* counters;  // [0] tag-0 cells, [1] tag-0 faces, [2] geometry error flags, [3] refine cells
   unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
+  int emfpa;    // flux polyhedra by EMFPA (else FMFPA)
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);

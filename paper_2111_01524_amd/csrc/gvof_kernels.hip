@@ -1,5 +1,6 @@
 // gVOF hot path on gfx950: grid geometry, tagging + cut-off, LSGIR + plane
-// constant, face flux volumes, FMFPA flux polyhedra with signed truncation,
+// constant, face flux volumes, FMFPA or EMFPA flux polyhedra with signed
+// truncation,
 // and the volume-fraction update (Lopez & Hernandez, arXiv 2111.01524).
 //
 // Sweeps over faces / cells / vertices use one lane per item in coalesced SoA
@@ -388,9 +389,12 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
   }
 }
 
-// ============================================================== FMFPA + truncation
+// ============================================================== flux polyhedra + truncation
 constexpr int kFluxLanes = 64;
-constexpr int kMaxPts = 2 * kMaxFaceVerts + 1;
+// Points of a polyhedron, in LDS and in its slot: x_0..x_{I-1}, b_0..b_{I-1},
+// apex (2I), face centre (2I+1), then for EMFPA the lateral-face centres
+// m_0..m_{I-1} (2I+2..3I+1).
+constexpr int kMaxPts = 3 * kMaxFaceVerts + 2;
 constexpr int kMaxCand = 2 + 2 * kMaxNeighbours;
 
 __device__ inline bool box_overlap(d3 alo, d3 ahi, d3 blo, d3 bhi) {
@@ -424,19 +428,34 @@ __device__ inline void cell_piece(const DevMesh& M, int k, int m, d3& t0, d3& t1
   t0 = t1 = t2 = mk3(0.0, 0.0, 0.0);
 }
 
-// Flux tet t of the polyhedron (apex at the face centre c): for edge i,
-// kind 0 (x_{i+1}, x_i, b_{i+1}), kind 1 (x_i, b_i, b_{i+1}), kind 2 (a, b_{i+1}, b_i).
-__device__ inline void flux_tet_points(int t, int I, int& i1, int& i2, int& i3) {
-  int i = t / 3, kind = t - 3 * i;
-  int j = (i + 1 == I) ? 0 : i + 1;
-  i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
-  i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
-  i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
+// Flux tets per face edge: three for FMFPA, five for EMFPA.
+__device__ inline int tets_per_edge(const DevMesh& M) { return M.emfpa ? 5 : 3; }
+
+// Flux tet t of the polyhedron (the fourth point is the face centre c), for
+// edge i (j = i+1):
+//   FMFPA kind 0 (x_j, x_i, b_j), 1 (x_i, b_i, b_j), 2 (a, b_j, b_i);
+//   EMFPA kind 0 (x_j, x_i, m_i), 1 (x_i, b_i, m_i), 2 (b_i, b_j, m_i),
+//         3 (b_j, x_j, m_i), 4 (a, b_j, b_i)
+// (EMFPA: the lateral quad x_j, x_i, b_i, b_j as four triangles to its centre).
+__device__ inline void flux_tet_points(int t, int I, bool em, int& i1, int& i2, int& i3) {
+  const int i3e = t / 3, i5e = t / 5;  // constant divisions, both cheap
+  const int i = em ? i5e : i3e, kind = t - (em ? 5 : 3) * i;
+  const int j = (i + 1 == I) ? 0 : i + 1;
+  if (em) {
+    const int mi = 2 * I + 2 + i;
+    i1 = kind == 0 ? j : kind == 1 ? i : kind == 2 ? I + i : kind == 3 ? I + j : 2 * I;
+    i2 = kind == 0 ? i : kind == 1 ? I + i : kind == 2 ? I + j : kind == 3 ? j : I + j;
+    i3 = kind == 4 ? I + i : mi;
+  } else {
+    i1 = kind == 0 ? j : (kind == 1 ? i : 2 * I);
+    i2 = kind == 0 ? i : (kind == 1 ? I + i : I + j);
+    i3 = kind == 0 ? I + j : (kind == 1 ? I + j : I + i);
+  }
 }
 
 // LDS working set of one wavefront building one flux polyhedron.
 struct FluxLds {
-  double px[kMaxPts], py[kMaxPts], pz[kMaxPts];  // x_0..x_{I-1}, b_0..b_{I-1}, apex
+  double px[kMaxPts], py[kMaxPts], pz[kMaxPts];  // the polyhedron's points (slot layout)
   double ux[kMaxFaceVerts], uy[kMaxFaceVerts], uz[kMaxFaceVerts];
   double mx[kMaxFaceVerts], my[kMaxFaceVerts], mz[kMaxFaceVerts];
   int cand[kMaxCand];
@@ -447,10 +466,11 @@ struct FluxLds {
   signed char ctag[kMaxCand], cbox[kMaxCand];
 };
 
-// FMFPA polyhedron of face f into S.px/py/pz, in phases over the lanes of
-// the face's group (lane = index within the group; the caller puts x_i, u_i
-// of the face's vertices in S.px/py/pz[i], S.ux/uy/uz[i] first, and
-// synchronises between phases).
+// Flux polyhedron of face f into S.px/py/pz, in phases over the lanes of the
+// face's group (lane = index within the group; the caller puts x_i, u_i of
+// the face's vertices in S.px/py/pz[i], S.ux/uy/uz[i] first, and
+// synchronises between phases).  FMFPA: lateral planes, back vertices, apex;
+// EMFPA: streak-line back vertices, lateral centres, apex.
 // Lateral planes: lanes 0..I-1 take the plane through edge i parallel to the
 // edge-centre velocity.
 template <class Lds>
@@ -489,10 +509,35 @@ __device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt, int
   }
 }
 
+// EMFPA back vertices: lanes 0..I-1 move x_i back along its streak line,
+// Eq. (streak-line2).  The value depends on the vertex alone, so every face
+// through the vertex gets the same bits.
+template <class Lds>
+__device__ inline void poly_streak(Lds& S, int I, double dt, int lane) {
+  if (lane < I) {
+    S.px[I + lane] = S.px[lane] - dt * S.ux[lane];
+    S.py[I + lane] = S.py[lane] - dt * S.uy[lane];
+    S.pz[I + lane] = S.pz[lane] - dt * S.uz[lane];
+  }
+}
+
+// EMFPA lateral-face centres: lanes 0..I-1 take the vertex mean of
+// (x_i, x_{i+1}, b_{i+1}, b_i), summed in pairs of like points so that the
+// faces on either side of the edge get the same bits.
+template <class Lds>
+__device__ inline void poly_centres(Lds& S, int I, int lane) {
+  if (lane < I) {
+    const int j = (lane + 1 == I) ? 0 : lane + 1, b = I + lane, bj = I + j, m = 2 * I + 2 + lane;
+    S.px[m] = ((S.px[lane] + S.px[j]) + (S.px[b] + S.px[bj])) * 0.25;
+    S.py[m] = ((S.py[lane] + S.py[j]) + (S.py[b] + S.py[bj])) * 0.25;
+    S.pz[m] = ((S.pz[lane] + S.pz[j]) + (S.pz[b] + S.pz[bj])) * 0.25;
+  }
+}
+
 // Apex: the back-vertex mean moved along S until the polyhedron's signed
 // volume equals V_d (every lane computes the same values; lane 0 stores).
 template <class Lds>
-__device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, double vd, int lane) {
+__device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, bool em, d3 c, d3 Sv, double vd, int lane) {
   d3 g = mk3(0.0, 0.0, 0.0);
   for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
   double dI = (double)I;
@@ -502,7 +547,17 @@ __device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, d
     int j = (i + 1 == I) ? 0 : i + 1;
     d3 xi = mk3(S.px[i], S.py[i], S.pz[i]) - c, xj = mk3(S.px[j], S.py[j], S.pz[j]) - c;
     d3 bi = mk3(S.px[I + i], S.py[I + i], S.pz[I + i]) - c, bj = mk3(S.px[I + j], S.py[I + j], S.pz[I + j]) - c;
-    V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
+    if (em) {
+      const int m = 2 * I + 2 + i;
+      const d3 mi = mk3(S.px[m], S.py[m], S.pz[m]) - c;
+      V0 += det3f(xj, xi, mi);
+      V0 += det3f(xi, bi, mi);
+      V0 += det3f(bi, bj, mi);
+      V0 += det3f(bj, xj, mi);
+      V0 += det3f(g - c, bj, bi);
+    } else {
+      V0 += det3f(xj, xi, bj) + det3f(xi, bi, bj) + det3f(g - c, bj, bi);
+    }
     W += det3f(Sv, bj, bi);
   }
   V0 *= (1.0 / 6.0);
@@ -520,7 +575,9 @@ __device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, d3 c, d3 Sv, d
   }
 }
 
-// Bounding box of the polyhedron (the face centre included).
+// Bounding box of the polyhedron (the face centre included; an EMFPA lateral
+// centre, a rounded mean of four points already in the box, cannot leave it:
+// rounding is monotone).
 template <class Lds>
 __device__ inline void poly_box(const Lds& S, int I, d3 c, d3& plo, d3& phi) {
   plo = c;
@@ -549,13 +606,19 @@ __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, 
     S.uz[lane] = uv[2 * nv + v];
   }
   __syncthreads();
-  poly_lateral(S, I, lane);
-  __syncthreads();
-  poly_back(M, S, I, dt, lane);
+  if (M.emfpa) {
+    poly_streak(S, I, dt, lane);
+    __syncthreads();
+    poly_centres(S, I, lane);
+  } else {
+    poly_lateral(S, I, lane);
+    __syncthreads();
+    poly_back(M, S, I, dt, lane);
+  }
   __syncthreads();
   c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
   Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-  poly_apex(M, S, I, c, Sv, M.Vd[f], lane);
+  poly_apex(M, S, I, M.emfpa != 0, c, Sv, M.Vd[f], lane);
   __syncthreads();
   poly_box(S, I, c, plo, phi);
 }
@@ -679,28 +742,33 @@ __device__ inline int candidate_cell(const DevMesh& M, int j, int o, int ob, int
   return M.nb_idx[nbb + j - on - 2];
 }
 
-// Pair word tm: bits 0-4 the flux tet, 5-10 the mask of the box planes that
-// cut it, bit 11 set when the first of those cuts keeps three tetrahedra,
-// 12-15 the face's vertex count.
-constexpr int kTmWideBit = 11;
-__device__ inline unsigned tm_mask(unsigned tm) { return (tm >> 5) & 63u; }
-__device__ inline int tm_verts(unsigned tm) { return (int)((tm >> 12) & 15u); }
+// Pair word tm: bits 0-5 the flux tet (< 5 kMaxFaceVerts), 6-11 the mask of
+// the box planes that cut it, bit 12 set when the first of those cuts keeps
+// three tetrahedra, 13-15 the face's vertex count minus 3.
+constexpr int kTmWideBit = 12;
+static_assert(5 * kMaxFaceVerts <= 64 && kMaxFaceVerts - 3 <= 7, "pair word fields");
+__device__ inline unsigned tm_tet(unsigned tm) { return tm & 63u; }
+__device__ inline unsigned tm_mask(unsigned tm) { return (tm >> 6) & 63u; }
+__device__ inline int tm_verts(unsigned tm) { return (int)((tm >> 13) & 7u) + 3; }
+__device__ inline unsigned tm_word(int t, unsigned mask, int I) {
+  return (unsigned)t | (mask << 6) | ((unsigned)(I - 3) << 13);
+}
 
 // Test of staged candidate kc against flux tet t: the tet's box meets the
 // cell's box and, for a box cell, the tet is not entirely outside one box
 // plane.
-__device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int T3, int q, unsigned& tm, int& kc) {
-  const int t = q % T3;
-  kc = q / T3;
+__device__ inline bool pair_test(const PrepLds& S, d3 c, int I, bool em, int TF, int q, unsigned& tm, int& kc) {
+  const int t = q % TF;
+  kc = q / TF;
   int i1, i2, i3;
-  flux_tet_points(t, I, i1, i2, i3);
+  flux_tet_points(t, I, em, i1, i2, i3);
   Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]), mk3(S.px[i3], S.py[i3], S.pz[i3])};
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
   bool keep = box_overlap(tlo, thi, B.lo, B.hi);
   unsigned mask = 0;
   if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
-  tm = (unsigned)t | (mask << 5) | ((unsigned)I << 12);
+  tm = tm_word(t, mask, I);
   if (mask) {
     // the first cut keeps three tetrahedra (two or more vertices inside) or one:
     // a hint for grouping pairs of like work in the truncation kernel
@@ -739,7 +807,7 @@ __device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, uns
 }
 
 // Stage the flux work of every listed face, a group of G lanes per face
-// (64 / G faces per wavefront): build its FMFPA polyhedron (stored per slot),
+// (64 / G faces per wavefront): build its flux polyhedron (stored per slot),
 // gather the candidate cells that hold fluid and whose boxes meet the
 // polyhedron's box, then emit one (face, cell, flux tet) pair for every flux
 // tet whose box meets such a cell's box (box cells: the tet is also not
@@ -750,7 +818,9 @@ __device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, uns
 // The loads of the face's vertices and of its first 64 listed cells form two
 // independent chains; they are issued together, straight-line with clamped
 // indices, and the cells' data go to LDS as soon as they arrive.
-template <int G>
+// EM selects EMFPA (the mesh's method; an instance per method keeps the
+// FMFPA instance's registers as they are).
+template <int G, bool EM>
 __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ uv, double dt) {
   static_assert(G == 32 || G == 64, "lanes per face");
   constexpr int NG = kFluxLanes / G;  // faces per wavefront
@@ -823,18 +893,30 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       S.chix[j] = hiq[r].x; S.chiy[j] = hiq[r].y; S.chiz[j] = hiq[r].z;
       S.cbox[j] = bq[r];
     }
-    wave_lds_sync();
-    poly_lateral(S, I, sub);
+    constexpr bool em = EM;
     const double fdt = face_dt(M, f, dt);
+    if (em) {  // the lane holding x_i, u_i moves it back, then the centres
+      if (sub < I) {
+        S.px[I + sub] = x.x - fdt * u.x;
+        S.py[I + sub] = x.y - fdt * u.y;
+        S.pz[I + sub] = x.z - fdt * u.z;
+      }
+      wave_lds_sync();
+      poly_centres(S, I, sub);
+    } else {
+      wave_lds_sync();
+      poly_lateral(S, I, sub);
+      wave_lds_sync();
+      poly_back(M, S, I, fdt, sub);
+    }
     wave_lds_sync();
-    poly_back(M, S, I, fdt, sub);
-    wave_lds_sync();
-    poly_apex(M, S, I, c, Sv, vd, sub);
+    poly_apex(M, S, I, em, c, Sv, vd, sub);
     wave_lds_sync();
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
-    if (sub <= 2 * I) {  // the points, then the face centre (the flux tets' common vertex)
+    // the points, the face centre (the flux tets' common vertex), the lateral centres
+    if (sub <= 2 * I || (em && sub >= 2 * I + 2 && sub <= 3 * I + 1)) {
       P[3 * sub] = S.px[sub];
       P[3 * sub + 1] = S.py[sub];
       P[3 * sub + 2] = S.pz[sub];
@@ -904,8 +986,8 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       }
       continue;
     }
-    const int T3 = 3 * I;
-    const int total = ncand * T3;
+    const int TF = (em ? 5 : 3) * I;
+    const int total = ncand * TF;
     if (total <= kFluxLanes) {
       // up to NR rounds: the tests stay in registers between counting and writing
       bool kp[NR];
@@ -918,7 +1000,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
         const int q = sub + G * r;
         tmq[r] = 0;
         kcq[r] = 0;
-        kp[r] = q < total && pair_test(S, c, I, T3, q, tmq[r], kcq[r]);
+        kp[r] = q < total && pair_test(S, c, I, em, TF, q, tmq[r], kcq[r]);
         bmq[r] = __ballot(kp[r]) & gmask;
         count += __popcll(bmq[r]);
       }
@@ -939,7 +1021,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       for (int q0 = 0; q0 < total; q0 += G) {
         unsigned tm;
         int kc;
-        const bool kp = q0 + sub < total && pair_test(S, c, I, T3, q0 + sub, tm, kc);
+        const bool kp = q0 + sub < total && pair_test(S, c, I, em, TF, q0 + sub, tm, kc);
         count += __popcll(__ballot(kp) & gmask);
       }
       int base = 0;
@@ -950,7 +1032,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
         for (int q0 = 0; q0 < total; q0 += G) {
           unsigned tm = 0;
           int kc = 0;
-          const bool kp = q0 + sub < total && pair_test(S, c, I, T3, q0 + sub, tm, kc);
+          const bool kp = q0 + sub < total && pair_test(S, c, I, em, TF, q0 + sub, tm, kc);
           const unsigned long long bm = __ballot(kp) & gmask;
           if (kp) write_pair(M, base + written + __popcll(bm & lbelow), it, S.cand[kc], tm);
           written += __popcll(bm);
@@ -967,10 +1049,10 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
 // Flux tet of a staged pair from its pair word alone: the tet and the face's
 // vertex count are in the word, the points and the face centre in the slot.
 __device__ inline Tet staged_tet(const DevMesh& M, int slot, unsigned tm) {
-  const int t = tm & 31, I = tm_verts(tm);
+  const int t = tm_tet(tm), I = tm_verts(tm);
   const double* P = M.poly + (size_t)slot * M.pts_per_slot * 3;
   int i1, i2, i3;
-  flux_tet_points(t, I, i1, i2, i3);
+  flux_tet_points(t, I, M.emfpa, i1, i2, i3);
   const int ic = 2 * I + 1;
   return Tet{mk3(P[3 * ic], P[3 * ic + 1], P[3 * ic + 2]), mk3(P[3 * i1], P[3 * i1 + 1], P[3 * i1 + 2]),
              mk3(P[3 * i2], P[3 * i2 + 1], P[3 * i2 + 2]), mk3(P[3 * i3], P[3 * i3 + 1], P[3 * i3 + 2])};
@@ -1559,17 +1641,17 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
     d3 c, Sv, plo, phi;
     flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
     const int ncand = flux_candidates(M, S, f, plo, phi);
-    const int T3 = 3 * I;
-    const int total = ncand * T3;
+    const int TF = tets_per_edge(M) * I;
+    const int total = ncand * TF;
     double acc = 0.0;  // identical in every lane
     for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
       const int q = q0 + lane;
       int keep = 0;
       double v = 0.0;
       if (q < total) {
-        const int t = q % T3, kc = q / T3;
+        const int t = q % TF, kc = q / TF;
         int i1, i2, i3;
-        flux_tet_points(t, I, i1, i2, i3);
+        flux_tet_points(t, I, M.emfpa, i1, i2, i3);
         Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
               mk3(S.px[i3], S.py[i3], S.pz[i3])};
         d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
@@ -2029,8 +2111,14 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   const int pair_grid = kItemRegions * L.pair_blocks_per_region;
   if (reset) k_reset_advect<<<1, 256, 0, s>>>(M);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
-  if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
-  else TIMED(K_FLUX_PREP, (k_flux_prep<64><<<blocks_for(M.nf, 1, L.prep_blocks), kFluxLanes, 0, s>>>(M, uv, dt)));
+  const int pb = blocks_for(M.nf, 1, L.prep_blocks);
+  if (M.emfpa) {
+    if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32, true><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+    else TIMED(K_FLUX_PREP, (k_flux_prep<64, true><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+  } else {
+    if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32, false><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+    else TIMED(K_FLUX_PREP, (k_flux_prep<64, false><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+  }
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, kItemsBlock, 0, s>>>(M)));
   if (!M.all_box) {
     if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("GVOF_LIB_PATH") or os.path.join(HERE, "libgvof.so")
 
 GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
+GVOF_FLAG_NONE, GVOF_FLAG_EMFPA = 0, 1
 
 
 class GvofError(RuntimeError):
@@ -304,13 +305,23 @@ def gvof_last_error(h=None) -> str:
 
 # ------------------------------------------------------------------ convenience wrapper
 class GvofMesh:
-    """A mesh handle bound to a torch-allocated device workspace."""
+    """A mesh handle bound to a torch-allocated device workspace.
 
-    def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None):
+    method "emfpa" sets GVOF_FLAG_EMFPA in the parameters (flux polyhedra by
+    EMFPA); "fmfpa" leaves the flags as given.
+    """
+
+    def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None,
+                 method: str = "fmfpa"):
         import torch
+        if method not in ("fmfpa", "emfpa"):
+            raise ValueError(f"unknown flux polyhedron method {method!r}")
         self.torch = torch
         self.device = torch.device(device)
         self.mesh = mesh
+        if method == "emfpa":
+            params = params if params is not None else gvof_params_default()
+            params.flags |= GVOF_FLAG_EMFPA
         if handle is None:
             handle = gvof_mesh_create(mesh.vx, mesh.vy, mesh.vz, mesh.fv_ptr, mesh.fv_idx, mesh.owner, mesh.neigh,
                                       mesh.nc, params)
@@ -387,9 +398,15 @@ class GvofBatch(GvofMesh):
     union (gvof_batch_create), bound to one torch-allocated workspace.
     `offsets` gives each problem's vertex / face / cell ranges."""
 
-    def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None, parts=None):
+    def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None, parts=None,
+                 method: str = "fmfpa"):
         """parts: optional handles already made by gvof_mesh_create for these
-        meshes (taken over and destroyed here)."""
+        meshes (taken over and destroyed here).  method as for GvofMesh."""
+        if method not in ("fmfpa", "emfpa"):
+            raise ValueError(f"unknown flux polyhedron method {method!r}")
+        if method == "emfpa":
+            params = params if params is not None else gvof_params_default()
+            params.flags |= GVOF_FLAG_EMFPA
         parts = list(parts) if parts is not None else []
         try:
             for m in meshes[len(parts):]:

@@ -189,3 +189,27 @@ def test_unit_buffer_only_for_meshes_with_general_cells():
     grown = ((4 << 20) - 256) * (16 + 4)  # all boxes: a minimal buffer of 256 entries
     assert moved - base >= grown
     assert ws(inputs.jittered_mesh(6, seed=2)) - base >= grown
+
+
+def test_flags_select_emfpa_and_unknown_bits_are_rejected():
+    """GVOF_FLAG_EMFPA is the one flag: EMFPA slots hold the lateral centres and
+    the pair buffer is sized for 5I flux tets per face (larger workspace); any
+    other bit is an argument error; a batch of mixed methods is rejected."""
+    m = inputs.cartesian_mesh(4)
+    pe = gvof.gvof_params_default()
+    pe.flags = gvof.GVOF_FLAG_EMFPA
+    a = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+    b = gvof.gvof_mesh_create(*m.arrays(), m.nc, pe)
+    try:
+        assert gvof.gvof_mesh_workspace_bytes(b) > gvof.gvof_mesh_workspace_bytes(a)
+        with pytest.raises(gvof.GvofError):
+            gvof.gvof_batch_create([a, b])
+    finally:
+        gvof.gvof_mesh_destroy(a)
+        gvof.gvof_mesh_destroy(b)
+    for bad in (2, 4, 0x80000000, 3):
+        p = gvof.gvof_params_default()
+        p.flags = bad
+        with pytest.raises(gvof.GvofError) as e:
+            gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
+        assert e.value.code == gvof.GVOF_E_ARG

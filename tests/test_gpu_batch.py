@@ -32,10 +32,10 @@ def gv():
     return gvof
 
 
-def build(gv, specs, stream=None):
+def build(gv, specs, stream=None, method="fmfpa"):
     torch, dev = torch_dev()
     P = [inputs.problem_inputs(s) for s in specs]
-    B = gv.GvofBatch([p["mesh"] for p in P], dev, stream=stream)
+    B = gv.GvofBatch([p["mesh"] for p in P], dev, stream=stream, method=method)
     uf = to_dev(torch, dev, inputs.concat_soa([p["uf"] for p in P]))
     uv = to_dev(torch, dev, inputs.concat_soa([p["uv"] for p in P]))
     return torch, dev, P, B, uf, uv
@@ -86,10 +86,12 @@ def test_batch_steps_bitwise_equal_alone(gv):
         assert np.array_equal(Fb[sl], Fa), q
 
 
-def test_batch_matches_oracle_teacher_forced(oracle_mod, gv):
-    torch, dev, P, B, uf, uv = build(gv, SPECS)
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method):
+    torch, dev, P, B, uf, uv = build(gv, SPECS, method=method)
+    log(f"batch vs oracle, {method}")
     act = to_dev(torch, dev, np.ones(len(P), np.uint8))
-    oms = [oracle_mod.OracleMesh(p["mesh"]) for p in P]
+    oms = [oracle_mod.OracleMesh(p["mesh"], method=method) for p in P]
     Fo = [om.init_fraction("sphere", p["shape"][1], 6) for om, p in zip(oms, P)]
     for s in range(4):
         F = to_dev(torch, dev, np.concatenate(Fo))
@@ -135,8 +137,10 @@ def test_graph_replay_equals_eager(gv):
         B.status()
 
 
-def test_launch_shapes_do_not_change_results(gv):
-    torch, dev, P, B, uf, uv = build(gv, SPECS)
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+def test_launch_shapes_do_not_change_results(gv, method):
+    torch, dev, P, B, uf, uv = build(gv, SPECS, method=method)
+    log(f"launch shapes, {method}")
     F = B.init_fraction_each([p["shape"] for p in P], 6)
     act = to_dev(torch, dev, np.ones(len(P), np.uint8))
     dt = dt_row(torch, dev, P, 0)

@@ -27,10 +27,11 @@ def gv():
     return gvof
 
 
-def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label):
+def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa"):
     torch, dev = torch_dev()
-    om = oracle_mod.OracleMesh(m)
-    g = gv.GvofMesh(m, dev)
+    om = oracle_mod.OracleMesh(m, method=method)
+    g = gv.GvofMesh(m, dev, method=method)
+    label = f"{label} {method}"
     ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
     V = om.geometry()["V"]
     for s, dt in enumerate(dts):
@@ -55,22 +56,25 @@ def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label):
     return F
 
 
-def test_polygon_face_general_cells(oracle_mod, gv):
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+def test_polygon_face_general_cells(oracle_mod, gv, method):
     m = inputs.jittered_mesh(7, seed=3, split=False)
     assert m.fv_ptr[1] == 4
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     F = oracle_mod.OracleMesh(m).init_fraction("sphere", [0.45, 0.5, 0.52, 0.27], 4)
-    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt, -dt], F, "quad-faced distorted 7^3")
+    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt, -dt], F, "quad-faced distorted 7^3", method)
 
 
-@pytest.mark.parametrize("kind,n", [("cartesian", 1), ("cartesian", 2), ("jittered", 2)])
-def test_smallest_meshes(oracle_mod, gv, kind, n):
+@pytest.mark.parametrize("kind,n,method", [("cartesian", 1, "fmfpa"), ("cartesian", 2, "fmfpa"),
+                                           ("jittered", 2, "fmfpa"), ("cartesian", 1, "emfpa"),
+                                           ("jittered", 2, "emfpa")])
+def test_smallest_meshes(oracle_mod, gv, kind, n, method):
     m = inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=5)
     uf, uv = inputs.velocity_uniform(m, (0.3, 0.2, 0.1))
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     F = oracle_mod.OracleMesh(m).init_fraction("sphere", [0.4, 0.45, 0.5, 0.3], 6)
-    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt], F, f"{kind} {n}^3")
+    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt], F, f"{kind} {n}^3", method)
 
 
 def test_empty_field_and_zero_step(oracle_mod, gv):

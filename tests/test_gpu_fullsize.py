@@ -4,7 +4,8 @@ face is compared with the oracle, teacher-forced from the oracle's state.
 
   - 64^3 Cartesian, Enright field with period 3, CFL 0.5: the first two steps
     and step 100 (the oracle runs the trajectory up to there);
-  - 64^3 distorted (+-0.25h, seed 1), same field: the first two steps.
+  - 64^3 distorted (+-0.25h, seed 1), same field: the first two steps, with
+    FMFPA and with EMFPA flux polyhedra.
 
 Bars as in the small-size parity tests: tags and upwind cells bit for bit,
 V_d bit for bit, |dV_F| <= 1e-12 V, |dF| <= 1e-12 per cell.
@@ -43,14 +44,15 @@ def _step_parity(oracle_mod, g, om, F, uf, uv, ufd, uvd, dts, V, torch, dev, lab
     return F1
 
 
-@pytest.mark.parametrize("kind,later", [("cartesian", 100), ("jittered", None)])
-def test_full_size_parity(oracle_mod, kind, later):
+@pytest.mark.parametrize("kind,later,method", [("cartesian", 100, "fmfpa"), ("jittered", None, "fmfpa"),
+                                               ("jittered", None, "emfpa")])
+def test_full_size_parity(oracle_mod, kind, later, method):
     from paper_2111_01524_amd import gvof
     torch, dev = torch_dev()
     m = inputs.cartesian_mesh(64) if kind == "cartesian" else inputs.jittered_mesh(64, seed=1)
-    log(f"full size {kind} 64^3: faces {m.nf} cells {m.nc}")
-    om = oracle_mod.OracleMesh(m)
-    g = gvof.GvofMesh(m, dev)
+    log(f"full size {kind} 64^3 {method}: faces {m.nf} cells {m.nc}")
+    om = oracle_mod.OracleMesh(m, method=method)
+    g = gvof.GvofMesh(m, dev, method=method)
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     sched = inputs.step_schedule(3.0, dt)

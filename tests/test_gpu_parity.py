@@ -101,17 +101,21 @@ def _velocity(kind_field, m):
     return inputs.velocity_enright(m)
 
 
-@pytest.mark.parametrize("kind,n,field,steps", [
-    ("cartesian", 16, "uniform", 20),     # the 16^3 translation workload, every step
-    ("cartesian", 20, "enright", 6),
-    ("jittered", 12, "enright", 4),
-    ("jittered", 10, "uniform", 4),
+@pytest.mark.parametrize("kind,n,field,steps,method", [
+    ("cartesian", 16, "uniform", 20, "fmfpa"),     # the 16^3 translation workload, every step
+    ("cartesian", 20, "enright", 6, "fmfpa"),
+    ("jittered", 12, "enright", 4, "fmfpa"),
+    ("jittered", 10, "uniform", 4, "fmfpa"),
+    ("cartesian", 16, "uniform", 6, "emfpa"),
+    ("cartesian", 20, "enright", 6, "emfpa"),
+    ("jittered", 12, "enright", 4, "emfpa"),
+    ("jittered", 10, "uniform", 3, "emfpa"),
 ])
-def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps):
+def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps, method):
     torch, dev = torch_dev()
     m = make_mesh(kind, n)
-    om = oracle_mod.OracleMesh(m)
-    g = gv.GvofMesh(m, dev)
+    om = oracle_mod.OracleMesh(m, method=method)
+    g = gv.GvofMesh(m, dev, method=method)
     uf, uv = _velocity(field, m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
@@ -119,7 +123,7 @@ def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps):
     V = om.geometry()["V"]
     worst = 0.0
     for s in range(steps):
-        log(f"advect {kind} n={n} {field} step {s}")
+        log(f"advect {method} {kind} n={n} {field} step {s}")
         sgn = 1.0 if field == "uniform" else inputs.enright_time_factor((s + 0.5) * dt, 3.0)
         dts = dt * sgn
         (Fd, T, tc_g, pl_g, Fcut_g), (Fc, Fs, tn, tf, tc, pl) = reconstruct_both(oracle_mod, g, om, F, torch, dev)
@@ -141,10 +145,12 @@ def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps):
     log(f"worst |dF| = {worst:.2e}")
 
 
-def test_step_is_deterministic(gv):
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+def test_step_is_deterministic(gv, method):
     torch, dev = torch_dev()
     m = make_mesh("jittered", 10)
-    g = gv.GvofMesh(m, dev)
+    log(f"determinism {method}")
+    g = gv.GvofMesh(m, dev, method=method)
     uf, uv = inputs.velocity_enright(m)
     ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
     F0 = g.init_fraction("sphere", SPHERE, 4)
