@@ -33,7 +33,7 @@ def main():
     ap.add_argument("--faces", type=int, default=300)
     ap.add_argument("--cells", type=int, default=300)
     ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa"])
+    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa", "nmfpa"])
     args = ap.parse_args()
     O.set_threads(args.threads)
     m = inputs.cartesian_mesh(args.n) if args.kind == "cartesian" else inputs.jittered_mesh(args.n, seed=1)
@@ -60,7 +60,7 @@ def main():
             face_flops += cm.flops(); face_n += sel.size
             cm.flops_reset()
             for f, vd in zip(sel, Vd_s):
-                cm.flux_polyhedron(int(f), uv, dts, float(vd))
+                cm.flux_polyhedron(int(f), uv, dts, float(vd), u_face=uf)
             poly_flops += cm.flops()
             cells = np.where(tc == 0)[0]
             csel = rng.choice(cells, min(args.cells, cells.size), replace=False)

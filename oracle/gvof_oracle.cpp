@@ -8,8 +8,9 @@
 //   plic-eq), LSGIR normals (Sec. LSGIR, Eqs. lsgir1, lsgir2, lsgir-beta),
 //   the plane constant enforcing the cell's volume fraction, face flux
 //   volumes (Eq. a-donacion), FMFPA flux polyhedra (Sec. "Face-matched flux
-//   polyhedron") or EMFPA ones (Sec. "Edge-matched flux polyhedron", chosen
-//   per mesh), their truncation by the PLIC half-spaces of the cells they
+//   polyhedron"), EMFPA ones (Sec. "Edge-matched flux polyhedron") or NMFPA
+//   ones (Sec. "Non-matched flux polyhedron"), chosen per mesh, their
+//   truncation by the PLIC half-spaces of the cells they
 //   overlap (Sec. "Fluid advected through cell faces") and the volume fraction
 //   update with clamp (Eq. fnext), plus the refinement initialisation (Sec.
 //   "Fluid volume fraction initialization").
@@ -217,7 +218,7 @@ struct OMesh {
   std::vector<real> V;
   std::vector<char> isbox;
   std::vector<std::vector<Tet>> tets;  // surface tets of every non-box cell
-  int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA
+  int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA, 2 NMFPA
 };
 
 // Surface triangles of cell c: triangle faces as they are, polygons fanned
@@ -682,9 +683,56 @@ void emfpa(const OMesh& M, int f, const double* uv, double dt_, real Vd, FluxPol
   }
 }
 
-// The flux polyhedron of face f by the mesh's method.
-void flux_poly(const OMesh& M, int f, const double* uv, double dt, real Vd, double degen, FluxPoly& P) {
+// --------------------------------------------------------------------------
+// NMFPA flux polyhedron (Sec. "Non-matched flux polyhedron").
+//   every vertex of the face moves back with the one face-centre velocity
+//   u_f: b_i = x_i - dt u_f (Eq. streak-line2 with u_f for every vertex);
+//   each lateral face (x_i, x_{i+1}, b_{i+1}, b_i) is then a planar
+//   parallelogram and the back face the translated cell face, so the
+//   polyhedron (I+2 faces, 2I vertices) has volume dt u_f.S = V_d with no
+//   adjustment.
+// Tets fanned from the face centre: for each edge i (j = i+1),
+//   (c; x_j, x_i, b_j), (c; x_i, b_i, b_j) (the FMFPA lateral split), and the
+//   planar back face fanned from b_0: (c; b_0, b_{k+1}, b_k), k = 1..I-2.
+// --------------------------------------------------------------------------
+void nmfpa(const OMesh& M, int f, const double* uf, double dt_, FluxPoly& P) {
+  int b0 = M.fptr[f], I = M.fptr[f + 1] - b0;
+  int nf = M.nf;
+  real dt = dt_;
+  V3 u = mk(uf[f], uf[nf + f], uf[2 * nf + f]);
+  P.I = I;
+  P.x.resize(I);
+  P.b.resize(I);
+  for (int i = 0; i < I; ++i) {
+    P.x[i] = M.X[M.fidx[b0 + i]];
+    P.b[i] = P.x[i] - dt * u;
+  }
+  P.c = M.fc[f];
+  P.a = P.b[0];
+  V3 c = P.c;
+  P.tets.clear();
+  P.sgn.clear();
+  std::vector<std::array<V3, 4>> t;
+  for (int i = 0; i < I; ++i) {
+    int j = (i + 1) % I;
+    t.push_back({c, P.x[j], P.x[i], P.b[j]});
+    t.push_back({c, P.x[i], P.b[i], P.b[j]});
+  }
+  for (int k = 1; k + 1 < I; ++k) t.push_back({c, P.b[0], P.b[k + 1], P.b[k]});
+  for (auto& T : t) {
+    real d = det3(T[1] - c, T[2] - c, T[3] - c);
+    if (d == real(0.0)) continue;
+    P.tets.push_back(T);
+    P.sgn.push_back(d > real(0.0) ? real(1.0) : real(-1.0));
+  }
+}
+
+// The flux polyhedron of face f by the mesh's method (uf: face velocities,
+// read by NMFPA only).
+void flux_poly(const OMesh& M, int f, const double* uf, const double* uv, double dt, real Vd, double degen,
+               FluxPoly& P) {
   if (M.method == 1) emfpa(M, f, uv, dt, Vd, P);
+  else if (M.method == 2) nmfpa(M, f, uf, dt, P);
   else fmfpa(M, f, uv, dt, Vd, degen, P);
 }
 
@@ -745,7 +793,7 @@ FaceOut face_flux(const OMesh& M, int f, const double* planes, const int8_t* tce
   else if (tface[f] == 1) o.VF = o.Vd;
   else {
     FluxPoly P;
-    flux_poly(M, f, uv, dt, o.Vd, degen, P);
+    flux_poly(M, f, uf, uv, dt, o.Vd, degen, P);
     o.degenerate = P.degenerate;
     o.VF = face_fluid_volume(M, f, P, planes, tcell);
   }
@@ -918,10 +966,10 @@ void* orc_mesh_new(int nv, const double* vx, const double* vy, const double* vz,
 
 void orc_mesh_free(void* h) { delete static_cast<OMesh*>(h); }
 
-// Flux polyhedra of the mesh: 0 FMFPA (default), 1 EMFPA.  Returns 0, or -1
-// for another value.
+// Flux polyhedra of the mesh: 0 FMFPA (default), 1 EMFPA, 2 NMFPA.  Returns
+// 0, or -1 for another value.
 int orc_mesh_set_method(void* h, int method) {
-  if (method != 0 && method != 1) return -1;
+  if (method < 0 || method > 2) return -1;
   static_cast<OMesh*>(h)->method = method;
   return 0;
 }
@@ -1056,15 +1104,16 @@ void orc_update(void* h, const double* Vd, const double* VF, const double* Fin, 
 }
 
 // The flux polyhedron of face f by the mesh's method: points x_0..x_{I-1},
-// b_0..b_{I-1}, apex, then (EMFPA) the lateral-face centres m_0..m_{I-1};
-// returns I (or -I when the apex is degenerate).  pts holds 3*(2I+1) doubles
-// (3*(3I+1) for EMFPA, xyz interleaved); vol_out gets the signed volume of
-// the tet fan.
-int orc_flux_polyhedron(void* h, int f, const double* uv, double dt, double Vd, double degen, double* pts,
-                        double* vol_out) {
+// b_0..b_{I-1}, apex (NMFPA: b_0 again, the back face's fan vertex), then
+// (EMFPA) the lateral-face centres m_0..m_{I-1}; returns I (or -I when the
+// apex is degenerate).  pts holds 3*(2I+1) doubles (3*(3I+1) for EMFPA, xyz
+// interleaved); vol_out gets the signed volume of the tet fan.  uf (face
+// velocities) is read by NMFPA only, uv (vertex velocities) by the others.
+int orc_flux_polyhedron(void* h, int f, const double* uf, const double* uv, double dt, double Vd, double degen,
+                        double* pts, double* vol_out) {
   OMesh& M = *static_cast<OMesh*>(h);
   FluxPoly P;
-  flux_poly(M, f, uv, dt, Vd, degen, P);
+  flux_poly(M, f, uf, uv, dt, Vd, degen, P);
   int I = P.I;
   for (size_t i = 0; i < P.m.size(); ++i) {
     double* q = pts + 3 * (2 * I + 1 + i);

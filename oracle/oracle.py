@@ -46,7 +46,8 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_advect.argtypes = [C.c_void_p, _d, _b, _b, _d, _d, C.c_double, C.c_double, _d, _d, _d, _d, _i]
         lib.orc_advect.restype = C.c_int
         lib.orc_update.argtypes = [C.c_void_p, _d, _d, _d, _d]
-        lib.orc_flux_polyhedron.argtypes = [C.c_void_p, C.c_int, _d, C.c_double, C.c_double, C.c_double, _d, _d]
+        lib.orc_flux_polyhedron.argtypes = [C.c_void_p, C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, _d,
+                                            _d]
         lib.orc_flux_polyhedron.restype = C.c_int
         lib.orc_tet_clip_volume.argtypes = [_d, C.c_int, _d]
         lib.orc_tet_clip_volume.restype = C.c_double
@@ -88,10 +89,11 @@ class OracleMesh:
     """The oracle's view of a mesh: topology and geometry built on the CPU.
 
     method selects the flux polyhedra: "fmfpa" (Sec. "Face-matched flux
-    polyhedron") or "emfpa" (Sec. "Edge-matched flux polyhedron").
+    polyhedron"), "emfpa" (Sec. "Edge-matched flux polyhedron") or "nmfpa"
+    (Sec. "Non-matched flux polyhedron").
     """
 
-    METHODS = {"fmfpa": 0, "emfpa": 1}
+    METHODS = {"fmfpa": 0, "emfpa": 1, "nmfpa": 2}
 
     def __init__(self, mesh, counting: bool = False, method: str = "fmfpa"):
         if method not in self.METHODS:
@@ -188,16 +190,18 @@ class OracleMesh:
         self.lib.orc_update(self.h, _p(Vd, _d), _p(VF, _d), _p(Fin, _d), _p(Fout, _d))
         return Fout
 
-    def flux_polyhedron(self, face, u_vert, dt, Vd, degen=1e-12):
+    def flux_polyhedron(self, face, u_vert, dt, Vd, degen=1e-12, u_face=None):
         """(points, signed volume of the tet fan, apex degenerate).
 
-        Points: x_0..x_{I-1}, b_0..b_{I-1}, apex, then for EMFPA the
-        lateral-face centres m_0..m_{I-1}.
+        Points: x_0..x_{I-1}, b_0..b_{I-1}, apex (NMFPA: b_0), then for EMFPA
+        the lateral-face centres m_0..m_{I-1}.  NMFPA reads u_face (3, nf),
+        the others u_vert (3, nv).
         """
-        uv = _dbl(u_vert)
+        uv = _dbl(u_vert) if u_vert is not None else np.zeros((3, self.nv))
+        uf = _dbl(u_face) if u_face is not None else np.zeros((3, self.nf))
         pts = np.zeros(3 * (3 * 8 + 1)); vol = np.zeros(1)
-        I = self.lib.orc_flux_polyhedron(self.h, int(face), _p(uv, _d), float(dt), float(Vd), degen, _p(pts, _d),
-                                         _p(vol, _d))
+        I = self.lib.orc_flux_polyhedron(self.h, int(face), _p(uf, _d), _p(uv, _d), float(dt), float(Vd), degen,
+                                         _p(pts, _d), _p(vol, _d))
         k = abs(I)
         npts = 3 * k + 1 if self.method == "emfpa" else 2 * k + 1
         return pts[: 3 * npts].reshape(-1, 3), float(vol[0]), I < 0

@@ -4,7 +4,8 @@ Given rational vertices, vertex/face velocities, dt and *unnormalised*
 rational PLIC planes, every quantity of the advection step is a rational
 function of the inputs: face area vectors, V_d, the FMFPA lateral-plane
 normals, line directions and back-vertex projections, the EMFPA streak-line
-back vertices and lateral-face centres, the apex shift, every clip point and
+back vertices and lateral-face centres, the NMFPA translated faces, the apex
+shift, every clip point and
 every volume.  This module recomputes them with Python
 Fractions, so its answers carry no rounding error at all.
 
@@ -293,6 +294,31 @@ class ExactMesh:
                 tets.append((t, 1 if d6 > 0 else -1))
         return tets, x, b, cen, apex, degenerate
 
+    def nmfpa(self, f, uf, dt):
+        """Exact NMFPA polyhedron (Sec. "Non-matched flux polyhedron"): the face
+        translated back by dt uf; its lateral faces and back face are planar, so
+        any triangulation bounds the same prism.  Here the lateral
+        parallelograms are split along (x_i, b_{i+1}) and the back face is
+        fanned from its vertex mean; tets join each surface triangle to the face
+        centre.  Returns (tets with signs, x, b)."""
+        vs = self.faces[f]
+        I = len(vs)
+        x = [self.X[v] for v in vs]
+        b = [sub(p, scl(dt, uf)) for p in x]
+        g = tuple(sum(p[a] for p in b) / I for a in range(3))
+        c = self.fc[f]
+        tris = []
+        for i in range(I):
+            j = (i + 1) % I
+            tris += [(x[j], x[i], b[i]), (x[j], b[i], b[j]), (g, b[j], b[i])]
+        tets = []
+        for (p, q, r) in tris:
+            t = (c, p, q, r)
+            d6 = tet_signed6(t)
+            if d6 != 0:
+                tets.append((t, 1 if d6 > 0 else -1))
+        return tets, x, b
+
     def face_flux(self, f, planes, tcell, tface, u_face, u_vert, dt, method="fmfpa"):
         """Exact (Vd, VF, upwind) of face f; planes[c] = ((nx,ny,nz), C) rational."""
         Vd = dt * dot(u_face[f], self.S[f])
@@ -305,6 +331,8 @@ class ExactMesh:
             return Vd, Vd, up
         if method == "emfpa":
             tets, *_ = self.emfpa(f, u_vert, dt, Vd)
+        elif method == "nmfpa":
+            tets, *_ = self.nmfpa(f, u_face[f], dt)
         else:
             tets, *_ = self.fmfpa(f, u_vert, dt, Vd)
         acc = ZERO
