@@ -31,8 +31,8 @@ sys.path.insert(0, ROOT)
 # performs), by flux polyhedron method, and per interfacial cell (LSGIR +
 # plane constant) on this workload, counted by the FLOP-counting build of the
 # CPU reference over a sample of the trajectory (oracle/count_flops.py).
-FLOPS_PER_FLUX_FACE = {"fmfpa": 38766.0, "emfpa": 49094.0}
-FLOPS_PER_FLUX_FACE_TRUNCATION = {"fmfpa": 37578.0, "emfpa": 47629.0}
+FLOPS_PER_FLUX_FACE = {"fmfpa": 38766.0, "emfpa": 49094.0, "nmfpa": 34525.0}
+FLOPS_PER_FLUX_FACE_TRUNCATION = {"fmfpa": 37578.0, "emfpa": 47629.0, "nmfpa": 34030.0}
 FLOPS_PER_RECON_CELL = 53202.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -60,8 +60,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
-    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa"],
-                    help="flux polyhedra: face-matched (the default workload) or edge-matched")
+    ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa", "nmfpa"],
+                    help="flux polyhedra: face-matched (the default workload), edge-matched or non-matched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")

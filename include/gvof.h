@@ -1,7 +1,7 @@
 /*
  * gvof.h -- C interface of the MI355X library for unsplit geometric VOF
- * advection with LSGIR reconstruction and face-matched (FMFPA) or
- * edge-matched (EMFPA) flux polyhedra.
+ * advection with LSGIR reconstruction and face-matched (FMFPA), edge-matched
+ * (EMFPA) or non-matched (NMFPA) flux polyhedra.
  *
  * Method: J. Lopez and J. Hernandez, "gVOF: An open-source package for
  * unsplit geometric volume of fluid methods on arbitrary grids",
@@ -47,7 +47,8 @@ enum {
   GVOF_E_LIMIT = -6    /* a mesh entity exceeds a compiled-in capacity */
 };
 
-/* Flags for gvof_params.flags (any other bit: GVOF_E_ARG from gvof_mesh_create) */
+/* Flags for gvof_params.flags (any other bit, or both method flags:
+ * GVOF_E_ARG from gvof_mesh_create); no method flag: FMFPA */
 #define GVOF_FLAG_NONE 0u
 /* Flux polyhedra by EMFPA (Sec. "Edge-matched flux polyhedron": vertices moved
  * back along their streak lines, Eq. streak-line2; each lateral face as four
@@ -56,6 +57,12 @@ enum {
  * faces with a common vertex share their back vertex and lateral faces to the
  * last bit.  fmfpa_degen is not used with this flag. */
 #define GVOF_FLAG_EMFPA 1u
+/* Flux polyhedra by NMFPA (Sec. "Non-matched flux polyhedron"): every vertex
+ * moved back with the face velocity u_face of the step, so the polyhedron is
+ * the face's prism of volume V_d with no adjustment (2I vertices, I+2 faces;
+ * neighbouring polyhedra may overlap).  u_vert is not read with this flag.
+ * Not together with GVOF_FLAG_EMFPA (GVOF_E_ARG). */
+#define GVOF_FLAG_NMFPA 2u
 
 typedef struct gvof_params {
   double eps;         /* volume-fraction tolerance (Sec. "Interface reconstruction"); 1e-12 as in all tests */
@@ -165,13 +172,14 @@ int gvof_get_tags(gvof_mesh* m, double* node_value, int8_t* node_tag, int8_t* fa
  *  - V_d = dt u_f . S_f per face (Eq. a-donacion, u_f the face velocity at
  *    t^{n+1/2}); upwind cell = owner if V_d >= 0 else neighbour (-1 outside);
  *  - V_F per face: 0 for faces tagged -1 and for inflow boundary faces; V_d
- *    for faces tagged 1; otherwise the signed fluid volume of the FMFPA flux
- *    polyhedron (Sec. "Face-matched flux polyhedron") built from the vertex
- *    velocities u_vert, truncated by the PLIC half-spaces of the cells it
- *    overlaps (candidates: the owner, the neighbour and every cell sharing a
- *    vertex with either);
+ *    for faces tagged 1; otherwise the signed fluid volume of the face's flux
+ *    polyhedron (FMFPA, or EMFPA / NMFPA by the mesh's flags) built from the
+ *    vertex velocities u_vert (NMFPA: from u_face), truncated by the PLIC
+ *    half-spaces of the cells it overlaps (candidates: the owner, the
+ *    neighbour and every cell sharing a vertex with either);
  *  - F_out = Eq. (fnext) with the face sums over each cell, clamped to [0, 1].
- * u_face (3 x nf), u_vert (3 x nv), F_in, F_out (nc): device.  F_out may alias
+ * u_face (3 x nf), u_vert (3 x nv; may be NULL with GVOF_FLAG_NMFPA), F_in,
+ * F_out (nc): device.  F_out may alias
  * F_in.  Optional device outputs (may be NULL): upwind_out (nf, int32),
  * vd_out (nf), vf_out (nf).  Needs a preceding gvof_reconstruct (it uses the
  * tags and planes made there).  dt must be finite; a negative dt advects

@@ -150,8 +150,11 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
     if (!std::isfinite(vx[v]) || !std::isfinite(vy[v]) || !std::isfinite(vz[v]))
       return fail(nullptr, GVOF_E_MESH, "vertex %d not finite", v);
 
-  if (params && (params->flags & ~GVOF_FLAG_EMFPA))
-    return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~GVOF_FLAG_EMFPA));
+  if (params) {
+    const uint32_t known = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA;
+    if (params->flags & ~known) return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~known));
+    if ((params->flags & known) == known) return fail(nullptr, GVOF_E_ARG, "GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA together");
+  }
 
   gvof_mesh* m = new gvof_mesh;
   m->nv = nv;
@@ -410,7 +413,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   {
     int maxI = 3;
     for (size_t f = 0; f < nf; ++f) maxI = std::max(maxI, m->fv_ptr[f + 1] - m->fv_ptr[f]);
-    const bool em = (m->p.flags & GVOF_FLAG_EMFPA) != 0;
+    const bool em = (m->p.flags & GVOF_FLAG_EMFPA) != 0;  // (NMFPA: 3I-2 tets, sized as FMFPA)
     // polyhedron points, the face centre, then the EMFPA lateral centres
     d.pts_per_slot = (em ? 3 : 2) * maxI + 2;
     d.poly_cap = (int)std::min<size_t>(nf, std::max<size_t>(65536, nf / 4));
@@ -456,7 +459,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
-  d.emfpa = (m->p.flags & GVOF_FLAG_EMFPA) ? 1 : 0;
+  d.method = (m->p.flags & GVOF_FLAG_EMFPA) ? gvof::kEMFPA : (m->p.flags & GVOF_FLAG_NMFPA) ? gvof::kNMFPA : gvof::kFMFPA;
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
 }
@@ -636,7 +639,8 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
   int r = need_bound(m);
   if (r) return r;
   if (!m->reconstructed) return fail(m, GVOF_E_ARG, "gvof_advect_step needs a preceding gvof_reconstruct");
-  if (!u_face || !u_vert || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
+  const bool nm = (m->p.flags & GVOF_FLAG_NMFPA) != 0;  // NMFPA reads no vertex velocities
+  if (!u_face || (!u_vert && !nm) || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
   if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
   m->prof.stream = m->stream;
   HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->cfg, m->stream,
@@ -844,7 +848,8 @@ static int batch_args(gvof_mesh* m, const double* uf, const double* uv, const do
                       double* F) {
   int r = need_bound(m);
   if (r) return r;
-  if (!uf || !uv || !dt || !active || !F) return fail(m, GVOF_E_ARG, "NULL array argument");
+  const bool nm = (m->p.flags & GVOF_FLAG_NMFPA) != 0;  // NMFPA reads no vertex velocities
+  if (!uf || (!uv && !nm) || !dt || !active || !F) return fail(m, GVOF_E_ARG, "NULL array argument");
   return GVOF_OK;
 }
 

@@ -70,7 +70,7 @@ struct DevMesh {
   int* counters;  // [0] tag-0 cells, [1] tag-0 faces, [2] geometry error flags, [3] refine cells
   unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
-  int emfpa;    // flux polyhedra by EMFPA (else FMFPA)
+  int method;   // flux polyhedra: kFMFPA, kEMFPA or kNMFPA
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);
@@ -110,6 +110,9 @@ enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_ITEMS = 4,
 enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16 };
 
 constexpr int kMaxFaceVerts = 8;
+// flux polyhedron methods (Secs. "Face-matched", "Edge-matched" and
+// "Non-matched flux polyhedron")
+constexpr int kFMFPA = 0, kEMFPA = 1, kNMFPA = 2;
 constexpr int kItemRegions = 256;
 constexpr int kMaxNeighbours = 62;  // vertex-sharing neighbours of one cell
 constexpr int kMaxCellVerts = 30;   // distinct vertices of one cell

@@ -428,17 +428,31 @@ __device__ inline void cell_piece(const DevMesh& M, int k, int m, d3& t0, d3& t1
   t0 = t1 = t2 = mk3(0.0, 0.0, 0.0);
 }
 
-// Flux tets per face edge: three for FMFPA, five for EMFPA.
-__device__ inline int tets_per_edge(const DevMesh& M) { return M.emfpa ? 5 : 3; }
+// Flux tets of a face of I vertices: 3I (FMFPA), 5I (EMFPA), 3I-2 (NMFPA).
+__device__ inline int flux_tet_count(int method, int I) {
+  return method == kEMFPA ? 5 * I : (method == kNMFPA ? 3 * I - 2 : 3 * I);
+}
 
 // Flux tet t of the polyhedron (the fourth point is the face centre c), for
 // edge i (j = i+1):
 //   FMFPA kind 0 (x_j, x_i, b_j), 1 (x_i, b_i, b_j), 2 (a, b_j, b_i);
 //   EMFPA kind 0 (x_j, x_i, m_i), 1 (x_i, b_i, m_i), 2 (b_i, b_j, m_i),
 //         3 (b_j, x_j, m_i), 4 (a, b_j, b_i)
-// (EMFPA: the lateral quad x_j, x_i, b_i, b_j as four triangles to its centre).
-__device__ inline void flux_tet_points(int t, int I, bool em, int& i1, int& i2, int& i3) {
+//   (the lateral quad x_j, x_i, b_i, b_j as four triangles to its centre);
+//   NMFPA t < 2I: kinds 0 and 1 of FMFPA for edge t/2; t = 2I + k - 1
+//   (k = 1..I-2): (b_0, b_{k+1}, b_k), the planar back face fanned from b_0.
+__device__ inline void flux_tet_points(int t, int I, int method, int& i1, int& i2, int& i3) {
+  const bool em = method == kEMFPA;
   const int i3e = t / 3, i5e = t / 5;  // constant divisions, both cheap
+  if (method == kNMFPA) {
+    const int i = t >> 1, kind = t & 1, k = t - 2 * I + 1;
+    const int j = (i + 1 == I) ? 0 : i + 1;
+    const bool back = k >= 1;
+    i1 = back ? I : (kind == 0 ? j : i);
+    i2 = back ? I + k + 1 : (kind == 0 ? i : I + i);
+    i3 = back ? I + k : I + j;
+    return;
+  }
   const int i = em ? i5e : i3e, kind = t - (em ? 5 : 3) * i;
   const int j = (i + 1 == I) ? 0 : i + 1;
   if (em) {
@@ -509,15 +523,25 @@ __device__ inline void poly_back(const DevMesh& M, Lds& S, int I, double dt, int
   }
 }
 
-// EMFPA back vertices: lanes 0..I-1 move x_i back along its streak line,
-// Eq. (streak-line2).  The value depends on the vertex alone, so every face
-// through the vertex gets the same bits.
+// EMFPA and NMFPA back vertices: lanes 0..I-1 move x_i back along the
+// streak line of Eq. (streak-line2), with the vertex's velocity (EMFPA: the
+// value depends on the vertex alone, so every face through it gets the same
+// bits) or the face-centre velocity (NMFPA, in S.ux/uy/uz[i] for every i).
+// NMFPA keeps b_0 in the apex slot as well: the back face's fan vertex.
 template <class Lds>
-__device__ inline void poly_streak(Lds& S, int I, double dt, int lane) {
+__device__ inline void poly_streak(Lds& S, int I, double dt, bool nm, int lane) {
   if (lane < I) {
-    S.px[I + lane] = S.px[lane] - dt * S.ux[lane];
-    S.py[I + lane] = S.py[lane] - dt * S.uy[lane];
-    S.pz[I + lane] = S.pz[lane] - dt * S.uz[lane];
+    const double bx = S.px[lane] - dt * S.ux[lane];
+    const double by = S.py[lane] - dt * S.uy[lane];
+    const double bz = S.pz[lane] - dt * S.uz[lane];
+    S.px[I + lane] = bx;
+    S.py[I + lane] = by;
+    S.pz[I + lane] = bz;
+    if (nm && lane == 0) {
+      S.px[2 * I] = bx;
+      S.py[2 * I] = by;
+      S.pz[2 * I] = bz;
+    }
   }
 }
 
@@ -538,6 +562,7 @@ __device__ inline void poly_centres(Lds& S, int I, int lane) {
 // volume equals V_d (every lane computes the same values; lane 0 stores).
 template <class Lds>
 __device__ inline void poly_apex(const DevMesh& M, Lds& S, int I, bool em, d3 c, d3 Sv, double vd, int lane) {
+  // (FMFPA and EMFPA; NMFPA needs no apex)
   d3 g = mk3(0.0, 0.0, 0.0);
   for (int i = 0; i < I; ++i) g = g + mk3(S.px[I + i], S.py[I + i], S.pz[I + i]);
   double dI = (double)I;
@@ -593,23 +618,25 @@ __device__ inline void poly_box(const Lds& S, int I, d3 c, d3& plo, d3& phi) {
 // Returns the face centre, area vector and the polyhedron's bounding box.
 template <class Lds>
 __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, int I,
-                                       const double* __restrict__ uv, double dt, d3& c, d3& Sv, d3& plo, d3& phi) {
+                                       const double* __restrict__ vel, double dt, d3& c, d3& Sv, d3& plo, d3& phi) {
   const int lane = threadIdx.x;
-  const int nv = M.nv;
+  const bool nm = M.method == kNMFPA;
+  const int vs = nm ? M.nf : M.nv;  // vel: face velocities (NMFPA) or vertex velocities
   if (lane < I) {
     int v = M.fv_idx[b0 + lane];
+    const int vi = nm ? f : v;
     S.px[lane] = M.vx[v];
     S.py[lane] = M.vy[v];
     S.pz[lane] = M.vz[v];
-    S.ux[lane] = uv[v];
-    S.uy[lane] = uv[nv + v];
-    S.uz[lane] = uv[2 * nv + v];
+    S.ux[lane] = vel[vi];
+    S.uy[lane] = vel[vs + vi];
+    S.uz[lane] = vel[2 * vs + vi];
   }
   __syncthreads();
-  if (M.emfpa) {
-    poly_streak(S, I, dt, lane);
+  if (M.method != kFMFPA) {
+    poly_streak(S, I, dt, nm, lane);
     __syncthreads();
-    poly_centres(S, I, lane);
+    if (!nm) poly_centres(S, I, lane);
   } else {
     poly_lateral(S, I, lane);
     __syncthreads();
@@ -618,7 +645,7 @@ __device__ inline void flux_polyhedron(const DevMesh& M, Lds& S, int f, int b0, 
   __syncthreads();
   c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
   Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
-  poly_apex(M, S, I, M.emfpa != 0, c, Sv, M.Vd[f], lane);
+  if (!nm) poly_apex(M, S, I, M.method == kEMFPA, c, Sv, M.Vd[f], lane);
   __syncthreads();
   poly_box(S, I, c, plo, phi);
 }
@@ -757,11 +784,11 @@ __device__ inline unsigned tm_word(int t, unsigned mask, int I) {
 // Test of staged candidate kc against flux tet t: the tet's box meets the
 // cell's box and, for a box cell, the tet is not entirely outside one box
 // plane.
-__device__ inline bool pair_test(const PrepLds& S, d3 c, int I, bool em, int TF, int q, unsigned& tm, int& kc) {
+__device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int method, int TF, int q, unsigned& tm, int& kc) {
   const int t = q % TF;
   kc = q / TF;
   int i1, i2, i3;
-  flux_tet_points(t, I, em, i1, i2, i3);
+  flux_tet_points(t, I, method, i1, i2, i3);
   Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]), mk3(S.px[i3], S.py[i3], S.pz[i3])};
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
@@ -818,10 +845,11 @@ __device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, uns
 // The loads of the face's vertices and of its first 64 listed cells form two
 // independent chains; they are issued together, straight-line with clamped
 // indices, and the cells' data go to LDS as soon as they arrive.
-// EM selects EMFPA (the mesh's method; an instance per method keeps the
-// FMFPA instance's registers as they are).
-template <int G, bool EM>
-__global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ uv, double dt) {
+// METHOD is the mesh's flux polyhedron method (an instance per method keeps
+// each instance's registers to its own path); vel holds the vertex
+// velocities (FMFPA, EMFPA) or the face velocities (NMFPA).
+template <int G, int METHOD>
+__global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ vel, double dt) {
   static_assert(G == 32 || G == 64, "lanes per face");
   constexpr int NG = kFluxLanes / G;  // faces per wavefront
   constexpr int NR = kFluxLanes / G;  // rounds of G lanes over the first 64 listed cells
@@ -866,7 +894,9 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     }
     const int v = M.fv_idx[b0 + min(sub, I - 1)];
     const d3 x = vert(M, v);
-    const d3 u = mk3(uv[v], uv[nv + v], uv[2 * nv + v]);
+    // the vertex's velocity, or for NMFPA the face's (one for all vertices)
+    const int vi = METHOD == kNMFPA ? f : v, vs = METHOD == kNMFPA ? M.nf : nv;
+    const d3 u = mk3(vel[vi], vel[vs + vi], vel[2 * vs + vi]);
     int8_t tq[NR];
     signed char bq[NR];
     d3 loq[NR], hiq[NR];
@@ -893,16 +923,22 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       S.chix[j] = hiq[r].x; S.chiy[j] = hiq[r].y; S.chiz[j] = hiq[r].z;
       S.cbox[j] = bq[r];
     }
-    constexpr bool em = EM;
+    constexpr bool em = METHOD == kEMFPA, nm = METHOD == kNMFPA;
     const double fdt = face_dt(M, f, dt);
-    if (em) {  // the lane holding x_i, u_i moves it back, then the centres
+    if (em || nm) {  // the lane holding x_i, u_i moves it back (EMFPA: then the centres)
       if (sub < I) {
-        S.px[I + sub] = x.x - fdt * u.x;
-        S.py[I + sub] = x.y - fdt * u.y;
-        S.pz[I + sub] = x.z - fdt * u.z;
+        const d3 b = mk3(x.x - fdt * u.x, x.y - fdt * u.y, x.z - fdt * u.z);
+        S.px[I + sub] = b.x;
+        S.py[I + sub] = b.y;
+        S.pz[I + sub] = b.z;
+        if (nm && sub == 0) {  // b_0 also in the apex slot: the back face's fan vertex
+          S.px[2 * I] = b.x;
+          S.py[2 * I] = b.y;
+          S.pz[2 * I] = b.z;
+        }
       }
       wave_lds_sync();
-      poly_centres(S, I, sub);
+      if (em) poly_centres(S, I, sub);
     } else {
       wave_lds_sync();
       poly_lateral(S, I, sub);
@@ -910,8 +946,10 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       poly_back(M, S, I, fdt, sub);
     }
     wave_lds_sync();
-    poly_apex(M, S, I, em, c, Sv, vd, sub);
-    wave_lds_sync();
+    if (!nm) {  // NMFPA's prism has the volume V_d as it is
+      poly_apex(M, S, I, em, c, Sv, vd, sub);
+      wave_lds_sync();
+    }
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
@@ -986,7 +1024,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       }
       continue;
     }
-    const int TF = (em ? 5 : 3) * I;
+    const int TF = flux_tet_count(METHOD, I);
     const int total = ncand * TF;
     if (total <= kFluxLanes) {
       // up to NR rounds: the tests stay in registers between counting and writing
@@ -1000,7 +1038,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
         const int q = sub + G * r;
         tmq[r] = 0;
         kcq[r] = 0;
-        kp[r] = q < total && pair_test(S, c, I, em, TF, q, tmq[r], kcq[r]);
+        kp[r] = q < total && pair_test(S, c, I, METHOD, TF, q, tmq[r], kcq[r]);
         bmq[r] = __ballot(kp[r]) & gmask;
         count += __popcll(bmq[r]);
       }
@@ -1021,7 +1059,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       for (int q0 = 0; q0 < total; q0 += G) {
         unsigned tm;
         int kc;
-        const bool kp = q0 + sub < total && pair_test(S, c, I, em, TF, q0 + sub, tm, kc);
+        const bool kp = q0 + sub < total && pair_test(S, c, I, METHOD, TF, q0 + sub, tm, kc);
         count += __popcll(__ballot(kp) & gmask);
       }
       int base = 0;
@@ -1032,7 +1070,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
         for (int q0 = 0; q0 < total; q0 += G) {
           unsigned tm = 0;
           int kc = 0;
-          const bool kp = q0 + sub < total && pair_test(S, c, I, em, TF, q0 + sub, tm, kc);
+          const bool kp = q0 + sub < total && pair_test(S, c, I, METHOD, TF, q0 + sub, tm, kc);
           const unsigned long long bm = __ballot(kp) & gmask;
           if (kp) write_pair(M, base + written + __popcll(bm & lbelow), it, S.cand[kc], tm);
           written += __popcll(bm);
@@ -1052,7 +1090,7 @@ __device__ inline Tet staged_tet(const DevMesh& M, int slot, unsigned tm) {
   const int t = tm_tet(tm), I = tm_verts(tm);
   const double* P = M.poly + (size_t)slot * M.pts_per_slot * 3;
   int i1, i2, i3;
-  flux_tet_points(t, I, M.emfpa, i1, i2, i3);
+  flux_tet_points(t, I, M.method, i1, i2, i3);
   const int ic = 2 * I + 1;
   return Tet{mk3(P[3 * ic], P[3 * ic + 1], P[3 * ic + 2]), mk3(P[3 * i1], P[3 * i1 + 1], P[3 * i1 + 2]),
              mk3(P[3 * i2], P[3 * i2 + 1], P[3 * i2 + 2]), mk3(P[3 * i3], P[3 * i3 + 1], P[3 * i3 + 2])};
@@ -1632,16 +1670,16 @@ __device__ inline void staged_face_sums(const DevMesh& M) {
 // (candidate, flux tet) pair computing the pair's volume with the same
 // functions as the staged path, summed in the same (candidate, tetrahedron)
 // order, so V_F does not depend on which path computed it.
-__device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double* __restrict__ uv, double dt) {
+__device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double* __restrict__ vel, double dt) {
   const int lane = threadIdx.x;
   const int nfaces = M.counters[CNT_OVER];
   for (int it = blockIdx.x; it < nfaces; it += gridDim.x) {
     const int f = M.list_over[it];
     const int b0 = fv_begin(M, f), I = fv_count(M, f);
     d3 c, Sv, plo, phi;
-    flux_polyhedron(M, S, f, b0, I, uv, face_dt(M, f, dt), c, Sv, plo, phi);
+    flux_polyhedron(M, S, f, b0, I, vel, face_dt(M, f, dt), c, Sv, plo, phi);
     const int ncand = flux_candidates(M, S, f, plo, phi);
-    const int TF = tets_per_edge(M) * I;
+    const int TF = flux_tet_count(M.method, I);
     const int total = ncand * TF;
     double acc = 0.0;  // identical in every lane
     for (int q0 = 0; q0 < total; q0 += kFluxLanes) {
@@ -1651,7 +1689,7 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
       if (q < total) {
         const int t = q % TF, kc = q / TF;
         int i1, i2, i3;
-        flux_tet_points(t, I, M.emfpa, i1, i2, i3);
+        flux_tet_points(t, I, M.method, i1, i2, i3);
         Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]),
               mk3(S.px[i3], S.py[i3], S.pz[i3])};
         d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
@@ -1684,11 +1722,13 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
 // the staged faces (grid-strided, a thread per face), then of the faces that
 // went to the overflow path (a block per face).  Neither reads what the other
 // writes.
-__global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double* __restrict__ uv, double dt) {
+// vel: the velocities the flux polyhedra are built from (vertex velocities,
+// or face velocities for NMFPA).
+__global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double* __restrict__ vel, double dt) {
   __shared__ FluxLds S;
   if (blockIdx.x == 0 && threadIdx.x == 0) M.totals[1] += (unsigned long long)M.counters[CNT_FACES];
   staged_face_sums(M);
-  overflow_faces(M, S, uv, dt);
+  overflow_faces(M, S, vel, dt);
 }
 
 __global__ void k_reset_advect(DevMesh M) { reset_advect_state(M); }
@@ -2112,12 +2152,17 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   if (reset) k_reset_advect<<<1, 256, 0, s>>>(M);
   TIMED(K_FACE_SWEEP, (k_face_sweep<<<blocks_for(M.nf, st), st, 0, s>>>(M, uf, dt)));
   const int pb = blocks_for(M.nf, 1, L.prep_blocks);
-  if (M.emfpa) {
-    if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32, true><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
-    else TIMED(K_FLUX_PREP, (k_flux_prep<64, true><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+  const double* vel = M.method == kNMFPA ? uf : uv;  // what the flux polyhedra are built from
+  const bool p32 = L.prep_lanes == 32;
+  if (M.method == kEMFPA) {
+    if (p32) TIMED(K_FLUX_PREP, (k_flux_prep<32, kEMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
+    else TIMED(K_FLUX_PREP, (k_flux_prep<64, kEMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
+  } else if (M.method == kNMFPA) {
+    if (p32) TIMED(K_FLUX_PREP, (k_flux_prep<32, kNMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
+    else TIMED(K_FLUX_PREP, (k_flux_prep<64, kNMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
   } else {
-    if (L.prep_lanes == 32) TIMED(K_FLUX_PREP, (k_flux_prep<32, false><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
-    else TIMED(K_FLUX_PREP, (k_flux_prep<64, false><<<pb, kFluxLanes, 0, s>>>(M, uv, dt)));
+    if (p32) TIMED(K_FLUX_PREP, (k_flux_prep<32, kFMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
+    else TIMED(K_FLUX_PREP, (k_flux_prep<64, kFMFPA><<<pb, kFluxLanes, 0, s>>>(M, vel, dt)));
   }
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, kItemsBlock, 0, s>>>(M)));
   if (!M.all_box) {
@@ -2130,7 +2175,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
     TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }
   TIMED(K_FLUX_DEEP, (k_flux_deep<<<1024, 64, 0, s>>>(M)));
-  TIMED(K_FLUX_SUM, (k_flux_sum<<<1024, kFluxLanes, 0, s>>>(M, uv, dt)));
+  TIMED(K_FLUX_SUM, (k_flux_sum<<<1024, kFluxLanes, 0, s>>>(M, vel, dt)));
   TIMED(K_UPDATE, (k_update<<<blocks_for(M.nc, st), st, 0, s>>>(M, Fin, Fout)));
   return hipGetLastError();
 }

@@ -18,7 +18,8 @@ LIB_PATH = os.environ.get("GVOF_LIB_PATH") or os.path.join(HERE, "libgvof.so")
 
 GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
-GVOF_FLAG_NONE, GVOF_FLAG_EMFPA = 0, 1
+GVOF_FLAG_NONE, GVOF_FLAG_EMFPA, GVOF_FLAG_NMFPA = 0, 1, 2
+METHOD_FLAGS = {"fmfpa": GVOF_FLAG_NONE, "emfpa": GVOF_FLAG_EMFPA, "nmfpa": GVOF_FLAG_NMFPA}
 
 
 class GvofError(RuntimeError):
@@ -304,24 +305,31 @@ def gvof_last_error(h=None) -> str:
 
 
 # ------------------------------------------------------------------ convenience wrapper
+def _with_method(params, method: str):
+    """params with the flag of a flux polyhedron method set ("fmfpa": unchanged)."""
+    if method not in METHOD_FLAGS:
+        raise ValueError(f"unknown flux polyhedron method {method!r}")
+    if method == "fmfpa":
+        return params
+    params = params if params is not None else gvof_params_default()
+    params.flags |= METHOD_FLAGS[method]
+    return params
+
+
 class GvofMesh:
     """A mesh handle bound to a torch-allocated device workspace.
 
-    method "emfpa" sets GVOF_FLAG_EMFPA in the parameters (flux polyhedra by
-    EMFPA); "fmfpa" leaves the flags as given.
+    method "emfpa" / "nmfpa" sets GVOF_FLAG_EMFPA / GVOF_FLAG_NMFPA in the
+    parameters (the flux polyhedron method); "fmfpa" leaves the flags as given.
     """
 
     def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None,
                  method: str = "fmfpa"):
         import torch
-        if method not in ("fmfpa", "emfpa"):
-            raise ValueError(f"unknown flux polyhedron method {method!r}")
+        params = _with_method(params, method)
         self.torch = torch
         self.device = torch.device(device)
         self.mesh = mesh
-        if method == "emfpa":
-            params = params if params is not None else gvof_params_default()
-            params.flags |= GVOF_FLAG_EMFPA
         if handle is None:
             handle = gvof_mesh_create(mesh.vx, mesh.vy, mesh.vz, mesh.fv_ptr, mesh.fv_idx, mesh.owner, mesh.neigh,
                                       mesh.nc, params)
@@ -402,11 +410,7 @@ class GvofBatch(GvofMesh):
                  method: str = "fmfpa"):
         """parts: optional handles already made by gvof_mesh_create for these
         meshes (taken over and destroyed here).  method as for GvofMesh."""
-        if method not in ("fmfpa", "emfpa"):
-            raise ValueError(f"unknown flux polyhedron method {method!r}")
-        if method == "emfpa":
-            params = params if params is not None else gvof_params_default()
-            params.flags |= GVOF_FLAG_EMFPA
+        params = _with_method(params, method)
         parts = list(parts) if parts is not None else []
         try:
             for m in meshes[len(parts):]:

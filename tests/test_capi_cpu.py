@@ -191,23 +191,30 @@ def test_unit_buffer_only_for_meshes_with_general_cells():
     assert ws(inputs.jittered_mesh(6, seed=2)) - base >= grown
 
 
-def test_flags_select_emfpa_and_unknown_bits_are_rejected():
-    """GVOF_FLAG_EMFPA is the one flag: EMFPA slots hold the lateral centres and
-    the pair buffer is sized for 5I flux tets per face (larger workspace); any
-    other bit is an argument error; a batch of mixed methods is rejected."""
+def test_flags_select_the_flux_polyhedron_method():
+    """GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA select the method: EMFPA slots hold the
+    lateral centres and the pair buffer is sized for 5I flux tets per face
+    (larger workspace), NMFPA sizes as FMFPA; both together, or any other bit,
+    is an argument error; a batch of mixed methods is rejected."""
     m = inputs.cartesian_mesh(4)
     pe = gvof.gvof_params_default()
     pe.flags = gvof.GVOF_FLAG_EMFPA
+    pn = gvof.gvof_params_default()
+    pn.flags = gvof.GVOF_FLAG_NMFPA
     a = gvof.gvof_mesh_create(*m.arrays(), m.nc)
     b = gvof.gvof_mesh_create(*m.arrays(), m.nc, pe)
+    c = gvof.gvof_mesh_create(*m.arrays(), m.nc, pn)
     try:
         assert gvof.gvof_mesh_workspace_bytes(b) > gvof.gvof_mesh_workspace_bytes(a)
-        with pytest.raises(gvof.GvofError):
-            gvof.gvof_batch_create([a, b])
+        assert gvof.gvof_mesh_workspace_bytes(c) == gvof.gvof_mesh_workspace_bytes(a)
+        for pair in ([a, b], [a, c], [b, c]):
+            with pytest.raises(gvof.GvofError):
+                gvof.gvof_batch_create(pair)
     finally:
         gvof.gvof_mesh_destroy(a)
         gvof.gvof_mesh_destroy(b)
-    for bad in (2, 4, 0x80000000, 3):
+        gvof.gvof_mesh_destroy(c)
+    for bad in (4, 0x80000000, 3):
         p = gvof.gvof_params_default()
         p.flags = bad
         with pytest.raises(gvof.GvofError) as e:

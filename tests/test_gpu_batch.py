@@ -86,7 +86,7 @@ def test_batch_steps_bitwise_equal_alone(gv):
         assert np.array_equal(Fb[sl], Fa), q
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
 def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method):
     torch, dev, P, B, uf, uv = build(gv, SPECS, method=method)
     log(f"batch vs oracle, {method}")
@@ -137,7 +137,7 @@ def test_graph_replay_equals_eager(gv):
         B.status()
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
 def test_launch_shapes_do_not_change_results(gv, method):
     torch, dev, P, B, uf, uv = build(gv, SPECS, method=method)
     log(f"launch shapes, {method}")

@@ -56,7 +56,7 @@ def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa"):
     return F
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
 def test_polygon_face_general_cells(oracle_mod, gv, method):
     m = inputs.jittered_mesh(7, seed=3, split=False)
     assert m.fv_ptr[1] == 4
@@ -68,7 +68,7 @@ def test_polygon_face_general_cells(oracle_mod, gv, method):
 
 @pytest.mark.parametrize("kind,n,method", [("cartesian", 1, "fmfpa"), ("cartesian", 2, "fmfpa"),
                                            ("jittered", 2, "fmfpa"), ("cartesian", 1, "emfpa"),
-                                           ("jittered", 2, "emfpa")])
+                                           ("jittered", 2, "emfpa"), ("jittered", 2, "nmfpa")])
 def test_smallest_meshes(oracle_mod, gv, kind, n, method):
     m = inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=5)
     uf, uv = inputs.velocity_uniform(m, (0.3, 0.2, 0.1))

@@ -5,7 +5,7 @@ face is compared with the oracle, teacher-forced from the oracle's state.
   - 64^3 Cartesian, Enright field with period 3, CFL 0.5: the first two steps
     and step 100 (the oracle runs the trajectory up to there);
   - 64^3 distorted (+-0.25h, seed 1), same field: the first two steps, with
-    FMFPA and with EMFPA flux polyhedra.
+    FMFPA, EMFPA and NMFPA flux polyhedra.
 
 Bars as in the small-size parity tests: tags and upwind cells bit for bit,
 V_d bit for bit, |dV_F| <= 1e-12 V, |dF| <= 1e-12 per cell.
@@ -45,7 +45,7 @@ def _step_parity(oracle_mod, g, om, F, uf, uv, ufd, uvd, dts, V, torch, dev, lab
 
 
 @pytest.mark.parametrize("kind,later,method", [("cartesian", 100, "fmfpa"), ("jittered", None, "fmfpa"),
-                                               ("jittered", None, "emfpa")])
+                                               ("jittered", None, "emfpa"), ("jittered", None, "nmfpa")])
 def test_full_size_parity(oracle_mod, kind, later, method):
     from paper_2111_01524_amd import gvof
     torch, dev = torch_dev()

@@ -110,6 +110,8 @@ def _velocity(kind_field, m):
     ("cartesian", 20, "enright", 6, "emfpa"),
     ("jittered", 12, "enright", 4, "emfpa"),
     ("jittered", 10, "uniform", 3, "emfpa"),
+    ("cartesian", 20, "enright", 6, "nmfpa"),
+    ("jittered", 12, "enright", 4, "nmfpa"),
 ])
 def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps, method):
     torch, dev = torch_dev()
@@ -145,7 +147,7 @@ def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps, met
     log(f"worst |dF| = {worst:.2e}")
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa"])
+@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
 def test_step_is_deterministic(gv, method):
     torch, dev = torch_dev()
     m = make_mesh("jittered", 10)
