@@ -5,7 +5,9 @@
 // volume of fluid methods on arbitrary grids" (arXiv 2111.01524):
 //   grid geometry (Sec. "Grid construction"), grid tagging (Sec. "Grid
 //   tagging"), cut-off and PLIC (Sec. "Interface reconstruction", Eq.
-//   plic-eq), LSGIR normals (Sec. LSGIR, Eqs. lsgir1, lsgir2, lsgir-beta),
+//   plic-eq), LSGIR normals (Sec. LSGIR, Eqs. lsgir1, lsgir2, lsgir-beta)
+//   optionally refined by LSFIR (Sec. "Least squares fit interface
+//   reconstruction"),
 //   the plane constant enforcing the cell's volume fraction, face flux
 //   volumes (Eq. a-donacion), FMFPA flux polyhedra (Sec. "Face-matched flux
 //   polyhedron"), EMFPA ones (Sec. "Edge-matched flux polyhedron") or NMFPA
@@ -219,6 +221,9 @@ struct OMesh {
   std::vector<char> isbox;
   std::vector<std::vector<Tet>> tets;  // surface tets of every non-box cell
   int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA, 2 NMFPA
+  int recon = 0;                       // normals: 0 LSGIR, 1 LSFIR
+  int lsfir_outer = 1;                 // LSFIR outer iterations at most
+  double lsfir_tol = 0.0;              // LSFIR: stop once no normal turns by this angle (rad) or more
 };
 
 // Surface triangles of cell c: triangle faces as they are, polygons fanned
@@ -505,6 +510,167 @@ real plane_constant(const OMesh& M, int c, V3 n, double Fc) {
     else hi = mid;
   }
   return -(real(0.5) * (lo + hi));
+}
+
+// --------------------------------------------------------------------------
+// LSFIR (Sec. "Least squares fit interface reconstruction").
+// --------------------------------------------------------------------------
+
+// Geometric centre of the PLIC polygon {n.x + C = 0} within cell c: the mean
+// of its vertices, which are the cell's vertices lying on the plane and the
+// crossing points of the cell's edges whose ends lie strictly on opposite
+// sides.  Vertices in ascending order, then edges (each once, as ascending
+// vertex pairs) in ascending order.  Returns the number of points (0: the
+// plane misses the cell, the centre is then the cell centre).
+int plic_centre(const OMesh& M, int c, V3 n, real C, V3& out) {
+  std::vector<std::pair<int, int>> edges;
+  for (auto& fs : M.cf[c]) {
+    int f = fs.first, b = M.fptr[f], k = M.fptr[f + 1] - b;
+    for (int i = 0; i < k; ++i) {
+      int a = M.fidx[b + i], e = M.fidx[b + (i + 1) % k];
+      edges.push_back({std::min(a, e), std::max(a, e)});
+    }
+  }
+  std::sort(edges.begin(), edges.end());
+  edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+  V3 sum = mk(0.0, 0.0, 0.0);
+  int cnt = 0;
+  for (int v : M.cv[c]) {
+    if (dot(n, M.X[v]) + C == real(0.0)) {
+      sum = sum + M.X[v];
+      ++cnt;
+    }
+  }
+  for (auto& e : edges) {
+    V3 xa = M.X[e.first], xb = M.X[e.second];
+    real sa = dot(n, xa) + C, sb = dot(n, xb) + C;
+    if ((sa > real(0.0) && sb < real(0.0)) || (sa < real(0.0) && sb > real(0.0))) {
+      real t = sa / (sa - sb);
+      sum = sum + (xa + t * (xb - xa));
+      ++cnt;
+    }
+  }
+  if (cnt == 0) {
+    out = M.cc[c];
+    return 0;
+  }
+  real k = real(double(cnt));
+  out = mk(sum.x / k, sum.y / k, sum.z / k);
+  return cnt;
+}
+
+// Eigen-decomposition of a symmetric 3x3 matrix by cyclic Jacobi rotations
+// (the textbook method): on return the diagonal of A holds the eigenvalues
+// and the columns of V the eigenvectors.
+void jacobi3(real A[3][3], real V[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = i == j ? real(1.0) : real(0.0);
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    real off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+    if (off == real(0.0)) break;
+    for (int p = 0; p < 2; ++p) {
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == real(0.0)) continue;
+        real theta = (A[q][q] - A[p][p]) / (real(2.0) * A[p][q]);
+        real t = real(1.0) / (fabs(theta) + sqrt(theta * theta + real(1.0)));
+        if (theta < real(0.0)) t = -t;
+        real cs = real(1.0) / sqrt(t * t + real(1.0)), sn = t * cs;
+        // A <- R^T A R with the rotation in the (p, q) plane
+        for (int k = 0; k < 3; ++k) {
+          real akp = A[k][p], akq = A[k][q];
+          A[k][p] = cs * akp - sn * akq;
+          A[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < 3; ++k) {
+          real apk = A[p][k], aqk = A[q][k];
+          A[p][k] = cs * apk - sn * aqk;
+          A[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {
+          real vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = cs * vkp - sn * vkq;
+          V[k][q] = sn * vkp + cs * vkq;
+        }
+      }
+    }
+  }
+}
+
+// One least-squares fit: the unit normal of the plane through the PLIC centre
+// x of cell c that minimises sum w_k (n.(x_k - x))^2 over the valid
+// neighbours k (interfacial cells sharing a vertex with c whose normals
+// differ from c's by less than 45 degrees), w_k = |x_k - x|^-2.5: the
+// eigenvector of the smallest eigenvalue of sum w_k d_k d_k^T, turned to
+// agree with c's normal.  Keeps c's normal when fewer than two neighbours
+// are valid or the smallest eigenvalue is not separated from the next.
+V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vector<V3>& xc, const int8_t* tc,
+             int& nvalid) {
+  const real cos45 = sqrt(real(0.5));
+  real A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  nvalid = 0;
+  for (int k : M.nb[c]) {
+    if (tc[k] != 0) continue;
+    if (!(dot(nrm[c], nrm[k]) > cos45)) continue;
+    V3 d = xc[k] - xc[c];
+    real dd = dot(d, d);
+    if (dd == real(0.0)) continue;
+    real w = pow(dd, real(-1.25));  // |d|^-2.5
+    real dv[3] = {d.x, d.y, d.z};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[i][j] = A[i][j] + w * dv[i] * dv[j];
+    ++nvalid;
+  }
+  if (nvalid < 2) return nrm[c];
+  real V[3][3];
+  jacobi3(A, V);
+  int i0 = 0, i1 = 1, i2 = 2;  // eigenvalues ascending
+  if (A[i1][i1] < A[i0][i0]) std::swap(i0, i1);
+  if (A[i2][i2] < A[i1][i1]) std::swap(i1, i2);
+  if (A[i1][i1] < A[i0][i0]) std::swap(i0, i1);
+  real l0 = A[i0][i0], l1 = A[i1][i1], l2 = A[i2][i2];
+  if (!(l1 - l0 > real(1e-12) * l2)) return nrm[c];
+  V3 e = mk(V[0][i0], V[1][i0], V[2][i0]);
+  real en = sqrt(dot(e, e));
+  e = mk(e.x / en, e.y / en, e.z / en);
+  if (dot(e, nrm[c]) < real(0.0)) e = mk(-e.x, -e.y, -e.z);
+  return e;
+}
+
+// The outer iteration (Sec. "Swartz interface reconstruction", applied to
+// LSFIR): from the LSGIR planes, repeatedly take every interfacial cell's
+// PLIC centre, fit each cell's normal, and adopt the fitted normal where it
+// turns by less than 30/I_out degrees (I_out = 1, 2, ...), all cells at once;
+// then place each changed plane to match F.  Stops after lsfir_outer passes,
+// or after a pass in which no normal turned by lsfir_tol or more.
+void lsfir_iterate(const OMesh& M, const double* F, const int8_t* tc, std::vector<V3>& nrm, std::vector<real>& Cc) {
+  const int nc = M.nc;
+  std::vector<V3> xc(nc, mk(0.0, 0.0, 0.0)), nn(nc);
+  for (int it = 1; it <= M.lsfir_outer; ++it) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int c = 0; c < nc; ++c)
+      if (tc[c] == 0) plic_centre(M, c, nrm[c], Cc[c], xc[c]);
+    const real lim = real(std::cos((3.14159265358979323846 / 6.0) / double(it)));  // constants
+    const real stop = real(std::cos(M.lsfir_tol));
+    int turned = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : turned)
+    for (int c = 0; c < nc; ++c) {
+      nn[c] = nrm[c];
+      if (tc[c] != 0) continue;
+      int nv;
+      V3 e = lsfir_fit(M, c, nrm, xc, tc, nv);
+      real d = dot(e, nrm[c]);
+      if (d > lim) nn[c] = e;
+      if (dot(nn[c], nrm[c]) < stop) ++turned;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int c = 0; c < nc; ++c) {
+      if (tc[c] != 0) continue;
+      bool same = nn[c].x == nrm[c].x && nn[c].y == nrm[c].y && nn[c].z == nrm[c].z;
+      nrm[c] = nn[c];
+      if (!same) Cc[c] = plane_constant(M, c, nrm[c], F[c]);
+    }
+    if (turned == 0) break;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -966,6 +1132,54 @@ void* orc_mesh_new(int nv, const double* vx, const double* vy, const double* vz,
 
 void orc_mesh_free(void* h) { delete static_cast<OMesh*>(h); }
 
+// Normals of the mesh's reconstruction: 0 LSGIR (default), 1 LSFIR with at
+// most `outer` outer iterations and stopping tolerance tol (rad).  Returns 0,
+// or -1 for a bad value.
+int orc_mesh_set_recon(void* h, int method, int outer, double tol) {
+  if ((method != 0 && method != 1) || outer < 1 || !(tol >= 0.0)) return -1;
+  OMesh& M = *static_cast<OMesh*>(h);
+  M.recon = method;
+  M.lsfir_outer = outer;
+  M.lsfir_tol = tol;
+  return 0;
+}
+
+// PLIC centres (3 x nc) of the tag-0 cells for the given planes (4 x nc);
+// other cells get 0.  cnt (nc) receives the number of polygon vertices.
+void orc_plic_centres(void* h, const int8_t* tc, const double* planes, double* out, int* cnt) {
+  OMesh& M = *static_cast<OMesh*>(h);
+  int nc = M.nc;
+  for (int c = 0; c < nc; ++c) {
+    out[c] = out[nc + c] = out[2 * nc + c] = 0.0;
+    cnt[c] = 0;
+    if (tc[c] != 0) continue;
+    V3 x;
+    cnt[c] = plic_centre(M, c, mk(planes[c], planes[nc + c], planes[2 * nc + c]), planes[3 * nc + c], x);
+    out[c] = to_double(x.x); out[nc + c] = to_double(x.y); out[2 * nc + c] = to_double(x.z);
+  }
+}
+
+// One LSFIR fit of every tag-0 cell from the given normals (3 x nc) and PLIC
+// centres (3 x nc): fitted normals (3 x nc, before the outer iteration's
+// turn limit) and the number of valid neighbours (nc).
+void orc_lsfir_fit(void* h, const int8_t* tc, const double* normals, const double* centres, double* out,
+                   int* nvalid) {
+  OMesh& M = *static_cast<OMesh*>(h);
+  int nc = M.nc;
+  std::vector<V3> nrm(nc), xc(nc);
+  for (int c = 0; c < nc; ++c) {
+    nrm[c] = mk(normals[c], normals[nc + c], normals[2 * nc + c]);
+    xc[c] = mk(centres[c], centres[nc + c], centres[2 * nc + c]);
+  }
+  for (int c = 0; c < nc; ++c) {
+    out[c] = out[nc + c] = out[2 * nc + c] = 0.0;
+    nvalid[c] = 0;
+    if (tc[c] != 0) continue;
+    V3 e = lsfir_fit(M, c, nrm, xc, tc, nvalid[c]);
+    out[c] = to_double(e.x); out[nc + c] = to_double(e.y); out[2 * nc + c] = to_double(e.z);
+  }
+}
+
 // Flux polyhedra of the mesh: 0 FMFPA (default), 1 EMFPA, 2 NMFPA.  Returns
 // 0, or -1 for another value.
 int orc_mesh_set_method(void* h, int method) {
@@ -1056,14 +1270,18 @@ void orc_reconstruct(void* h, double* F, double eps, double beta, double* Fstar,
     if (real(F[c]) < real(eps)) F[c] = 0.0;
     else if (real(F[c]) > real(1.0) - real(eps)) F[c] = 1.0;
   }
+  std::vector<V3> nrm(nc, mk(0.0, 0.0, 0.0));
+  std::vector<real> Cc(nc, real(0.0));
 #pragma omp parallel for schedule(dynamic, 16)
   for (int c = 0; c < nc; ++c) {
-    planes[c] = planes[nc + c] = planes[2 * nc + c] = planes[3 * nc + c] = 0.0;
     if (tc[c] != 0) continue;
-    V3 n = lsgir_normal(M, F, c, beta);
-    real C = plane_constant(M, c, n, F[c]);
-    planes[c] = to_double(n.x); planes[nc + c] = to_double(n.y); planes[2 * nc + c] = to_double(n.z);
-    planes[3 * nc + c] = to_double(C);
+    nrm[c] = lsgir_normal(M, F, c, beta);
+    Cc[c] = plane_constant(M, c, nrm[c], F[c]);
+  }
+  if (M.recon == 1) lsfir_iterate(M, F, tc, nrm, Cc);
+  for (int c = 0; c < nc; ++c) {
+    planes[c] = to_double(nrm[c].x); planes[nc + c] = to_double(nrm[c].y); planes[2 * nc + c] = to_double(nrm[c].z);
+    planes[3 * nc + c] = to_double(Cc[c]);
   }
 }
 

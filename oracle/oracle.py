@@ -31,6 +31,10 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_mesh_free.argtypes = [C.c_void_p]
         lib.orc_mesh_set_method.argtypes = [C.c_void_p, C.c_int]
         lib.orc_mesh_set_method.restype = C.c_int
+        lib.orc_mesh_set_recon.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double]
+        lib.orc_mesh_set_recon.restype = C.c_int
+        lib.orc_plic_centres.argtypes = [C.c_void_p, _b, _d, _d, _i]
+        lib.orc_lsfir_fit.argtypes = [C.c_void_p, _b, _d, _d, _d, _i]
         lib.orc_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d, _d, _d, _b]
         lib.orc_neighbours.argtypes = [C.c_void_p, _i, _i]
         lib.orc_neighbours.restype = C.c_int
@@ -90,12 +94,16 @@ class OracleMesh:
 
     method selects the flux polyhedra: "fmfpa" (Sec. "Face-matched flux
     polyhedron"), "emfpa" (Sec. "Edge-matched flux polyhedron") or "nmfpa"
-    (Sec. "Non-matched flux polyhedron").
+    (Sec. "Non-matched flux polyhedron").  recon selects the normals:
+    "lsgir" (Sec. LSGIR) or "lsfir" (Sec. "Least squares fit interface
+    reconstruction", at most lsfir_outer outer iterations, stopping once no
+    normal turns by lsfir_tol radians or more).
     """
 
     METHODS = {"fmfpa": 0, "emfpa": 1, "nmfpa": 2}
 
-    def __init__(self, mesh, counting: bool = False, method: str = "fmfpa"):
+    def __init__(self, mesh, counting: bool = False, method: str = "fmfpa", recon: str = "lsgir",
+                 lsfir_outer: int = 1, lsfir_tol: float = 0.0):
         if method not in self.METHODS:
             raise ValueError(f"unknown flux polyhedron method {method!r}")
         self.lib = _lib(counting)
@@ -110,6 +118,11 @@ class OracleMesh:
                                        _p(fi, _i), _p(ow, _i), _p(ne, _i), self.nc)
         if self.lib.orc_mesh_set_method(self.h, self.METHODS[method]) != 0:
             raise RuntimeError("oracle rejected the flux polyhedron method")
+        if recon not in ("lsgir", "lsfir"):
+            raise ValueError(f"unknown reconstruction {recon!r}")
+        self.recon = recon
+        if self.lib.orc_mesh_set_recon(self.h, 1 if recon == "lsfir" else 0, int(lsfir_outer), float(lsfir_tol)):
+            raise ValueError("oracle rejected the reconstruction settings")
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -149,6 +162,19 @@ class OracleMesh:
         F = _dbl(F); tc = _i8(tcell); n = _dbl(n); Cc = np.zeros(self.nc)
         self.lib.orc_plane_constant(self.h, _p(F, _d), _p(tc, _b), _p(n, _d), _p(Cc, _d))
         return Cc
+
+    def plic_centres(self, tcell, planes):
+        """Vertex means of the PLIC polygons of the tag-0 cells (3, nc) and their vertex counts."""
+        tc = _i8(tcell); pl = _dbl(planes); out = np.zeros((3, self.nc)); cnt = np.zeros(self.nc, np.int32)
+        self.lib.orc_plic_centres(self.h, _p(tc, _b), _p(pl, _d), _p(out, _d), _p(cnt, _i))
+        return out, cnt
+
+    def lsfir_fit(self, tcell, normals, centres):
+        """One LSFIR fit per tag-0 cell: fitted normals (3, nc) and valid-neighbour counts."""
+        tc = _i8(tcell); nr = _dbl(normals); xc = _dbl(centres)
+        out = np.zeros((3, self.nc)); nv = np.zeros(self.nc, np.int32)
+        self.lib.orc_lsfir_fit(self.h, _p(tc, _b), _p(nr, _d), _p(xc, _d), _p(out, _d), _p(nv, _i))
+        return out, nv
 
     def cell_cut_volume(self, c, n, Cst):
         return self.lib.orc_cell_cut_volume(self.h, int(c), float(n[0]), float(n[1]), float(n[2]), float(Cst))
