@@ -603,9 +603,16 @@ void jacobi3(real A[3][3], real V[3][3]) {
 // eigenvector of the smallest eigenvalue of sum w_k d_k d_k^T, turned to
 // agree with c's normal.  Keeps c's normal when fewer than two neighbours
 // are valid or the smallest eigenvalue is not separated from the next.
+// The weight is singular where two PLIC centres coincide, and a centre very
+// close to x has a direction set by rounding alone; the weight is therefore
+// taken at |d| = 0.05 h for closer centres (h: the largest extent of c's
+// box), which changes nothing for centres farther apart.
 V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vector<V3>& xc, const int8_t* tc,
              int& nvalid) {
   const real cos45 = sqrt(real(0.5));
+  V3 ext = M.bbmax[c] - M.bbmin[c];
+  real hc = std::max(std::max(ext.x, ext.y), ext.z);
+  real dmin2 = (real(0.05) * hc) * (real(0.05) * hc);
   real A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   nvalid = 0;
   for (int k : M.nb[c]) {
@@ -614,7 +621,8 @@ V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vecto
     V3 d = xc[k] - xc[c];
     real dd = dot(d, d);
     if (dd == real(0.0)) continue;
-    real w = pow(dd, real(-1.25));  // |d|^-2.5
+    real dw = std::max(dd, dmin2);
+    real w = real(1.0) / (dw * sqrt(sqrt(dw)));  // |d|^-2.5, bounded at |d| = 0.05 h
     real dv[3] = {d.x, d.y, d.z};
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) A[i][j] = A[i][j] + w * dv[i] * dv[j];

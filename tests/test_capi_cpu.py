@@ -214,9 +214,43 @@ def test_flags_select_the_flux_polyhedron_method():
         gvof.gvof_mesh_destroy(a)
         gvof.gvof_mesh_destroy(b)
         gvof.gvof_mesh_destroy(c)
-    for bad in (4, 0x80000000, 3):
+    for bad in (8, 0x80000000, 3):
         p = gvof.gvof_params_default()
         p.flags = bad
         with pytest.raises(gvof.GvofError) as e:
             gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
         assert e.value.code == gvof.GVOF_E_ARG
+
+
+def test_lsfir_settings():
+    """GVOF_FLAG_LSFIR takes 1..GVOF_MAX_LSFIR_OUTER outer passes and a finite
+    tolerance >= 0, adds the PLIC-centre and fitted-normal buffers to the
+    workspace, and combines with any flux polyhedron method; batches need
+    equal settings."""
+    m = inputs.cartesian_mesh(4)
+    d = gvof.gvof_params_default()
+    assert d.lsfir_outer == 1 and d.lsfir_tol == 0.0
+    base = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+    handles = [base]
+    try:
+        for flags in (gvof.GVOF_FLAG_LSFIR, gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_EMFPA,
+                      gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_NMFPA):
+            p = gvof.gvof_params_default()
+            p.flags = flags
+            p.lsfir_outer = gvof.GVOF_MAX_LSFIR_OUTER
+            h = gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
+            handles.append(h)
+            assert gvof.gvof_mesh_workspace_bytes(h) >= gvof.gvof_mesh_workspace_bytes(base) + 48 * m.nc
+        with pytest.raises(gvof.GvofError):
+            gvof.gvof_batch_create([base, handles[1]])
+        for outer, tol in ((0, 0.0), (gvof.GVOF_MAX_LSFIR_OUTER + 1, 0.0), (1, -1e-3), (1, float("nan")),
+                           (1, float("inf"))):
+            p = gvof.gvof_params_default()
+            p.flags = gvof.GVOF_FLAG_LSFIR
+            p.lsfir_outer, p.lsfir_tol = outer, tol
+            with pytest.raises(gvof.GvofError) as e:
+                gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
+            assert e.value.code == gvof.GVOF_E_ARG
+    finally:
+        for h in handles:
+            gvof.gvof_mesh_destroy(h)

@@ -32,10 +32,10 @@ def gv():
     return gvof
 
 
-def build(gv, specs, stream=None, method="fmfpa"):
+def build(gv, specs, stream=None, method="fmfpa", recon="lsgir"):
     torch, dev = torch_dev()
     P = [inputs.problem_inputs(s) for s in specs]
-    B = gv.GvofBatch([p["mesh"] for p in P], dev, stream=stream, method=method)
+    B = gv.GvofBatch([p["mesh"] for p in P], dev, stream=stream, method=method, recon=recon, lsfir_outer=2)
     uf = to_dev(torch, dev, inputs.concat_soa([p["uf"] for p in P]))
     uv = to_dev(torch, dev, inputs.concat_soa([p["uv"] for p in P]))
     return torch, dev, P, B, uf, uv
@@ -86,12 +86,13 @@ def test_batch_steps_bitwise_equal_alone(gv):
         assert np.array_equal(Fb[sl], Fa), q
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
-def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method):
-    torch, dev, P, B, uf, uv = build(gv, SPECS, method=method)
-    log(f"batch vs oracle, {method}")
+@pytest.mark.parametrize("method,recon", [("fmfpa", "lsgir"), ("emfpa", "lsgir"), ("nmfpa", "lsgir"),
+                                          ("fmfpa", "lsfir")])
+def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method, recon):
+    torch, dev, P, B, uf, uv = build(gv, SPECS, method=method, recon=recon)
+    log(f"batch vs oracle, {method} {recon}")
     act = to_dev(torch, dev, np.ones(len(P), np.uint8))
-    oms = [oracle_mod.OracleMesh(p["mesh"], method=method) for p in P]
+    oms = [oracle_mod.OracleMesh(p["mesh"], method=method, recon=recon, lsfir_outer=2) for p in P]
     Fo = [om.init_fraction("sphere", p["shape"][1], 6) for om, p in zip(oms, P)]
     for s in range(4):
         F = to_dev(torch, dev, np.concatenate(Fo))
@@ -109,11 +110,13 @@ def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method):
     B.status()
 
 
-def test_graph_replay_equals_eager(gv):
+@pytest.mark.parametrize("recon", ["lsgir", "lsfir"])
+def test_graph_replay_equals_eager(gv, recon):
     torch, dev = torch_dev()
     st = torch.cuda.Stream()
+    log(f"graph replay, {recon}")
     with torch.cuda.stream(st):
-        _, _, P, B, uf, uv = build(gv, SPECS, stream=st)
+        _, _, P, B, uf, uv = build(gv, SPECS, stream=st, recon=recon)
         Fe = B.init_fraction_each([p["shape"] for p in P], 6)
         Fg = Fe.clone()
         dt_e = dt_row(torch, dev, P, 0)

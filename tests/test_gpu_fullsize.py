@@ -5,7 +5,7 @@ face is compared with the oracle, teacher-forced from the oracle's state.
   - 64^3 Cartesian, Enright field with period 3, CFL 0.5: the first two steps
     and step 100 (the oracle runs the trajectory up to there);
   - 64^3 distorted (+-0.25h, seed 1), same field: the first two steps, with
-    FMFPA, EMFPA and NMFPA flux polyhedra.
+    FMFPA, EMFPA and NMFPA flux polyhedra, and with LSFIR normals.
 
 Bars as in the small-size parity tests: tags and upwind cells bit for bit,
 V_d bit for bit, |dV_F| <= 1e-12 V, |dF| <= 1e-12 per cell.
@@ -44,15 +44,18 @@ def _step_parity(oracle_mod, g, om, F, uf, uv, ufd, uvd, dts, V, torch, dev, lab
     return F1
 
 
-@pytest.mark.parametrize("kind,later,method", [("cartesian", 100, "fmfpa"), ("jittered", None, "fmfpa"),
-                                               ("jittered", None, "emfpa"), ("jittered", None, "nmfpa")])
-def test_full_size_parity(oracle_mod, kind, later, method):
+@pytest.mark.parametrize("kind,later,method,recon", [("cartesian", 100, "fmfpa", "lsgir"),
+                                                      ("jittered", None, "fmfpa", "lsgir"),
+                                                      ("jittered", None, "emfpa", "lsgir"),
+                                                      ("jittered", None, "nmfpa", "lsgir"),
+                                                      ("jittered", None, "fmfpa", "lsfir")])
+def test_full_size_parity(oracle_mod, kind, later, method, recon):
     from paper_2111_01524_amd import gvof
     torch, dev = torch_dev()
     m = inputs.cartesian_mesh(64) if kind == "cartesian" else inputs.jittered_mesh(64, seed=1)
-    log(f"full size {kind} 64^3 {method}: faces {m.nf} cells {m.nc}")
-    om = oracle_mod.OracleMesh(m, method=method)
-    g = gvof.GvofMesh(m, dev, method=method)
+    log(f"full size {kind} 64^3 {method} {recon}: faces {m.nf} cells {m.nc}")
+    om = oracle_mod.OracleMesh(m, method=method, recon=recon)
+    g = gvof.GvofMesh(m, dev, method=method, recon=recon)
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     sched = inputs.step_schedule(3.0, dt)

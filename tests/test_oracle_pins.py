@@ -348,7 +348,8 @@ def test_plic_centre_exact_on_general_cells(oracle_mod):
 def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod):
     """The fit against numpy.linalg.eigh of the weighted scatter matrix of the
     valid neighbours' PLIC centres (vertex-sharing interfacial cells within
-    45 degrees, w = |d|^-2.5), on a sphere on the distorted grid."""
+    45 degrees, w = |d|^-2.5 with |d| taken as at least 0.05 of the cell's
+    largest box extent), on a sphere on the distorted grid."""
     m = inputs.jittered_mesh(10, seed=2)
     om = oracle_mod.OracleMesh(m)
     F = om.init_fraction("sphere", [0.525, 0.464, 0.516, 0.325], 6)
@@ -356,14 +357,16 @@ def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod):
     xc, cnt = om.plic_centres(tc, pl)
     fit, nvalid = om.lsfir_fit(tc, pl[:3], xc)
     ptr, idx = om.neighbours()
+    geo = om.geometry()
     checked = 0
     for c in np.where(tc == 0)[0]:
         A = np.zeros((3, 3)); k_ok = 0
+        hc = (geo["bbmax"][:, c] - geo["bbmin"][:, c]).max()
         for k in idx[ptr[c]:ptr[c + 1]]:
             if tc[k] != 0 or not pl[:3, c] @ pl[:3, k] > np.sqrt(0.5):
                 continue
             d = xc[:, k] - xc[:, c]
-            A += np.linalg.norm(d) ** -2.5 * np.outer(d, d)
+            A += max(np.linalg.norm(d), 0.05 * hc) ** -2.5 * np.outer(d, d)
             k_ok += 1
         assert nvalid[c] == k_ok
         if k_ok < 2:
