@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
     ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa", "nmfpa"],
                     help="flux polyhedra: face-matched (the default workload), edge-matched or non-matched")
+    ap.add_argument("--recon", default="lsgir", choices=["lsgir", "lsfir"],
+                    help="interface normals: LSGIR (the default workload) or LSFIR")
+    ap.add_argument("--lsfir-outer", type=int, default=1, help="LSFIR outer passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
@@ -115,7 +118,7 @@ def main():
     dev = torch.device("cuda:0")
     n, T_end, cfl = args.n, 3.0, 0.5
     mesh = inputs.cartesian_mesh(n) if args.kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
-    g = gvof.GvofMesh(mesh, dev, method=args.method)
+    g = gvof.GvofMesh(mesh, dev, method=args.method, recon=args.recon, lsfir_outer=args.lsfir_outer)
     uf, uv = inputs.velocity_enright(mesh)
     dt = inputs.cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
     sched = inputs.step_schedule(T_end, dt)
@@ -210,7 +213,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.kind} {n}^3 unit cube, sphere r=0.15 at 0.35, Enright deformation T=3, CFL 0.5, "
-                        f"LSGIR+{args.method.upper()}, {len(sched)} steps per trajectory",
+                        f"{args.recon.upper()}{f' ({args.lsfir_outer} outer)' if args.recon == 'lsfir' else ''}"
+                        f"+{args.method.upper()}, {len(sched)} steps per trajectory",
             "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
         },
         "cells_per_s": mesh.nc * K / (ms_total / 1e3),
@@ -247,7 +251,8 @@ def main():
         torch.cuda.empty_cache()
         out["served"] = served_leg(args, served, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds, args.method)
+        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds, args.method, args.recon,
+                                           args.lsfir_outer)
     print(json.dumps(out), flush=True)
 
 
@@ -356,11 +361,11 @@ def batched_leg(args, problems, dev):
     return res
 
 
-def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s, method):
+def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s, method, recon, lsfir_outer):
     """The CPU reference (as it stands) on the host cores: the first steps of the same trajectory."""
     from oracle import oracle as O
     threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
-    om = O.OracleMesh(mesh, method=method)
+    om = O.OracleMesh(mesh, method=method, recon=recon, lsfir_outer=lsfir_outer)
     F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
     t0 = time.perf_counter()
     done = 0

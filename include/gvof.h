@@ -47,8 +47,9 @@ enum {
   GVOF_E_LIMIT = -6    /* a mesh entity exceeds a compiled-in capacity */
 };
 
-/* Flags for gvof_params.flags (any other bit, or both method flags:
- * GVOF_E_ARG from gvof_mesh_create); no method flag: FMFPA */
+/* Flags for gvof_params.flags (any other bit, both method flags, or LSFIR
+ * settings out of range: GVOF_E_ARG from gvof_mesh_create); no method flag:
+ * FMFPA; no GVOF_FLAG_LSFIR: LSGIR normals */
 #define GVOF_FLAG_NONE 0u
 /* Flux polyhedra by EMFPA (Sec. "Edge-matched flux polyhedron": vertices moved
  * back along their streak lines, Eq. streak-line2; each lateral face as four
@@ -63,12 +64,25 @@ enum {
  * neighbouring polyhedra may overlap).  u_vert is not read with this flag.
  * Not together with GVOF_FLAG_EMFPA (GVOF_E_ARG). */
 #define GVOF_FLAG_NMFPA 2u
+/* Normals by LSFIR (Sec. "Least squares fit interface reconstruction"): after
+ * LSGIR, each interfacial cell's normal is refitted as the plane through its
+ * PLIC centre (the vertex mean of its PLIC polygon) nearest, in the weighted
+ * least-squares sense (w = |dx|^-2.5), to the PLIC centres of the vertex-
+ * sharing interfacial cells whose normals are within 45 degrees; the outer
+ * iteration adopts a fit that turns the normal by less than 30/I degrees in
+ * pass I, all cells at once, then places the changed planes; at most
+ * lsfir_outer passes, stopping early after a pass in which no normal turned
+ * by lsfir_tol (radians) or more. */
+#define GVOF_FLAG_LSFIR 4u
+#define GVOF_MAX_LSFIR_OUTER 32
 
 typedef struct gvof_params {
   double eps;         /* volume-fraction tolerance (Sec. "Interface reconstruction"); 1e-12 as in all tests */
   double beta;        /* LSGIR weight exponent of Eq. (lsgir-beta); 1.5 */
   double fmfpa_degen; /* FMFPA: two lateral planes count as parallel when |d|^2 <= degen |m1|^2 |m2|^2; 1e-12 */
   uint32_t flags;     /* GVOF_FLAG_* */
+  int32_t lsfir_outer; /* LSFIR outer passes at most, 1..GVOF_MAX_LSFIR_OUTER; 1 */
+  double lsfir_tol;    /* LSFIR stopping angle (rad), >= 0; 0: stop only when no normal moved */
 } gvof_params;
 
 /* Fills the defaults quoted above. */
@@ -209,7 +223,7 @@ int gvof_work_totals(gvof_mesh* m, int64_t* cells, int64_t* faces);
  * synchronises, writes for every kernel k < n the summed milliseconds and the
  * number of timed launches, and clears the record.
  */
-#define GVOF_NUM_KERNELS 15
+#define GVOF_NUM_KERNELS 16
 int gvof_profile_enable(gvof_mesh* m, uint32_t mask);
 int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches);
 const char* gvof_kernel_name(int32_t k);

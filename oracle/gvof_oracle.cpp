@@ -494,22 +494,29 @@ V3 lsgir_normal(const OMesh& M, const double* F, int c, double beta) {
 }
 
 // Plane constant: the unique C with vol(cell ∩ {n.x + C >= 0}) = F V, by
-// bisection on the level s = -C between the extreme vertex levels.
+// bisection on a level between the extreme vertex levels.  The smaller of
+// the fluid and empty volumes is matched: for F > 1/2 the empty part
+// vol(cell ∩ {-n.x >= s}) = (1 - F) V (1 - F exact there), which defines the
+// same plane but is evaluated with rounding relative to the small volume, so
+// a nearly full cell's plane is as well determined as a nearly empty one's.
 real plane_constant(const OMesh& M, int c, V3 n, double Fc) {
-  real lo = dot(n, M.X[M.cv[c][0]]), hi = lo;
+  const bool flip = Fc > 0.5;
+  const V3 m = flip ? mk(-n.x, -n.y, -n.z) : n;
+  real lo = dot(m, M.X[M.cv[c][0]]), hi = lo;
   for (int v : M.cv[c]) {
-    real s = dot(n, M.X[v]);
+    real s = dot(m, M.X[v]);
     lo = std::min(lo, s);
     hi = std::max(hi, s);
   }
-  real target = real(Fc) * M.V[c];
+  real target = (flip ? real(1.0) - real(Fc) : real(Fc)) * M.V[c];
   for (int it = 0; it < 400; ++it) {
     real mid = real(0.5) * (lo + hi);
     if (!(mid > lo && mid < hi)) break;
-    if (cell_level_volume(M, c, n, mid) > target) lo = mid;
+    if (cell_level_volume(M, c, m, mid) > target) lo = mid;
     else hi = mid;
   }
-  return -(real(0.5) * (lo + hi));
+  real s = real(0.5) * (lo + hi);
+  return flip ? s : -s;  // fluid {n.x >= -s}, or the complement of {-n.x >= s}
 }
 
 // --------------------------------------------------------------------------

@@ -94,9 +94,20 @@ struct gvof_mesh {
   bool advect_state_clear = false;  // a reconstruction cleared the step counters and no advection used them yet
   std::string err;
   EventProf prof;
+  gvof::LsfirConsts lsfir{};  // LSFIR thresholds (set at creation)
 };
 
 static thread_local std::string g_create_err;
+
+// LSFIR thresholds from the parameters: cos 45 degrees, cos of the stopping
+// tolerance, cos(30/I degrees) for each outer pass I.
+static void set_lsfir_consts(gvof_mesh* m) {
+  const double pi = 3.14159265358979323846;
+  m->lsfir.cos_valid = std::sqrt(0.5);
+  m->lsfir.cos_stop = std::cos(m->p.lsfir_tol);
+  m->lsfir.cos_turn[0] = 1.0;
+  for (int i = 1; i <= gvof::kMaxLsfirOuter; ++i) m->lsfir.cos_turn[i] = std::cos((pi / 6.0) / double(i));
+}
 
 static int fail(gvof_mesh* m, int code, const char* fmt, ...) {
   char buf[512];
@@ -125,6 +136,8 @@ void gvof_params_default(gvof_params* p) {
   p->beta = 1.5;
   p->fmfpa_degen = 1e-12;
   p->flags = GVOF_FLAG_NONE;
+  p->lsfir_outer = 1;
+  p->lsfir_tol = 0.0;
 }
 
 int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double* vy, const double* vz, int32_t nf,
@@ -151,9 +164,15 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
       return fail(nullptr, GVOF_E_MESH, "vertex %d not finite", v);
 
   if (params) {
-    const uint32_t known = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA;
+    const uint32_t methods = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA, known = methods | GVOF_FLAG_LSFIR;
     if (params->flags & ~known) return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~known));
-    if ((params->flags & known) == known) return fail(nullptr, GVOF_E_ARG, "GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA together");
+    if ((params->flags & methods) == methods)
+      return fail(nullptr, GVOF_E_ARG, "GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA together");
+    if ((params->flags & GVOF_FLAG_LSFIR) &&
+        (params->lsfir_outer < 1 || params->lsfir_outer > GVOF_MAX_LSFIR_OUTER || !(params->lsfir_tol >= 0.0) ||
+         !std::isfinite(params->lsfir_tol)))
+      return fail(nullptr, GVOF_E_ARG, "lsfir_outer=%d (1..%d) or lsfir_tol=%g (>= 0) invalid", params->lsfir_outer,
+                  GVOF_MAX_LSFIR_OUTER, params->lsfir_tol);
   }
 
   gvof_mesh* m = new gvof_mesh;
@@ -162,6 +181,7 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
   m->nc = nc;
   if (params) m->p = *params;
   else gvof_params_default(&m->p);
+  set_lsfir_consts(m);
   m->vx.assign(vx, vx + nv);
   m->vy.assign(vy, vy + nv);
   m->vz.assign(vz, vz + nv);
@@ -447,6 +467,11 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.unit_vol = C.take<double>(d.unit_cap);
   d.list_udeep = C.take<int>(d.unit_cap);
   d.counters = C.take<int>(gvof::CNT_N);
+  if (m->p.flags & GVOF_FLAG_LSFIR) {
+    d.lsfir_xc = C.take<double>(3 * (size_t)nc);
+    d.lsfir_nn = C.take<double>(3 * (size_t)nc);
+    d.lsfir_turned = C.take<int>(gvof::kMaxLsfirOuter + 1);
+  }
   d.totals = C.take<unsigned long long>(4);
   d.nprob = m->nprob;
   if (m->nprob > 1) {
@@ -460,6 +485,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
   d.method = (m->p.flags & GVOF_FLAG_EMFPA) ? gvof::kEMFPA : (m->p.flags & GVOF_FLAG_NMFPA) ? gvof::kNMFPA : gvof::kFMFPA;
+  d.lsfir_outer = (m->p.flags & GVOF_FLAG_LSFIR) ? m->p.lsfir_outer : 0;
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
 }
@@ -614,7 +640,7 @@ int gvof_reconstruct(gvof_mesh* m, double* F, int8_t* cell_tag_out, double* plan
   if (r) return r;
   if (!F) return fail(m, GVOF_E_ARG, "F is NULL");
   m->prof.stream = m->stream;
-  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->cfg, m->stream, m->prof.mask ? &m->prof : nullptr));
+  HIPCHECK(m, gvof::launch_reconstruct(m->dm, F, m->cfg, m->stream, m->prof.mask ? &m->prof : nullptr, &m->lsfir));
   m->reconstructed = true;
   m->advect_state_clear = true;
   if ((r = d2d(m, cell_tag_out, m->dm.tag_cell, m->nc))) return r;
@@ -728,7 +754,8 @@ int gvof_batch_create(gvof_mesh** out, int32_t nprob, gvof_mesh* const* parts) {
     if (!a) return fail(nullptr, GVOF_E_ARG, "part %d is NULL", q);
     if (a->nprob != 1) return fail(nullptr, GVOF_E_ARG, "part %d is itself a batch", q);
     const gvof_params& p0 = parts[0]->p;
-    if (a->p.eps != p0.eps || a->p.beta != p0.beta || a->p.fmfpa_degen != p0.fmfpa_degen || a->p.flags != p0.flags)
+    if (a->p.eps != p0.eps || a->p.beta != p0.beta || a->p.fmfpa_degen != p0.fmfpa_degen || a->p.flags != p0.flags ||
+        a->p.lsfir_outer != p0.lsfir_outer || a->p.lsfir_tol != p0.lsfir_tol)
       return fail(nullptr, GVOF_E_ARG, "part %d has parameters different from part 0", q);
     nv += a->nv;
     nf += a->nf;
@@ -745,6 +772,7 @@ int gvof_batch_create(gvof_mesh** out, int32_t nprob, gvof_mesh* const* parts) {
                 (long long)nf, (long long)nc);
   gvof_mesh* m = new gvof_mesh;
   m->p = parts[0]->p;
+  set_lsfir_consts(m);
   m->nv = (int)nv;
   m->nf = (int)nf;
   m->nc = (int)nc;
@@ -838,7 +866,7 @@ static int batch_launch(gvof_mesh* m, const double* uf, const double* uv, const 
   DevMesh d = m->dm;
   d.prob_dt = dt;
   d.prob_active = active;
-  HIPCHECK(m, gvof::launch_reconstruct(d, F, m->cfg, m->stream, prof));
+  HIPCHECK(m, gvof::launch_reconstruct(d, F, m->cfg, m->stream, prof, &m->lsfir));
   HIPCHECK(m, gvof::launch_advect(d, uf, uv, 0.0, F, F, m->cfg, m->stream, prof, false));
   m->advect_state_clear = false;
   return GVOF_OK;
@@ -1029,7 +1057,7 @@ const char* gvof_kernel_name(int32_t k) {
                                              "k_face_sweep", "k_flux_items_box", "k_update", "k_flux_prep",
                                              "k_flux_sum", "(unused)", "k_flux_gen_filter",
                                              "k_flux_deep", "k_flux_gen_units", "k_flux_gen_sum",
-                                             "k_flux_gen_units_deep"};
+                                             "k_flux_gen_units_deep", "k_lsfir_fit"};
   return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";
 }
 

@@ -71,6 +71,11 @@ struct DevMesh {
   unsigned long long* totals;  // [0] cells reconstructed, [1] faces with flux polyhedra, [2] staged pairs (cumulative)
   double eps, beta, degen;
   int method;   // flux polyhedra: kFMFPA, kEMFPA or kNMFPA
+  // LSFIR (normals refined after LSGIR; lsfir_outer == 0: LSGIR only)
+  int lsfir_outer;
+  double* lsfir_xc;   // [3][nc] PLIC centres of the current planes
+  double* lsfir_nn;   // [3][nc] fitted normals of the current pass
+  int* lsfir_turned;  // [kMaxLsfirOuter + 1] cells whose normal turned by the tolerance or more, per pass
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);
@@ -113,6 +118,7 @@ constexpr int kMaxFaceVerts = 8;
 // flux polyhedron methods (Secs. "Face-matched", "Edge-matched" and
 // "Non-matched flux polyhedron")
 constexpr int kFMFPA = 0, kEMFPA = 1, kNMFPA = 2;
+constexpr int kMaxLsfirOuter = 32;  // LSFIR outer passes at most
 constexpr int kItemRegions = 256;
 constexpr int kMaxNeighbours = 62;  // vertex-sharing neighbours of one cell
 constexpr int kMaxCellVerts = 30;   // distinct vertices of one cell

@@ -220,6 +220,7 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   // follows it (which then needs no reset kernel of its own)
   if (blockIdx.x == 0) {
     if (threadIdx.x == 0) M.counters[CNT_CELLS] = 0;
+    if (M.lsfir_outer > 0 && threadIdx.x <= kMaxLsfirOuter) M.lsfir_turned[threadIdx.x] = 0;
     reset_advect_state(M);
   }
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
@@ -1733,6 +1734,170 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double
 
 __global__ void k_reset_advect(DevMesh M) { reset_advect_state(M); }
 
+// ============================================================== LSFIR
+// (Sec. "Least squares fit interface reconstruction")
+
+// Vertex mean of the PLIC polygon {n.x + C = 0} within cell c: the cell's
+// vertices on the plane, then the strict crossings of its edges.  Each edge
+// is taken once, from the face in which the cell's outward orientation runs
+// it from the lower vertex index to the higher (on a closed, consistently
+// oriented cell exactly one of its two faces does).  Signed distances in the
+// exact-order form, crossing points without contraction.  No point: the
+// cell centre.
+__device__ inline d3 plic_centre(const DevMesh& M, int c, d3 n, double C) {
+  d3 sum = mk3(0.0, 0.0, 0.0);
+  int cnt = 0;
+  for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1]; ++i) {
+    const d3 x = vert(M, M.cv_idx[i]);
+    if (dot_x(n, x) + C == 0.0) {
+      sum = sum + x;
+      ++cnt;
+    }
+  }
+  const int fb = cf_begin(M, c), fn = cf_count(M, c);
+  for (int q = 0; q < fn; ++q) {
+    const int e = M.cf_idx[fb + q];
+    const int f = e >= 0 ? e : ~e;
+    const int b = fv_begin(M, f), k = fv_count(M, f);
+    for (int i = 0; i < k; ++i) {
+      const int p = M.fv_idx[b + i], r = M.fv_idx[b + (i + 1 == k ? 0 : i + 1)];
+      const int from = e >= 0 ? p : r, to = e >= 0 ? r : p;  // outward direction
+      if (from > to) continue;
+      const d3 xa = vert(M, from), xb = vert(M, to);
+      const double sa = dot_x(n, xa) + C, sb = dot_x(n, xb) + C;
+      if ((sa > 0.0 && sb < 0.0) || (sa < 0.0 && sb > 0.0)) {
+        const double t = sa / (sa - sb);
+        sum = sum + (xa + t * (xb - xa));
+        ++cnt;
+      }
+    }
+  }
+  if (cnt == 0) return cell_centre(M, c);
+  const double k = (double)cnt;
+  return mk3(sum.x / k, sum.y / k, sum.z / k);
+}
+
+// PLIC centres of the interfacial cells' current planes (a lane per cell),
+// before the first LSFIR pass and after each placement pass.
+__global__ void k_plic_centres(DevMesh M, int pass) {
+  if (pass > 0 && M.lsfir_turned[pass] == 0) return;  // no plane moved
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
+    const int c = M.list_cells[it];
+    const d3 x = plic_centre(M, c, mk3(M.pnx[c], M.pny[c], M.pnz[c]), M.pC[c]);
+    M.lsfir_xc[c] = x.x;
+    M.lsfir_xc[nc + c] = x.y;
+    M.lsfir_xc[2 * nc + c] = x.z;
+  }
+}
+
+// One Jacobi rotation of the symmetric 3x3 matrix A (and of the eigenvector
+// matrix V) in the (P, Q) plane, zeroing A[P][Q] up to rounding.  Compile-time
+// indices keep both matrices in registers.
+template <int P, int Q>
+__device__ inline void jacobi_rotate(double (&A)[3][3], double (&V)[3][3]) {
+  const double apq = A[P][Q];
+  if (apq == 0.0) return;
+  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * apq);
+  double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));  // the smaller root of t^2 + 2 theta t = 1
+  t = theta < 0.0 ? -t : t;
+  const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = A[k][P], w = A[k][Q];
+    A[k][P] = cs * u - sn * w;
+    A[k][Q] = sn * u + cs * w;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = A[P][k], w = A[Q][k];
+    A[P][k] = cs * u - sn * w;
+    A[Q][k] = sn * u + cs * w;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = V[k][P], w = V[k][Q];
+    V[k][P] = cs * u - sn * w;
+    V[k][Q] = sn * u + cs * w;
+  }
+}
+
+// One outer pass of LSFIR, a lane per interfacial cell: the plane through
+// the cell's PLIC centre x minimising sum w_k (n.(x_k - x))^2 over the valid
+// neighbours (interfacial cells sharing a vertex whose normals are within
+// 45 degrees), w_k = |x_k - x|^-2.5, accumulated in neighbour order (the
+// weight is singular where two centres coincide and a very close centre's
+// direction is set by rounding, so |d| is taken as at least 0.05 of the
+// cell's largest box extent; with 1/(d^2 sqrt(sqrt(d^2))), every operation
+// correctly rounded); its
+// normal is the eigenvector of the smallest eigenvalue (cyclic Jacobi), turned
+// to agree with the current normal.  The fit is adopted when it turns the
+// normal by less than 30/I degrees (cos_turn); with fewer than two valid
+// neighbours or a smallest eigenvalue not separated from the next, the
+// normal stays.  Results go to lsfir_nn, so every cell reads the current
+// normals; the placement pass then moves them over.  After a pass in which
+// no normal turned by the tolerance, the later passes do nothing.
+__global__ void k_lsfir_fit(DevMesh M, int pass, double cos_valid, double cos_turn, double cos_stop) {
+  if (pass > 1 && M.lsfir_turned[pass - 1] == 0) return;
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
+    const int c = M.list_cells[it];
+    const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+    const d3 x = mk3(M.lsfir_xc[c], M.lsfir_xc[nc + c], M.lsfir_xc[2 * nc + c]);
+    const double hc = fmax(fmax(M.hix[c] - M.lox[c], M.hiy[c] - M.loy[c]), M.hiz[c] - M.loz[c]);
+    const double dmin2 = (0.05 * hc) * (0.05 * hc);
+    double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    int nvalid = 0;
+    for (int i = M.nb_ptr[c]; i < M.nb_ptr[c + 1]; ++i) {
+      const int k = M.nb_idx[i];
+      if (M.tag_cell[k] != 0) continue;
+      const d3 nk = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
+      if (!(dot_x(n, nk) > cos_valid)) continue;
+      const d3 d = mk3(M.lsfir_xc[k], M.lsfir_xc[nc + k], M.lsfir_xc[2 * nc + k]) - x;
+      const double dd = dot_x(d, d);
+      if (dd == 0.0) continue;
+      const double dw = fmax(dd, dmin2);
+      const double w = 1.0 / (dw * sqrt(sqrt(dw)));  // |d|^-2.5
+      const double dv[3] = {d.x, d.y, d.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + w * dv[a] * dv[b];
+      ++nvalid;
+    }
+    d3 e = n;
+    if (nvalid >= 2) {
+      double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+      for (int sweep = 0; sweep < 64; ++sweep) {
+        if (fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]) == 0.0) break;
+        jacobi_rotate<0, 1>(A, V);
+        jacobi_rotate<0, 2>(A, V);
+        jacobi_rotate<1, 2>(A, V);
+      }
+      // the smallest eigenvalue's column, and the gap to the next
+      const double l0 = A[0][0], l1 = A[1][1], l2 = A[2][2];
+      const int imin = (l0 <= l1 && l0 <= l2) ? 0 : (l1 <= l2 ? 1 : 2);
+      const double lo = imin == 0 ? l0 : (imin == 1 ? l1 : l2);
+      const double mid = imin == 0 ? fmin(l1, l2) : (imin == 1 ? fmin(l0, l2) : fmin(l0, l1));
+      const double hi = fmax(fmax(l0, l1), l2);
+      if (mid - lo > 1e-12 * hi) {
+        d3 v = imin == 0 ? mk3(V[0][0], V[1][0], V[2][0]) : (imin == 1 ? mk3(V[0][1], V[1][1], V[2][1])
+                                                                         : mk3(V[0][2], V[1][2], V[2][2]));
+        const double vn = sqrt(dot_x(v, v));
+        v = mk3(v.x / vn, v.y / vn, v.z / vn);
+        e = dot_x(v, n) < 0.0 ? mk3(-v.x, -v.y, -v.z) : v;
+      }
+    }
+    const d3 nn = dot_x(e, n) > cos_turn ? e : n;
+    M.lsfir_nn[c] = nn.x;
+    M.lsfir_nn[nc + c] = nn.y;
+    M.lsfir_nn[2 * nc + c] = nn.z;
+    if (dot_x(nn, n) < cos_stop) atomicAdd(&M.lsfir_turned[pass], 1);
+  }
+}
+
 // ============================================================== LSGIR + plane constant
 // A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
 // the GPU nearly idle: a few thousand cells, each a long dependent chain).
@@ -1766,8 +1931,12 @@ __device__ inline double general_level_volume(const DevMesh& M, int c, d3 n, d3 
 // Two instances: BOX handles the axis-aligned box cells, whose plane constant
 // needs only the eight corner levels (held one per lane of the group, so the
 // instance keeps no per-lane arrays), and !BOX the general cells.
-template <bool BOX>
-__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F, int count_cells) {
+// GIVEN: the LSFIR placement pass `pass`: cells whose fitted normal in
+// lsfir_nn differs from the current one take it, with their plane constant;
+// the others are left alone.  Otherwise the LSGIR pass.
+template <bool BOX, bool GIVEN>
+__global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restrict__ F, int count_cells, int pass) {
+  if (GIVEN && pass > 1 && M.lsfir_turned[pass - 1] == 0) return;
   const int ncell = M.counters[CNT_CELLS];
   if (count_cells && blockIdx.x == 0 && threadIdx.x == 0) M.totals[0] += (unsigned long long)ncell;
   const double beta = M.beta;
@@ -1794,6 +1963,12 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
     asm volatile("" : "+v"(isb), "+v"(Fc), "+v"(Vc), "+v"(blo.x), "+v"(blo.y), "+v"(blo.z), "+v"(bhi.x),
                  "+v"(bhi.y), "+v"(bhi.z));
     if ((isb != 0) != BOX) continue;  // uniform over the group
+    d3 n;
+    if constexpr (GIVEN) {
+      const int nc = M.nc;
+      n = mk3(M.lsfir_nn[c], M.lsfir_nn[nc + c], M.lsfir_nn[2 * nc + c]);
+      if (n.x == M.pnx[c] && n.y == M.pny[c] && n.z == M.pnz[c]) continue;  // unchanged (uniform over the group)
+    } else {
     // ---- LSGIR: normal equations sum w^2 d d^T g = sum w^2 d dF, w = |d|^-beta.
     // The lanes gather the neighbours' terms, a round of kReconLanes at a time,
     // and every lane accumulates all terms in neighbour order: the sums keep the
@@ -1836,15 +2011,21 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
                fma(c02, r0, fma(c12, r1, c22 * r2)));
     if (det < 0.0) g = mk3(-g.x, -g.y, -g.z);
     double gg = dotf(g, g);
-    d3 n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
+    n = (gg > 0.0 && det != 0.0) ? (1.0 / sqrt(gg)) * g : mk3(0.0, 0.0, 1.0);
+    }
     // ---- plane constant: G(s) = vol(cell ∩ {n.x >= s}) = F V, G decreasing from V to 0
     // over the sorted vertex levels
-    const double T = Fc * Vc;
+    // the smaller of the fluid and empty volumes is matched: for F > 1/2 the
+    // empty part {-n.x >= s} with (1 - F) V (1 - F exact there), the same
+    // plane, evaluated with rounding relative to the small volume
+    const bool flip = Fc > 0.5;
+    const d3 ns = flip ? mk3(-n.x, -n.y, -n.z) : n;
+    const double T = (flip ? 1.0 - Fc : Fc) * Vc;
     double s0, w, glo, ghi;
     if constexpr (BOX) {
       // lane sub holds the level of corner sub; every lane gathers all eight
       const d3 p = mk3((sub & 1) ? bhi.x : blo.x, (sub & 2) ? bhi.y : blo.y, (sub & 4) ? bhi.z : blo.z);
-      const double bl = dotf(n, p);
+      const double bl = dotf(ns, p);
       double blev[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) blev[q] = __shfl(bl, gbase + q);
@@ -1884,25 +2065,25 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
     } else {
       double lev[kMaxLevels];
       int nl = 0;
-      insert_sorted(lev, nl, dotf(n, xc));
+      insert_sorted(lev, nl, dotf(ns, xc));
       for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1] && nl < kMaxLevels; ++i)
-        insert_sorted(lev, nl, dotf(n, vert(M, M.cv_idx[i])));
+        insert_sorted(lev, nl, dotf(ns, vert(M, M.cv_idx[i])));
       int fb = cf_begin(M, c), fn = cf_count(M, c);
       for (int i = 0; i < fn && nl < kMaxLevels; ++i) {
         int e = M.cf_idx[fb + i];
         int f = e >= 0 ? e : ~e;
-        if (fv_count(M, f) > 3) insert_sorted(lev, nl, dotf(n, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
+        if (fv_count(M, f) > 3) insert_sorted(lev, nl, dotf(ns, mk3(M.fcx[f], M.fcy[f], M.fcz[f])));
       }
       if (sub == 0 && M.cv_ptr[c + 1] - M.cv_ptr[c] + 1 > kMaxLevels) atomicOr(&M.counters[CNT_ERR], ERR_LEVELS);
       const int np = cell_piece_count(M, c);
       const bool tri_only = np == fn;
       // bisection over the levels; every evaluation is spread over the group
       int lo_i = 0, hi_i = nl - 1;
-      glo = general_level_volume(M, c, n, xc, lev[0], sub, np, tri_only);
+      glo = general_level_volume(M, c, ns, xc, lev[0], sub, np, tri_only);
       ghi = 0.0;
       while (hi_i - lo_i > 1) {
         int mid = (lo_i + hi_i) >> 1;
-        double gm = general_level_volume(M, c, n, xc, lev[mid], sub, np, tri_only);
+        double gm = general_level_volume(M, c, ns, xc, lev[mid], sub, np, tri_only);
         if (gm >= T) {
           lo_i = mid;
           glo = gm;
@@ -1914,8 +2095,8 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
       s0 = lev[lo_i];
       w = lev[hi_i] - s0;
       if (w > 0.0) {
-        double y1 = general_level_volume(M, c, n, xc, fma(w, 1.0 / 3.0, s0), sub, np, tri_only);
-        double y2 = general_level_volume(M, c, n, xc, fma(w, 2.0 / 3.0, s0), sub, np, tri_only);
+        double y1 = general_level_volume(M, c, ns, xc, fma(w, 1.0 / 3.0, s0), sub, np, tri_only);
+        double y2 = general_level_volume(M, c, ns, xc, fma(w, 2.0 / 3.0, s0), sub, np, tri_only);
         s0 = cubic_root(s0, w, glo, y1, y2, ghi, T);
       }
     }
@@ -1923,7 +2104,7 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
       M.pnx[c] = n.x;
       M.pny[c] = n.y;
       M.pnz[c] = n.z;
-      M.pC[c] = -s0;
+      M.pC[c] = flip ? s0 : -s0;  // fluid {n.x >= -s0}, or the complement of {-n.x >= s0}
     }
   }
 }
@@ -2128,14 +2309,26 @@ hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
     if (prof) prof->after(k);     \
   } while (0)
 
-hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof) {
+hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof,
+                              const LsfirConsts* lsfir) {
   const int st = L.sweep_threads;
   TIMED(K_NODE_TAG, (k_node_tag<<<blocks_for(M.nv, st), st, 0, s>>>(M, F)));
   TIMED(K_CELL_TAG, (k_cell_tag<<<blocks_for(M.nc, st), st, 0, s>>>(M, F)));
   const int rb = blocks_for((long)M.nc * kReconLanes, L.recon_threads, 4096);
   // the first instance launched adds the interfacial cells to the running total
-  if (M.any_box) TIMED(K_RECON, (k_recon<true><<<rb, L.recon_threads, 0, s>>>(M, F, 1)));
-  if (!M.all_box) TIMED(K_RECON, (k_recon<false><<<rb, L.recon_threads, 0, s>>>(M, F, M.any_box ? 0 : 1)));
+  if (M.any_box) TIMED(K_RECON, (k_recon<true, false><<<rb, L.recon_threads, 0, s>>>(M, F, 1, 0)));
+  if (!M.all_box) TIMED(K_RECON, (k_recon<false, false><<<rb, L.recon_threads, 0, s>>>(M, F, M.any_box ? 0 : 1, 0)));
+  if (M.lsfir_outer > 0 && lsfir) {
+    const int fb = blocks_for(M.nc, st, 1024);
+    TIMED(K_LSFIR_FIT, (k_plic_centres<<<fb, st, 0, s>>>(M, 0)));
+    for (int pass = 1; pass <= M.lsfir_outer; ++pass) {
+      TIMED(K_LSFIR_FIT, (k_lsfir_fit<<<fb, st, 0, s>>>(M, pass, lsfir->cos_valid, lsfir->cos_turn[pass],
+                                                          lsfir->cos_stop)));
+      if (M.any_box) TIMED(K_RECON, (k_recon<true, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, pass)));
+      if (!M.all_box) TIMED(K_RECON, (k_recon<false, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, pass)));
+      if (pass < M.lsfir_outer) TIMED(K_LSFIR_FIT, (k_plic_centres<<<fb, st, 0, s>>>(M, pass)));
+    }
+  }
   return hipGetLastError();
 }
 

@@ -18,7 +18,8 @@ LIB_PATH = os.environ.get("GVOF_LIB_PATH") or os.path.join(HERE, "libgvof.so")
 
 GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
-GVOF_FLAG_NONE, GVOF_FLAG_EMFPA, GVOF_FLAG_NMFPA = 0, 1, 2
+GVOF_FLAG_NONE, GVOF_FLAG_EMFPA, GVOF_FLAG_NMFPA, GVOF_FLAG_LSFIR = 0, 1, 2, 4
+GVOF_MAX_LSFIR_OUTER = 32
 METHOD_FLAGS = {"fmfpa": GVOF_FLAG_NONE, "emfpa": GVOF_FLAG_EMFPA, "nmfpa": GVOF_FLAG_NMFPA}
 
 
@@ -29,7 +30,8 @@ class GvofError(RuntimeError):
 
 
 class gvof_params(C.Structure):
-    _fields_ = [("eps", C.c_double), ("beta", C.c_double), ("fmfpa_degen", C.c_double), ("flags", C.c_uint32)]
+    _fields_ = [("eps", C.c_double), ("beta", C.c_double), ("fmfpa_degen", C.c_double), ("flags", C.c_uint32),
+                ("lsfir_outer", C.c_int32), ("lsfir_tol", C.c_double)]
 
 
 class gvof_shape(C.Structure):
@@ -220,7 +222,7 @@ def gvof_status(h):
     return code
 
 
-GVOF_NUM_KERNELS = 15
+GVOF_NUM_KERNELS = 16
 
 
 def gvof_work_totals(h):
@@ -305,14 +307,22 @@ def gvof_last_error(h=None) -> str:
 
 
 # ------------------------------------------------------------------ convenience wrapper
-def _with_method(params, method: str):
-    """params with the flag of a flux polyhedron method set ("fmfpa": unchanged)."""
+def _with_method(params, method: str, recon: str = "lsgir", lsfir_outer: int | None = None):
+    """params with the flags of a flux polyhedron method and of a
+    reconstruction set ("fmfpa" / "lsgir": unchanged); lsfir_outer, when
+    given, sets the LSFIR outer passes."""
     if method not in METHOD_FLAGS:
         raise ValueError(f"unknown flux polyhedron method {method!r}")
-    if method == "fmfpa":
+    if recon not in ("lsgir", "lsfir"):
+        raise ValueError(f"unknown reconstruction {recon!r}")
+    if method == "fmfpa" and recon == "lsgir":
         return params
     params = params if params is not None else gvof_params_default()
     params.flags |= METHOD_FLAGS[method]
+    if recon == "lsfir":
+        params.flags |= GVOF_FLAG_LSFIR
+        if lsfir_outer is not None:
+            params.lsfir_outer = int(lsfir_outer)
     return params
 
 
@@ -320,13 +330,15 @@ class GvofMesh:
     """A mesh handle bound to a torch-allocated device workspace.
 
     method "emfpa" / "nmfpa" sets GVOF_FLAG_EMFPA / GVOF_FLAG_NMFPA in the
-    parameters (the flux polyhedron method); "fmfpa" leaves the flags as given.
+    parameters (the flux polyhedron method), recon "lsfir" sets
+    GVOF_FLAG_LSFIR (with lsfir_outer passes when given); "fmfpa" and "lsgir"
+    leave the flags as given.
     """
 
     def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None,
-                 method: str = "fmfpa"):
+                 method: str = "fmfpa", recon: str = "lsgir", lsfir_outer: int | None = None):
         import torch
-        params = _with_method(params, method)
+        params = _with_method(params, method, recon, lsfir_outer)
         self.torch = torch
         self.device = torch.device(device)
         self.mesh = mesh
@@ -407,10 +419,11 @@ class GvofBatch(GvofMesh):
     `offsets` gives each problem's vertex / face / cell ranges."""
 
     def __init__(self, meshes, device="cuda", params: gvof_params | None = None, stream=None, parts=None,
-                 method: str = "fmfpa"):
+                 method: str = "fmfpa", recon: str = "lsgir", lsfir_outer: int | None = None):
         """parts: optional handles already made by gvof_mesh_create for these
-        meshes (taken over and destroyed here).  method as for GvofMesh."""
-        params = _with_method(params, method)
+        meshes (taken over and destroyed here).  method, recon and lsfir_outer
+        as for GvofMesh."""
+        params = _with_method(params, method, recon, lsfir_outer)
         parts = list(parts) if parts is not None else []
         try:
             for m in meshes[len(parts):]:

@@ -448,6 +448,27 @@ def test_lsfir_outer_iteration_as_described(oracle_mod):
     assert np.abs(pl3[:3, sel] - pl[:3, sel]).max() > 1e-3  # the passes did change normals
 
 
+def test_plane_constant_nearly_full_and_empty_corner(oracle_mod):
+    """Unit cube, n = -(1,1,1)/sqrt(3) (F = 1 - delta: the empty part is the
+    corner x+y+z > 3 - t with t^3/6 = delta) and n = +(1,1,1)/sqrt(3)
+    (F = delta: the fluid is that corner): C = (3 - t)/sqrt(3) and
+    -(3 - t)/sqrt(3), to rounding of the corner size t, down to delta = 1e-14
+    (Eq. plic-eq; a volume near V evaluated with rounding relative to V would
+    leave C uncertain by ~1e-16/delta of t)."""
+    m = inputs.cartesian_mesh(1)
+    om = oracle_mod.OracleMesh(m)
+    r3 = np.sqrt(3.0)
+    tc = np.zeros(1, np.int8)
+    for delta in (1e-6, 1e-11, 1e-14):
+        for sign, F in ((-1.0, 1.0 - delta), (1.0, delta)):
+            small = Q(1) - Q(F) if F > 0.5 else Q(F)  # the corner's volume, exact (1 - F is exact for F > 1/2)
+            t = (6 * float(small)) ** (1 / 3)
+            n = np.full((3, 1), sign / r3)
+            C = om.plane_constant(np.array([F]), tc, n)[0]
+            want = -sign * (3 - t) / r3
+            assert abs(C - want) <= 8e-16, (delta, sign, C - want)
+
+
 # ----------------------------------------------------------------------------- FMFPA
 
 @pytest.mark.parametrize("kind", ["cartesian", "jittered"])
