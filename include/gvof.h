@@ -223,7 +223,7 @@ int gvof_work_totals(gvof_mesh* m, int64_t* cells, int64_t* faces);
  * synchronises, writes for every kernel k < n the summed milliseconds and the
  * number of timed launches, and clears the record.
  */
-#define GVOF_NUM_KERNELS 16
+#define GVOF_NUM_KERNELS 17
 int gvof_profile_enable(gvof_mesh* m, uint32_t mask);
 int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches);
 const char* gvof_kernel_name(int32_t k);

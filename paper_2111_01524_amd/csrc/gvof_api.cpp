@@ -470,6 +470,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   if (m->p.flags & GVOF_FLAG_LSFIR) {
     d.lsfir_xc = C.take<double>(3 * (size_t)nc);
     d.lsfir_nn = C.take<double>(3 * (size_t)nc);
+    d.lsfir_A = C.take<double>(7 * (size_t)nc);
     d.lsfir_turned = C.take<int>(gvof::kMaxLsfirOuter + 1);
   }
   d.totals = C.take<unsigned long long>(4);
@@ -1057,7 +1058,8 @@ const char* gvof_kernel_name(int32_t k) {
                                              "k_face_sweep", "k_flux_items_box", "k_update", "k_flux_prep",
                                              "k_flux_sum", "(unused)", "k_flux_gen_filter",
                                              "k_flux_deep", "k_flux_gen_units", "k_flux_gen_sum",
-                                             "k_flux_gen_units_deep", "k_lsfir_fit"};
+                                             "k_flux_gen_units_deep", "k_lsfir_fit",
+                                             "k_plic_centres"};
   return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";
 }
 

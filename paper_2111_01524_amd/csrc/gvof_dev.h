@@ -75,6 +75,7 @@ struct DevMesh {
   int lsfir_outer;
   double* lsfir_xc;   // [3][nc] PLIC centres of the current planes
   double* lsfir_nn;   // [3][nc] fitted normals of the current pass
+  double* lsfir_A;    // [7][nc] per listed cell: scatter matrix (upper triangle) and valid-neighbour count
   int* lsfir_turned;  // [kMaxLsfirOuter + 1] cells whose normal turned by the tolerance or more, per pass
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)

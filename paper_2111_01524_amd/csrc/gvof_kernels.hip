@@ -1734,170 +1734,6 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_sum(DevMesh M, const double
 
 __global__ void k_reset_advect(DevMesh M) { reset_advect_state(M); }
 
-// ============================================================== LSFIR
-// (Sec. "Least squares fit interface reconstruction")
-
-// Vertex mean of the PLIC polygon {n.x + C = 0} within cell c: the cell's
-// vertices on the plane, then the strict crossings of its edges.  Each edge
-// is taken once, from the face in which the cell's outward orientation runs
-// it from the lower vertex index to the higher (on a closed, consistently
-// oriented cell exactly one of its two faces does).  Signed distances in the
-// exact-order form, crossing points without contraction.  No point: the
-// cell centre.
-__device__ inline d3 plic_centre(const DevMesh& M, int c, d3 n, double C) {
-  d3 sum = mk3(0.0, 0.0, 0.0);
-  int cnt = 0;
-  for (int i = M.cv_ptr[c]; i < M.cv_ptr[c + 1]; ++i) {
-    const d3 x = vert(M, M.cv_idx[i]);
-    if (dot_x(n, x) + C == 0.0) {
-      sum = sum + x;
-      ++cnt;
-    }
-  }
-  const int fb = cf_begin(M, c), fn = cf_count(M, c);
-  for (int q = 0; q < fn; ++q) {
-    const int e = M.cf_idx[fb + q];
-    const int f = e >= 0 ? e : ~e;
-    const int b = fv_begin(M, f), k = fv_count(M, f);
-    for (int i = 0; i < k; ++i) {
-      const int p = M.fv_idx[b + i], r = M.fv_idx[b + (i + 1 == k ? 0 : i + 1)];
-      const int from = e >= 0 ? p : r, to = e >= 0 ? r : p;  // outward direction
-      if (from > to) continue;
-      const d3 xa = vert(M, from), xb = vert(M, to);
-      const double sa = dot_x(n, xa) + C, sb = dot_x(n, xb) + C;
-      if ((sa > 0.0 && sb < 0.0) || (sa < 0.0 && sb > 0.0)) {
-        const double t = sa / (sa - sb);
-        sum = sum + (xa + t * (xb - xa));
-        ++cnt;
-      }
-    }
-  }
-  if (cnt == 0) return cell_centre(M, c);
-  const double k = (double)cnt;
-  return mk3(sum.x / k, sum.y / k, sum.z / k);
-}
-
-// PLIC centres of the interfacial cells' current planes (a lane per cell),
-// before the first LSFIR pass and after each placement pass.
-__global__ void k_plic_centres(DevMesh M, int pass) {
-  if (pass > 0 && M.lsfir_turned[pass] == 0) return;  // no plane moved
-  const int ncell = M.counters[CNT_CELLS];
-  const int nc = M.nc;
-  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
-    const int c = M.list_cells[it];
-    const d3 x = plic_centre(M, c, mk3(M.pnx[c], M.pny[c], M.pnz[c]), M.pC[c]);
-    M.lsfir_xc[c] = x.x;
-    M.lsfir_xc[nc + c] = x.y;
-    M.lsfir_xc[2 * nc + c] = x.z;
-  }
-}
-
-// One Jacobi rotation of the symmetric 3x3 matrix A (and of the eigenvector
-// matrix V) in the (P, Q) plane, zeroing A[P][Q] up to rounding.  Compile-time
-// indices keep both matrices in registers.
-template <int P, int Q>
-__device__ inline void jacobi_rotate(double (&A)[3][3], double (&V)[3][3]) {
-  const double apq = A[P][Q];
-  if (apq == 0.0) return;
-  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * apq);
-  double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));  // the smaller root of t^2 + 2 theta t = 1
-  t = theta < 0.0 ? -t : t;
-  const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double u = A[k][P], w = A[k][Q];
-    A[k][P] = cs * u - sn * w;
-    A[k][Q] = sn * u + cs * w;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double u = A[P][k], w = A[Q][k];
-    A[P][k] = cs * u - sn * w;
-    A[Q][k] = sn * u + cs * w;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double u = V[k][P], w = V[k][Q];
-    V[k][P] = cs * u - sn * w;
-    V[k][Q] = sn * u + cs * w;
-  }
-}
-
-// One outer pass of LSFIR, a lane per interfacial cell: the plane through
-// the cell's PLIC centre x minimising sum w_k (n.(x_k - x))^2 over the valid
-// neighbours (interfacial cells sharing a vertex whose normals are within
-// 45 degrees), w_k = |x_k - x|^-2.5, accumulated in neighbour order (the
-// weight is singular where two centres coincide and a very close centre's
-// direction is set by rounding, so |d| is taken as at least 0.05 of the
-// cell's largest box extent; with 1/(d^2 sqrt(sqrt(d^2))), every operation
-// correctly rounded); its
-// normal is the eigenvector of the smallest eigenvalue (cyclic Jacobi), turned
-// to agree with the current normal.  The fit is adopted when it turns the
-// normal by less than 30/I degrees (cos_turn); with fewer than two valid
-// neighbours or a smallest eigenvalue not separated from the next, the
-// normal stays.  Results go to lsfir_nn, so every cell reads the current
-// normals; the placement pass then moves them over.  After a pass in which
-// no normal turned by the tolerance, the later passes do nothing.
-__global__ void k_lsfir_fit(DevMesh M, int pass, double cos_valid, double cos_turn, double cos_stop) {
-  if (pass > 1 && M.lsfir_turned[pass - 1] == 0) return;
-  const int ncell = M.counters[CNT_CELLS];
-  const int nc = M.nc;
-  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
-    const int c = M.list_cells[it];
-    const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
-    const d3 x = mk3(M.lsfir_xc[c], M.lsfir_xc[nc + c], M.lsfir_xc[2 * nc + c]);
-    const double hc = fmax(fmax(M.hix[c] - M.lox[c], M.hiy[c] - M.loy[c]), M.hiz[c] - M.loz[c]);
-    const double dmin2 = (0.05 * hc) * (0.05 * hc);
-    double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    int nvalid = 0;
-    for (int i = M.nb_ptr[c]; i < M.nb_ptr[c + 1]; ++i) {
-      const int k = M.nb_idx[i];
-      if (M.tag_cell[k] != 0) continue;
-      const d3 nk = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
-      if (!(dot_x(n, nk) > cos_valid)) continue;
-      const d3 d = mk3(M.lsfir_xc[k], M.lsfir_xc[nc + k], M.lsfir_xc[2 * nc + k]) - x;
-      const double dd = dot_x(d, d);
-      if (dd == 0.0) continue;
-      const double dw = fmax(dd, dmin2);
-      const double w = 1.0 / (dw * sqrt(sqrt(dw)));  // |d|^-2.5
-      const double dv[3] = {d.x, d.y, d.z};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + w * dv[a] * dv[b];
-      ++nvalid;
-    }
-    d3 e = n;
-    if (nvalid >= 2) {
-      double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
-      for (int sweep = 0; sweep < 64; ++sweep) {
-        if (fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]) == 0.0) break;
-        jacobi_rotate<0, 1>(A, V);
-        jacobi_rotate<0, 2>(A, V);
-        jacobi_rotate<1, 2>(A, V);
-      }
-      // the smallest eigenvalue's column, and the gap to the next
-      const double l0 = A[0][0], l1 = A[1][1], l2 = A[2][2];
-      const int imin = (l0 <= l1 && l0 <= l2) ? 0 : (l1 <= l2 ? 1 : 2);
-      const double lo = imin == 0 ? l0 : (imin == 1 ? l1 : l2);
-      const double mid = imin == 0 ? fmin(l1, l2) : (imin == 1 ? fmin(l0, l2) : fmin(l0, l1));
-      const double hi = fmax(fmax(l0, l1), l2);
-      if (mid - lo > 1e-12 * hi) {
-        d3 v = imin == 0 ? mk3(V[0][0], V[1][0], V[2][0]) : (imin == 1 ? mk3(V[0][1], V[1][1], V[2][1])
-                                                                         : mk3(V[0][2], V[1][2], V[2][2]));
-        const double vn = sqrt(dot_x(v, v));
-        v = mk3(v.x / vn, v.y / vn, v.z / vn);
-        e = dot_x(v, n) < 0.0 ? mk3(-v.x, -v.y, -v.z) : v;
-      }
-    }
-    const d3 nn = dot_x(e, n) > cos_turn ? e : n;
-    M.lsfir_nn[c] = nn.x;
-    M.lsfir_nn[nc + c] = nn.y;
-    M.lsfir_nn[2 * nc + c] = nn.z;
-    if (dot_x(nn, n) < cos_stop) atomicAdd(&M.lsfir_turned[pass], 1);
-  }
-}
-
 // ============================================================== LSGIR + plane constant
 // A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
 // the GPU nearly idle: a few thousand cells, each a long dependent chain).
@@ -2106,6 +1942,220 @@ __global__ __launch_bounds__(128) void k_recon(DevMesh M, const double* __restri
       M.pnz[c] = n.z;
       M.pC[c] = flip ? s0 : -s0;  // fluid {n.x >= -s0}, or the complement of {-n.x >= s0}
     }
+  }
+}
+
+// ============================================================== LSFIR
+// (Sec. "Least squares fit interface reconstruction")
+
+// PLIC centres of the interfacial cells' current planes, a group of
+// kReconLanes lanes per cell: the vertex mean of the polygon {n.x + C = 0}
+// within the cell, i.e. of the cell's vertices on the plane (a lane per
+// vertex) and of the strict crossings of its edges (a lane per face, over
+// the face's edges).  Each edge is taken once, from the face in which the
+// cell's outward orientation runs it from the lower vertex index to the
+// higher (on a closed, consistently oriented cell exactly one of its two
+// faces does).  Signed distances in the exact-order form, crossing points
+// without contraction, group sums in a fixed order.  No point: the cell
+// centre.  Runs before the first LSFIR pass and after each placement pass
+// in which some normal turned.
+__global__ __launch_bounds__(128) void k_plic_centres(DevMesh M, int pass) {
+  if (pass > 0 && M.lsfir_turned[pass] == 0) return;  // no plane moved
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  const int sub = threadIdx.x & (kReconLanes - 1);
+  const int ngroups = (gridDim.x * blockDim.x) / kReconLanes;
+  for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kReconLanes; it < ncell; it += ngroups) {
+    const int c = M.list_cells[it];
+    const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+    const double C = M.pC[c];
+    d3 sv = mk3(0.0, 0.0, 0.0), se = sv;
+    double cv = 0.0, ce = 0.0;
+    for (int i = M.cv_ptr[c] + sub; i < M.cv_ptr[c + 1]; i += kReconLanes) {
+      const d3 x = vert(M, M.cv_idx[i]);
+      if (dot_x(n, x) + C == 0.0) {
+        sv = sv + x;
+        cv += 1.0;
+      }
+    }
+    const int fb = cf_begin(M, c), fn = cf_count(M, c);
+    for (int q = sub; q < fn; q += kReconLanes) {
+      const int e = M.cf_idx[fb + q];
+      const int f = e >= 0 ? e : ~e;
+      const int b = fv_begin(M, f), k = fv_count(M, f);
+      for (int i = 0; i < k; ++i) {
+        const int p = M.fv_idx[b + i], r = M.fv_idx[b + (i + 1 == k ? 0 : i + 1)];
+        const int from = e >= 0 ? p : r, to = e >= 0 ? r : p;  // outward direction
+        if (from > to) continue;
+        const d3 xa = vert(M, from), xb = vert(M, to);
+        const double sa = dot_x(n, xa) + C, sb = dot_x(n, xb) + C;
+        if ((sa > 0.0 && sb < 0.0) || (sa < 0.0 && sb > 0.0)) {
+          const double t = sa / (sa - sb);
+          se = se + (xa + t * (xb - xa));
+          ce += 1.0;
+        }
+      }
+    }
+    const double cnt = group_sum(cv) + group_sum(ce);
+    const d3 sum = mk3(group_sum(sv.x) + group_sum(se.x), group_sum(sv.y) + group_sum(se.y),
+                       group_sum(sv.z) + group_sum(se.z));
+    if (sub == 0) {
+      const d3 x = cnt > 0.0 ? mk3(sum.x / cnt, sum.y / cnt, sum.z / cnt) : cell_centre(M, c);
+      M.lsfir_xc[c] = x.x;
+      M.lsfir_xc[nc + c] = x.y;
+      M.lsfir_xc[2 * nc + c] = x.z;
+    }
+  }
+}
+
+// One Jacobi rotation of the symmetric 3x3 matrix A (and of the eigenvector
+// matrix V) in the (P, Q) plane, zeroing A[P][Q] up to rounding.  An entry
+// below 1e-18 of its diagonal pair is set to zero instead (it moves the
+// eigenvectors by less than that), so the sweeps end once converged rather
+// than chasing rounding.  Compile-time indices keep both matrices in
+// registers.
+template <int P, int Q>
+__device__ inline void jacobi_rotate(double (&A)[3][3], double (&V)[3][3]) {
+  const double apq = A[P][Q];
+  if (fabs(apq) <= 1e-18 * (fabs(A[P][P]) + fabs(A[Q][Q]))) {
+    A[P][Q] = 0.0;
+    A[Q][P] = 0.0;
+    return;
+  }
+  const double theta = (A[Q][Q] - A[P][P]) / (2.0 * apq);
+  double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));  // the smaller root of t^2 + 2 theta t = 1
+  t = theta < 0.0 ? -t : t;
+  const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = A[k][P], w = A[k][Q];
+    A[k][P] = cs * u - sn * w;
+    A[k][Q] = sn * u + cs * w;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = A[P][k], w = A[Q][k];
+    A[P][k] = cs * u - sn * w;
+    A[Q][k] = sn * u + cs * w;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = V[k][P], w = V[k][Q];
+    V[k][P] = cs * u - sn * w;
+    V[k][Q] = sn * u + cs * w;
+  }
+}
+
+// The scatter matrix of one outer pass of LSFIR, a group of kReconLanes
+// lanes per interfacial cell; k_lsfir_eig then finds the plane through the cell's PLIC centre x minimising
+// sum w_k (n.(x_k - x))^2 over the valid neighbours (interfacial cells
+// sharing a vertex whose normals are within 45 degrees), w_k = |x_k - x|^-2.5
+// (singular where two centres coincide, and a very close centre's direction
+// is set by rounding, so |d| is taken as at least 0.05 of the cell's largest
+// box extent; evaluated as 1/(d^2 sqrt(sqrt(d^2))), every operation
+// correctly rounded).  The lanes load a neighbour each; every lane then
+// accumulates the terms in neighbour order through shuffles, the order of a
+// serial loop.  In k_lsfir_eig, the normal is the eigenvector of the smallest eigenvalue
+// (cyclic Jacobi), turned to agree with the current normal, and is adopted
+// when it turns the normal by less than 30/I degrees (cos_turn); with fewer
+// than two valid neighbours or a smallest eigenvalue not separated from the
+// next, the normal stays.  Results go to lsfir_nn, so every cell reads the
+// current normals; the placement pass then moves them over.  After a pass in
+// which no normal turned by the tolerance, the later passes do nothing.
+__global__ __launch_bounds__(128) void k_lsfir_fit(DevMesh M, int pass, double cos_valid) {
+  if (pass > 1 && M.lsfir_turned[pass - 1] == 0) return;
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  const int sub = threadIdx.x & (kReconLanes - 1);
+  const int gbase = __lane_id() & ~(kReconLanes - 1);
+  const int ngroups = (gridDim.x * blockDim.x) / kReconLanes;
+  for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kReconLanes; it < ncell; it += ngroups) {
+    const int c = M.list_cells[it];
+    const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+    const d3 x = mk3(M.lsfir_xc[c], M.lsfir_xc[nc + c], M.lsfir_xc[2 * nc + c]);
+    const double hc = fmax(fmax(M.hix[c] - M.lox[c], M.hiy[c] - M.loy[c]), M.hiz[c] - M.loz[c]);
+    const double dmin2 = (0.05 * hc) * (0.05 * hc);
+    const int nb0 = M.nb_ptr[c], nnb = M.nb_ptr[c + 1] - nb0;
+    double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    int nvalid = 0;
+    for (int r = 0; r < nnb; r += kReconLanes) {
+      d3 d = mk3(0.0, 0.0, 0.0);
+      double w = 0.0;
+      int ok = 0;
+      if (r + sub < nnb) {
+        const int k = M.nb_idx[nb0 + r + sub];
+        if (M.tag_cell[k] == 0 && dot_x(n, mk3(M.pnx[k], M.pny[k], M.pnz[k])) > cos_valid) {
+          d = mk3(M.lsfir_xc[k], M.lsfir_xc[nc + k], M.lsfir_xc[2 * nc + k]) - x;
+          const double dd = dot_x(d, d);
+          if (dd != 0.0) {
+            const double dw = fmax(dd, dmin2);
+            w = 1.0 / (dw * sqrt(sqrt(dw)));  // |d|^-2.5
+            ok = 1;
+          }
+        }
+      }
+      const int nq = min(kReconLanes, nnb - r);
+      for (int j = 0; j < nq; ++j) {
+        if (!__shfl(ok, gbase + j)) continue;  // uniform over the group
+        const double dv[3] = {__shfl(d.x, gbase + j), __shfl(d.y, gbase + j), __shfl(d.z, gbase + j)};
+        const double wj = __shfl(w, gbase + j);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) A[a][b] = A[a][b] + wj * dv[a] * dv[b];
+        ++nvalid;
+      }
+    }
+    if (sub == 0) {  // the matrix and the valid count, for the eigen-solve (a lane per cell)
+      double* S6 = M.lsfir_A + 7 * (size_t)it;
+      S6[0] = A[0][0]; S6[1] = A[0][1]; S6[2] = A[0][2];
+      S6[3] = A[1][1]; S6[4] = A[1][2]; S6[5] = A[2][2];
+      S6[6] = (double)nvalid;
+    }
+  }
+}
+
+// The eigen-solve of one LSFIR pass, a lane per interfacial cell (the
+// matrices come from k_lsfir_fit): 64 cells' Jacobi iterations run side by
+// side in a wavefront.
+__global__ void k_lsfir_eig(DevMesh M, int pass, double cos_turn, double cos_stop) {
+  if (pass > 1 && M.lsfir_turned[pass - 1] == 0) return;
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  for (int it = grid_stride_start(); it < ncell; it += grid_stride()) {
+    const int c = M.list_cells[it];
+    const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+    const double* S6 = M.lsfir_A + 7 * (size_t)it;
+    double A[3][3] = {{S6[0], S6[1], S6[2]}, {S6[1], S6[3], S6[4]}, {S6[2], S6[4], S6[5]}};
+    const int nvalid = (int)S6[6];
+    d3 e = n;
+    if (nvalid >= 2) {
+      double V[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+      for (int sweep = 0; sweep < 64; ++sweep) {
+        if (fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]) == 0.0) break;
+        jacobi_rotate<0, 1>(A, V);
+        jacobi_rotate<0, 2>(A, V);
+        jacobi_rotate<1, 2>(A, V);
+      }
+      // the smallest eigenvalue's column, and the gap to the next
+      const double l0 = A[0][0], l1 = A[1][1], l2 = A[2][2];
+      const int imin = (l0 <= l1 && l0 <= l2) ? 0 : (l1 <= l2 ? 1 : 2);
+      const double lo = imin == 0 ? l0 : (imin == 1 ? l1 : l2);
+      const double mid = imin == 0 ? fmin(l1, l2) : (imin == 1 ? fmin(l0, l2) : fmin(l0, l1));
+      const double hi = fmax(fmax(l0, l1), l2);
+      if (mid - lo > 1e-12 * hi) {
+        d3 v = imin == 0 ? mk3(V[0][0], V[1][0], V[2][0]) : (imin == 1 ? mk3(V[0][1], V[1][1], V[2][1])
+                                                                         : mk3(V[0][2], V[1][2], V[2][2]));
+        const double vn = sqrt(dot_x(v, v));
+        v = mk3(v.x / vn, v.y / vn, v.z / vn);
+        e = dot_x(v, n) < 0.0 ? mk3(-v.x, -v.y, -v.z) : v;
+      }
+    }
+    const d3 nn = dot_x(e, n) > cos_turn ? e : n;
+    M.lsfir_nn[c] = nn.x;
+    M.lsfir_nn[nc + c] = nn.y;
+    M.lsfir_nn[2 * nc + c] = nn.z;
+    if (dot_x(nn, n) < cos_stop) atomicAdd(&M.lsfir_turned[pass], 1);
   }
 }
 
@@ -2319,14 +2369,15 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
   if (M.any_box) TIMED(K_RECON, (k_recon<true, false><<<rb, L.recon_threads, 0, s>>>(M, F, 1, 0)));
   if (!M.all_box) TIMED(K_RECON, (k_recon<false, false><<<rb, L.recon_threads, 0, s>>>(M, F, M.any_box ? 0 : 1, 0)));
   if (M.lsfir_outer > 0 && lsfir) {
-    const int fb = blocks_for(M.nc, st, 1024);
-    TIMED(K_LSFIR_FIT, (k_plic_centres<<<fb, st, 0, s>>>(M, 0)));
+    const int lb = blocks_for((long)M.nc * kReconLanes, 128, 4096);  // a group of kReconLanes lanes per cell
+    TIMED(K_PLIC, (k_plic_centres<<<lb, 128, 0, s>>>(M, 0)));
+    const int eb = blocks_for(M.nc, 64, 1024);
     for (int pass = 1; pass <= M.lsfir_outer; ++pass) {
-      TIMED(K_LSFIR_FIT, (k_lsfir_fit<<<fb, st, 0, s>>>(M, pass, lsfir->cos_valid, lsfir->cos_turn[pass],
-                                                          lsfir->cos_stop)));
+      TIMED(K_LSFIR_FIT, (k_lsfir_fit<<<lb, 128, 0, s>>>(M, pass, lsfir->cos_valid)));
+      TIMED(K_LSFIR_FIT, (k_lsfir_eig<<<eb, 64, 0, s>>>(M, pass, lsfir->cos_turn[pass], lsfir->cos_stop)));
       if (M.any_box) TIMED(K_RECON, (k_recon<true, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, pass)));
       if (!M.all_box) TIMED(K_RECON, (k_recon<false, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, pass)));
-      if (pass < M.lsfir_outer) TIMED(K_LSFIR_FIT, (k_plic_centres<<<fb, st, 0, s>>>(M, pass)));
+      if (pass < M.lsfir_outer) TIMED(K_PLIC, (k_plic_centres<<<lb, 128, 0, s>>>(M, pass)));
     }
   }
   return hipGetLastError();

@@ -7,7 +7,7 @@
 namespace gvof {
 // (K_FLUX_OVER keeps its index but is no longer a launch of its own: the
 // overflow faces are computed by the k_flux_sum launch)
-enum KernelId { K_NODE_TAG = 0, K_FACE_TAG, K_CELL_TAG, K_RECON, K_FACE_SWEEP, K_FLUX, K_UPDATE, K_FLUX_PREP, K_FLUX_SUM, K_FLUX_OVER, K_FLUX_GEN, K_FLUX_DEEP, K_FLUX_GEN_UNITS, K_FLUX_GEN_SUM, K_FLUX_GEN_UDEEP, K_LSFIR_FIT, K_COUNT };
+enum KernelId { K_NODE_TAG = 0, K_FACE_TAG, K_CELL_TAG, K_RECON, K_FACE_SWEEP, K_FLUX, K_UPDATE, K_FLUX_PREP, K_FLUX_SUM, K_FLUX_OVER, K_FLUX_GEN, K_FLUX_DEEP, K_FLUX_GEN_UNITS, K_FLUX_GEN_SUM, K_FLUX_GEN_UDEEP, K_LSFIR_FIT, K_PLIC, K_COUNT };
 // Optional per-kernel event bracketing: before(k)/after(k) are called around kernel k's launch.
 struct Prof {
   virtual ~Prof() {}

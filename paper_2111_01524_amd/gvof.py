@@ -222,7 +222,7 @@ def gvof_status(h):
     return code
 
 
-GVOF_NUM_KERNELS = 16
+GVOF_NUM_KERNELS = 17
 
 
 def gvof_work_totals(h):
