@@ -221,7 +221,7 @@ struct OMesh {
   std::vector<char> isbox;
   std::vector<std::vector<Tet>> tets;  // surface tets of every non-box cell
   int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA, 2 NMFPA
-  int recon = 0;                       // normals: 0 LSGIR, 1 LSFIR
+  int recon = 0;                       // normals: 0 LSGIR, 1 LSFIR, 2 LLCIR, 3 ELCIR, 4 CLCIR
   int lsfir_outer = 1;                 // LSFIR outer iterations at most
   double lsfir_tol = 0.0;              // LSFIR: stop once no normal turns by this angle (rad) or more
 };
@@ -649,6 +649,183 @@ V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vecto
   e = mk(e.x / en, e.y / en, e.z / en);
   if (dot(e, nrm[c]) < real(0.0)) e = mk(-e.x, -e.y, -e.z);
   return e;
+}
+
+
+// --------------------------------------------------------------------------
+// Isosurface-based reconstruction (Sec. "Isosurface based interface
+// reconstruction": LLCIR, ELCIR, CLCIR).
+// --------------------------------------------------------------------------
+
+// The isosurface F* = 1/2 of cell c as one polygon.  A vertex is inside when
+// F* >= 1/2.  Every cell edge whose ends differ crosses the isosurface at the
+// linear-interpolation point (computed from the edge's lower vertex index,
+// so both faces of the edge get the same point).  On each face, taken in
+// the cell's outward orientation, the crossings go in pairs: a segment from
+// the crossing where the walk enters the inside to the one where it leaves.
+// The segments, chained end to start, form the polygon.  Returns false (no
+// usable isosurface) when min F* < 1/2 < max F* fails, a face has more than
+// two crossings, or the segments form more than one loop.  cyc: the points
+// in loop order from the segment of the cell's first face that has one;
+// cface: the face each polygon edge (cyc[i], cyc[i+1]) lies on.
+bool iso_polygon(const OMesh& M, int c, const std::vector<real>& Fs, std::vector<V3>& cyc, std::vector<int>& cface) {
+  cyc.clear();
+  cface.clear();
+  real fmin = Fs[M.cv[c][0]], fmax = fmin;
+  for (int v : M.cv[c]) {
+    fmin = std::min(fmin, Fs[v]);
+    fmax = std::max(fmax, Fs[v]);
+  }
+  const real half = real(0.5);
+  if (!(fmin < half && half < fmax)) return false;
+  struct Seg {
+    int from_a, from_b, to_a, to_b;  // edges (lower, higher vertex) of the start and end crossings
+    int face;
+    bool used;
+  };
+  std::vector<Seg> seg;
+  for (auto& fs : M.cf[c]) {
+    int f = fs.first, b = M.fptr[f], k = M.fptr[f + 1] - b;
+    std::vector<int> vs(k);
+    for (int i = 0; i < k; ++i) vs[i] = M.fidx[b + i];
+    if (fs.second < 0) std::reverse(vs.begin(), vs.end());  // outward orientation of c
+    int enter_a = -1, enter_b = -1, leave_a = -1, leave_b = -1, ncross = 0;
+    for (int i = 0; i < k; ++i) {
+      int a = vs[i], e = vs[(i + 1) % k];
+      bool ia = Fs[a] >= half, ie = Fs[e] >= half;
+      if (ia == ie) continue;
+      ++ncross;
+      if (ie) {
+        enter_a = std::min(a, e);
+        enter_b = std::max(a, e);
+      } else {
+        leave_a = std::min(a, e);
+        leave_b = std::max(a, e);
+      }
+    }
+    if (ncross == 0) continue;
+    if (ncross != 2) return false;
+    seg.push_back({enter_a, enter_b, leave_a, leave_b, f, false});
+  }
+  if (seg.size() < 3) return false;
+  auto point = [&](int a, int e) {
+    real t = (half - Fs[a]) / (Fs[e] - Fs[a]);
+    return M.X[a] + t * (M.X[e] - M.X[a]);
+  };
+  size_t cur = 0;
+  seg[0].used = true;
+  for (size_t n = 0; n < seg.size(); ++n) {
+    cyc.push_back(point(seg[cur].from_a, seg[cur].from_b));
+    cface.push_back(seg[cur].face);
+    if (n + 1 == seg.size()) break;
+    size_t nxt = seg.size();
+    for (size_t j = 0; j < seg.size(); ++j)
+      if (!seg[j].used && seg[j].from_a == seg[cur].to_a && seg[j].from_b == seg[cur].to_b) {
+        nxt = j;
+        break;
+      }
+    if (nxt == seg.size()) return false;  // the loop closed early: more than one isosurface
+    seg[nxt].used = true;
+    cur = nxt;
+  }
+  // the last segment must end where the first starts
+  return seg[cur].to_a == seg[0].from_a && seg[cur].to_b == seg[0].from_b;
+}
+
+V3 vmean(const std::vector<V3>& p) {
+  V3 g = mk(0.0, 0.0, 0.0);
+  for (auto& q : p) g = g + q;
+  real k = real(double(p.size()));
+  return mk(g.x / k, g.y / k, g.z / k);
+}
+
+// Area-weighted mean of the unit normals of the fan triangles (o, r_j,
+// r_{j+1}) over a closed ring: the sum of the triangles' cross products.
+V3 fan_normal(V3 o, const std::vector<V3>& ring) {
+  V3 s = mk(0.0, 0.0, 0.0);
+  size_t k = ring.size();
+  for (size_t j = 0; j < k; ++j) s = s + cross(ring[j] - o, ring[(j + 1) % k] - o);
+  return s;
+}
+
+// Unit vector of s, zero when s is.  The loop runs with the inside (F* >=
+// 1/2) on its left as seen from the side s points to, which puts s on the
+// outside; the unit normal is turned to the fluid.
+V3 iso_unit(V3 s) {
+  real ss = dot(s, s);
+  if (ss == real(0.0)) return mk(0.0, 0.0, 0.0);
+  real inv = real(-1.0) / sqrt(ss);  // turned from the outside to the fluid
+  return mk(s.x * inv, s.y * inv, s.z * inv);
+}
+
+// Isosurface normals of the interfacial cells.  LLCIR: the local polygon's
+// fan about its vertex mean g_c.  ELCIR: the fan about g_c over the ring
+// through the polygon's points and, after the point starting each polygon
+// edge, the isosurface centre g_k of the cell across the face that edge lies
+// on (when that cell has an isosurface); kept only within 1.2 rad of the
+// LLCIR normal.  CLCIR: after the ELCIR planes are placed, the same ring with
+// g_c and the g_k replaced by the PLIC centres of those cells' planes; kept
+// only within 1.2 rad of the ELCIR normal.  ok[c]: the cell has an
+// isosurface (otherwise its normal stays as given, LSGIR).  level: 2 LLCIR,
+// 3 ELCIR, 4 CLCIR.  On entry nrm/Cc hold the LSGIR planes.
+void iso_reconstruct(const OMesh& M, const double* F, const std::vector<real>& Fs, const int8_t* tc, int level,
+                     std::vector<V3>& nrm, std::vector<real>& Cc, std::vector<char>& ok) {
+  const int nc = M.nc;
+  const real cos12 = real(std::cos(1.2));
+  std::vector<std::vector<V3>> cyc(nc);
+  std::vector<std::vector<int>> cface(nc);
+  std::vector<V3> g(nc, mk(0.0, 0.0, 0.0)), nl(nc, mk(0.0, 0.0, 0.0));
+  ok.assign(nc, 0);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int c = 0; c < nc; ++c) {
+    if (tc[c] != 0 || !iso_polygon(M, c, Fs, cyc[c], cface[c])) continue;
+    g[c] = vmean(cyc[c]);
+    V3 u = iso_unit(fan_normal(g[c], cyc[c]));
+    if (dot(u, u) == real(0.0)) continue;
+    nl[c] = u;
+    ok[c] = 1;
+  }
+  auto ring_normal = [&](int c, const std::vector<V3>& cen) {
+    std::vector<V3> ring;
+    for (size_t i = 0; i < cyc[c].size(); ++i) {
+      int f = cface[c][i];
+      int k = M.owner[f] == c ? M.neigh[f] : M.owner[f];
+      ring.push_back((k >= 0 && ok[k]) ? cen[k] : cyc[c][i]);
+    }
+    return iso_unit(fan_normal(cen[c], ring));
+  };
+  auto place = [&](const std::vector<V3>& nn) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int c = 0; c < nc; ++c) {
+      if (!ok[c]) continue;
+      nrm[c] = nn[c];
+      Cc[c] = plane_constant(M, c, nrm[c], F[c]);
+    }
+  };
+  if (level == 2) {
+    place(nl);
+    return;
+  }
+  std::vector<V3> ne(nc, mk(0.0, 0.0, 0.0));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int c = 0; c < nc; ++c) {
+    if (!ok[c]) continue;
+    V3 u = ring_normal(c, g);
+    ne[c] = (dot(u, u) > real(0.0) && dot(u, nl[c]) > cos12) ? u : nl[c];
+  }
+  place(ne);
+  if (level == 3) return;
+  std::vector<V3> x(nc, mk(0.0, 0.0, 0.0)), nk(nc, mk(0.0, 0.0, 0.0));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int c = 0; c < nc; ++c)
+    if (ok[c]) plic_centre(M, c, nrm[c], Cc[c], x[c]);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int c = 0; c < nc; ++c) {
+    if (!ok[c]) continue;
+    V3 u = ring_normal(c, x);
+    nk[c] = (dot(u, u) > real(0.0) && dot(u, ne[c]) > cos12) ? u : ne[c];
+  }
+  place(nk);
 }
 
 // The outer iteration (Sec. "Swartz interface reconstruction", applied to
@@ -1148,15 +1325,59 @@ void* orc_mesh_new(int nv, const double* vx, const double* vy, const double* vz,
 void orc_mesh_free(void* h) { delete static_cast<OMesh*>(h); }
 
 // Normals of the mesh's reconstruction: 0 LSGIR (default), 1 LSFIR with at
-// most `outer` outer iterations and stopping tolerance tol (rad).  Returns 0,
-// or -1 for a bad value.
+// most `outer` outer iterations and stopping tolerance tol (rad), 2 LLCIR,
+// 3 ELCIR, 4 CLCIR.  Returns 0, or -1 for a bad value.
 int orc_mesh_set_recon(void* h, int method, int outer, double tol) {
-  if ((method != 0 && method != 1) || outer < 1 || !(tol >= 0.0)) return -1;
+  if (method < 0 || method > 4 || outer < 1 || !(tol >= 0.0)) return -1;
   OMesh& M = *static_cast<OMesh*>(h);
   M.recon = method;
   M.lsfir_outer = outer;
   M.lsfir_tol = tol;
   return 0;
+}
+
+// Isosurface of F* = 1/2 in cell c from the given node values (nv): the
+// polygon's points in loop order (3 doubles each, at most cap points) and the
+// face of each polygon edge.  Returns the number of points, or -1 when the
+// cell has no usable isosurface.
+int orc_iso_polygon(void* h, int c, const double* Fs_in, int cap, double* pts, int* faces) {
+  OMesh& M = *static_cast<OMesh*>(h);
+  std::vector<real> Fs(M.nv);
+  for (int v = 0; v < M.nv; ++v) Fs[v] = Fs_in[v];
+  std::vector<V3> cyc;
+  std::vector<int> cf;
+  if (!iso_polygon(M, c, Fs, cyc, cf)) return -1;
+  int n = (int)cyc.size();
+  for (int i = 0; i < n && i < cap; ++i) {
+    pts[3 * i] = to_double(cyc[i].x); pts[3 * i + 1] = to_double(cyc[i].y); pts[3 * i + 2] = to_double(cyc[i].z);
+    faces[i] = cf[i];
+  }
+  return n;
+}
+
+// Isosurface-based planes (level 2 LLCIR, 3 ELCIR, 4 CLCIR) from given node
+// values (nv), cell values F (nc, after the cut-off), tags and LSGIR planes
+// (4 x nc, replaced in place for the cells with an isosurface; ok (nc) = 1
+// for those).
+void orc_iso_planes(void* h, const double* Fs_in, const double* F, const int8_t* tc, int level, double* planes,
+                    int8_t* ok_out) {
+  OMesh& M = *static_cast<OMesh*>(h);
+  int nc = M.nc;
+  std::vector<real> Fs(M.nv);
+  for (int v = 0; v < M.nv; ++v) Fs[v] = Fs_in[v];
+  std::vector<V3> nrm(nc);
+  std::vector<real> Cc(nc);
+  for (int c = 0; c < nc; ++c) {
+    nrm[c] = mk(planes[c], planes[nc + c], planes[2 * nc + c]);
+    Cc[c] = planes[3 * nc + c];
+  }
+  std::vector<char> ok;
+  iso_reconstruct(M, F, Fs, tc, level, nrm, Cc, ok);
+  for (int c = 0; c < nc; ++c) {
+    planes[c] = to_double(nrm[c].x); planes[nc + c] = to_double(nrm[c].y); planes[2 * nc + c] = to_double(nrm[c].z);
+    planes[3 * nc + c] = to_double(Cc[c]);
+    ok_out[c] = ok[c];
+  }
 }
 
 // PLIC centres (3 x nc) of the tag-0 cells for the given planes (4 x nc);
@@ -1294,6 +1515,10 @@ void orc_reconstruct(void* h, double* F, double eps, double beta, double* Fstar,
     Cc[c] = plane_constant(M, c, nrm[c], F[c]);
   }
   if (M.recon == 1) lsfir_iterate(M, F, tc, nrm, Cc);
+  if (M.recon >= 2) {
+    std::vector<char> ok;
+    iso_reconstruct(M, F, Fs, tc, M.recon, nrm, Cc, ok);
+  }
   for (int c = 0; c < nc; ++c) {
     planes[c] = to_double(nrm[c].x); planes[nc + c] = to_double(nrm[c].y); planes[2 * nc + c] = to_double(nrm[c].z);
     planes[3 * nc + c] = to_double(Cc[c]);

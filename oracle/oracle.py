@@ -35,6 +35,9 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_mesh_set_recon.restype = C.c_int
         lib.orc_plic_centres.argtypes = [C.c_void_p, _b, _d, _d, _i]
         lib.orc_lsfir_fit.argtypes = [C.c_void_p, _b, _d, _d, _d, _i]
+        lib.orc_iso_polygon.argtypes = [C.c_void_p, C.c_int, _d, C.c_int, _d, _i]
+        lib.orc_iso_polygon.restype = C.c_int
+        lib.orc_iso_planes.argtypes = [C.c_void_p, _d, _d, _b, C.c_int, _d, _b]
         lib.orc_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d, _d, _d, _b]
         lib.orc_neighbours.argtypes = [C.c_void_p, _i, _i]
         lib.orc_neighbours.restype = C.c_int
@@ -95,12 +98,14 @@ class OracleMesh:
     method selects the flux polyhedra: "fmfpa" (Sec. "Face-matched flux
     polyhedron"), "emfpa" (Sec. "Edge-matched flux polyhedron") or "nmfpa"
     (Sec. "Non-matched flux polyhedron").  recon selects the normals:
-    "lsgir" (Sec. LSGIR) or "lsfir" (Sec. "Least squares fit interface
+    "lsgir" (Sec. LSGIR), "lsfir" (Sec. "Least squares fit interface
     reconstruction", at most lsfir_outer outer iterations, stopping once no
-    normal turns by lsfir_tol radians or more).
+    normal turns by lsfir_tol radians or more), or "llcir" / "elcir" /
+    "clcir" (Sec. "Isosurface based interface reconstruction").
     """
 
     METHODS = {"fmfpa": 0, "emfpa": 1, "nmfpa": 2}
+    RECONS = {"lsgir": 0, "lsfir": 1, "llcir": 2, "elcir": 3, "clcir": 4}
 
     def __init__(self, mesh, counting: bool = False, method: str = "fmfpa", recon: str = "lsgir",
                  lsfir_outer: int = 1, lsfir_tol: float = 0.0):
@@ -118,10 +123,10 @@ class OracleMesh:
                                        _p(fi, _i), _p(ow, _i), _p(ne, _i), self.nc)
         if self.lib.orc_mesh_set_method(self.h, self.METHODS[method]) != 0:
             raise RuntimeError("oracle rejected the flux polyhedron method")
-        if recon not in ("lsgir", "lsfir"):
+        if recon not in self.RECONS:
             raise ValueError(f"unknown reconstruction {recon!r}")
         self.recon = recon
-        if self.lib.orc_mesh_set_recon(self.h, 1 if recon == "lsfir" else 0, int(lsfir_outer), float(lsfir_tol)):
+        if self.lib.orc_mesh_set_recon(self.h, self.RECONS[recon], int(lsfir_outer), float(lsfir_tol)):
             raise ValueError("oracle rejected the reconstruction settings")
 
     def __del__(self):
@@ -162,6 +167,24 @@ class OracleMesh:
         F = _dbl(F); tc = _i8(tcell); n = _dbl(n); Cc = np.zeros(self.nc)
         self.lib.orc_plane_constant(self.h, _p(F, _d), _p(tc, _b), _p(n, _d), _p(Cc, _d))
         return Cc
+
+    def iso_polygon(self, c, node_values):
+        """The isosurface F* = 1/2 of cell c: (points (k, 3) in loop order, faces of the polygon edges),
+        or None when the cell has no usable isosurface."""
+        fs = _dbl(node_values); pts = np.zeros(3 * 64); fc = np.zeros(64, np.int32)
+        n = self.lib.orc_iso_polygon(self.h, int(c), _p(fs, _d), 64, _p(pts, _d), _p(fc, _i))
+        if n < 0:
+            return None
+        return pts[: 3 * n].reshape(-1, 3), fc[:n]
+
+    def iso_planes(self, node_values, F, tcell, planes, level):
+        """Isosurface planes (level "llcir" / "elcir" / "clcir") from given node values, F after the
+        cut-off, tags and LSGIR planes: (planes (4, nc), has-isosurface flags)."""
+        fs = _dbl(node_values); Fc = _dbl(F); tc = _i8(tcell); pl = _dbl(planes).copy()
+        ok = np.zeros(self.nc, np.int8)
+        self.lib.orc_iso_planes(self.h, _p(fs, _d), _p(Fc, _d), _p(tc, _b), self.RECONS[level], _p(pl, _d),
+                                _p(ok, _b))
+        return pl, ok
 
     def plic_centres(self, tcell, planes):
         """Vertex means of the PLIC polygons of the tag-0 cells (3, nc) and their vertex counts."""
