@@ -62,8 +62,8 @@ def parse():
     ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
     ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa", "nmfpa"],
                     help="flux polyhedra: face-matched (the default workload), edge-matched or non-matched")
-    ap.add_argument("--recon", default="lsgir", choices=["lsgir", "lsfir"],
-                    help="interface normals: LSGIR (the default workload) or LSFIR")
+    ap.add_argument("--recon", default="lsgir", choices=["lsgir", "lsfir", "llcir", "elcir", "clcir"],
+                    help="interface normals: LSGIR (the default workload), LSFIR, LLCIR, ELCIR or CLCIR")
     ap.add_argument("--lsfir-outer", type=int, default=1, help="LSFIR outer passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

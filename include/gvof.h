@@ -75,6 +75,18 @@ enum {
  * by lsfir_tol (radians) or more. */
 #define GVOF_FLAG_LSFIR 4u
 #define GVOF_MAX_LSFIR_OUTER 32
+/* Normals from the isosurface F* = 1/2 of the node values (Sec. "Isosurface
+ * based interface reconstruction"; cells without one polygon of it keep
+ * LSGIR).  LLCIR: the area-weighted normal of the cell's isosurface polygon
+ * fanned about its vertex mean.  ELCIR: the fan about that centre over the
+ * isosurface centres of the cells across the polygon's faces, kept within
+ * 1.2 rad of LLCIR.  CLCIR: after the ELCIR planes are placed, the same fan
+ * over the cells' PLIC centres, kept within 1.2 rad of ELCIR.  Every cell may
+ * have at most 32 faces with these flags (GVOF_E_LIMIT).  At most one of the
+ * reconstruction flags (LSFIR, LLCIR, ELCIR, CLCIR). */
+#define GVOF_FLAG_LLCIR 8u
+#define GVOF_FLAG_ELCIR 16u
+#define GVOF_FLAG_CLCIR 32u
 
 typedef struct gvof_params {
   double eps;         /* volume-fraction tolerance (Sec. "Interface reconstruction"); 1e-12 as in all tests */
@@ -223,7 +235,7 @@ int gvof_work_totals(gvof_mesh* m, int64_t* cells, int64_t* faces);
  * synchronises, writes for every kernel k < n the summed milliseconds and the
  * number of timed launches, and clears the record.
  */
-#define GVOF_NUM_KERNELS 17
+#define GVOF_NUM_KERNELS 18
 int gvof_profile_enable(gvof_mesh* m, uint32_t mask);
 int gvof_profile_read(gvof_mesh* m, int32_t n, double* ms, int64_t* launches);
 const char* gvof_kernel_name(int32_t k);

@@ -105,6 +105,7 @@ static void set_lsfir_consts(gvof_mesh* m) {
   const double pi = 3.14159265358979323846;
   m->lsfir.cos_valid = std::sqrt(0.5);
   m->lsfir.cos_stop = std::cos(m->p.lsfir_tol);
+  m->lsfir.cos_iso = std::cos(1.2);
   m->lsfir.cos_turn[0] = 1.0;
   for (int i = 1; i <= gvof::kMaxLsfirOuter; ++i) m->lsfir.cos_turn[i] = std::cos((pi / 6.0) / double(i));
 }
@@ -164,10 +165,14 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
       return fail(nullptr, GVOF_E_MESH, "vertex %d not finite", v);
 
   if (params) {
-    const uint32_t methods = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA, known = methods | GVOF_FLAG_LSFIR;
+    const uint32_t methods = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA;
+    const uint32_t recons = GVOF_FLAG_LSFIR | GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR;
+    const uint32_t known = methods | recons;
     if (params->flags & ~known) return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~known));
     if ((params->flags & methods) == methods)
       return fail(nullptr, GVOF_E_ARG, "GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA together");
+    if (__builtin_popcount(params->flags & recons) > 1)
+      return fail(nullptr, GVOF_E_ARG, "more than one reconstruction flag (0x%x)", (unsigned)(params->flags & recons));
     if ((params->flags & GVOF_FLAG_LSFIR) &&
         (params->lsfir_outer < 1 || params->lsfir_outer > GVOF_MAX_LSFIR_OUTER || !(params->lsfir_tol >= 0.0) ||
          !std::isfinite(params->lsfir_tol)))
@@ -234,6 +239,12 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
       delete m;
       return fail(nullptr, GVOF_E_LIMIT, "cell %d has %zu vertices and %d polygon faces (limits %d / %d levels)", c,
                   tmp.size(), npoly, gvof::kMaxCellVerts, gvof::kMaxLevels);
+    }
+    const int nfc = m->cf_ptr[c + 1] - m->cf_ptr[c];
+    if ((m->p.flags & (GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR)) && nfc > gvof::kMaxIsoFaces) {
+      delete m;
+      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %d faces (the isosurface reconstructions take at most %d)", c,
+                  nfc, gvof::kMaxIsoFaces);
     }
     cv.insert(cv.end(), tmp.begin(), tmp.end());
     m->cv_ptr[c + 1] = (int)cv.size();
@@ -467,7 +478,12 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.unit_vol = C.take<double>(d.unit_cap);
   d.list_udeep = C.take<int>(d.unit_cap);
   d.counters = C.take<int>(gvof::CNT_N);
-  if (m->p.flags & GVOF_FLAG_LSFIR) {
+  if (m->p.flags & (GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR)) {
+    d.iso_g = C.take<double>(3 * (size_t)nc);
+    d.iso_nl = C.take<double>(3 * (size_t)nc);
+    d.iso_ok = C.take<int8_t>(nc);
+  }
+  if (m->p.flags & (GVOF_FLAG_LSFIR | GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR)) {
     d.lsfir_xc = C.take<double>(3 * (size_t)nc);
     d.lsfir_nn = C.take<double>(3 * (size_t)nc);
     d.lsfir_A = C.take<double>(7 * (size_t)nc);
@@ -487,6 +503,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.degen = m->p.fmfpa_degen;
   d.method = (m->p.flags & GVOF_FLAG_EMFPA) ? gvof::kEMFPA : (m->p.flags & GVOF_FLAG_NMFPA) ? gvof::kNMFPA : gvof::kFMFPA;
   d.lsfir_outer = (m->p.flags & GVOF_FLAG_LSFIR) ? m->p.lsfir_outer : 0;
+  d.iso_level = (m->p.flags & GVOF_FLAG_LLCIR) ? 2 : (m->p.flags & GVOF_FLAG_ELCIR) ? 3 : (m->p.flags & GVOF_FLAG_CLCIR) ? 4 : 0;
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
 }
@@ -1059,7 +1076,7 @@ const char* gvof_kernel_name(int32_t k) {
                                              "k_flux_sum", "(unused)", "k_flux_gen_filter",
                                              "k_flux_deep", "k_flux_gen_units", "k_flux_gen_sum",
                                              "k_flux_gen_units_deep", "k_lsfir_fit",
-                                             "k_plic_centres"};
+                                             "k_plic_centres", "k_iso"};
   return (k >= 0 && k < gvof::K_COUNT) ? names[k] : "";
 }
 

@@ -77,6 +77,12 @@ struct DevMesh {
   double* lsfir_nn;   // [3][nc] fitted normals of the current pass
   double* lsfir_A;    // [7][nc] per listed cell: scatter matrix (upper triangle) and valid-neighbour count
   int* lsfir_turned;  // [kMaxLsfirOuter + 1] cells whose normal turned by the tolerance or more, per pass
+  // isosurface-based normals: 0 none, 2 LLCIR, 3 ELCIR, 4 CLCIR (the LSFIR
+  // buffers above are shared: lsfir_xc PLIC centres, lsfir_nn normals to place)
+  int iso_level;
+  double* iso_g;      // [3][nc] isosurface centres
+  double* iso_nl;     // [3][nc] LLCIR normals
+  int8_t* iso_ok;     // [nc] 1: the interfacial cell has a usable isosurface
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);
@@ -120,6 +126,7 @@ constexpr int kMaxFaceVerts = 8;
 // "Non-matched flux polyhedron")
 constexpr int kFMFPA = 0, kEMFPA = 1, kNMFPA = 2;
 constexpr int kMaxLsfirOuter = 32;  // LSFIR outer passes at most
+constexpr int kMaxIsoFaces = 32;    // faces of a cell at most for the isosurface reconstructions (a lane each)
 constexpr int kItemRegions = 256;
 constexpr int kMaxNeighbours = 62;  // vertex-sharing neighbours of one cell
 constexpr int kMaxCellVerts = 30;   // distinct vertices of one cell

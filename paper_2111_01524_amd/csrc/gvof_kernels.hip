@@ -312,6 +312,9 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
       if (t == -1) F[c] = 0.0;
       if (t == 1) F[c] = 1.0;
       inter = t == 0;
+      // no isosurface until k_iso_local finds one (the ELCIR / CLCIR rings read
+      // this flag for every neighbour, interfacial or not)
+      if (M.iso_level > 0) M.iso_ok[c] = 0;
       if (!inter) {
         M.pnx[c] = 0.0;
         M.pny[c] = 0.0;
@@ -2159,6 +2162,201 @@ __global__ void k_lsfir_eig(DevMesh M, int pass, double cos_turn, double cos_sto
   }
 }
 
+// ============================================================== isosurface-based normals
+// (Sec. "Isosurface based interface reconstruction": LLCIR, ELCIR, CLCIR)
+constexpr int kIsoLanes = kReconLanes;  // a lane per face of the cell
+static_assert(kMaxIsoFaces <= kIsoLanes, "a lane per face");
+
+// The isosurface F* = 1/2 of cell c as one polygon, a lane per face of the
+// cell.  A vertex is inside when F* >= 1/2; on its face, taken in the cell's
+// outward orientation, a lane finds the edge where the walk enters the
+// inside and the one where it leaves (0 or 2 crossings; more: no usable
+// isosurface).  The polygon is the chain of these segments, each starting at
+// the crossing where the previous one ends, from the segment of the cell's
+// first face that has one; the chaining broadcasts the current end edge and
+// lets the lanes match it by ballot.  On return pos is the lane's place in
+// the loop (-1: its face has no segment), p its segment's first point, m the
+// loop length; false when min F* < 1/2 < max F* fails, a face has more than
+// two crossings or the segments form more than one loop.
+__device__ inline bool iso_loop(const DevMesh& M, int c, int sub, int gbase, int& face, int& pos, d3& p, int& m) {
+  const int fb = cf_begin(M, c), fn = cf_count(M, c);
+  face = -1;
+  pos = -1;
+  p = mk3(0.0, 0.0, 0.0);
+  m = 0;
+  int ea = -1, eb = -1, la = -1, lb = -1, ncross = 0;
+  double fmn = 2.0, fmx = -1.0;
+  if (sub < fn) {
+    const int e = M.cf_idx[fb + sub];
+    const int f = e >= 0 ? e : ~e;
+    face = f;
+    const int b = fv_begin(M, f), k = fv_count(M, f);
+    for (int i = 0; i < k; ++i) {
+      // outward order: as stored for the owner, reversed for the neighbour
+      const int ja = e >= 0 ? i : k - 1 - i;
+      const int jw = e >= 0 ? (i + 1 == k ? 0 : i + 1) : (i == k - 1 ? k - 1 : k - 2 - i);
+      const int a = M.fv_idx[b + ja], w = M.fv_idx[b + jw];
+      const double fa = M.Fstar[a], fw = M.Fstar[w];
+      fmn = fmin(fmn, fa);
+      fmx = fmax(fmx, fa);
+      const bool ia = fa >= 0.5, iw = fw >= 0.5;
+      if (ia == iw) continue;
+      ++ncross;
+      if (iw) {
+        ea = min(a, w);
+        eb = max(a, w);
+      } else {
+        la = min(a, w);
+        lb = max(a, w);
+      }
+    }
+  }
+  // min F* < 1/2 < max F* over the cell's vertices (every vertex is on a face)
+  double gmn = fmn, gmx = fmx;
+#pragma unroll
+  for (int o = 1; o < kIsoLanes; o <<= 1) {
+    gmn = fmin(gmn, __shfl_xor(gmn, o));
+    gmx = fmax(gmx, __shfl_xor(gmx, o));
+  }
+  const unsigned long long gm = (kIsoLanes == 64 ? ~0ull : ((1ull << kIsoLanes) - 1ull));
+  const unsigned long long bad = (__ballot(ncross > 2 || ncross == 1) >> gbase) & gm;
+  const unsigned long long valid = (__ballot(ncross == 2) >> gbase) & gm;
+  const int nseg = __popcll(valid);
+  if (!(gmn < 0.5 && 0.5 < gmx) || bad || nseg < 3) return false;
+  const int first = __builtin_ctzll(valid);
+  const int fa0 = __shfl(ea, gbase + first), fb0 = __shfl(eb, gbase + first);
+  int cur = first;
+  for (int n = 0; n < nseg; ++n) {
+    if (sub == cur) pos = n;
+    const int ca = __shfl(la, gbase + cur), cb = __shfl(lb, gbase + cur);
+    if (n == nseg - 1) {
+      if (!(ca == fa0 && cb == fb0)) return false;  // the last segment must end where the first starts
+      break;
+    }
+    const unsigned long long mt = (__ballot(ncross == 2 && pos < 0 && ea == ca && eb == cb) >> gbase) & gm;
+    if (mt == 0) return false;  // the loop closed early: more than one isosurface
+    cur = __builtin_ctzll(mt);
+  }
+  if (ncross == 2) {
+    const double t = (0.5 - M.Fstar[ea]) / (M.Fstar[eb] - M.Fstar[ea]);
+    const d3 xa = vert(M, ea), xb = vert(M, eb);
+    p = xa + t * (xb - xa);
+  }
+  m = nseg;
+  return true;
+}
+
+// Sum over the loop (positions 0..m-1) of cross(r_n - o, r_{n+1} - o), in
+// loop order, every lane of the group taking part (r: the lane's ring entry).
+__device__ inline d3 iso_fan(d3 o, d3 r, int pos, int m, int gbase) {
+  d3 s = mk3(0.0, 0.0, 0.0);
+  const unsigned long long gm = (kIsoLanes == 64 ? ~0ull : ((1ull << kIsoLanes) - 1ull));
+  int ln = __builtin_ctzll((__ballot(pos == 0) >> gbase) & gm);
+  const int l0 = ln;
+  for (int n = 0; n < m; ++n) {
+    const int lnext = n + 1 < m ? __builtin_ctzll((__ballot(pos == n + 1) >> gbase) & gm) : l0;
+    const d3 a = mk3(__shfl(r.x, gbase + ln), __shfl(r.y, gbase + ln), __shfl(r.z, gbase + ln)) - o;
+    const d3 b = mk3(__shfl(r.x, gbase + lnext), __shfl(r.y, gbase + lnext), __shfl(r.z, gbase + lnext)) - o;
+    s = s + cross_x(a, b);
+    ln = lnext;
+  }
+  return s;
+}
+
+// Unit vector of s turned from the loop's side to the fluid (zero for zero s).
+__device__ inline d3 iso_unit(d3 s) {
+  const double ss = dot_x(s, s);
+  if (ss == 0.0) return mk3(0.0, 0.0, 0.0);
+  const double inv = -1.0 / sqrt(ss);
+  return mk3(s.x * inv, s.y * inv, s.z * inv);
+}
+
+// LLCIR, a group per interfacial cell: the isosurface loop, its vertex mean
+// g (summed in loop order) and the fan normal about g, turned to the fluid.
+// Records whether the cell has a usable isosurface, g and the normal; for
+// LLCIR also the normal to place (the cell's current one where there is no
+// isosurface).
+__global__ __launch_bounds__(128) void k_iso_local(DevMesh M) {
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  const int sub = threadIdx.x & (kIsoLanes - 1);
+  const int gbase = __lane_id() & ~(kIsoLanes - 1);
+  const int ngroups = (gridDim.x * blockDim.x) / kIsoLanes;
+  const unsigned long long gm = (kIsoLanes == 64 ? ~0ull : ((1ull << kIsoLanes) - 1ull));
+  for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kIsoLanes; it < ncell; it += ngroups) {
+    const int c = M.list_cells[it];
+    int face, pos, m;
+    d3 p;
+    bool ok = iso_loop(M, c, sub, gbase, face, pos, p, m);
+    d3 g = mk3(0.0, 0.0, 0.0), u = g;
+    if (ok) {
+      for (int n = 0; n < m; ++n) {  // vertex mean in loop order
+        const int ln = __builtin_ctzll((__ballot(pos == n) >> gbase) & gm);
+        g = g + mk3(__shfl(p.x, gbase + ln), __shfl(p.y, gbase + ln), __shfl(p.z, gbase + ln));
+      }
+      const double k = (double)m;
+      g = mk3(g.x / k, g.y / k, g.z / k);
+      u = iso_unit(iso_fan(g, p, pos, m, gbase));
+      ok = dot_x(u, u) != 0.0;
+    }
+    if (sub == 0) {
+      M.iso_ok[c] = ok ? 1 : 0;
+      M.iso_g[c] = g.x;
+      M.iso_g[nc + c] = g.y;
+      M.iso_g[2 * nc + c] = g.z;
+      M.iso_nl[c] = u.x;
+      M.iso_nl[nc + c] = u.y;
+      M.iso_nl[2 * nc + c] = u.z;
+      if (M.iso_level == 2) {
+        const d3 nn = ok ? u : mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+        M.lsfir_nn[c] = nn.x;
+        M.lsfir_nn[nc + c] = nn.y;
+        M.lsfir_nn[2 * nc + c] = nn.z;
+      }
+    }
+  }
+}
+
+// ELCIR (clcir = 0) or CLCIR (clcir = 1), a group per interfacial cell with
+// an isosurface: the fan about the cell's centre over a ring with one entry
+// per polygon edge, the centre of the cell across the face that edge lies on
+// (isosurface centres for ELCIR, PLIC centres of the placed ELCIR planes for
+// CLCIR), or the edge's first point where that cell has no isosurface.  Kept
+// when within 1.2 rad (cos_keep) of the reference normal (LLCIR for ELCIR,
+// the placed ELCIR normal for CLCIR); written as the normal to place.
+__global__ __launch_bounds__(128) void k_iso_ext(DevMesh M, int clcir, double cos_keep) {
+  const int ncell = M.counters[CNT_CELLS];
+  const int nc = M.nc;
+  const int sub = threadIdx.x & (kIsoLanes - 1);
+  const int gbase = __lane_id() & ~(kIsoLanes - 1);
+  const int ngroups = (gridDim.x * blockDim.x) / kIsoLanes;
+  const double* cen = clcir ? M.lsfir_xc : M.iso_g;
+  for (int it = (blockIdx.x * blockDim.x + threadIdx.x) / kIsoLanes; it < ncell; it += ngroups) {
+    const int c = M.list_cells[it];
+    const d3 cur = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
+    d3 nn = cur;
+    int face, pos, m;
+    d3 p;
+    // the same loop k_iso_local found usable (both uniform over the group)
+    if (M.iso_ok[c] && iso_loop(M, c, sub, gbase, face, pos, p, m)) {
+      d3 r = p;
+      if (pos >= 0) {
+        const int k = M.owner[face] == c ? M.neigh[face] : M.owner[face];
+        if (k >= 0 && M.iso_ok[k]) r = mk3(cen[k], cen[nc + k], cen[2 * nc + k]);
+      }
+      const d3 o = mk3(cen[c], cen[nc + c], cen[2 * nc + c]);
+      const d3 u = iso_unit(iso_fan(o, r, pos, m, gbase));
+      const d3 ref = clcir ? cur : mk3(M.iso_nl[c], M.iso_nl[nc + c], M.iso_nl[2 * nc + c]);
+      nn = (dot_x(u, u) > 0.0 && dot_x(u, ref) > cos_keep) ? u : ref;
+    }
+    if (sub == 0) {
+      M.lsfir_nn[c] = nn.x;
+      M.lsfir_nn[nc + c] = nn.y;
+      M.lsfir_nn[2 * nc + c] = nn.z;
+    }
+  }
+}
+
 // ============================================================== update
 // Eq. (fnext) with face sums in ascending face order, then the clamp.
 constexpr int kUpdateFaces = 6;
@@ -2368,6 +2566,19 @@ hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, h
   // the first instance launched adds the interfacial cells to the running total
   if (M.any_box) TIMED(K_RECON, (k_recon<true, false><<<rb, L.recon_threads, 0, s>>>(M, F, 1, 0)));
   if (!M.all_box) TIMED(K_RECON, (k_recon<false, false><<<rb, L.recon_threads, 0, s>>>(M, F, M.any_box ? 0 : 1, 0)));
+  if (M.iso_level > 0 && lsfir) {
+    const int ib = blocks_for((long)M.nc * kIsoLanes, 128, 4096);  // a group of kIsoLanes lanes per cell
+    TIMED(K_ISO, (k_iso_local<<<ib, 128, 0, s>>>(M)));
+    if (M.iso_level >= 3) TIMED(K_ISO, (k_iso_ext<<<ib, 128, 0, s>>>(M, 0, lsfir->cos_iso)));
+    if (M.any_box) TIMED(K_RECON, (k_recon<true, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, 1)));
+    if (!M.all_box) TIMED(K_RECON, (k_recon<false, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, 1)));
+    if (M.iso_level == 4) {
+      TIMED(K_PLIC, (k_plic_centres<<<ib, 128, 0, s>>>(M, 0)));
+      TIMED(K_ISO, (k_iso_ext<<<ib, 128, 0, s>>>(M, 1, lsfir->cos_iso)));
+      if (M.any_box) TIMED(K_RECON, (k_recon<true, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, 1)));
+      if (!M.all_box) TIMED(K_RECON, (k_recon<false, true><<<rb, L.recon_threads, 0, s>>>(M, F, 0, 1)));
+    }
+  }
   if (M.lsfir_outer > 0 && lsfir) {
     const int lb = blocks_for((long)M.nc * kReconLanes, 128, 4096);  // a group of kReconLanes lanes per cell
     TIMED(K_PLIC, (k_plic_centres<<<lb, 128, 0, s>>>(M, 0)));

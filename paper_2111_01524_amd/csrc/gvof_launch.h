@@ -7,7 +7,7 @@
 namespace gvof {
 // (K_FLUX_OVER keeps its index but is no longer a launch of its own: the
 // overflow faces are computed by the k_flux_sum launch)
-enum KernelId { K_NODE_TAG = 0, K_FACE_TAG, K_CELL_TAG, K_RECON, K_FACE_SWEEP, K_FLUX, K_UPDATE, K_FLUX_PREP, K_FLUX_SUM, K_FLUX_OVER, K_FLUX_GEN, K_FLUX_DEEP, K_FLUX_GEN_UNITS, K_FLUX_GEN_SUM, K_FLUX_GEN_UDEEP, K_LSFIR_FIT, K_PLIC, K_COUNT };
+enum KernelId { K_NODE_TAG = 0, K_FACE_TAG, K_CELL_TAG, K_RECON, K_FACE_SWEEP, K_FLUX, K_UPDATE, K_FLUX_PREP, K_FLUX_SUM, K_FLUX_OVER, K_FLUX_GEN, K_FLUX_DEEP, K_FLUX_GEN_UNITS, K_FLUX_GEN_SUM, K_FLUX_GEN_UDEEP, K_LSFIR_FIT, K_PLIC, K_ISO, K_COUNT };
 // Optional per-kernel event bracketing: before(k)/after(k) are called around kernel k's launch.
 struct Prof {
   virtual ~Prof() {}
@@ -33,11 +33,13 @@ struct LaunchCfg {
 };
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);
-// LSFIR thresholds (host-computed, so every side takes the same bits): the
-// cosines of 45 degrees (valid neighbours), of the stopping tolerance and of
-// 30/I degrees for each outer pass I = 1..kMaxLsfirOuter.
+// LSFIR and isosurface thresholds (host-computed, so every side takes the
+// same bits): the cosines of 45 degrees (valid neighbours), of the stopping
+// tolerance, of 1.2 rad and of 30/I degrees for each outer pass
+// I = 1..kMaxLsfirOuter.
 struct LsfirConsts {
   double cos_valid, cos_stop;
+  double cos_iso;  // cos 1.2 rad: ELCIR / CLCIR keep their normal within this of the reference
   double cos_turn[kMaxLsfirOuter + 1];
 };
 hipError_t launch_reconstruct(const DevMesh& M, double* F, const LaunchCfg& L, hipStream_t s, Prof* prof = nullptr,

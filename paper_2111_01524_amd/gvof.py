@@ -19,6 +19,9 @@ LIB_PATH = os.environ.get("GVOF_LIB_PATH") or os.path.join(HERE, "libgvof.so")
 GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_LIMIT = 0, -1, -2, -3, -4, -5, -6
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
 GVOF_FLAG_NONE, GVOF_FLAG_EMFPA, GVOF_FLAG_NMFPA, GVOF_FLAG_LSFIR = 0, 1, 2, 4
+GVOF_FLAG_LLCIR, GVOF_FLAG_ELCIR, GVOF_FLAG_CLCIR = 8, 16, 32
+RECON_FLAGS = {"lsgir": 0, "lsfir": GVOF_FLAG_LSFIR, "llcir": GVOF_FLAG_LLCIR, "elcir": GVOF_FLAG_ELCIR,
+               "clcir": GVOF_FLAG_CLCIR}
 GVOF_MAX_LSFIR_OUTER = 32
 METHOD_FLAGS = {"fmfpa": GVOF_FLAG_NONE, "emfpa": GVOF_FLAG_EMFPA, "nmfpa": GVOF_FLAG_NMFPA}
 
@@ -222,7 +225,7 @@ def gvof_status(h):
     return code
 
 
-GVOF_NUM_KERNELS = 17
+GVOF_NUM_KERNELS = 18
 
 
 def gvof_work_totals(h):
@@ -313,16 +316,14 @@ def _with_method(params, method: str, recon: str = "lsgir", lsfir_outer: int | N
     given, sets the LSFIR outer passes."""
     if method not in METHOD_FLAGS:
         raise ValueError(f"unknown flux polyhedron method {method!r}")
-    if recon not in ("lsgir", "lsfir"):
+    if recon not in RECON_FLAGS:
         raise ValueError(f"unknown reconstruction {recon!r}")
     if method == "fmfpa" and recon == "lsgir":
         return params
     params = params if params is not None else gvof_params_default()
-    params.flags |= METHOD_FLAGS[method]
-    if recon == "lsfir":
-        params.flags |= GVOF_FLAG_LSFIR
-        if lsfir_outer is not None:
-            params.lsfir_outer = int(lsfir_outer)
+    params.flags |= METHOD_FLAGS[method] | RECON_FLAGS[recon]
+    if recon == "lsfir" and lsfir_outer is not None:
+        params.lsfir_outer = int(lsfir_outer)
     return params
 
 
@@ -330,9 +331,9 @@ class GvofMesh:
     """A mesh handle bound to a torch-allocated device workspace.
 
     method "emfpa" / "nmfpa" sets GVOF_FLAG_EMFPA / GVOF_FLAG_NMFPA in the
-    parameters (the flux polyhedron method), recon "lsfir" sets
-    GVOF_FLAG_LSFIR (with lsfir_outer passes when given); "fmfpa" and "lsgir"
-    leave the flags as given.
+    parameters (the flux polyhedron method), recon "lsfir" / "llcir" /
+    "elcir" / "clcir" sets that reconstruction's flag (LSFIR with lsfir_outer
+    passes when given); "fmfpa" and "lsgir" leave the flags as given.
     """
 
     def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None,

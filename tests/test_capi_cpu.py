@@ -194,8 +194,9 @@ def test_unit_buffer_only_for_meshes_with_general_cells():
 def test_flags_select_the_flux_polyhedron_method():
     """GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA select the method: EMFPA slots hold the
     lateral centres and the pair buffer is sized for 5I flux tets per face
-    (larger workspace), NMFPA sizes as FMFPA; both together, or any other bit,
-    is an argument error; a batch of mixed methods is rejected."""
+    (larger workspace), NMFPA sizes as FMFPA; both together, two
+    reconstruction flags, or any other bit, is an argument error; a batch of
+    mixed methods is rejected."""
     m = inputs.cartesian_mesh(4)
     pe = gvof.gvof_params_default()
     pe.flags = gvof.GVOF_FLAG_EMFPA
@@ -214,7 +215,7 @@ def test_flags_select_the_flux_polyhedron_method():
         gvof.gvof_mesh_destroy(a)
         gvof.gvof_mesh_destroy(b)
         gvof.gvof_mesh_destroy(c)
-    for bad in (8, 0x80000000, 3):
+    for bad in (64, 0x80000000, 3, 4 | 8, 8 | 32, 16 | 32):
         p = gvof.gvof_params_default()
         p.flags = bad
         with pytest.raises(gvof.GvofError) as e:
@@ -251,6 +252,26 @@ def test_lsfir_settings():
             with pytest.raises(gvof.GvofError) as e:
                 gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
             assert e.value.code == gvof.GVOF_E_ARG
+    finally:
+        for h in handles:
+            gvof.gvof_mesh_destroy(h)
+
+
+def test_isosurface_reconstruction_flags():
+    """LLCIR, ELCIR and CLCIR each add the isosurface and PLIC-centre buffers,
+    combine with any flux polyhedron method, and take any mesh whose cells
+    have at most 32 faces (the distorted grid's cells have 24)."""
+    m = inputs.jittered_mesh(3, seed=1)
+    base = gvof.gvof_mesh_create(*m.arrays(), m.nc)
+    handles = [base]
+    try:
+        for flags in (gvof.GVOF_FLAG_LLCIR, gvof.GVOF_FLAG_ELCIR | gvof.GVOF_FLAG_EMFPA,
+                      gvof.GVOF_FLAG_CLCIR | gvof.GVOF_FLAG_NMFPA):
+            p = gvof.gvof_params_default()
+            p.flags = flags
+            h = gvof.gvof_mesh_create(*m.arrays(), m.nc, p)
+            handles.append(h)
+            assert gvof.gvof_mesh_workspace_bytes(h) >= gvof.gvof_mesh_workspace_bytes(base) + 97 * m.nc
     finally:
         for h in handles:
             gvof.gvof_mesh_destroy(h)

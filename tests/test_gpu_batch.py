@@ -87,7 +87,7 @@ def test_batch_steps_bitwise_equal_alone(gv):
 
 
 @pytest.mark.parametrize("method,recon", [("fmfpa", "lsgir"), ("emfpa", "lsgir"), ("nmfpa", "lsgir"),
-                                          ("fmfpa", "lsfir")])
+                                          ("fmfpa", "lsfir"), ("fmfpa", "clcir")])
 def test_batch_matches_oracle_teacher_forced(oracle_mod, gv, method, recon):
     torch, dev, P, B, uf, uv = build(gv, SPECS, method=method, recon=recon)
     log(f"batch vs oracle, {method} {recon}")

@@ -146,6 +146,57 @@ def test_advect_parity_lsfir(oracle_mod, gv, kind, n, steps):
         F = F1
 
 
+@pytest.mark.parametrize("level", ["llcir", "elcir", "clcir"])
+@pytest.mark.parametrize("kind,n", [("cartesian", 16), ("jittered", 12)])
+def test_reconstruct_parity_isosurface(oracle_mod, gv, kind, n, level):
+    """LLCIR / ELCIR / CLCIR planes against the oracle on the paper's static
+    sphere: tags bit for bit, normals and plane constants within 1e-12."""
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    log(f"reconstruct {level} {kind} n={n}")
+    om = oracle_mod.OracleMesh(m, recon=level)
+    g = gv.GvofMesh(m, dev, recon=level)
+    F = om.init_fraction("sphere", [0.525, 0.464, 0.516, 0.325], 6)
+    (Fd, T, tc_g, pl_g, Fcut_g), (Fc, Fs, tn, tf, tc, pl) = reconstruct_both(oracle_mod, g, om, F, torch, dev)
+    assert np.array_equal(T["cell"], tc) and np.array_equal(T["node_value"], Fs)
+    sel = tc == 0
+    lsgir = oracle_mod.OracleMesh(m).reconstruct(F)[5]
+    moved = int((np.abs(pl[:3, sel] - lsgir[:3, sel]).max(axis=0) > 1e-6).sum())
+    dn = np.abs(pl_g[:3, sel] - pl[:3, sel]).max()
+    dC = np.abs(pl_g[3, sel] - pl[3, sel]).max()
+    log(f"  interfacial={sel.sum()} from the isosurface={moved} max|dn|={dn:.2e} max|dC|={dC:.2e}")
+    assert moved > sel.sum() // 2
+    assert dn <= 1e-12 and dC <= 1e-12
+    g.status()
+
+
+@pytest.mark.parametrize("kind,n,steps", [("cartesian", 16, 4), ("jittered", 10, 3)])
+def test_advect_parity_clcir(oracle_mod, gv, kind, n, steps):
+    """Steps with CLCIR planes, teacher-forced from the oracle."""
+    torch, dev = torch_dev()
+    m = make_mesh(kind, n)
+    om = oracle_mod.OracleMesh(m, recon="clcir")
+    g = gv.GvofMesh(m, dev, recon="clcir")
+    uf, uv = inputs.velocity_enright(m)
+    dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
+    ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
+    F = om.init_fraction("sphere", SPHERE, 6)
+    V = om.geometry()["V"]
+    for s in range(steps):
+        log(f"advect clcir {kind} n={n} step {s}")
+        dts = dt * inputs.enright_time_factor((s + 0.5) * dt, 3.0)
+        (Fd, T, tc_g, pl_g, Fcut_g), (Fc, Fs, tn, tf, tc, pl) = reconstruct_both(oracle_mod, g, om, F, torch, dev)
+        Fout = torch.empty_like(Fd)
+        up_g, vd_g, vf_g = g.advect_step(ufd, uvd, dts, Fd, Fout, want_faces=True)
+        F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dts, Fc)
+        g.status()
+        dVF = np.abs(host(vf_g) - VF).max() / V.max()
+        dF = max_abs(host(Fout), F1)
+        log(f"  max|dVF|/V={dVF:.2e} max|dF|={dF:.2e}")
+        assert np.array_equal(host(up_g), up) and dVF <= 1e-12 and dF <= 1e-12
+        F = F1
+
+
 def _velocity(kind_field, m):
     if kind_field == "uniform":
         return inputs.velocity_uniform(m, (1.0, 1.0, 1.0))
