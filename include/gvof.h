@@ -179,7 +179,11 @@ int gvof_init_fraction(gvof_mesh* m, const gvof_shape* shape, int32_t n_div, dou
  *     the weighted least-squares solution of Eqs. (lsgir1), (lsgir2),
  *     (lsgir-beta) over the vertex-sharing neighbours, and the constant C of
  *     the PLIC plane n.x + C = 0 (Eq. plic-eq), fluid on n.x + C >= 0, such
- *     that the fluid part of the cell has volume F V.
+ *     that the fluid part of the cell has volume F V (for F > 1/2 solved on
+ *     the empty part, (1 - F) V, the same plane);
+ *  4. with GVOF_FLAG_LSFIR, GVOF_FLAG_LLCIR, GVOF_FLAG_ELCIR or
+ *     GVOF_FLAG_CLCIR in the mesh's parameters, the normals are then replaced
+ *     as that flag describes and the changed planes placed again as in 3.
  * F_inout (device, nc) in: fractions, out: cut-off fractions.  Optional
  * device outputs (may be NULL): cell_tag_out (nc), plane_out (4 x nc: nx, ny,
  * nz, C; zero for cells not tagged 0).  The tags and planes are also kept in
