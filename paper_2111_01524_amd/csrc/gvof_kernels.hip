@@ -1740,7 +1740,7 @@ __global__ void k_reset_advect(DevMesh M) { reset_advect_state(M); }
 // ============================================================== LSGIR + plane constant
 // A group of kReconLanes lanes per interfacial cell (one lane per cell leaves
 // the GPU nearly idle: a few thousand cells, each a long dependent chain).
-constexpr int kReconLanes = 32;
+constexpr int kReconLanes = 16;
 
 // Sum over the lanes of a group.  Each butterfly level adds a lane's value
 // and its partner's, which gives the same bits on both lanes, so every lane
@@ -2164,7 +2164,7 @@ __global__ void k_lsfir_eig(DevMesh M, int pass, double cos_turn, double cos_sto
 
 // ============================================================== isosurface-based normals
 // (Sec. "Isosurface based interface reconstruction": LLCIR, ELCIR, CLCIR)
-constexpr int kIsoLanes = kReconLanes;  // a lane per face of the cell
+constexpr int kIsoLanes = 32;  // a lane per face of the cell
 static_assert(kMaxIsoFaces <= kIsoLanes, "a lane per face");
 
 // The isosurface F* = 1/2 of cell c as one polygon, a lane per face of the
