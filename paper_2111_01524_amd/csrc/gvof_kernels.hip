@@ -376,11 +376,33 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
     bool geo = false;
     if (f < n && face_live(M, f)) {
       // every load before the first store (the compiler cannot move loads
-      // above stores through these pointers), so the tag chain overlaps the rest
-      d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
-      d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
+      // above stores through these pointers).  The face's vertex list goes
+      // first and is taken alone by the empty asm, so the wait before the
+      // node-tag loads it feeds covers only it: the tag chain then overlaps the
+      // velocity and area loads (the face tag of face_tag_of, inlined)
+      const int fb = fv_begin(M, f), fk = fv_count(M, f);  // 3 <= fk <= kMaxFaceVerts
+      int vq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vq[q] = M.fv_idx[fb + min(q, fk - 1)];
+      const d3 u = mk3(uf[f], uf[n + f], uf[2 * n + f]);
+      const d3 S = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
       const int nb = M.neigh[f], ow = M.owner[f];
-      const int8_t t = face_tag_of(M, f);
+      asm volatile("" : "+v"(vq[0]), "+v"(vq[1]), "+v"(vq[2]), "+v"(vq[3]));
+      int tq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] = M.tag_node[vq[q]];
+      bool allm = true, allp = true;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        allm = allm && tq[q] == -1;
+        allp = allp && tq[q] == 1;
+      }
+      for (int i = fb + 4; i < fb + fk; ++i) {
+        const int tv = M.tag_node[M.fv_idx[i]];
+        allm = allm && tv == -1;
+        allp = allp && tv == 1;
+      }
+      const int8_t t = allm ? -1 : (allp ? 1 : 0);
       double vd = face_dt(M, f, dt) * dot_x(u, S);
       M.Vd[f] = vd;
       M.upwind[f] = vd >= 0.0 ? ow : nb;
@@ -2370,6 +2392,12 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
     int eq[kUpdateFaces];
 #pragma unroll
     for (int q = 0; q < kUpdateFaces; ++q) eq[q] = M.cf_idx[b + min(q, n - 1)];
+    // the cell's own values in the same round trip as its face list (the
+    // compiler would otherwise load them after the face sums, a third
+    // dependent round trip); the empty asm takes them all at once
+    double V = M.V[c], Fc = Fin[c];
+    static_assert(kUpdateFaces == 6, "the asm below names six face entries");
+    asm volatile("" : "+v"(V), "+v"(Fc), "+v"(eq[0]), "+v"(eq[1]), "+v"(eq[2]), "+v"(eq[3]), "+v"(eq[4]), "+v"(eq[5]));
     double dq[kUpdateFaces], fq[kUpdateFaces];
 #pragma unroll
     for (int q = 0; q < kUpdateFaces; ++q) {
@@ -2399,9 +2427,8 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
         VFT = VFT - M.VF[~e];
       }
     }
-    double V = M.V[c];
     double h = VdT / (2.0 * V);
-    double Fn = (Fin[c] * (1.0 + h) - VFT / V) / (1.0 - h);
+    double Fn = (Fc * (1.0 + h) - VFT / V) / (1.0 - h);
     Fout[c] = fmin(fmax(Fn, 0.0), 1.0);
   }
 }
