@@ -2,8 +2,11 @@
 
   - general cells bounded by non-planar quadrilaterals (fanned from their
     vertex mean: the polygon paths of the truncation and of the plane
-    constant, which the triangulated grid does not reach);
-  - the smallest meshes (1^3 and 2^3: every cell touches the boundary);
+    constant, which the triangulated grid does not reach), with every flux
+    polyhedron method and with the LSFIR, LLCIR and CLCIR normals (saddle
+    quadrilateral faces send cells back to LSGIR);
+  - the smallest meshes (1^3 and 2^3: every cell touches the boundary; a
+    single cell has no neighbour for LSFIR's fit or CLCIR's ring);
   - an empty field (no interface: nothing changes, bit for bit);
   - a zero time step (no flux: F after the step equals F after the cut-off to rounding);
   - velocity reversed (negative time step);
@@ -27,11 +30,11 @@ def gv():
     return gvof
 
 
-def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa"):
+def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa", recon="lsgir"):
     torch, dev = torch_dev()
-    om = oracle_mod.OracleMesh(m, method=method)
-    g = gv.GvofMesh(m, dev, method=method)
-    label = f"{label} {method}"
+    om = oracle_mod.OracleMesh(m, method=method, recon=recon, lsfir_outer=2)
+    g = gv.GvofMesh(m, dev, method=method, recon=recon, lsfir_outer=2)
+    label = f"{label} {method} {recon}"
     ufd, uvd = to_dev(torch, dev, uf), to_dev(torch, dev, uv)
     V = om.geometry()["V"]
     for s, dt in enumerate(dts):
@@ -40,8 +43,13 @@ def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa"):
         Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
         assert np.array_equal(host(tags), tc) and np.array_equal(host(Fd), Fc)
         sel = tc == 0
+        # LSFIR's fit and the isosurface rings amplify the rounding of the PLIC
+        # centres and node values they are built from (most on coarse meshes with
+        # non-planar faces): their planes are compared at 1e-11, the fractions
+        # below at the 1e-12 bar as everywhere
+        ptol = 1e-12 if recon == "lsgir" else 1e-11
         if sel.any():
-            assert np.abs(host(planes)[:, sel] - pl[:, sel]).max() <= 1e-12
+            assert np.abs(host(planes)[:, sel] - pl[:, sel]).max() <= ptol
         Fout = torch.empty_like(Fd)
         up_g, vd_g, vf_g = g.advect_step(ufd, uvd, dt, Fd, Fout, want_faces=True)
         F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dt, Fc)
@@ -56,25 +64,28 @@ def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa"):
     return F
 
 
-@pytest.mark.parametrize("method", ["fmfpa", "emfpa", "nmfpa"])
-def test_polygon_face_general_cells(oracle_mod, gv, method):
+@pytest.mark.parametrize("method,recon", [("fmfpa", "lsgir"), ("emfpa", "lsgir"), ("nmfpa", "lsgir"),
+                                          ("fmfpa", "lsfir"), ("fmfpa", "llcir"), ("fmfpa", "clcir")])
+def test_polygon_face_general_cells(oracle_mod, gv, method, recon):
     m = inputs.jittered_mesh(7, seed=3, split=False)
     assert m.fv_ptr[1] == 4
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     F = oracle_mod.OracleMesh(m).init_fraction("sphere", [0.45, 0.5, 0.52, 0.27], 4)
-    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt, -dt], F, "quad-faced distorted 7^3", method)
+    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt, -dt], F, "quad-faced distorted 7^3", method, recon)
 
 
-@pytest.mark.parametrize("kind,n,method", [("cartesian", 1, "fmfpa"), ("cartesian", 2, "fmfpa"),
-                                           ("jittered", 2, "fmfpa"), ("cartesian", 1, "emfpa"),
-                                           ("jittered", 2, "emfpa"), ("jittered", 2, "nmfpa")])
-def test_smallest_meshes(oracle_mod, gv, kind, n, method):
+@pytest.mark.parametrize("kind,n,method,recon", [("cartesian", 1, "fmfpa", "lsgir"), ("cartesian", 2, "fmfpa", "lsgir"),
+                                                 ("jittered", 2, "fmfpa", "lsgir"), ("cartesian", 1, "emfpa", "lsgir"),
+                                                 ("jittered", 2, "emfpa", "lsgir"), ("jittered", 2, "nmfpa", "lsgir"),
+                                                 ("cartesian", 1, "fmfpa", "lsfir"), ("jittered", 2, "fmfpa", "lsfir"),
+                                                 ("cartesian", 1, "fmfpa", "clcir"), ("jittered", 2, "fmfpa", "clcir")])
+def test_smallest_meshes(oracle_mod, gv, kind, n, method, recon):
     m = inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=5)
     uf, uv = inputs.velocity_uniform(m, (0.3, 0.2, 0.1))
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     F = oracle_mod.OracleMesh(m).init_fraction("sphere", [0.4, 0.45, 0.5, 0.3], 6)
-    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt], F, f"{kind} {n}^3", method)
+    _parity_steps(oracle_mod, gv, m, uf, uv, [dt, dt], F, f"{kind} {n}^3", method, recon)
 
 
 def test_empty_field_and_zero_step(oracle_mod, gv):
