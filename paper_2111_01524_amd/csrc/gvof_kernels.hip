@@ -1142,14 +1142,17 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
 // of one kind.  Each pair's volume goes to its own slot, so the order changes
 // no result.
 constexpr int kItemsBlock = 256;
+constexpr int kItemsPerThread = 2;  // pairs ranked together per block: kItemsBlock x this
 __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
-  __shared__ int s_list[kItemsBlock], s_cell[kItemsBlock], s_slot[kItemsBlock];
-  __shared__ unsigned short s_tm[kItemsBlock];
+  constexpr int CHUNK = kItemsBlock * kItemsPerThread;
+  constexpr int VW = CHUNK / 64;  // the chunk as wavefront-sized runs ("virtual wavefronts")
+  __shared__ int s_list[CHUNK], s_cell[CHUNK], s_slot[CHUNK];
+  __shared__ unsigned short s_tm[CHUNK];
   // classes: 2 x (none; then per cut count, first cut keeping one or three),
   // the factor 2 for cells cut by their interface (the leaves then take the
   // half-space fraction) or not
   constexpr int NCLS = 2 * (2 * kMaxRegCuts + 1);
-  __shared__ int s_off[kItemsBlock / 64][NCLS];
+  __shared__ int s_off[VW][NCLS];
   __shared__ int s_n;
   const int rsize = M.item_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
@@ -1157,35 +1160,48 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
   const int lane = __lane_id(), w = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
   // every thread of a block makes the same number of passes (block barriers)
-  for (int b = sub * kItemsBlock; b < fill; b += region_blocks() * kItemsBlock) {
-    const int li = b + threadIdx.x;
-    int cls = -1;  // work class (more work, higher), or -1: nothing for the register clip
-    const int i = r * rsize + li;
-    int k = 0, slot = 0;
-    unsigned tm = 0;
-    if (li < fill) {
-      k = M.item_cell[i];
-      tm = M.item_tm[i];
-      slot = M.item_slot[i];
-      const int8_t tg = M.tag_cell[k];
-      if (M.isbox[k]) {
-        const int nc = cut_count(tm_mask(tm));
-        if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
-        else cls = 2 * (nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u)) + (tg == 0 ? 1 : 0);
+  for (int b = sub * CHUNK; b < fill; b += region_blocks() * CHUNK) {
+    // each thread classifies kItemsPerThread pairs, b + threadIdx.x + h kItemsBlock
+    int cls[kItemsPerThread], idx[kItemsPerThread], kc[kItemsPerThread], sl[kItemsPerThread];
+    unsigned tmh[kItemsPerThread];
+    unsigned long long mh[kItemsPerThread];
+#pragma unroll
+    for (int h = 0; h < kItemsPerThread; ++h) {
+      const int li = b + threadIdx.x + h * kItemsBlock;
+      int c = -1;  // work class (more work, higher), or -1: nothing for the register clip
+      const int i = r * rsize + li;
+      int k = 0, slot = 0;
+      unsigned tm = 0;
+      if (li < fill) {
+        k = M.item_cell[i];
+        tm = M.item_tm[i];
+        slot = M.item_slot[i];
+        const int8_t tg = M.tag_cell[k];
+        if (M.isbox[k]) {
+          const int nc = cut_count(tm_mask(tm));
+          if (nc > kMaxRegCuts) M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;  // deferred (rare)
+          else c = 2 * (nc == 0 ? 0 : 2 * nc - 1 + (int)((tm >> kTmWideBit) & 1u)) + (tg == 0 ? 1 : 0);
+        }
       }
-    }
-    unsigned long long bm[NCLS];
+      unsigned long long m = 0;
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) bm[c] = __ballot(cls == c);
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < NCLS; ++c) s_off[w][c] = __popcll(bm[c]);
+      for (int q = 0; q < NCLS; ++q) {
+        const unsigned long long bq = __ballot(c == q);
+        if (lane == 0) s_off[h * (kItemsBlock / 64) + w][q] = __popcll(bq);
+        m = c == q ? bq : m;
+      }
+      cls[h] = c;
+      idx[h] = i;
+      kc[h] = k;
+      sl[h] = slot;
+      tmh[h] = tm;
+      mh[h] = m;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int t = 0;
       for (int c = NCLS - 1; c >= 0; --c)
-        for (int v = 0; v < kItemsBlock / 64; ++v) {
+        for (int v = 0; v < VW; ++v) {
           const int n = s_off[v][c];
           s_off[v][c] = t;
           t += n;
@@ -1193,22 +1209,22 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
       s_n = t;
     }
     __syncthreads();
-    if (cls >= 0) {
-      unsigned long long m = bm[0];
 #pragma unroll
-      for (int c = 1; c < NCLS; ++c) m = cls == c ? bm[c] : m;
-      const int pos = s_off[w][cls] + __popcll(m & below);
-      s_list[pos] = i;  // the pair and what the clip needs of it first
-      s_cell[pos] = k;
-      s_slot[pos] = slot;
-      s_tm[pos] = (unsigned short)tm;
+    for (int h = 0; h < kItemsPerThread; ++h) {
+      if (cls[h] >= 0) {
+        const int pos = s_off[h * (kItemsBlock / 64) + w][cls[h]] + __popcll(mh[h] & below);
+        s_list[pos] = idx[h];  // the pair and what the clip needs of it first
+        s_cell[pos] = kc[h];
+        s_slot[pos] = sl[h];
+        s_tm[pos] = (unsigned short)tmh[h];
+      }
     }
     __syncthreads();
-    if (threadIdx.x < s_n) {
-      const int ip = s_list[threadIdx.x];
-      const int k = s_cell[threadIdx.x];
-      const unsigned tm = s_tm[threadIdx.x];
-      const Tet T = staged_tet(M, s_slot[threadIdx.x], tm);
+    for (int q = threadIdx.x; q < s_n; q += kItemsBlock) {  // ranks in order of work, most first
+      const int ip = s_list[q];
+      const int k = s_cell[q];
+      const unsigned tm = s_tm[q];
+      const Tet T = staged_tet(M, s_slot[q], tm);
       const double sT = tet6(T);
       double v = 0.0;
       if (sT != 0.0) {
