@@ -1407,14 +1407,18 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 // distorted-grid workload) go to a list for k_flux_gen_units_deep, which runs
 // the same register clip one level deeper (so every unit has one value
 // whichever kernel computes it).
+constexpr int kUnitsPerThread = 4;  // units ranked together per block: kItemsBlock x this
 __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   // As in the box-pair kernel, each block ranks its units by their work (the
   // number of cutting planes, 0..3, and whether the cell's interface cuts the
-  // leaves) before clipping, so that most wavefronts run one kind of unit.
+  // leaves) before clipping, so that most wavefronts run one kind of unit;
+  // kUnitsPerThread units per thread are ranked together.
   constexpr int NCLS = 14;  // none; then per cut count 1..3, first cut keeping one or three; x interface
-  __shared__ int s_unit[kItemsBlock], s_item[kItemsBlock];
-  __shared__ unsigned s_code[kItemsBlock];
-  __shared__ int s_off[kItemsBlock / 64][NCLS];
+  constexpr int CHUNK = kItemsBlock * kUnitsPerThread;
+  constexpr int VW = CHUNK / 64;
+  __shared__ int s_unit[CHUNK], s_item[CHUNK];
+  __shared__ unsigned s_code[CHUNK];
+  __shared__ int s_off[VW][NCLS];
   __shared__ int s_n;
   const int rsize = M.unit_cap / kItemRegions;
   const int r = blockIdx.x % kItemRegions, sub = blockIdx.x / kItemRegions;
@@ -1422,32 +1426,43 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   const int lane = __lane_id(), w = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
   // every thread of a block makes the same number of passes (block barriers)
-  for (int b = sub * kItemsBlock; b < fill; b += region_blocks() * kItemsBlock) {
-    const int lu = b + threadIdx.x;
-    const int u = r * rsize + lu;
-    int cls = -1, i = 0;
-    unsigned code = 0;
-    if (lu < fill) {
-      i = M.unit_item[u];
-      code = M.unit_code[u];
-      const int nc = cut_count(unit_mask(code));
-      const int8_t tg = M.tag_cell[M.item_cell[i]];
-      const int wide = (int)((code >> (16 + kUnitWideBit)) & 1u);
-      if (nc > 3) M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;  // four cutting planes: the deep instance
-      else cls = nc == 0 ? (tg == 0 ? 1 : 0) : 2 + 4 * (nc - 1) + 2 * wide + (tg == 0 ? 1 : 0);
-    }
-    unsigned long long bm[NCLS];
+  for (int b = sub * CHUNK; b < fill; b += region_blocks() * CHUNK) {
+    int cls[kUnitsPerThread], uh[kUnitsPerThread], ih[kUnitsPerThread];
+    unsigned codeh[kUnitsPerThread];
+    unsigned long long mh[kUnitsPerThread];
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) bm[c] = __ballot(cls == c);
-    if (lane == 0) {
+    for (int h = 0; h < kUnitsPerThread; ++h) {
+      const int lu = b + threadIdx.x + h * kItemsBlock;
+      const int u = r * rsize + lu;
+      int c = -1, i = 0;
+      unsigned code = 0;
+      if (lu < fill) {
+        i = M.unit_item[u];
+        code = M.unit_code[u];
+        const int nc = cut_count(unit_mask(code));
+        const int8_t tg = M.tag_cell[M.item_cell[i]];
+        const int wide = (int)((code >> (16 + kUnitWideBit)) & 1u);
+        if (nc > 3) M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;  // four cutting planes: the deep instance
+        else c = nc == 0 ? (tg == 0 ? 1 : 0) : 2 + 4 * (nc - 1) + 2 * wide + (tg == 0 ? 1 : 0);
+      }
+      unsigned long long m = 0;
 #pragma unroll
-      for (int c = 0; c < NCLS; ++c) s_off[w][c] = __popcll(bm[c]);
+      for (int q = 0; q < NCLS; ++q) {
+        const unsigned long long bq = __ballot(c == q);
+        if (lane == 0) s_off[h * (kItemsBlock / 64) + w][q] = __popcll(bq);
+        m = c == q ? bq : m;
+      }
+      cls[h] = c;
+      uh[h] = u;
+      ih[h] = i;
+      codeh[h] = code;
+      mh[h] = m;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int t = 0;
       for (int c = NCLS - 1; c >= 0; --c)
-        for (int v = 0; v < kItemsBlock / 64; ++v) {
+        for (int v = 0; v < VW; ++v) {
           const int n = s_off[v][c];
           s_off[v][c] = t;
           t += n;
@@ -1455,19 +1470,19 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       s_n = t;
     }
     __syncthreads();
-    if (cls >= 0) {
-      unsigned long long m = bm[0];
 #pragma unroll
-      for (int c = 1; c < NCLS; ++c) m = cls == c ? bm[c] : m;
-      const int pos = s_off[w][cls] + __popcll(m & below);
-      s_unit[pos] = u;
-      s_item[pos] = i;
-      s_code[pos] = code;
+    for (int h = 0; h < kUnitsPerThread; ++h) {
+      if (cls[h] >= 0) {
+        const int pos = s_off[h * (kItemsBlock / 64) + w][cls[h]] + __popcll(mh[h] & below);
+        s_unit[pos] = uh[h];
+        s_item[pos] = ih[h];
+        s_code[pos] = codeh[h];
+      }
     }
     __syncthreads();
-    if (threadIdx.x < s_n) {
-      const int uu = s_unit[threadIdx.x], ii = s_item[threadIdx.x];
-      const unsigned cd = s_code[threadIdx.x];
+    for (int q = threadIdx.x; q < s_n; q += kItemsBlock) {  // ranks in order of work, most first
+      const int uu = s_unit[q], ii = s_item[q];
+      const unsigned cd = s_code[q];
       const int p = cd & 0xffff;
       const unsigned cm = unit_mask(cd);
       const int k = M.item_cell[ii];
