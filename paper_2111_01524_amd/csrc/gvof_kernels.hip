@@ -2448,14 +2448,30 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
         }
       }
     }
-    for (int i = b + kUpdateFaces; i < b + n; ++i) {
-      int e = M.cf_idx[i];
-      if (e >= 0) {
-        VdT = VdT + M.Vd[e];
-        VFT = VFT + M.VF[e];
-      } else {
-        VdT = VdT - M.Vd[~e];
-        VFT = VFT - M.VF[~e];
+    // the remaining faces (24 on a cell of the distorted grid) in chunks of
+    // kUpdateFaces, each chunk's loads in flight together, summed in face order
+    for (int i0 = b + kUpdateFaces; i0 < b + n; i0 += kUpdateFaces) {
+      int er[kUpdateFaces];
+#pragma unroll
+      for (int q = 0; q < kUpdateFaces; ++q) er[q] = M.cf_idx[min(i0 + q, b + n - 1)];
+      double dr[kUpdateFaces], fr[kUpdateFaces];
+#pragma unroll
+      for (int q = 0; q < kUpdateFaces; ++q) {
+        const int fi = er[q] >= 0 ? er[q] : ~er[q];
+        dr[q] = M.Vd[fi];
+        fr[q] = M.VF[fi];
+      }
+#pragma unroll
+      for (int q = 0; q < kUpdateFaces; ++q) {
+        if (i0 + q < b + n) {
+          if (er[q] >= 0) {
+            VdT = VdT + dr[q];
+            VFT = VFT + fr[q];
+          } else {
+            VdT = VdT - dr[q];
+            VFT = VFT - fr[q];
+          }
+        }
       }
     }
     double h = VdT / (2.0 * V);
