@@ -1538,10 +1538,20 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
     if (M.isbox[k]) continue;
     const int cnt = M.item_ucnt[i];
     if (cnt < 0) continue;  // deferred
+    // the flux tet (for its sign) first, then the units eight at a time,
+    // loads in flight together and added in order
+    const Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
     const double* v = M.unit_vol + M.item_uoff[i];
     double acc = 0.0;
-    for (int q = 0; q < cnt; ++q) acc += v[q];
-    Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
+    int q = 0;
+    for (; q + 8 <= cnt; q += 8) {
+      double t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = v[q + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += t[j];
+    }
+    for (; q < cnt; ++q) acc += v[q];
     M.item_vol[i] = tet6(T) < 0.0 ? -acc : acc;
   }
 }
