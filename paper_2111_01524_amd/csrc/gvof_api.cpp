@@ -400,6 +400,8 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.cv_idx = C.take<int>(m->cv_idx.size());
   d.vc_ptr = C.take<int>(nv + 1);
   d.vc_idx = C.take<int>(m->vc_idx.size());
+  d.vc_w = C.take<double>(m->vc_idx.size());
+  d.vc_den = C.take<double>(nv);
   d.nb_ptr = C.take<int>(nc + 1);
   d.nb_idx = C.take<int>(std::max<size_t>(m->nb_idx.size(), 1));
   d.cell_np = C.take<short>(nc);

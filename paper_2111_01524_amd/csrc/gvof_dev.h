@@ -31,6 +31,7 @@ struct DevMesh {
   int fv_stride, cf_stride;    // vertices of every face / faces of every cell when all equal, else 0
   const int *cv_ptr, *cv_idx;  // cell -> distinct vertices ascending
   const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
+  double *vc_w, *vc_den;       // node-value weights per vertex-cell entry, and their sum per vertex (set at bind)
   const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
   const short* cell_np;        // surface triangles of each cell (triangles as they are, polygons fanned)
   // surface triangles of the cells bounded by triangles only, in the order and

@@ -213,6 +213,25 @@ __device__ inline void reset_advect_state(const DevMesh& M) {
 }
 
 constexpr int kNodeCells = 8;
+
+// Node weights of the inverse-distance interpolation, once per mesh: w =
+// 1/|x_v - x_c|^2 for every cell of every vertex (list order) and their sum
+// per vertex, in the operations and order the node values use them.
+__global__ void k_node_weights(DevMesh M) {
+  for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
+    const d3 x = vert(M, v);
+    double den = 0.0;
+    for (int i = M.vc_ptr[v]; i < M.vc_ptr[v + 1]; ++i) {
+      const d3 d = x - cell_centre(M, M.vc_idx[i]);
+      const double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
+      const double w = 1.0 / d2;
+      M.vc_w[i] = w;
+      den = den + w;
+    }
+    M.vc_den[v] = den;
+  }
+}
+
 __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   const double eps = M.eps, one_m = 1.0 - M.eps;
   // the interfacial-cell counter of this reconstruction (first incremented by
@@ -225,39 +244,27 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   }
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
     if (!vert_live(M, v)) continue;
-    d3 x = vert(M, v);
-    double num = 0.0, den = 0.0;
+    double num = 0.0;
     const int b = M.vc_ptr[v], n = M.vc_ptr[v + 1] - b;  // n >= 1
-    // the first kNodeCells cells' loads issued together (clamped indices), then
-    // summed in list order like the rest
+    // the weights and their sum come from k_node_weights (the geometry does not
+    // change); the first kNodeCells cells' loads issued together (clamped
+    // indices), then summed in list order like the rest
+    const double den = M.vc_den[v];
     int cq[kNodeCells];
+    double wq[kNodeCells];
 #pragma unroll
-    for (int q = 0; q < kNodeCells; ++q) cq[q] = M.vc_idx[b + min(q, n - 1)];
-    d3 xq[kNodeCells];
+    for (int q = 0; q < kNodeCells; ++q) {
+      cq[q] = M.vc_idx[b + min(q, n - 1)];
+      wq[q] = M.vc_w[b + min(q, n - 1)];
+    }
     double fq[kNodeCells];
 #pragma unroll
-    for (int q = 0; q < kNodeCells; ++q) {
-      xq[q] = cell_centre(M, cq[q]);
-      fq[q] = F[cq[q]];
-    }
+    for (int q = 0; q < kNodeCells; ++q) fq[q] = F[cq[q]];
 #pragma unroll
     for (int q = 0; q < kNodeCells; ++q) {
-      if (q < n) {
-        d3 d = x - xq[q];
-        double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
-        double w = 1.0 / d2;
-        num = num + w * fq[q];
-        den = den + w;
-      }
+      if (q < n) num = num + wq[q] * fq[q];
     }
-    for (int i = b + kNodeCells; i < b + n; ++i) {
-      int c = M.vc_idx[i];
-      d3 d = x - cell_centre(M, c);
-      double d2 = (d.x * d.x + d.y * d.y) + d.z * d.z;
-      double w = 1.0 / d2;
-      num = num + w * F[c];
-      den = den + w;
-    }
+    for (int i = b + kNodeCells; i < b + n; ++i) num = num + M.vc_w[i] * F[M.vc_idx[i]];
     double fs = num / den;
     M.Fstar[v] = fs;
     M.tag_node[v] = fs < eps ? -1 : (fs > one_m ? 1 : 0);
@@ -2631,6 +2638,7 @@ hipError_t launch_zero(int* p, int n, hipStream_t s) {
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s) {
   k_face_geom<<<blocks_for(M.nf, 256), 256, 0, s>>>(M);
   k_cell_geom<<<blocks_for(M.nc, 256), 256, 0, s>>>(M);
+  k_node_weights<<<blocks_for(M.nv, 256), 256, 0, s>>>(M);
   return hipGetLastError();
 }
 
