@@ -66,6 +66,8 @@ def parse():
                     help="interface normals: LSGIR (the default workload), LSFIR, LLCIR, ELCIR or CLCIR")
     ap.add_argument("--lsfir-outer", type=int, default=1, help="LSFIR outer passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the measured FP64 FMA and copy ceilings (reported beside the published peaks)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
     ap.add_argument("--event-every", type=int, default=8,
@@ -241,6 +243,13 @@ def main():
             "launches_timed": flux_n,
         },
     }
+    if not args.no_probes:
+        # measured ceilings: an FP64 FMA loop (libgvof_probe) and a plain copy
+        from paper_2111_01524_amd import probe
+        fma_tflops = probe.measure_fp64_fma(dev)
+        out["probes"] = {"fp64_fma_tflops": fma_tflops, "copy_gbs": probe.measure_copy(dev)}
+        out["roofline"]["peak_measured"] = fma_tflops
+        out["roofline"]["frac_measured"] = achieved_tflops / fma_tflops
     if args.profile_all:
         out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     if batch_problems is not None:

@@ -1,4 +1,4 @@
-"""Build libgvof.so (HIP, gfx950) in-tree.
+"""Build libgvof.so (HIP, gfx950) and the probe library libgvof_probe.so in-tree.
 
     python -m paper_2111_01524_amd.build
 
@@ -18,6 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgvof.so")
 SOURCES = ["gvof_kernels.hip", "gvof_api.cpp"]
+PROBE_LIB = os.path.join(HERE, "libgvof_probe.so")
+PROBE_SOURCES = ["gvof_probe.hip"]
 ARCH = os.environ.get("GVOF_ARCH", "gfx950")
 
 
@@ -35,12 +37,19 @@ def common_flags():
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Builds both libraries; returns the path of libgvof.so."""
+    _build_lib(LIB, SOURCES, verbose)
+    _build_lib(PROBE_LIB, PROBE_SOURCES, verbose)
+    return LIB
+
+
+def _build_lib(lib_path: str, sources, verbose: bool) -> None:
     cc = hipcc()
     tmp = tempfile.mkdtemp(prefix="gvof_build_")
     try:
         procs = []
         objs = []
-        for src in SOURCES:
+        for src in sources:
             obj = os.path.join(tmp, src + ".o")
             cmd = [cc] + common_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
@@ -57,7 +66,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
                 sys.stderr.write(out)
         if failed:
             raise RuntimeError("HIP build failed")
-        tmp_lib = LIB + ".tmp"
+        tmp_lib = lib_path + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib] + objs
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -65,8 +74,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError("HIP link failed")
-        os.replace(tmp_lib, LIB)
-        return LIB
+        os.replace(tmp_lib, lib_path)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
 

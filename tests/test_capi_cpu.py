@@ -27,6 +27,17 @@ def test_library_exports_every_declared_symbol():
     assert sorted(gvof.exported_symbols()) == names
 
 
+def test_probe_library_exports_every_declared_symbol():
+    from paper_2111_01524_amd import probe
+    txt = open(os.path.join(ROOT, "include", "gvof_probe.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = sorted(set(re.findall(r"\b(gvof_[a-z0-9_]+)\s*\(", txt)))
+    assert names == sorted(probe.exported_symbols())
+    L = probe.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
 def test_params_default():
     p = gvof.gvof_params_default()
     assert p.eps == 1e-12 and p.beta == 1.5 and p.fmfpa_degen == 1e-12
