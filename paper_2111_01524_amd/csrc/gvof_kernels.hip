@@ -817,6 +817,17 @@ __device__ inline unsigned tm_word(int t, unsigned mask, int I) {
 // Test of staged candidate kc against flux tet t: the tet's box meets the
 // cell's box and, for a box cell, the tet is not entirely outside one box
 // plane.
+// Cut mask of a tetrahedron with bounding box [tlo, thi] against box cell B,
+// for a tetrahedron whose box meets B's (so it lies entirely outside no box
+// plane): plane 2a (x_a >= lo_a) cuts it when a vertex has x_a < lo_a, plane
+// 2a+1 (x_a <= hi_a) when a vertex has x_a > hi_a.  A box plane's distance
+// is one rounded difference of two coordinates, whose sign is that of the
+// exact difference, so this is cut_mask's result bit for bit.
+__device__ inline unsigned box_cut_mask(d3 tlo, d3 thi, const BoxCont& B) {
+  return (tlo.x < B.lo.x ? 1u : 0u) | (thi.x > B.hi.x ? 2u : 0u) | (tlo.y < B.lo.y ? 4u : 0u) |
+         (thi.y > B.hi.y ? 8u : 0u) | (tlo.z < B.lo.z ? 16u : 0u) | (thi.z > B.hi.z ? 32u : 0u);
+}
+
 __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int method, int TF, int q, unsigned& tm, int& kc) {
   const int t = q % TF;
   kc = q / TF;
@@ -825,15 +836,21 @@ __device__ inline bool pair_test(const PrepLds& S, d3 c, int I, int method, int 
   Tet T{c, mk3(S.px[i1], S.py[i1], S.pz[i1]), mk3(S.px[i2], S.py[i2], S.pz[i2]), mk3(S.px[i3], S.py[i3], S.pz[i3])};
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   BoxCont B{mk3(S.clox[kc], S.cloy[kc], S.cloz[kc]), mk3(S.chix[kc], S.chiy[kc], S.chiz[kc])};
-  bool keep = box_overlap(tlo, thi, B.lo, B.hi);
-  unsigned mask = 0;
-  if (keep && S.cbox[kc]) keep = cut_mask(T, B, mask);
+  const bool keep = box_overlap(tlo, thi, B.lo, B.hi);
+  const unsigned mask = keep && S.cbox[kc] ? box_cut_mask(tlo, thi, B) : 0u;
   tm = tm_word(t, mask, I);
   if (mask) {
     // the first cut keeps three tetrahedra (two or more vertices inside) or one:
-    // a hint for grouping pairs of like work in the truncation kernel
-    const Plane P = B.plane(__builtin_ctz(mask));
-    const int inside = (P.dist(T.p0) > 0.0) + (P.dist(T.p1) > 0.0) + (P.dist(T.p2) > 0.0) + (P.dist(T.p3) > 0.0);
+    // a hint for grouping pairs of like work in the truncation kernel.  Inside
+    // plane 2a means x_a > lo_a, inside plane 2a+1 means x_a < hi_a (the sign
+    // of the plane's distance, as in box_cut_mask).
+    const int l = __builtin_ctz(mask), a = l >> 1;
+    const bool up = (l & 1) != 0;
+    const double bound = a == 0 ? (up ? B.hi.x : B.lo.x) : (a == 1 ? (up ? B.hi.y : B.lo.y) : (up ? B.hi.z : B.lo.z));
+    const double c0 = a == 0 ? T.p0.x : (a == 1 ? T.p0.y : T.p0.z), c1 = a == 0 ? T.p1.x : (a == 1 ? T.p1.y : T.p1.z);
+    const double c2 = a == 0 ? T.p2.x : (a == 1 ? T.p2.y : T.p2.z), c3 = a == 0 ? T.p3.x : (a == 1 ? T.p3.y : T.p3.z);
+    const int inside = up ? (c0 < bound) + (c1 < bound) + (c2 < bound) + (c3 < bound)
+                          : (c0 > bound) + (c1 > bound) + (c2 > bound) + (c3 > bound);
     tm |= (inside >= 2 ? 1u : 0u) << kTmWideBit;
   }
   return keep;
