@@ -66,6 +66,8 @@ def parse():
                     help="interface normals: LSGIR (the default workload), LSFIR, LLCIR, ELCIR or CLCIR")
     ap.add_argument("--lsfir-outer", type=int, default=1, help="LSFIR outer passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recon-leg", action="store_true",
+                    help="skip the leg that times the reconstruction alone (cells/s)")
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the measured FP64 FMA and copy ceilings (reported beside the published peaks)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -154,12 +156,13 @@ def main():
     # ping-pong without copies
     bufs = [F0.clone(), torch.empty_like(F0)]
 
-    def step_pp():
+    def step_pp(reconstructs=1):
         s = state["s"]
         if s == len(sched):
             bufs[0].copy_(F0)
             s = 0
-        g.reconstruct(bufs[0])
+        for _ in range(reconstructs):
+            g.reconstruct(bufs[0])
         g.advect_step(ufd, uvd, dteff[s], bufs[0], bufs[1])
         bufs[0], bufs[1] = bufs[1], bufs[0]
         state["s"] = s + 1
@@ -195,6 +198,25 @@ def main():
     ncells_work, nfaces_work = c1 - c0, f1 - f0
     K = args.steps
     value = mesh.nf * K / (ms_total / 1e3)
+    # Reconstruction time: the same warm-up and timed steps again with
+    # gvof_reconstruct called twice per step.  The second call sees the
+    # fractions it has already cut off and repeats the same work, so the
+    # difference of the two timed runs is the reconstruction time.
+    recon_ms = None
+    if not args.no_recon_leg:
+        bufs[0].copy_(F0)
+        state["s"] = 0
+        for _ in range(args.warmup):
+            step_pp()
+        torch.cuda.synchronize()
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _ in range(args.steps):
+            step_pp(reconstructs=2)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        g.status()
+        recon_ms = (r0.elapsed_time(r1) - ms_total) / args.steps
     flux_ms, flux_n = prof["k_flux_items_box"]
     flux_ms_avg = flux_ms / max(flux_n, 1)
     flops_per_face = FLOPS_PER_FLUX_FACE_TRUNCATION[args.method]
@@ -219,7 +241,9 @@ def main():
                         f"+{args.method.upper()}, {len(sched)} steps per trajectory",
             "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
         },
-        "cells_per_s": mesh.nc * K / (ms_total / 1e3),
+        "cells_per_s": (mesh.nc / (recon_ms / 1e3) if recon_ms and recon_ms > 0 else None),
+        "reconstruct_ms_per_step": recon_ms,
+        "interfacial_faces_steps_per_s": nfaces_work / (ms_total / 1e3),
         "launch_config": tuned if tuned is not None else gvof.gvof_get_launch_config(g.h).as_dict(),
         "launch_config_autotuned": tuned is not None,
         "interfacial_faces_per_step": nfaces_work / K,
