@@ -433,6 +433,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.tag_node = C.take<int8_t>(nv);
   d.tag_face = C.take<int8_t>(nf);
   d.tag_cell = C.take<int8_t>(nc);
+  d.flux_near = C.take<int8_t>(nc);
   double* pl = C.take<double>(4 * nc);
   d.pnx = pl;
   d.pny = pl ? pl + nc : nullptr;

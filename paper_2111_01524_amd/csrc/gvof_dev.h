@@ -46,6 +46,9 @@ struct DevMesh {
   // per-step state
   double* Fstar;
   int8_t *tag_node, *tag_face, *tag_cell;
+  // per cell: some face of the cell may carry fluid this step (its face tag
+  // is not -1); cleared by the cell tagging, set by the face sweep
+  int8_t* flux_near;
   double *pnx, *pny, *pnz, *pC;  // PLIC planes of tag-0 cells
   double *Vd, *VF;
   int* upwind;

@@ -130,6 +130,7 @@ __device__ inline int face_triangle_count(const DevMesh& M, int e) {
 // surface triangles.  Flags cells that are not closed or not positive.
 __global__ void k_cell_geom(DevMesh M) {
   for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
+    M.flux_near[c] = 1;  // until a reconstruction clears it: no cell is skipped by the update
     int vb = M.cv_ptr[c], vn = M.cv_ptr[c + 1] - vb;
     d3 s = mk3(0.0, 0.0, 0.0);
     d3 lo = vert(M, M.cv_idx[vb]), hi = lo;
@@ -316,6 +317,7 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
       double f = F[c];
       int8_t t = f < eps ? -1 : (f > one_m ? 1 : 0);
       M.tag_cell[c] = t;
+      M.flux_near[c] = 0;  // set again by the face sweep for the cells of faces that carry fluid
       if (t == -1) F[c] = 0.0;
       if (t == 1) F[c] = 1.0;
       inter = t == 0;
@@ -417,6 +419,10 @@ __global__ void k_face_sweep(DevMesh M, const double* __restrict__ uf, double dt
       else if (t == -1) M.VF[f] = 0.0;
       else if (t == 1) M.VF[f] = vd;
       else geo = true;
+      if (t != -1) {  // V_F may be nonzero: the update of both cells needs the face sums
+        M.flux_near[ow] = 1;
+        if (nb >= 0) M.flux_near[nb] = 1;
+      }
     }
     block_append(geo, f, &M.counters[CNT_FACES], M.list_faces, nullptr);  // counted once per step by k_flux_sum
   }
@@ -2461,8 +2467,17 @@ __global__ void k_update(DevMesh M, const double* __restrict__ Fin, double* __re
     // compiler would otherwise load them after the face sums, a third
     // dependent round trip); the empty asm takes them all at once
     double V = M.V[c], Fc = Fin[c];
+    int near = M.flux_near[c];
     static_assert(kUpdateFaces == 6, "the asm below names six face entries");
-    asm volatile("" : "+v"(V), "+v"(Fc), "+v"(eq[0]), "+v"(eq[1]), "+v"(eq[2]), "+v"(eq[3]), "+v"(eq[4]), "+v"(eq[5]));
+    asm volatile("" : "+v"(V), "+v"(Fc), "+v"(near), "+v"(eq[0]), "+v"(eq[1]), "+v"(eq[2]), "+v"(eq[3]), "+v"(eq[4]),
+                 "+v"(eq[5]));
+    // An empty cell none of whose faces carries fluid (every face tag -1, so
+    // every V_F is +0): the update gives (0 (1 + h) - 0 / V) / (1 - h) = +0,
+    // so its face sums are not gathered.
+    if (near == 0 && Fc == 0.0) {
+      Fout[c] = 0.0;
+      continue;
+    }
     double dq[kUpdateFaces], fq[kUpdateFaces];
 #pragma unroll
     for (int q = 0; q < kUpdateFaces; ++q) {
