@@ -245,6 +245,11 @@ def test_advect_parity_teacher_forced(oracle_mod, gv, kind, n, field, steps, met
         log(f"  tag0 faces={(tf == 0).sum()} max|dVF|/V={dVF:.2e} max|dF|={dF:.2e}")
         assert dVF <= 1e-12
         assert dF <= 1e-12
+        # the same step without per-face outputs (faces with tag -1 then keep
+        # no V_d of their own; the update recomputes it): the same bits
+        Fout2 = torch.empty_like(Fd)
+        g.advect_step(ufd, uvd, dts, Fd, Fout2)
+        assert torch.equal(Fout2, Fout)
         F = F1
     log(f"worst |dF| = {worst:.2e}")
 
