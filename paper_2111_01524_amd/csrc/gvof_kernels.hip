@@ -245,28 +245,35 @@ __global__ void k_node_tag(DevMesh M, const double* __restrict__ F) {
   }
   for (int v = grid_stride_start(); v < M.nv; v += grid_stride()) {
     if (!vert_live(M, v)) continue;
-    double num = 0.0;
     const int b = M.vc_ptr[v], n = M.vc_ptr[v + 1] - b;  // n >= 1
-    // the weights and their sum come from k_node_weights (the geometry does not
-    // change); the first kNodeCells cells' loads issued together (clamped
-    // indices), then summed in list order like the rest
-    const double den = M.vc_den[v];
+    // the first kNodeCells cells' fractions, loads issued together (clamped indices)
     int cq[kNodeCells];
-    double wq[kNodeCells];
 #pragma unroll
-    for (int q = 0; q < kNodeCells; ++q) {
-      cq[q] = M.vc_idx[b + min(q, n - 1)];
-      wq[q] = M.vc_w[b + min(q, n - 1)];
-    }
+    for (int q = 0; q < kNodeCells; ++q) cq[q] = M.vc_idx[b + min(q, n - 1)];
     double fq[kNodeCells];
 #pragma unroll
     for (int q = 0; q < kNodeCells; ++q) fq[q] = F[cq[q]];
+    bool any = n > kNodeCells;
 #pragma unroll
-    for (int q = 0; q < kNodeCells; ++q) {
-      if (q < n) num = num + wq[q] * fq[q];
+    for (int q = 0; q < kNodeCells; ++q) any = any || (q < n && fq[q] != 0.0);
+    // Every fraction 0 (either sign): each product w F is a zero, their sum
+    // from +0 is +0, and so is F* = +0 / den, whatever the weights.  Otherwise
+    // the weights and their sum (from k_node_weights: the geometry does not
+    // change), summed in list order.
+    double fs = 0.0;
+    if (any) {
+      const double den = M.vc_den[v];
+      double wq[kNodeCells];
+#pragma unroll
+      for (int q = 0; q < kNodeCells; ++q) wq[q] = M.vc_w[b + min(q, n - 1)];
+      double num = 0.0;
+#pragma unroll
+      for (int q = 0; q < kNodeCells; ++q) {
+        if (q < n) num = num + wq[q] * fq[q];
+      }
+      for (int i = b + kNodeCells; i < b + n; ++i) num = num + M.vc_w[i] * F[M.vc_idx[i]];
+      fs = num / den;
     }
-    for (int i = b + kNodeCells; i < b + n; ++i) num = num + M.vc_w[i] * F[M.vc_idx[i]];
-    double fs = num / den;
     M.Fstar[v] = fs;
     M.tag_node[v] = fs < eps ? -1 : (fs > one_m ? 1 : 0);
   }
