@@ -131,6 +131,7 @@ __device__ inline int face_triangle_count(const DevMesh& M, int e) {
 __global__ void k_cell_geom(DevMesh M) {
   for (int c = grid_stride_start(); c < M.nc; c += grid_stride()) {
     M.flux_near[c] = 1;  // until a reconstruction clears it: no cell is skipped by the update
+    M.tag_cell[c] = 0;   // so the first reconstruction clears every plane it does not place
     int vb = M.cv_ptr[c], vn = M.cv_ptr[c + 1] - vb;
     d3 s = mk3(0.0, 0.0, 0.0);
     d3 lo = vert(M, M.cv_idx[vb]), hi = lo;
@@ -322,6 +323,7 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
     bool inter = false;
     if (c < n && cell_live(M, c)) {
       double f = F[c];
+      const int8_t prev = M.tag_cell[c];
       int8_t t = f < eps ? -1 : (f > one_m ? 1 : 0);
       M.tag_cell[c] = t;
       M.flux_near[c] = 0;  // set again by the face sweep for the cells of faces that carry fluid
@@ -331,7 +333,9 @@ __global__ void k_cell_tag(DevMesh M, double* __restrict__ F) {
       // no isosurface until k_iso_local finds one (the ELCIR / CLCIR rings read
       // this flag for every neighbour, interfacial or not)
       if (M.iso_level > 0) M.iso_ok[c] = 0;
-      if (!inter) {
+      // a plane is placed only in an interfacial cell, so a cell that was not
+      // interfacial in the last reconstruction holds a zero plane already
+      if (!inter && prev == 0) {
         M.pnx[c] = 0.0;
         M.pny[c] = 0.0;
         M.pnz[c] = 0.0;
