@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counters, scaled by the same counters on a plain copy kernel of
 # known size; profiles/hbm_traffic_cartesian64_enright.md), valid for the
 # kernel sources whose digest is recorded beside it.
-ITEMS_BOX_TRAFFIC_BYTES = 2.82745e7
-ITEMS_BOX_TRAFFIC_SOURCES = "4249b2e33f012032"
+ITEMS_BOX_TRAFFIC_BYTES = 2.82545e7
+ITEMS_BOX_TRAFFIC_SOURCES = "eb4e382cf8ee7eb5"
 
 
 def kernel_sources_digest() -> str:
