@@ -67,13 +67,20 @@ enum {
 /* Normals by LSFIR (Sec. "Least squares fit interface reconstruction"): after
  * LSGIR, each interfacial cell's normal is refitted as the plane through its
  * PLIC centre (the vertex mean of its PLIC polygon) nearest, in the weighted
- * least-squares sense (w = |dx|^-2.5), to the PLIC centres of the vertex-
- * sharing interfacial cells whose normals are within 45 degrees; the outer
+ * least-squares sense (w = |dx|^-2.5; a neighbour whose centre coincides
+ * with the cell's is skipped), to the PLIC centres of the vertex-sharing
+ * interfacial cells whose normals are within 45 degrees; the outer
  * iteration adopts a fit that turns the normal by less than 30/I degrees in
  * pass I, all cells at once, then places the changed planes; at most
  * lsfir_outer passes, stopping early after a pass in which no normal turned
  * by lsfir_tol (radians) or more. */
 #define GVOF_FLAG_LSFIR 4u
+/* With GVOF_FLAG_LSFIR: the weight of a neighbour whose PLIC centre is closer
+ * than 0.05 h (h the largest extent of the cell's box) is taken at
+ * |dx| = 0.05 h.  Not part of the paper's method: an option that bounds the
+ * weight where two centres nearly coincide and the direction between them
+ * is set by rounding.  Ignored without GVOF_FLAG_LSFIR. */
+#define GVOF_FLAG_LSFIR_CAP 64u
 #define GVOF_MAX_LSFIR_OUTER 32
 /* Normals from the isosurface F* = 1/2 of the node values (Sec. "Isosurface
  * based interface reconstruction"; cells without one polygon of it keep
@@ -93,8 +100,10 @@ typedef struct gvof_params {
   double beta;        /* LSGIR weight exponent of Eq. (lsgir-beta); 1.5 */
   double fmfpa_degen; /* FMFPA: two lateral planes count as parallel when |d|^2 <= degen |m1|^2 |m2|^2; 1e-12 */
   uint32_t flags;     /* GVOF_FLAG_* */
-  int32_t lsfir_outer; /* LSFIR outer passes at most, 1..GVOF_MAX_LSFIR_OUTER; 1 */
-  double lsfir_tol;    /* LSFIR stopping angle (rad), >= 0; 0: stop only when no normal moved */
+  int32_t lsfir_outer; /* LSFIR outer passes at most, 1..GVOF_MAX_LSFIR_OUTER; 4, the paper's test setting
+                          (Sec. "Test programs and performance analysis") */
+  double lsfir_tol;    /* LSFIR stopping angle (rad), >= 0 (0: stop only when no normal moved); 1e-3, the
+                          paper's test setting */
 } gvof_params;
 
 /* Fills the defaults quoted above. */

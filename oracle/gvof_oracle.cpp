@@ -217,13 +217,15 @@ struct OMesh {
   std::vector<std::vector<int>> nb;                  // cell -> vertex-sharing cells (not itself) ascending
   // geometry
   std::vector<V3> S, fc, cc, bbmin, bbmax;
+  V3 dom_lo, dom_hi;  // enclosing box of every vertex (of the whole domain)
   std::vector<real> V;
   std::vector<char> isbox;
   std::vector<std::vector<Tet>> tets;  // surface tets of every non-box cell
   int method = 0;                      // flux polyhedra: 0 FMFPA, 1 EMFPA, 2 NMFPA
   int recon = 0;                       // normals: 0 LSGIR, 1 LSFIR, 2 LLCIR, 3 ELCIR, 4 CLCIR
-  int lsfir_outer = 1;                 // LSFIR outer iterations at most
-  double lsfir_tol = 0.0;              // LSFIR: stop once no normal turns by this angle (rad) or more
+  int lsfir_outer = 4;                 // LSFIR outer iterations at most (the paper's tests: 4)
+  double lsfir_tol = 1e-3;             // LSFIR: stop once no normal turns by this angle (rad) or more (1e-3)
+  bool lsfir_cap = false;              // LSFIR weight floor at |d| = 0.05 h (not the paper's; opt-in)
 };
 
 // Surface triangles of cell c: triangle faces as they are, polygons fanned
@@ -249,6 +251,11 @@ void cell_triangles(const OMesh& M, int c, std::vector<std::array<V3, 3>>& tri) 
 
 void build_mesh(OMesh& M) {
   int nv = M.nv, nf = M.nf, nc = M.nc;
+  M.dom_lo = M.dom_hi = M.X[0];
+  for (int v = 1; v < nv; ++v) {
+    M.dom_lo = mk(std::min(M.dom_lo.x, M.X[v].x), std::min(M.dom_lo.y, M.X[v].y), std::min(M.dom_lo.z, M.X[v].z));
+    M.dom_hi = mk(std::max(M.dom_hi.x, M.X[v].x), std::max(M.dom_hi.y, M.X[v].y), std::max(M.dom_hi.z, M.X[v].z));
+  }
   M.cf.assign(nc, {});
   for (int f = 0; f < nf; ++f) {
     M.cf[M.owner[f]].push_back({f, +1});
@@ -606,20 +613,20 @@ void jacobi3(real A[3][3], real V[3][3]) {
 // One least-squares fit: the unit normal of the plane through the PLIC centre
 // x of cell c that minimises sum w_k (n.(x_k - x))^2 over the valid
 // neighbours k (interfacial cells sharing a vertex with c whose normals
-// differ from c's by less than 45 degrees), w_k = |x_k - x|^-2.5: the
-// eigenvector of the smallest eigenvalue of sum w_k d_k d_k^T, turned to
-// agree with c's normal.  Keeps c's normal when fewer than two neighbours
-// are valid or the smallest eigenvalue is not separated from the next.
-// The weight is singular where two PLIC centres coincide, and a centre very
-// close to x has a direction set by rounding alone; the weight is therefore
-// taken at |d| = 0.05 h for closer centres (h: the largest extent of c's
-// box), which changes nothing for centres farther apart.
+// differ from c's by less than 45 degrees), w_k = |x_k - x|^-2.5 (the
+// section's weight; a neighbour whose centre coincides with x has no
+// direction and is skipped): the eigenvector of the smallest eigenvalue of
+// sum w_k d_k d_k^T, turned to agree with c's normal.  Keeps c's normal when
+// fewer than two neighbours are valid or the smallest eigenvalue is not
+// separated from the next.  With lsfir_cap (an option the paper does not
+// have) the weight of a centre closer than 0.05 h is taken at |d| = 0.05 h
+// (h: the largest extent of c's box).
 V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vector<V3>& xc, const int8_t* tc,
              int& nvalid) {
   const real cos45 = sqrt(real(0.5));
   V3 ext = M.bbmax[c] - M.bbmin[c];
   real hc = std::max(std::max(ext.x, ext.y), ext.z);
-  real dmin2 = (real(0.05) * hc) * (real(0.05) * hc);
+  real dmin2 = M.lsfir_cap ? (real(0.05) * hc) * (real(0.05) * hc) : real(0.0);
   real A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   nvalid = 0;
   for (int k : M.nb[c]) {
@@ -628,8 +635,8 @@ V3 lsfir_fit(const OMesh& M, int c, const std::vector<V3>& nrm, const std::vecto
     V3 d = xc[k] - xc[c];
     real dd = dot(d, d);
     if (dd == real(0.0)) continue;
-    real dw = std::max(dd, dmin2);
-    real w = real(1.0) / (dw * sqrt(sqrt(dw)));  // |d|^-2.5, bounded at |d| = 0.05 h
+    real dw = std::max(dd, dmin2);  // dd itself unless the floor is on
+    real w = real(1.0) / (dw * sqrt(sqrt(dw)));  // |d|^-2.5
     real dv[3] = {d.x, d.y, d.z};
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) A[i][j] = A[i][j] + w * dv[i] * dv[j];
@@ -1109,6 +1116,35 @@ void candidates(const OMesh& M, int f, std::vector<int>& out) {
   out.erase(std::unique(out.begin(), out.end()), out.end());
 }
 
+// Whether the flux polyhedron of face f stays within the cells the
+// truncation visits (the candidates; "donating regions from several cells",
+// Sec. "Fluid advected through cell faces"): every point it is built from
+// (x_i, b_i, the apex, the face centre, EMFPA's lateral centres) lies in the
+// closed enclosing box of some candidate cell, or outside the enclosing box
+// of the whole mesh (outside the domain, which holds no fluid).  The
+// polyhedron lies in the convex hull of these points, so on a Cartesian grid,
+// whose candidates' boxes tile one box, this is exact; elsewhere it tests
+// boxes, not cells.
+bool flux_covered(const OMesh& M, int f, const FluxPoly& P) {
+  std::vector<int> cand;
+  candidates(M, f, cand);
+  std::vector<V3> pts(P.x);
+  pts.insert(pts.end(), P.b.begin(), P.b.end());
+  pts.insert(pts.end(), P.m.begin(), P.m.end());
+  pts.push_back(P.a);
+  pts.push_back(P.c);
+  auto in_box = [](V3 p, V3 lo, V3 hi) {
+    return lo.x <= p.x && p.x <= hi.x && lo.y <= p.y && p.y <= hi.y && lo.z <= p.z && p.z <= hi.z;
+  };
+  for (V3 p : pts) {
+    if (!in_box(p, M.dom_lo, M.dom_hi)) continue;
+    bool in = false;
+    for (int k : cand) in = in || in_box(p, M.bbmin[k], M.bbmax[k]);
+    if (!in) return false;
+  }
+  return true;
+}
+
 // V_F of a tag-0 face: signed truncation of the flux polyhedron by the fluid
 // of every candidate cell (full cells whole, interfacial cells by their PLIC
 // half-space, empty cells skipped).
@@ -1325,14 +1361,16 @@ void* orc_mesh_new(int nv, const double* vx, const double* vy, const double* vz,
 void orc_mesh_free(void* h) { delete static_cast<OMesh*>(h); }
 
 // Normals of the mesh's reconstruction: 0 LSGIR (default), 1 LSFIR with at
-// most `outer` outer iterations and stopping tolerance tol (rad), 2 LLCIR,
-// 3 ELCIR, 4 CLCIR.  Returns 0, or -1 for a bad value.
-int orc_mesh_set_recon(void* h, int method, int outer, double tol) {
+// most `outer` outer iterations and stopping tolerance tol (rad), the weight
+// floored at 0.05 h when cap is nonzero, 2 LLCIR, 3 ELCIR, 4 CLCIR.  Returns
+// 0, or -1 for a bad value.
+int orc_mesh_set_recon(void* h, int method, int outer, double tol, int cap) {
   if (method < 0 || method > 4 || outer < 1 || !(tol >= 0.0)) return -1;
   OMesh& M = *static_cast<OMesh*>(h);
   M.recon = method;
   M.lsfir_outer = outer;
   M.lsfir_tol = tol;
+  M.lsfir_cap = cap != 0;
   return 0;
 }
 
@@ -1543,6 +1581,29 @@ int orc_face_flux(void* h, const double* planes, const int8_t* tc, const int8_t*
     if (o.degenerate) ++bad;
   }
   return bad;
+}
+
+// Coverage of the flux polyhedra of a step (flux_covered): uncovered[f] = 1
+// for each face that builds a polyhedron (tag 0, not an inflow boundary face)
+// whose polyhedron leaves its candidate cells, else 0.  Returns their number.
+int orc_flux_coverage(void* h, const int8_t* tf, const double* uf, const double* uv, double dt, double degen,
+                      int8_t* uncovered) {
+  OMesh& M = *static_cast<OMesh*>(h);
+  int n = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : n)
+  for (int f = 0; f < M.nf; ++f) {
+    uncovered[f] = 0;
+    V3 u = mk(uf[f], uf[M.nf + f], uf[2 * M.nf + f]);
+    real Vd = real(dt) * dot(u, M.S[f]);
+    if (tf[f] != 0 || (M.neigh[f] < 0 && Vd < real(0.0))) continue;
+    FluxPoly P;
+    flux_poly(M, f, uf, uv, dt, Vd, degen, P);
+    if (!flux_covered(M, f, P)) {
+      uncovered[f] = 1;
+      ++n;
+    }
+  }
+  return n;
 }
 
 // One advection step over the whole mesh (faceflux + vofadv).

@@ -31,7 +31,7 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_mesh_free.argtypes = [C.c_void_p]
         lib.orc_mesh_set_method.argtypes = [C.c_void_p, C.c_int]
         lib.orc_mesh_set_method.restype = C.c_int
-        lib.orc_mesh_set_recon.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double]
+        lib.orc_mesh_set_recon.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int]
         lib.orc_mesh_set_recon.restype = C.c_int
         lib.orc_plic_centres.argtypes = [C.c_void_p, _b, _d, _d, _i]
         lib.orc_lsfir_fit.argtypes = [C.c_void_p, _b, _d, _d, _d, _i]
@@ -53,6 +53,8 @@ def _lib(counting: bool = False) -> C.CDLL:
         lib.orc_advect.argtypes = [C.c_void_p, _d, _b, _b, _d, _d, C.c_double, C.c_double, _d, _d, _d, _d, _i]
         lib.orc_advect.restype = C.c_int
         lib.orc_update.argtypes = [C.c_void_p, _d, _d, _d, _d]
+        lib.orc_flux_coverage.argtypes = [C.c_void_p, _b, _d, _d, C.c_double, C.c_double, _b]
+        lib.orc_flux_coverage.restype = C.c_int
         lib.orc_flux_polyhedron.argtypes = [C.c_void_p, C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, _d,
                                             _d]
         lib.orc_flux_polyhedron.restype = C.c_int
@@ -100,7 +102,9 @@ class OracleMesh:
     (Sec. "Non-matched flux polyhedron").  recon selects the normals:
     "lsgir" (Sec. LSGIR), "lsfir" (Sec. "Least squares fit interface
     reconstruction", at most lsfir_outer outer iterations, stopping once no
-    normal turns by lsfir_tol radians or more), or "llcir" / "elcir" /
+    normal turns by lsfir_tol radians or more; the paper's test settings 4
+    and 1e-3 by default; lsfir_cap floors the weight at |d| = 0.05 h, an
+    option the paper does not have), or "llcir" / "elcir" /
     "clcir" (Sec. "Isosurface based interface reconstruction").
     """
 
@@ -108,7 +112,7 @@ class OracleMesh:
     RECONS = {"lsgir": 0, "lsfir": 1, "llcir": 2, "elcir": 3, "clcir": 4}
 
     def __init__(self, mesh, counting: bool = False, method: str = "fmfpa", recon: str = "lsgir",
-                 lsfir_outer: int = 1, lsfir_tol: float = 0.0):
+                 lsfir_outer: int = 4, lsfir_tol: float = 1e-3, lsfir_cap: bool = False):
         if method not in self.METHODS:
             raise ValueError(f"unknown flux polyhedron method {method!r}")
         self.lib = _lib(counting)
@@ -126,7 +130,8 @@ class OracleMesh:
         if recon not in self.RECONS:
             raise ValueError(f"unknown reconstruction {recon!r}")
         self.recon = recon
-        if self.lib.orc_mesh_set_recon(self.h, self.RECONS[recon], int(lsfir_outer), float(lsfir_tol)):
+        if self.lib.orc_mesh_set_recon(self.h, self.RECONS[recon], int(lsfir_outer), float(lsfir_tol),
+                                       int(bool(lsfir_cap))):
             raise ValueError("oracle rejected the reconstruction settings")
 
     def __del__(self):
@@ -233,6 +238,13 @@ class OracleMesh:
         bad = self.lib.orc_advect(self.h, _p(pl, _d), _p(tc, _b), _p(tf, _b), _p(uf, _d), _p(uv, _d), float(dt),
                                   degen, _p(Fin, _d), _p(Fout, _d), _p(Vd, _d), _p(VF, _d), _p(up, _i))
         return Fout, Vd, VF, up, bad
+
+    def coverage(self, tface, u_face, u_vert, dt, degen=1e-12):
+        """Per face, 1 where the face builds a flux polyhedron that leaves the
+        enclosing boxes of its candidate cells (inside the domain's box), else 0."""
+        tf = _i8(tface); uf = _dbl(u_face); uv = _dbl(u_vert); out = np.zeros(self.nf, np.int8)
+        self.lib.orc_flux_coverage(self.h, _p(tf, _b), _p(uf, _d), _p(uv, _d), float(dt), degen, _p(out, _b))
+        return out
 
     def update(self, Vd, VF, F_in):
         Vd = _dbl(Vd); VF = _dbl(VF); Fin = _dbl(F_in); Fout = np.zeros(self.nc)

@@ -137,8 +137,8 @@ void gvof_params_default(gvof_params* p) {
   p->beta = 1.5;
   p->fmfpa_degen = 1e-12;
   p->flags = GVOF_FLAG_NONE;
-  p->lsfir_outer = 1;
-  p->lsfir_tol = 0.0;
+  p->lsfir_outer = 4;
+  p->lsfir_tol = 1e-3;
 }
 
 int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double* vy, const double* vz, int32_t nf,
@@ -167,7 +167,7 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
   if (params) {
     const uint32_t methods = GVOF_FLAG_EMFPA | GVOF_FLAG_NMFPA;
     const uint32_t recons = GVOF_FLAG_LSFIR | GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR;
-    const uint32_t known = methods | recons;
+    const uint32_t known = methods | recons | GVOF_FLAG_LSFIR_CAP;
     if (params->flags & ~known) return fail(nullptr, GVOF_E_ARG, "unknown flags 0x%x", (unsigned)(params->flags & ~known));
     if ((params->flags & methods) == methods)
       return fail(nullptr, GVOF_E_ARG, "GVOF_FLAG_EMFPA and GVOF_FLAG_NMFPA together");
@@ -501,11 +501,13 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   }
   gvof::Shape* shp = C.take<gvof::Shape>(m->nprob);
   if (dm) m->shape_area = shp;
+  d.dom_box = C.take<double>(6 * (size_t)m->nprob);
   d.eps = m->p.eps;
   d.beta = m->p.beta;
   d.degen = m->p.fmfpa_degen;
   d.method = (m->p.flags & GVOF_FLAG_EMFPA) ? gvof::kEMFPA : (m->p.flags & GVOF_FLAG_NMFPA) ? gvof::kNMFPA : gvof::kFMFPA;
   d.lsfir_outer = (m->p.flags & GVOF_FLAG_LSFIR) ? m->p.lsfir_outer : 0;
+  d.lsfir_cap = (m->p.flags & GVOF_FLAG_LSFIR_CAP) ? 1 : 0;
   d.iso_level = (m->p.flags & GVOF_FLAG_LLCIR) ? 2 : (m->p.flags & GVOF_FLAG_ELCIR) ? 3 : (m->p.flags & GVOF_FLAG_CLCIR) ? 4 : 0;
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
@@ -564,6 +566,20 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
       HIPCHECK(m, up(dst[a], pid[a].data(), pid[a].size() * 4));
     }
   }
+  std::vector<double> dom(6 * (size_t)m->nprob);
+  for (int q = 0; q < m->nprob; ++q) {
+    const int v0 = m->nprob > 1 ? m->voff[q] : 0, v1 = m->nprob > 1 ? m->voff[q + 1] : m->nv;
+    double* b = dom.data() + 6 * (size_t)q;
+    b[0] = b[3] = m->vx[v0];
+    b[1] = b[4] = m->vy[v0];
+    b[2] = b[5] = m->vz[v0];
+    for (int v = v0 + 1; v < v1; ++v) {
+      b[0] = std::min(b[0], m->vx[v]); b[3] = std::max(b[3], m->vx[v]);
+      b[1] = std::min(b[1], m->vy[v]); b[4] = std::max(b[4], m->vy[v]);
+      b[2] = std::min(b[2], m->vz[v]); b[5] = std::max(b[5], m->vz[v]);
+    }
+  }
+  HIPCHECK(m, up(d.dom_box, dom.data(), dom.size() * 8));
   HIPCHECK(m, gvof::launch_zero(d.counters, gvof::CNT_N, s));
   HIPCHECK(m, gvof::launch_zero(reinterpret_cast<int*>(d.totals), 8, s));
   HIPCHECK(m, gvof::launch_geometry(d, s));
@@ -717,10 +733,11 @@ int gvof_status(gvof_mesh* m) {
   HIPCHECK(m, hipStreamSynchronize(m->stream));
   int e = cnt[gvof::CNT_ERR];
   if (e) {
-    return fail(m, GVOF_E_GEOM, "device geometry error flags 0x%x (%s%s%s)", e,
+    return fail(m, GVOF_E_GEOM, "device geometry error flags 0x%x (%s%s%s%s)", e,
                 (e & gvof::ERR_APEX) ? "flux-polyhedron apex degenerate " : "",
                 (e & gvof::ERR_LEVELS) ? "too many vertex levels " : "",
-                (e & gvof::ERR_STACK) ? "clip stack overflow" : "");
+                (e & gvof::ERR_STACK) ? "clip stack overflow " : "",
+                (e & gvof::ERR_COVER) ? "flux polyhedron leaves the cells around its face (time step too large)" : "");
   }
   return GVOF_OK;
 }

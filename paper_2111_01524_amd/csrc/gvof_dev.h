@@ -77,6 +77,7 @@ struct DevMesh {
   int method;   // flux polyhedra: kFMFPA, kEMFPA or kNMFPA
   // LSFIR (normals refined after LSGIR; lsfir_outer == 0: LSGIR only)
   int lsfir_outer;
+  int lsfir_cap;      // weight floor at |d| = 0.05 h (an option, not the paper's weight)
   double* lsfir_xc;   // [3][nc] PLIC centres of the current planes
   double* lsfir_nn;   // [3][nc] fitted normals of the current pass
   double* lsfir_A;    // [7][nc] per listed cell: scatter matrix (upper triangle) and valid-neighbour count
@@ -87,6 +88,10 @@ struct DevMesh {
   double* iso_g;      // [3][nc] isosurface centres
   double* iso_nl;     // [3][nc] LLCIR normals
   int8_t* iso_ok;     // [nc] 1: the interfacial cell has a usable isosurface
+  // enclosing box of each problem's vertices ([6][nprob]: lo x y z, hi x y z):
+  // flux polyhedron points outside it lie outside the domain (no fluid there)
+  // and need no candidate cell
+  const double* dom_box;
   int all_box;  // every cell is an axis-aligned box (set at bind)
   int any_box;  // some cell is an axis-aligned box (set at bind)
   // problem partition of a batch (a disjoint union of independent meshes);
@@ -123,7 +128,7 @@ __device__ inline double face_dt(const DevMesh& M, int f, double dt) {
 }
 
 enum { CNT_CELLS = 0, CNT_FACES = 1, CNT_ERR = 2, CNT_REFINE = 3, CNT_ITEMS = 4, CNT_OVER = 5, CNT_DEEP = 6, CNT_UDEEP = 7, CNT_N = 8 };
-enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16 };
+enum { ERR_APEX = 1, ERR_LEVELS = 2, ERR_STACK = 4, ERR_MESH = 16, ERR_COVER = 32 };
 
 constexpr int kMaxFaceVerts = 8;
 // flux polyhedron methods (Secs. "Face-matched", "Edge-matched" and

@@ -451,6 +451,39 @@ __device__ inline bool box_overlap(d3 alo, d3 ahi, d3 blo, d3 bhi) {
   return alo.x < bhi.x && blo.x < ahi.x && alo.y < bhi.y && blo.y < ahi.y && alo.z < bhi.z && blo.z < ahi.z;
 }
 
+// Coverage of a flux polyhedron by the cells its truncation visits (the
+// owner, the neighbour and the cells sharing a vertex with either: the
+// "several cells" a flux region takes fluid from, Sec. "Fluid advected
+// through cell faces").  The polyhedron lies in the convex hull of its points,
+// so it stays within those cells when every point lies in one of their
+// closed boxes (exactly so on a Cartesian grid, whose candidates' boxes tile
+// one box).  Points outside the domain's box need no cell: no fluid is there.
+// Bit q of the result: point q of the slot layout lies in [lo, hi].  The
+// face's own vertices (q < I) lie in the owner's box and are not tested.
+__device__ inline bool in_closed_box(d3 p, d3 lo, d3 hi) {
+  return lo.x <= p.x && p.x <= hi.x && lo.y <= p.y && p.y <= hi.y && lo.z <= p.z && p.z <= hi.z;
+}
+template <class Lds>
+__device__ inline d3 slot_point(const Lds& S, int q, int I, d3 c) {
+  return q == 2 * I + 1 ? c : mk3(S.px[q], S.py[q], S.pz[q]);
+}
+template <class Lds>
+__device__ inline unsigned cover_bits(const Lds& S, int I, int np, d3 c, d3 lo, d3 hi) {
+  unsigned bits = 0;
+  for (int q = I; q < np; ++q) bits |= in_closed_box(slot_point(S, q, I, c), lo, hi) ? (1u << q) : 0u;
+  return bits;
+}
+// The points outside the domain's box (the same for every lane).
+template <class Lds>
+__device__ inline unsigned outside_bits(const DevMesh& M, const Lds& S, int f, int I, int np, d3 c) {
+  const double* db = M.dom_box + 6 * problem_of(M, M.face_pid, f);
+  return ~cover_bits(S, I, np, c, mk3(db[0], db[1], db[2]), mk3(db[3], db[4], db[5]));
+}
+// Points of the slot layout that the test covers: 2I + 2 (x, b, apex, face
+// centre), and for EMFPA the lateral centres.
+__device__ inline int slot_points(int method, int I) { return (method == kEMFPA ? 3 : 2) * I + 2; }
+__device__ inline unsigned needed_bits(int I, int np) { return ((np >= 32 ? 0u : (1u << np)) - 1u) & ~((1u << I) - 1u); }
+
 __device__ inline bool sorted_contains(const int* a, int n, int key) {
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -1019,6 +1052,15 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     }
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
+    // coverage: every point of the polyhedron in the box of a listed cell
+    // (lanes past the list hold the owner, itself listed)
+    const int npt = slot_points(METHOD, I);
+    unsigned cov = outside_bits(M, S, f, I, npt, c);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = sub + G * r;
+      cov |= cover_bits(S, I, npt, c, mk3(S.clox[j], S.cloy[j], S.cloz[j]), mk3(S.chix[j], S.chiy[j], S.chiz[j]));
+    }
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
     // the points, the face centre (the flux tets' common vertex), the lateral centres
     if (sub <= 2 * I || (em && sub >= 2 * I + 2 && sub <= 3 * I + 1)) {
@@ -1063,10 +1105,11 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       signed char kb = 0;
       if (j < L) {
         k = candidate_cell(M, j, o, ob, on, nbr, nbb);
+        klo = mk3(M.lox[k], M.loy[k], M.loz[k]);  // every listed cell's box: the coverage test
+        khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
+        cov |= cover_bits(S, I, npt, c, klo, khi);
         keep = M.tag_cell[k] != -1 && !(k == o || sorted_contains(S.onb, on, k));
         if (keep) {
-          klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
-          khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
           kb = M.isbox[k];
           keep = box_overlap(plo, phi, klo, khi);
         }
@@ -1083,6 +1126,9 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       }
       ncand += __popcll(bm);
     }
+#pragma unroll
+    for (int o2 = 1; o2 < G; o2 <<= 1) cov |= __shfl_xor(cov, o2);
+    if (sub == 0 && (cov & needed_bits(I, npt)) != needed_bits(I, npt)) atomicOr(&M.counters[CNT_ERR], ERR_COVER);
     wave_lds_sync();
     if (ncand > kPrepCand) {
       if (sub == 0) {
@@ -1786,6 +1832,20 @@ __device__ inline void overflow_faces(const DevMesh& M, FluxLds& S, const double
     const int b0 = fv_begin(M, f), I = fv_count(M, f);
     d3 c, Sv, plo, phi;
     flux_polyhedron(M, S, f, b0, I, vel, face_dt(M, f, dt), c, Sv, plo, phi);
+    {  // coverage, as in the staging kernel, over every listed cell
+      const int npt = slot_points(M.method, I);
+      const int o = M.owner[f], nbr = M.neigh[f];
+      const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
+      const int nbb = nbr >= 0 ? M.nb_ptr[nbr] : 0, nbn = nbr >= 0 ? M.nb_ptr[nbr + 1] - nbb : 0;
+      const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
+      unsigned cov = outside_bits(M, S, f, I, npt, c);
+      for (int j = lane; j < L; j += kFluxLanes) {
+        const int k = candidate_cell(M, j, o, ob, on, nbr, nbb);
+        cov |= cover_bits(S, I, npt, c, mk3(M.lox[k], M.loy[k], M.loz[k]), mk3(M.hix[k], M.hiy[k], M.hiz[k]));
+      }
+      for (int o2 = 1; o2 < kFluxLanes; o2 <<= 1) cov |= __shfl_xor(cov, o2);
+      if (lane == 0 && (cov & needed_bits(I, npt)) != needed_bits(I, npt)) atomicOr(&M.counters[CNT_ERR], ERR_COVER);
+    }
     const int ncand = flux_candidates(M, S, f, plo, phi);
     const int TF = flux_tet_count(M.method, I);
     const int total = ncand * TF;
@@ -2157,8 +2217,8 @@ __device__ inline void jacobi_rotate(double (&A)[3][3], double (&V)[3][3]) {
 // lanes per interfacial cell; k_lsfir_eig then finds the plane through the cell's PLIC centre x minimising
 // sum w_k (n.(x_k - x))^2 over the valid neighbours (interfacial cells
 // sharing a vertex whose normals are within 45 degrees), w_k = |x_k - x|^-2.5
-// (singular where two centres coincide, and a very close centre's direction
-// is set by rounding, so |d| is taken as at least 0.05 of the cell's largest
+// (a neighbour whose centre coincides with x is skipped; with the mesh's
+// optional weight floor, |d| is taken as at least 0.05 of the cell's largest
 // box extent; evaluated as 1/(d^2 sqrt(sqrt(d^2))), every operation
 // correctly rounded).  The lanes load a neighbour each; every lane then
 // accumulates the terms in neighbour order through shuffles, the order of a
@@ -2181,7 +2241,7 @@ __global__ __launch_bounds__(128) void k_lsfir_fit(DevMesh M, int pass, double c
     const d3 n = mk3(M.pnx[c], M.pny[c], M.pnz[c]);
     const d3 x = mk3(M.lsfir_xc[c], M.lsfir_xc[nc + c], M.lsfir_xc[2 * nc + c]);
     const double hc = fmax(fmax(M.hix[c] - M.lox[c], M.hiy[c] - M.loy[c]), M.hiz[c] - M.loz[c]);
-    const double dmin2 = (0.05 * hc) * (0.05 * hc);
+    const double dmin2 = M.lsfir_cap ? (0.05 * hc) * (0.05 * hc) : 0.0;
     const int nb0 = M.nb_ptr[c], nnb = M.nb_ptr[c + 1] - nb0;
     double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     int nvalid = 0;

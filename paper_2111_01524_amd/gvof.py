@@ -20,6 +20,7 @@ GVOF_OK, GVOF_E_ARG, GVOF_E_MESH, GVOF_E_NOMEM, GVOF_E_HIP, GVOF_E_GEOM, GVOF_E_
 GVOF_SHAPE_SPHERE, GVOF_SHAPE_PLANE = 0, 1
 GVOF_FLAG_NONE, GVOF_FLAG_EMFPA, GVOF_FLAG_NMFPA, GVOF_FLAG_LSFIR = 0, 1, 2, 4
 GVOF_FLAG_LLCIR, GVOF_FLAG_ELCIR, GVOF_FLAG_CLCIR = 8, 16, 32
+GVOF_FLAG_LSFIR_CAP = 64
 RECON_FLAGS = {"lsgir": 0, "lsfir": GVOF_FLAG_LSFIR, "llcir": GVOF_FLAG_LLCIR, "elcir": GVOF_FLAG_ELCIR,
                "clcir": GVOF_FLAG_CLCIR}
 GVOF_MAX_LSFIR_OUTER = 32
@@ -310,10 +311,12 @@ def gvof_last_error(h=None) -> str:
 
 
 # ------------------------------------------------------------------ convenience wrapper
-def _with_method(params, method: str, recon: str = "lsgir", lsfir_outer: int | None = None):
+def _with_method(params, method: str, recon: str = "lsgir", lsfir_outer: int | None = None,
+                 lsfir_tol: float | None = None, lsfir_cap: bool = False):
     """params with the flags of a flux polyhedron method and of a
-    reconstruction set ("fmfpa" / "lsgir": unchanged); lsfir_outer, when
-    given, sets the LSFIR outer passes."""
+    reconstruction set ("fmfpa" / "lsgir": unchanged); lsfir_outer and
+    lsfir_tol, when given, set the LSFIR outer passes and stopping angle;
+    lsfir_cap sets GVOF_FLAG_LSFIR_CAP."""
     if method not in METHOD_FLAGS:
         raise ValueError(f"unknown flux polyhedron method {method!r}")
     if recon not in RECON_FLAGS:
@@ -322,8 +325,13 @@ def _with_method(params, method: str, recon: str = "lsgir", lsfir_outer: int | N
         return params
     params = params if params is not None else gvof_params_default()
     params.flags |= METHOD_FLAGS[method] | RECON_FLAGS[recon]
-    if recon == "lsfir" and lsfir_outer is not None:
-        params.lsfir_outer = int(lsfir_outer)
+    if recon == "lsfir":
+        if lsfir_outer is not None:
+            params.lsfir_outer = int(lsfir_outer)
+        if lsfir_tol is not None:
+            params.lsfir_tol = float(lsfir_tol)
+        if lsfir_cap:
+            params.flags |= GVOF_FLAG_LSFIR_CAP
     return params
 
 
@@ -333,13 +341,15 @@ class GvofMesh:
     method "emfpa" / "nmfpa" sets GVOF_FLAG_EMFPA / GVOF_FLAG_NMFPA in the
     parameters (the flux polyhedron method), recon "lsfir" / "llcir" /
     "elcir" / "clcir" sets that reconstruction's flag (LSFIR with lsfir_outer
-    passes when given); "fmfpa" and "lsgir" leave the flags as given.
+    passes, lsfir_tol and the optional weight floor lsfir_cap when given);
+    "fmfpa" and "lsgir" leave the flags as given.
     """
 
     def __init__(self, mesh, device="cuda", params: gvof_params | None = None, stream=None, handle=None,
-                 method: str = "fmfpa", recon: str = "lsgir", lsfir_outer: int | None = None):
+                 method: str = "fmfpa", recon: str = "lsgir", lsfir_outer: int | None = None,
+                 lsfir_tol: float | None = None, lsfir_cap: bool = False):
         import torch
-        params = _with_method(params, method, recon, lsfir_outer)
+        params = _with_method(params, method, recon, lsfir_outer, lsfir_tol, lsfir_cap)
         self.torch = torch
         self.device = torch.device(device)
         self.mesh = mesh

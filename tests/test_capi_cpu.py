@@ -226,7 +226,7 @@ def test_flags_select_the_flux_polyhedron_method():
         gvof.gvof_mesh_destroy(a)
         gvof.gvof_mesh_destroy(b)
         gvof.gvof_mesh_destroy(c)
-    for bad in (64, 0x80000000, 3, 4 | 8, 8 | 32, 16 | 32):
+    for bad in (128, 0x80000000, 3, 4 | 8, 8 | 32, 16 | 32):
         p = gvof.gvof_params_default()
         p.flags = bad
         with pytest.raises(gvof.GvofError) as e:
@@ -236,17 +236,20 @@ def test_flags_select_the_flux_polyhedron_method():
 
 def test_lsfir_settings():
     """GVOF_FLAG_LSFIR takes 1..GVOF_MAX_LSFIR_OUTER outer passes and a finite
-    tolerance >= 0, adds the PLIC-centre and fitted-normal buffers to the
-    workspace, and combines with any flux polyhedron method; batches need
-    equal settings."""
+    tolerance >= 0 (by default the paper's test settings, 4 passes and
+    1e-3 rad: Sec. "Test programs and performance analysis"), adds the
+    PLIC-centre and fitted-normal buffers to the workspace, and combines with
+    any flux polyhedron method and with the optional weight floor; batches
+    need equal settings."""
     m = inputs.cartesian_mesh(4)
     d = gvof.gvof_params_default()
-    assert d.lsfir_outer == 1 and d.lsfir_tol == 0.0
+    assert d.lsfir_outer == 4 and d.lsfir_tol == 1e-3
     base = gvof.gvof_mesh_create(*m.arrays(), m.nc)
     handles = [base]
     try:
         for flags in (gvof.GVOF_FLAG_LSFIR, gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_EMFPA,
-                      gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_NMFPA):
+                      gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_NMFPA,
+                      gvof.GVOF_FLAG_LSFIR | gvof.GVOF_FLAG_LSFIR_CAP):
             p = gvof.gvof_params_default()
             p.flags = flags
             p.lsfir_outer = gvof.GVOF_MAX_LSFIR_OUTER

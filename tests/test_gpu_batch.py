@@ -212,3 +212,33 @@ def test_batch_workload_sample_equals_alone(oracle_mod, gv):
     F1 = to_dev(torch, dev, F0)
     B.step(uf, uv, dt_row(torch, dev, P, 0), act, F1)
     assert max_abs(host(F1)[B.cells(small)], Fn) <= 1e-12
+
+
+def test_batch_workload_sample_matches_oracle(oracle_mod, gv):
+    """All twelve problems of the workload sample (sides 16..48, both grid
+    kinds, their own spheres, periods and time steps) against the oracle over
+    two steps, teacher-forced per problem, under autotuned launch shapes."""
+    specs = inputs.batch_problem_specs()[:12]
+    torch, dev, P, B, uf, uv = build(gv, specs)
+    log(f"workload sample vs oracle: nf={B.nf} nc={B.nc} sides={[s['side'] for s in specs]}")
+    act = to_dev(torch, dev, np.ones(len(P), np.uint8))
+    oms = [oracle_mod.OracleMesh(p["mesh"]) for p in P]
+    Fo = [om.init_fraction("sphere", p["shape"][1], 10) for om, p in zip(oms, P)]
+    F = to_dev(torch, dev, np.concatenate(Fo))
+    cfg, ms = B.autotune(uf, uv, dt_row(torch, dev, P, 0), act, F, reps=2)
+    log(f"autotuned {cfg.as_dict()} {ms:.3f} ms/step")
+    for s in range(2):
+        F = to_dev(torch, dev, np.concatenate(Fo))
+        B.step(uf, uv, dt_row(torch, dev, P, s), act, F)
+        Fb = host(F)
+        nxt = []
+        for q, (om, p) in enumerate(zip(oms, P)):
+            Fc, Fs, tn, tf, tc, pl = om.reconstruct(Fo[q])
+            Fn, Vd, VF, up, bad = om.advect(pl, tc, tf, p["uf"], p["uv"], p["dt_eff"][min(s, p["nsteps"] - 1)], Fc)
+            assert bad == 0
+            err = max_abs(Fb[B.cells(q)], Fn)
+            log(f"step {s} problem {q} ({specs[q]['kind']} {specs[q]['side']}): max |dF| = {err:.3g}")
+            assert err <= 1e-12, (s, q)
+            nxt.append(Fn)
+        Fo = nxt
+    B.status()

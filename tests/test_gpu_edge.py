@@ -43,13 +43,9 @@ def _parity_steps(oracle_mod, gv, m, uf, uv, dts, F, label, method="fmfpa", reco
         Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
         assert np.array_equal(host(tags), tc) and np.array_equal(host(Fd), Fc)
         sel = tc == 0
-        # LSFIR's fit and the isosurface rings amplify the rounding of the PLIC
-        # centres and node values they are built from (most on coarse meshes with
-        # non-planar faces): their planes are compared at 1e-11, the fractions
-        # below at the 1e-12 bar as everywhere
-        ptol = 1e-12 if recon == "lsgir" else 1e-11
-        if sel.any():
-            assert np.abs(host(planes)[:, sel] - pl[:, sel]).max() <= ptol
+        dpl = float(np.abs(host(planes)[:, sel] - pl[:, sel]).max()) if sel.any() else 0.0
+        log(f"{label} step {s}: max|d plane| = {dpl:.2e}")
+        assert dpl <= 1e-12
         Fout = torch.empty_like(Fd)
         up_g, vd_g, vf_g = g.advect_step(ufd, uvd, dt, Fd, Fout, want_faces=True)
         F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dt, Fc)

@@ -345,20 +345,22 @@ def test_plic_centre_exact_on_general_cells(oracle_mod):
         assert np.abs(xc[:, c] - want).max() <= 2e-16, c
 
 
-def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod):
+@pytest.mark.parametrize("cap", [False, True])
+def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod, cap):
     """The fit against numpy.linalg.eigh of the weighted scatter matrix of the
     valid neighbours' PLIC centres (vertex-sharing interfacial cells within
-    45 degrees, w = |d|^-2.5 with |d| taken as at least 0.05 of the cell's
-    largest box extent), on a sphere on the distorted grid."""
+    45 degrees), on a sphere on the distorted grid: with the section's weight
+    w = |d|^-2.5 (a coincident centre skipped), and with the optional floor
+    that takes |d| as at least 0.05 of the cell's largest box extent."""
     m = inputs.jittered_mesh(10, seed=2)
-    om = oracle_mod.OracleMesh(m)
+    om = oracle_mod.OracleMesh(m, lsfir_cap=cap)
     F = om.init_fraction("sphere", [0.525, 0.464, 0.516, 0.325], 6)
     Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
     xc, cnt = om.plic_centres(tc, pl)
     fit, nvalid = om.lsfir_fit(tc, pl[:3], xc)
     ptr, idx = om.neighbours()
     geo = om.geometry()
-    checked = 0
+    checked = floored = 0
     for c in np.where(tc == 0)[0]:
         A = np.zeros((3, 3)); k_ok = 0
         hc = (geo["bbmax"][:, c] - geo["bbmin"][:, c]).max()
@@ -366,7 +368,11 @@ def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod):
             if tc[k] != 0 or not pl[:3, c] @ pl[:3, k] > np.sqrt(0.5):
                 continue
             d = xc[:, k] - xc[:, c]
-            A += max(np.linalg.norm(d), 0.05 * hc) ** -2.5 * np.outer(d, d)
+            dn = np.linalg.norm(d)
+            if dn == 0.0:
+                continue
+            floored += dn < 0.05 * hc
+            A += (max(dn, 0.05 * hc) if cap else dn) ** -2.5 * np.outer(d, d)
             k_ok += 1
         assert nvalid[c] == k_ok
         if k_ok < 2:
@@ -379,6 +385,7 @@ def test_lsfir_fit_is_the_weighted_smallest_eigenvector(oracle_mod):
         assert np.abs(fit[:, c] - e).max() <= 1e-12 * lam[2] / (lam[1] - lam[0]), c
         checked += 1
     assert checked > 100
+    assert floored > 0  # the sample has centres closer than 0.05 h, where the two weights differ
 
 
 def test_lsfir_exact_for_a_planar_interface(oracle_mod):
@@ -423,29 +430,40 @@ def test_lsfir_converges_faster_than_lsgir(oracle_mod, kind):
     assert err["lsfir", 40] < 0.7 * err["lsgir", 40], err
 
 
-def test_lsfir_outer_iteration_as_described(oracle_mod):
-    """Three outer passes rebuilt here from the oracle's pieces, following the
+@pytest.mark.parametrize("outer,tol", [(3, 0.0), (4, 1e-3), (8, 0.25)])
+def test_lsfir_outer_iteration_as_described(oracle_mod, outer, tol):
+    """Outer passes rebuilt here from the oracle's pieces, following the
     section: centres of the current planes, a fit per cell, adoption where the
     fit turns the normal by less than 30/I_out degrees, all cells at once,
-    then planes placed to match F; equal to the oracle's reconstruction."""
+    then planes placed to match F; repeated until a pass turns no normal by
+    the tolerance or more, or n_out passes (the paper's tests: 4 and 1e-3 rad);
+    equal to the oracle's reconstruction.  The last case stops early."""
     m = inputs.jittered_mesh(8, seed=5)
     om0 = oracle_mod.OracleMesh(m)
-    om3 = oracle_mod.OracleMesh(m, recon="lsfir", lsfir_outer=3)
+    omk = oracle_mod.OracleMesh(m, recon="lsfir", lsfir_outer=outer, lsfir_tol=tol)
     F = om0.init_fraction("sphere", [0.5, 0.48, 0.52, 0.3], 6)
     Fc, Fs, tn, tf, tc, pl = om0.reconstruct(F)
     sel = tc == 0
     nrm = pl[:3].copy()
     C = pl[3].copy()
-    for it in (1, 2, 3):
+    passes = 0
+    for it in range(1, outer + 1):
         xc, _ = om0.plic_centres(tc, np.vstack([nrm, C]))
         fit, _ = om0.lsfir_fit(tc, nrm, xc)
         take = sel & ((fit * nrm).sum(0) > np.cos(np.pi / 6 / it))
-        nrm = np.where(take[None, :], fit, nrm)
+        new = np.where(take[None, :], fit, nrm)
+        turned = int((sel & ((new * nrm).sum(0) < np.cos(tol))).sum())
+        nrm = new
         C = np.where(sel, om0.plane_constant(Fc, tc, nrm), 0.0)
-    Fc3, _, _, _, tc3, pl3 = om3.reconstruct(F)
-    assert np.array_equal(tc3, tc)
-    assert np.array_equal(pl3[:3], nrm) and np.array_equal(pl3[3], C)
-    assert np.abs(pl3[:3, sel] - pl[:3, sel]).max() > 1e-3  # the passes did change normals
+        passes = it
+        if turned == 0:
+            break
+    Fck, _, _, _, tck, plk = omk.reconstruct(F)
+    assert np.array_equal(tck, tc)
+    assert np.array_equal(plk[:3], nrm) and np.array_equal(plk[3], C)
+    assert np.abs(plk[:3, sel] - pl[:3, sel]).max() > 1e-3  # the passes did change normals
+    if tol == 0.25:
+        assert passes == 1 < outer  # no normal turns by 0.25 rad in the first pass
 
 
 def test_plane_constant_nearly_full_and_empty_corner(oracle_mod):
@@ -968,3 +986,49 @@ def test_zero_step_and_empty_field_invariants(oracle_mod):
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     Z1, *_ = om.advect(zp, zc, zf, uf, uv, dt, Zc)
     assert not Z1.any()
+
+
+@pytest.mark.parametrize("U,cfl", [((1.0, 0.5, -0.25), 0.9), ((1.0, 0.5, -0.25), 2.5), ((0.3, 1.0, 0.6), 1.6),
+                                   ((-0.7, 0.4, 1.0), 1.2)])
+def test_flux_coverage_check_cartesian(oracle_mod, U, cfl):
+    """The coverage check (Sec. "Fluid advected through cell faces": the flux
+    region takes fluid from several cells, and the truncation visits the
+    owner, the neighbour and the cells sharing a vertex with either) against
+    the geometry of a Cartesian grid, where those cells tile one box R: under
+    a uniform velocity the FMFPA polyhedron is the swept prism with back
+    vertices x - dt u and apex c - dt u, and a face is flagged exactly when
+    one of these points lies inside the domain but outside R.  Below CFL 1
+    nothing is flagged; the larger steps flag faces."""
+    n = 6
+    m = inputs.cartesian_mesh(n)
+    om = oracle_mod.OracleMesh(m)
+    geo = om.geometry()
+    lo, hi = geo["bbmin"], geo["bbmax"]
+    dt = cfl * (1.0 / n) / max(abs(u) for u in U)
+    uf, uv = inputs.velocity_uniform(m, U)
+    got = om.coverage(np.zeros(m.nf, np.int8), uf, uv, dt)
+    X = np.stack([m.vx, m.vy, m.vz])
+    u = np.array(U)
+    want = np.zeros(m.nf, np.int8)
+    for f in range(m.nf):
+        o, nb = m.owner[f], m.neigh[f]
+        vd = dt * (u @ geo["S"][:, f])
+        if nb < 0 and vd < 0:
+            continue  # inflow boundary: no polyhedron
+        near = [o] + ([nb] if nb >= 0 else [])
+        # cells sharing a vertex with the owner or the neighbour: closed boxes that meet theirs
+        touch = np.zeros(m.nc, bool)
+        for c in near:
+            touch |= np.all((lo <= hi[:, c:c + 1] + 1e-12) & (lo[:, c:c + 1] <= hi + 1e-12), axis=0)
+        Rlo, Rhi = lo[:, touch].min(axis=1), hi[:, touch].max(axis=1)
+        xs = X[:, m.fv_idx[m.fv_ptr[f]:m.fv_ptr[f + 1]]]
+        cf = geo["fc"][:, f]
+        pts = np.concatenate([xs, xs - dt * u[:, None], cf[:, None], (cf - dt * u)[:, None]], axis=1)
+        inside_dom = np.all((pts >= 0.0) & (pts <= 1.0), axis=0)
+        in_R = np.all((pts >= Rlo[:, None] - 1e-13) & (pts <= Rhi[:, None] + 1e-13), axis=0)
+        want[f] = 1 if np.any(inside_dom & ~in_R) else 0
+    assert np.array_equal(got, want), (int(got.sum()), int(want.sum()))
+    if cfl < 1.0:
+        assert not got.any()
+    else:
+        assert got.sum() > 20
