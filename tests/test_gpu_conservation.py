@@ -93,7 +93,7 @@ def test_distorted_trajectory_scheme_identity(method):
     n, T_end = 64, 3.0
     m = inputs.jittered_mesh(n, seed=1)
     g = gvof.GvofMesh(m, dev, method=method)
-    Vt = torch.from_numpy(g.geometry()["V"]).to(dev)
+    Vt = g.geometry()["V"]
     uf, uv = inputs.velocity_enright(m)
     dt = inputs.cfl_dt(m, np.abs(uf).max(axis=1), 0.5)
     sched = inputs.step_schedule(T_end, dt)
