@@ -228,6 +228,27 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
                      double* F_out, int32_t* upwind_out, double* vd_out, double* vf_out);
 
 /*
+ * gvof_advect_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, the same results bit for bit, the same errors.  The
+ * step's flux staging (polyhedron slots, (face, cell, flux tetrahedron)
+ * pairs, general-cell units, the overflow and deferred lists and the region
+ * counters) lives in a 16 MiB device array inside the library instead of the
+ * mesh's workspace: one array on each GPU the library runs on, held until the
+ * process ends.  Faces and pairs that do not fit it are computed by the
+ * overflow and deferred kernels, with the same values.  Each call clears the
+ * array's counters first; every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads) race.  The
+ * current device must be the mesh's (the current device at gvof_mesh_bind;
+ * GVOF_E_ARG otherwise).  A mesh whose overflow list does not fit the array
+ * (more than about 3.4 million faces) is rejected with GVOF_E_LIMIT before
+ * anything is enqueued.  Calls no hipMalloc, hipFree or allocating routine.
+ */
+int gvof_advect_step_static(gvof_mesh* m, const double* u_face, const double* u_vert, double dt,
+                            const double* F_in, double* F_out, int32_t* upwind_out, double* vd_out,
+                            double* vf_out);
+
+/*
  * Number of interfacial cells of the last reconstruction and of faces needing
  * flux polyhedra in the last advection (0 when a reconstruction came after
  * it).  Synchronous (reads two device counters).

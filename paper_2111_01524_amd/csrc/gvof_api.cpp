@@ -89,6 +89,7 @@ struct gvof_mesh {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
+  int device = -1;  // current device at bind
   DevMesh dm{};
   bool bound = false, reconstructed = false;
   bool advect_state_clear = false;  // a reconstruction cleared the step counters and no advection used them yet
@@ -512,6 +513,51 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   if (dm) *dm = d;
   return (C.off + 255) & ~size_t(255);
 }
+
+// The flux staging of one advection step carved from `bytes` at `base` (the
+// static staging array) into d: the region counters, the list of faces left
+// to the overflow kernel (one entry per face of the mesh), then polyhedron
+// slots, (face, cell, flux tet) pairs and general-cell units, which share the
+// rest (slots an eighth; units half when the mesh has general cells).
+// Returns the bytes the smallest such layout needs; it fits when that is at
+// most `bytes`.
+size_t carve_static(const gvof_mesh* m, DevMesh& d, char* base, size_t bytes) {
+  constexpr size_t R = gvof::kItemRegions;
+  const size_t nf = m->nf;
+  const bool gen = m->gen_faces != 0;
+  const size_t slot_b = (size_t)d.pts_per_slot * 24 + 8, pair_b = 30, unit_b = 20;
+  const size_t fixed = R * sizeof(gvof::RegionCounters) + 4 * nf + 16 * 256;  // alignment slack included
+  const size_t min_slots = std::min<size_t>(nf, 256), min_pairs = R * 256, min_units = gen ? R * 256 : R;
+  const size_t need = fixed + min_slots * slot_b + min_pairs * pair_b + min_units * unit_b;
+  if (need > bytes) return need;
+  const size_t rest = bytes - fixed;
+  size_t slots = std::max(min_slots, std::min(nf, rest / 8 / slot_b));
+  if (rest - slots * slot_b < min_pairs * pair_b + min_units * unit_b) slots = min_slots;
+  const size_t left = rest - slots * slot_b;
+  const size_t units = gen ? std::max(min_units, ((left - min_pairs * pair_b) / 2 / unit_b) / R * R) : min_units;
+  const size_t pairs = ((left - units * unit_b) / pair_b) / R * R;  // >= min_pairs
+  Carver C{base};
+  d.regions = C.take<gvof::RegionCounters>(R);
+  d.list_over = C.take<int>(nf);
+  d.poly_cap = (int)slots;
+  d.poly = C.take<double>(slots * d.pts_per_slot * 3);
+  d.item_off = C.take<int>(slots);
+  d.item_cnt = C.take<int>(slots);
+  d.item_cap = (int)pairs;
+  d.item_slot = C.take<int>(pairs);
+  d.item_cell = C.take<int>(pairs);
+  d.item_tm = C.take<unsigned short>(pairs);
+  d.item_vol = C.take<double>(pairs);
+  d.list_deep = C.take<int>(pairs);
+  d.item_uoff = C.take<int>(pairs);
+  d.item_ucnt = C.take<int>(pairs);
+  d.unit_cap = (int)units;
+  d.unit_item = C.take<int>(units);
+  d.unit_code = C.take<unsigned>(units);
+  d.unit_vol = C.take<double>(units);
+  d.list_udeep = C.take<int>(units);
+  return C.off <= bytes ? need : bytes + 1;
+}
 }  // namespace
 
 extern "C" {
@@ -531,6 +577,7 @@ int gvof_mesh_bind(gvof_mesh* m, void* ws, size_t ws_bytes, void* stream) {
   m->ws = static_cast<char*>(ws);
   m->ws_bytes = ws_bytes;
   m->stream = static_cast<hipStream_t>(stream);
+  HIPCHECK(m, hipGetDevice(&m->device));
   carve(m, m->ws, &m->dm);
   DevMesh& d = m->dm;
   hipStream_t s = m->stream;
@@ -708,6 +755,35 @@ int gvof_advect_step(gvof_mesh* m, const double* u_face, const double* u_vert, d
   m->prof.stream = m->stream;
   HIPCHECK(m, gvof::launch_advect(m->dm, u_face, u_vert, dt, F_in, F_out, m->cfg, m->stream,
                                   m->prof.mask ? &m->prof : nullptr, !m->advect_state_clear));
+  m->advect_state_clear = false;
+  if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
+  if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;
+  return d2d(m, vf_out, m->dm.VF, (size_t)m->nf * 8);
+}
+
+int gvof_advect_step_static(gvof_mesh* m, const double* u_face, const double* u_vert, double dt, const double* F_in,
+                            double* F_out, int32_t* upwind_out, double* vd_out, double* vf_out) {
+  int r = need_bound(m);
+  if (r) return r;
+  if (!m->reconstructed) return fail(m, GVOF_E_ARG, "gvof_advect_step_static needs a preceding gvof_reconstruct");
+  const bool nm = (m->p.flags & GVOF_FLAG_NMFPA) != 0;
+  if (!u_face || (!u_vert && !nm) || !F_in || !F_out) return fail(m, GVOF_E_ARG, "NULL array argument");
+  if (!std::isfinite(dt)) return fail(m, GVOF_E_ARG, "dt is not finite");
+  int dev = -1;
+  HIPCHECK(m, hipGetDevice(&dev));
+  if (dev != m->device) return fail(m, GVOF_E_ARG, "current device %d is not the mesh's device %d", dev, m->device);
+  void* base = nullptr;
+  size_t bytes = 0;
+  HIPCHECK(m, gvof::static_scratch(&base, &bytes));
+  DevMesh d = m->dm;
+  const size_t need = carve_static(m, d, static_cast<char*>(base), bytes);
+  if (need > bytes)
+    return fail(m, GVOF_E_LIMIT, "mesh of %d faces needs %zu bytes of static staging, more than the %zu the library holds "
+                "(use gvof_advect_step)", m->nf, need, bytes);
+  m->prof.stream = m->stream;
+  // the static array keeps the last call's contents: the step clears its region counters first
+  HIPCHECK(m, gvof::launch_advect(d, u_face, u_vert, dt, F_in, F_out, m->cfg, m->stream,
+                                  m->prof.mask ? &m->prof : nullptr, true));
   m->advect_state_clear = false;
   if ((r = d2d(m, upwind_out, m->dm.upwind, (size_t)m->nf * 4))) return r;
   if ((r = d2d(m, vd_out, m->dm.Vd, (size_t)m->nf * 8))) return r;

@@ -10,6 +10,8 @@
 // reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "clip.h"
 #include "gvof_dev.h"
 #include "gvof_launch.h"
@@ -2846,6 +2848,36 @@ hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, do
   k_init_classify<<<blocks_for(M.nc, 256), 256, 0, s>>>(M, sh, F);
   k_init_refine<<<blocks_for(M.nc, 1, 4096), 64, 0, s>>>(M, sh, ndiv, F);
   return hipGetLastError();
+}
+
+// ============================================================== static staging
+// The flux staging of gvof_advect_step_static lives in this file-scope array
+// instead of the mesh's workspace: one copy on each GPU the library runs on,
+// held until the process ends.  In host code the array's name is only a
+// stand-in for the symbol: its device address comes from hipGetSymbolAddress,
+// resolved once per device with that device current, and only that address
+// is handed to kernels.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
 }
 
 }  // namespace gvof

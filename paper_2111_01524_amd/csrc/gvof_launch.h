@@ -51,4 +51,7 @@ hipError_t launch_advect(const DevMesh& M, const double* uf, const double* uv, d
 hipError_t launch_face_tags(const DevMesh& M, hipStream_t s);
 hipError_t launch_tri_cache(const DevMesh& M, hipStream_t s);
 hipError_t launch_init(const DevMesh& M, int kind, const double* p, int ndiv, double* F, hipStream_t s);
+// Device address and size of the library's static staging array on the
+// current device (resolved on the first call on each device).
+hipError_t static_scratch(void** ptr, size_t* bytes);
 }  // namespace gvof

@@ -81,6 +81,7 @@ def lib() -> C.CDLL:
         L.gvof_reconstruct.argtypes = [_vp, _vp, _vp, _vp]
         L.gvof_get_tags.argtypes = [_vp] * 5
         L.gvof_advect_step.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _vp]
+        L.gvof_advect_step_static.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _vp]
         L.gvof_interface_counts.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.gvof_status.argtypes = [_vp]
         L.gvof_last_error.argtypes = [_vp]
@@ -101,8 +102,8 @@ def lib() -> C.CDLL:
         L.gvof_autotune.argtypes = [_vp] * 7 + [C.c_int32, C.POINTER(gvof_launch_config), C.POINTER(C.c_double)]
         for name in ("gvof_mesh_create", "gvof_mesh_workspace_bytes", "gvof_mesh_bind", "gvof_set_stream",
                      "gvof_mesh_sizes", "gvof_get_geometry", "gvof_init_fraction", "gvof_reconstruct",
-                     "gvof_get_tags", "gvof_advect_step", "gvof_interface_counts", "gvof_status",
-                     "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_batch_create",
+                     "gvof_get_tags", "gvof_advect_step", "gvof_advect_step_static", "gvof_interface_counts",
+                     "gvof_status", "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_batch_create",
                      "gvof_batch_offsets", "gvof_batch_init_fraction", "gvof_batch_step", "gvof_graph_capture",
                      "gvof_graph_launch", "gvof_get_launch_config", "gvof_set_launch_config", "gvof_autotune"):
             getattr(L, name).restype = C.c_int
@@ -118,7 +119,7 @@ def exported_symbols():
             "gvof_last_error", "gvof_work_totals", "gvof_profile_enable", "gvof_profile_read", "gvof_kernel_name",
             "gvof_batch_create", "gvof_batch_offsets", "gvof_batch_init_fraction", "gvof_batch_step",
             "gvof_graph_capture", "gvof_graph_launch", "gvof_get_launch_config", "gvof_set_launch_config",
-            "gvof_autotune"]
+            "gvof_autotune", "gvof_advect_step_static"]
 
 
 def _check(code, handle=None):
@@ -212,6 +213,11 @@ def gvof_get_tags(h, node_value=None, node_tag=None, face_tag=None, cell_tag=Non
 def gvof_advect_step(h, u_face, u_vert, dt, F_in, F_out, upwind_out=None, vd_out=None, vf_out=None):
     _check(lib().gvof_advect_step(h, _ptr(u_face), _ptr(u_vert), float(dt), _ptr(F_in), _ptr(F_out),
                                   _ptr(upwind_out), _ptr(vd_out), _ptr(vf_out)), h)
+
+
+def gvof_advect_step_static(h, u_face, u_vert, dt, F_in, F_out, upwind_out=None, vd_out=None, vf_out=None):
+    _check(lib().gvof_advect_step_static(h, _ptr(u_face), _ptr(u_vert), float(dt), _ptr(F_in), _ptr(F_out),
+                                         _ptr(upwind_out), _ptr(vd_out), _ptr(vf_out)), h)
 
 
 def gvof_interface_counts(h):
@@ -416,6 +422,11 @@ class GvofMesh:
             vf = self.dzeros(self.nf)
         gvof_advect_step(self.h, u_face, u_vert, dt, F_in, F_out, up, vd, vf)
         return up, vd, vf
+
+    def advect_step_static(self, u_face, u_vert, dt, F_in, F_out, up=None, vd=None, vf=None):
+        """gvof_advect_step_static: the step with its staging in the library's
+        static array; optional outputs are caller-allocated device tensors."""
+        gvof_advect_step_static(self.h, u_face, u_vert, dt, F_in, F_out, up, vd, vf)
 
     def interface_counts(self):
         return gvof_interface_counts(self.h)
