@@ -333,7 +333,9 @@ int gvof_graph_launch(gvof_mesh* m);
  *   recon_threads           block size of the reconstruction kernel (64 or 128)
  *   prep_blocks             grid of the flux-polyhedron staging kernel, blocks of one wavefront (1..2^20)
  *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256)
- *   filter_lanes            lanes per (face, cell, flux tetrahedron) pair in the general-cell filter (8, 16, 32, 64)
+ *   filter_lanes            general-cell filter: 0 takes each run of a face's pairs with one cell together
+ *                           (32 lanes, the default); 8, 16, 32, 64 give each (face, cell, flux tetrahedron)
+ *                           pair that many lanes.  Every choice gives the same units.
  *   staged_faces            most faces whose flux work is staged per step (0: as many as the workspace
  *                           holds); the others are computed whole by the overflow kernel, with the same
  *                           values.  Not tuned by gvof_autotune.

@@ -462,7 +462,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
     // computed whole by the deferred kernel)
     d.unit_cap = m->gen_faces == 0
                      ? gvof::kItemRegions
-                     : (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 6 * (size_t)m->gen_faces));
+                     : (int)std::min<size_t>(size_t(1) << 30, std::max<size_t>(size_t(1) << 22, 8 * (size_t)m->gen_faces));
     d.unit_cap -= d.unit_cap % gvof::kItemRegions;
   }
   d.poly = C.take<double>((size_t)d.poly_cap * d.pts_per_slot * 3);
@@ -1066,8 +1066,9 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
     return fail(m, GVOF_E_ARG, "prep_blocks=%d (1..2^20)", c->prep_blocks);
   if (c->pair_blocks_per_region < 1 || c->pair_blocks_per_region > 256)
     return fail(m, GVOF_E_ARG, "pair_blocks_per_region=%d (1..256)", c->pair_blocks_per_region);
-  if (c->filter_lanes != 8 && c->filter_lanes != 16 && c->filter_lanes != 32 && c->filter_lanes != 64)
-    return fail(m, GVOF_E_ARG, "filter_lanes=%d (8, 16, 32 or 64)", c->filter_lanes);
+  if (c->filter_lanes != 0 && c->filter_lanes != 8 && c->filter_lanes != 16 && c->filter_lanes != 32 &&
+      c->filter_lanes != 64)
+    return fail(m, GVOF_E_ARG, "filter_lanes=%d (0, 8, 16, 32 or 64)", c->filter_lanes);
   if (c->staged_faces < 0) return fail(m, GVOF_E_ARG, "staged_faces=%d (>= 0)", c->staged_faces);
   if (c->staged_pairs < 0) return fail(m, GVOF_E_ARG, "staged_pairs=%d (>= 0)", c->staged_pairs);
   if (c->prep_lanes != 32 && c->prep_lanes != 64)
@@ -1131,7 +1132,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   // coordinate descent over the launch shapes, each with the others fixed
   const int prep[] = {4096, 8192, 16384, 32768};
   const int pbr[] = {4, 8, 16, 32, 64};
-  const int lanes[] = {8, 16, 32, 64};
+  const int lanes[] = {0, 8, 16, 32, 64};
   const int sweep[] = {128, 256, 512, 1024};
   const int recon[] = {64, 128};
   const int plan[] = {64, 32};
@@ -1153,7 +1154,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   if ((r = sweep_param(&gvof::LaunchCfg::prep_lanes, plan, 2))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::prep_blocks, prep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::pair_blocks_per_region, pbr, 5))) return r;
-  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 4))) return r;
+  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 5))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::sweep_threads, sweep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::recon_threads, recon, 2))) return r;
   m->cfg = cur;

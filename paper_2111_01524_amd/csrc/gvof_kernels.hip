@@ -796,6 +796,77 @@ __device__ inline int flux_candidates(const DevMesh& M, FluxLds& S, int f, d3 pl
   return ncand;
 }
 
+// Pairs with a general cell: which of the cell's surface tetrahedra (sigma)
+// can share volume with the flux tet T, and how that volume is clipped.
+// Every path (the staged filters, the deferred and overflow kernels) applies
+// the same rule, so each unit set, each unit's value and hence each pair's sum
+// are the same whichever path computes them:
+//  - a sigma counts when its box meets T's, it is not flat, T is not entirely
+//    outside one of its face planes, and it is not entirely outside one face
+//    plane of T (then only a plane is common to both);
+//  - the unit's volume vol(T ∩ sigma ∩ H) is found by clipping one of the two
+//    by the face planes of the other that cut it: sigma by T's when fewer of
+//    T's planes cut sigma than sigma's cut T, else T by sigma's.
+// Unit word: the mask of the cutting planes (bits 0-3), whether the first of
+// them keeps three tetrahedra (kUnitWideBit, a hint for grouping units of like
+// work), and whether sigma is the one clipped (kUnitFlipBit).  Tc holds T's
+// inward face planes and sc[l] the distance of the cell's vertex mean (the
+// apex of every sigma) from plane l; the planes of sigma are those of
+// tet_container(cc, t0, t1, t2), the planes of T those of
+// tet_container(T.p0, T.p1, T.p2, T.p3).
+constexpr int kUnitWideBit = 4;
+constexpr int kUnitFlipBit = 5;
+__device__ inline unsigned wide_bit(double s0, double s1, double s2, double s3) {
+  return (s0 > 0.0) + (s1 > 0.0) + (s2 > 0.0) + (s3 > 0.0) >= 2 ? 1u : 0u;
+}
+__device__ inline bool unit_rule(const Tet& T, d3 tlo, d3 thi, const TetCont& Tc, const double (&sc)[4], d3 cc, d3 t0,
+                                 d3 t1, d3 t2, unsigned& word) {
+  word = 0;
+  if (!box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2))) ||
+      det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0)
+    return false;
+  const TetCont TC = tet_container(cc, t0, t1, t2);
+  unsigned cm = 0, wa = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {  // sigma's planes against T
+    const Plane P = TC.plane(l);
+    const double s0 = P.dist(T.p0), s1 = P.dist(T.p1), s2 = P.dist(T.p2), s3 = P.dist(T.p3);
+    if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
+    if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+      if (cm == 0u) wa = wide_bit(s0, s1, s2, s3);
+      cm |= 1u << l;
+    }
+  }
+  unsigned rm = 0, wb = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {  // T's planes against sigma
+    const Plane P = Tc.plane(l);
+    const double s0 = sc[l], s1 = P.dist(t0), s2 = P.dist(t1), s3 = P.dist(t2);
+    if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
+    if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+      if (rm == 0u) wb = wide_bit(s0, s1, s2, s3);
+      rm |= 1u << l;
+    }
+  }
+  const bool flip = __popc(rm) < __popc(cm);
+  word = flip ? (rm | (rm ? wb << kUnitWideBit : 0u) | (1u << kUnitFlipBit)) : (cm | (cm ? wa << kUnitWideBit : 0u));
+  return true;
+}
+// The unit's value as its word says: the clipped tet X, the other's planes C.
+__device__ inline double unit_clip_value_setup(const Tet& T, d3 cc, d3 t0, d3 t1, d3 t2, unsigned word, Tet& X,
+                                               TetCont& C) {
+  const bool flip = (word >> kUnitFlipBit) & 1u;
+  const Tet Sg{cc, t0, t1, t2};
+  X = flip ? Sg : T;
+  const Tet Y = flip ? T : Sg;
+  C = tet_container(Y.p0, Y.p1, Y.p2, Y.p3);
+  return 0.0;
+}
+// Distances of the cell's vertex mean from T's face planes.
+__device__ inline void apex_dists(const TetCont& Tc, d3 cc, double (&sc)[4]) {
+#pragma unroll
+  for (int l = 0; l < 4; ++l) sc[l] = Tc.plane(l).dist(cc);
+}
 // vol(cell k ∩ T [∩ PLIC half-space]) for a non-box cell: signed sum over the
 // cell's surface tetrahedra.  With DEEP false, a piece cut by more than
 // kMaxRegCuts planes makes the call return false (the caller defers the pair).
@@ -804,6 +875,9 @@ __device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(con
                                               double& out) {
   d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
   double acc = 0.0;
+  const TetCont Tc = tet_container(T.p0, T.p1, T.p2, T.p3);
+  double sc[4];
+  apex_dists(Tc, cc, sc);
   int fb = cf_begin(M, k), fn = cf_count(M, k);
   for (int i = 0; i < fn; ++i) {
     int e = M.cf_idx[fb + i];
@@ -811,13 +885,13 @@ __device__ __attribute__((always_inline)) inline bool tet_cell_pieces_volume(con
     for (int q = 0; q < nt; ++q) {
       d3 t0, t1, t2;
       face_triangle(M, e, q, t0, t1, t2);
-      if (!box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)))) continue;
-      double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-      if (s6 == 0.0) continue;
-      TetCont TC = tet_container(cc, t0, t1, t2);
-      unsigned tm;
-      if (!cut_mask(T, TC, tm)) continue;
-      double v = clip_masked_tet(T, TC, tm, leaf);
+      unsigned w;
+      if (!unit_rule(T, tlo, thi, Tc, sc, cc, t0, t1, t2, w)) continue;
+      const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+      Tet X;
+      TetCont C;
+      unit_clip_value_setup(T, cc, t0, t1, t2, w, X, C);
+      double v = clip_masked_tet(X, C, w & 15u, leaf);
       acc += s6 > 0.0 ? v : -v;
     }
   }
@@ -1376,7 +1450,6 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_
 // Unit word: bits 0-15 the surface tetrahedron, 16-19 the mask of its
 // planes that cut the flux tet, bit 16 + kUnitWideBit set when the first of
 // those cuts keeps three tetrahedra.
-constexpr int kUnitWideBit = 4;
 __device__ inline unsigned unit_mask(unsigned code) { return (code >> 16) & 15u; }
 
 template <int LPP>
@@ -1399,25 +1472,17 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
     const int np = cell_piece_count(M, k);
     const bool tri_only = np == cf_count(M, k);
-    const bool live = tet6(T) != 0.0;
+    const TetCont Tc = tet_container(T.p0, T.p1, T.p2, T.p3);
+    const bool live = tet6(T) != 0.0;  // a flat flux tet has no units
+    double sc[4];
+    apex_dists(Tc, cc, sc);
     // test of surface tetrahedron p against T: keep, and the mask of its planes that cut T
     auto test = [&](int p, unsigned& cm) -> bool {
       cm = 0;
       if (!live || p >= np) return false;
       d3 t0, t1, t2;
       cell_sigma(M, k, p, tri_only, t0, t1, t2);
-      if (!box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2))) ||
-          det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0)
-        return false;
-      TetCont TC = tet_container(cc, t0, t1, t2);
-      if (!cut_mask(T, TC, cm)) return false;
-      if (cm) {
-        // the first cut keeps three tetrahedra or one: a hint for grouping units of like work
-        const Plane P = TC.plane(__builtin_ctz(cm));
-        const int inside = (P.dist(T.p0) > 0.0) + (P.dist(T.p1) > 0.0) + (P.dist(T.p2) > 0.0) + (P.dist(T.p3) > 0.0);
-        cm |= (inside >= 2 ? 1u : 0u) << kUnitWideBit;
-      }
-      return true;
+      return unit_rule(T, tlo, thi, Tc, sc, cc, t0, t1, t2, cm);
     };
     // reserves count units (lane 0 of the group); -1 when the region is full
     auto reserve = [&](int count) -> int {
@@ -1491,6 +1556,323 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
   }
 }
 
+// Pairs with a general cell, stage 1 by runs (the default; k_flux_gen_filter
+// gives the same units).  The staging kernel writes a face's pairs candidate
+// by candidate, so the pairs of one face with one cell are consecutive in the
+// pair buffer: a run, whose flux tets all meet the same surface tetrahedra.
+// A group of kRunLanes lanes takes a run and
+//  - stages up to kRunTets of its flux tets in LDS (vertices, box, inward
+//    face planes);
+//  - gives each surface tetrahedron a lane, which loads it once for the run
+//    and tests its box against every flux tet's;
+//  - lists the (flux tet, surface tetrahedron) pairs whose boxes meet, flux
+//    tet by flux tet in surface order, and gives the list's entries one lane
+//    each for the plane tests of unit_rule (the rule every path applies);
+//  - writes each pair's survivors in surface order into a range of the unit
+//    buffer reserved with one atomic per run.
+// So each pair gets the units k_flux_gen_filter gives it, in the same order.
+// Cells with more than kRunLanes surface pieces leave their pairs to the
+// deferred kernel.
+constexpr int kRunLanes = 32;
+constexpr int kRunTets = 10;
+constexpr int kRunBlock = 128;
+constexpr int kRunGroups = kRunBlock / kRunLanes;
+constexpr int kRunChunk = 256;  // pairs scanned for runs per block pass
+constexpr int kRunPool = 448;   // units reserved per block pass, shared by the block's runs
+struct RunLds {
+  double tv[kRunTets][12];  // flux tet vertices
+  double tp[kRunTets][16];  // inward face planes: normals n0..n3, then offsets d0..d3
+  double tb[kRunTets][6];   // box: lo, hi
+  unsigned short list[kRunTets * kRunLanes];  // flux tet << 8 | surface tetrahedron
+  unsigned short code[kRunTets * kRunLanes];  // survivor: 0x8000 | unit word (cut mask, first-cut width)
+  unsigned char rank[kRunTets * kRunLanes];   // survivor's place among its pair's units
+  double tsc[kRunTets][4];  // distances of the cell's vertex mean from each flux tet's face planes
+  int seg[kRunTets + 1];                      // start of each flux tet's part of the list
+  int off[kRunTets];                          // each pair's first unit within the run's range
+};
+__device__ inline Tet run_tet(const RunLds& S, int t) {
+  const double* v = S.tv[t];
+  return Tet{mk3(v[0], v[1], v[2]), mk3(v[3], v[4], v[5]), mk3(v[6], v[7], v[8]), mk3(v[9], v[10], v[11])};
+}
+__device__ inline TetCont run_planes(const RunLds& S, int t) {
+  const double* q = S.tp[t];
+  TetCont C;
+  C.n0 = mk3(q[0], q[1], q[2]);
+  C.n1 = mk3(q[3], q[4], q[5]);
+  C.n2 = mk3(q[6], q[7], q[8]);
+  C.n3 = mk3(q[9], q[10], q[11]);
+  C.d0 = q[12];
+  C.d1 = q[13];
+  C.d2 = q[14];
+  C.d3_ = q[15];
+  return C;
+}
+
+// unit_rule for entry (flux tet t, surface tetrahedron q0 q1 q2 about cc) of a
+// run, with the flux tet's data read from LDS as each test needs it and the
+// surface tetrahedron's planes computed one at a time, as tet_container
+// computes them (fewer live registers); the same operations, so the same
+// decisions and the same unit word.
+__device__ inline bool run_unit_rule(const RunLds& S, int t, d3 cc, d3 q0, d3 q1, d3 q2, unsigned& word) {
+  word = 0;
+  {
+    const double* bx = S.tb[t];
+    if (!box_overlap(mk3(bx[0], bx[1], bx[2]), mk3(bx[3], bx[4], bx[5]), vmin(vmin(cc, q0), vmin(q1, q2)),
+                     vmax(vmax(cc, q0), vmax(q1, q2))))
+      return false;
+  }
+  const double s6 = det3f(q0 - cc, q1 - cc, q2 - cc);
+  if (s6 == 0.0) return false;
+  unsigned cm = 0, wa = 0;
+  {
+    const Tet T = run_tet(S, t);
+    const d3 a = cc, b = q0, c = s6 < 0.0 ? q2 : q1, d = s6 < 0.0 ? q1 : q2;
+#pragma unroll 1
+    for (int l = 0; l < 4; ++l) {
+      const d3 u = l == 0 ? c - a : (l == 1 ? b - a : (l == 2 ? d - a : c - b));
+      const d3 w = l == 0 ? b - a : (l == 1 ? d - a : (l == 2 ? c - a : d - b));
+      const d3 N = crossf(u, w);
+      const Plane P{mk3(-N.x, -N.y, -N.z), dotf(N, l == 3 ? b : a)};
+      const double s0 = P.dist(T.p0), s1 = P.dist(T.p1), s2 = P.dist(T.p2), s3 = P.dist(T.p3);
+      if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
+      if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+        if (cm == 0u) wa = wide_bit(s0, s1, s2, s3);
+        cm |= 1u << l;
+      }
+    }
+  }
+  unsigned rm = 0, wb = 0;
+  const double* q = S.tp[t];
+#pragma unroll 1
+  for (int l = 0; l < 4; ++l) {
+    const Plane P{mk3(q[3 * l], q[3 * l + 1], q[3 * l + 2]), q[12 + l]};
+    const double s0 = S.tsc[t][l], s1 = P.dist(q0), s2 = P.dist(q1), s3 = P.dist(q2);
+    if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
+    if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+      if (rm == 0u) wb = wide_bit(s0, s1, s2, s3);
+      rm |= 1u << l;
+    }
+  }
+  const bool flip = __popc(rm) < __popc(cm);
+  word = flip ? (rm | (rm ? wb << kUnitWideBit : 0u) | (1u << kUnitFlipBit)) : (cm | (cm ? wa << kUnitWideBit : 0u));
+  return true;
+}
+
+__global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
+  __shared__ RunLds SS[kRunGroups];
+  __shared__ int s_head[kRunChunk];
+  __shared__ int s_nhead;
+  // the block's pool of units: [s_pool, s_pool + kRunPool) of the unit buffer,
+  // handed out to runs with LDS atomics (one device atomic per pass instead of
+  // one per run); runs that do not fit take ranges of their own
+  __shared__ int s_pool, s_pool_used, s_pool_fail;
+  const int rsize = M.item_cap / kItemRegions, ursize = M.unit_cap / kItemRegions;
+  const int r = blockIdx.x % kItemRegions, bsub = blockIdx.x / kItemRegions;
+  const int fill = region_items(M, r, rsize);
+  const int base = r * rsize;
+  const int lane = __lane_id();
+  const int grp = threadIdx.x / kRunLanes, sub = threadIdx.x & (kRunLanes - 1);
+  const int gbase = lane & ~(kRunLanes - 1);  // the group's first lane in the wavefront
+  const unsigned long long gmask = 0xffffffffull << gbase;
+  const unsigned long long lbelow = ((1ull << lane) - 1ull) & gmask;
+  RunLds& S = SS[grp];
+  // every thread of a block makes the same number of passes (block barriers)
+  for (int b = bsub * kRunChunk; b < fill; b += region_blocks() * kRunChunk) {
+    if (threadIdx.x == 0) s_nhead = 0;
+    __syncthreads();
+    // the first pair of every general run among pairs b .. b + kRunChunk - 1
+#pragma unroll
+    for (int h = 0; h < kRunChunk / kRunBlock; ++h) {
+      const int li = b + threadIdx.x + h * kRunBlock;
+      bool head = false;
+      if (li < fill) {
+        const int i = base + li;
+        const int k = M.item_cell[i];
+        head = !M.isbox[k] && (li == 0 || M.item_cell[i - 1] != k || M.item_slot[i - 1] != M.item_slot[i]);
+      }
+      const unsigned long long bm = __ballot(head);
+      int wb = 0;
+      if (lane == 0 && bm) wb = atomicAdd(&s_nhead, __popcll(bm));
+      wb = __shfl(wb, 0);
+      if (head) s_head[wb + __popcll(bm & ((1ull << lane) - 1ull))] = li;
+    }
+    __syncthreads();
+    const int nh = s_nhead;
+    if (threadIdx.x == 0) {
+      s_pool = -1;
+      s_pool_used = 0;
+      s_pool_fail = 0;
+      if (nh > 0) {
+        const int pb = atomicAdd(&M.regions[r].unit_fill, kRunPool);
+        if (pb + kRunPool > ursize) {
+          atomicMin(&M.regions[r].unit_okend, pb);  // the region's written part ends before the pool
+        } else {
+          s_pool = r * ursize + pb;
+          s_pool_fail = kRunPool;
+        }
+      }
+    }
+    __syncthreads();
+    for (int hh = grp; hh < nh; hh += kRunGroups) {  // group-uniform from here on
+      const int li0 = s_head[hh];
+      const int i0 = base + li0;
+      const int k = M.item_cell[i0], sl = M.item_slot[i0];
+      // run length: the following pairs of the same face and cell (at most 5 kMaxFaceVerts)
+      int R = 1;
+      for (int j0 = 1;; j0 += kRunLanes) {
+        const int lj = li0 + j0 + sub;
+        const bool same = lj < fill && M.item_cell[base + lj] == k && M.item_slot[base + lj] == sl;
+        const unsigned long long bm = (__ballot(same) & gmask) >> gbase;
+        const int lead = __builtin_ctzll(~bm);
+        R += lead;
+        if (lead < kRunLanes) break;
+      }
+      const int np = cell_piece_count(M, k);
+      if (np > kRunLanes) {  // more surface pieces than lanes: the deferred kernel takes these pairs
+        for (int t = sub; t < R; t += kRunLanes) {
+          M.item_ucnt[i0 + t] = -1;
+          M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i0 + t;
+        }
+        continue;
+      }
+      const bool tri_only = np == cf_count(M, k);
+      const d3 cc = cell_centre(M, k);
+      for (int c0 = 0; c0 < R; c0 += kRunTets) {
+        const int Rc = min(kRunTets, R - c0);
+        // the run's flux tets, staged in steps so that few values are live at once
+        bool dead = true;
+        if (sub < Rc) {
+          const Tet T = staged_tet(M, sl, M.item_tm[i0 + c0 + sub]);
+          const d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
+          double* v = S.tv[sub];
+          v[0] = T.p0.x; v[1] = T.p0.y; v[2] = T.p0.z; v[3] = T.p1.x; v[4] = T.p1.y; v[5] = T.p1.z;
+          v[6] = T.p2.x; v[7] = T.p2.y; v[8] = T.p2.z; v[9] = T.p3.x; v[10] = T.p3.y; v[11] = T.p3.z;
+          double* bx = S.tb[sub];
+          bx[0] = tlo.x; bx[1] = tlo.y; bx[2] = tlo.z; bx[3] = thi.x; bx[4] = thi.y; bx[5] = thi.z;
+          dead = tet6(T) == 0.0;
+        }
+        wave_lds_sync();
+        if (sub < Rc) {  // face planes, as tet_container computes them, one at a time
+          const Tet T = run_tet(S, sub);
+          const bool swp = det3f(T.p1 - T.p0, T.p2 - T.p0, T.p3 - T.p0) < 0.0;
+          const d3 a = T.p0, b = T.p1, c = swp ? T.p3 : T.p2, d = swp ? T.p2 : T.p3;
+          double* q = S.tp[sub];
+#pragma unroll 1
+          for (int l = 0; l < 4; ++l) {
+            const d3 u = l == 0 ? c - a : (l == 1 ? b - a : (l == 2 ? d - a : c - b));
+            const d3 w = l == 0 ? b - a : (l == 1 ? d - a : (l == 2 ? c - a : d - b));
+            const d3 N = crossf(u, w);
+            const double off = dotf(N, l == 3 ? b : a);
+            const Plane P{mk3(-N.x, -N.y, -N.z), off};
+            q[3 * l] = P.n.x; q[3 * l + 1] = P.n.y; q[3 * l + 2] = P.n.z; q[12 + l] = off;
+            S.tsc[sub][l] = P.dist(cc);
+          }
+        }
+        wave_lds_sync();  // flux tets staged (the group is within one wavefront)
+        const unsigned deadm = (unsigned)((__ballot(dead) & gmask) >> gbase);
+        // boxes: bit t set when flux tet t's box meets this lane's surface tetrahedron's
+        unsigned pb = 0;
+        d3 t0 = cc, t1 = cc, t2 = cc;
+        bool flat = true;
+        if (sub < np) {
+          cell_sigma(M, k, sub, tri_only, t0, t1, t2);
+          flat = det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0;
+        }
+        const d3 slo = vmin(vmin(cc, t0), vmin(t1, t2)), shi = vmax(vmax(cc, t0), vmax(t1, t2));
+        if (sub < np && !flat) {
+          for (int t = 0; t < Rc; ++t) {
+            if ((deadm >> t) & 1u) continue;
+            const double* bx = S.tb[t];
+            if (box_overlap(mk3(bx[0], bx[1], bx[2]), mk3(bx[3], bx[4], bx[5]), slo, shi)) pb |= 1u << t;
+          }
+        }
+        // the list, flux tet by flux tet, each in surface order
+        int ncombo = 0;
+        for (int t = 0; t < Rc; ++t) {
+          const bool in = (pb >> t) & 1u;
+          const unsigned long long bt = __ballot(in) & gmask;
+          if (sub == 0) S.seg[t] = ncombo;
+          if (in) S.list[ncombo + __popcll(bt & lbelow)] = (unsigned short)((t << 8) | sub);
+          ncombo += __popcll(bt);
+        }
+        if (sub == 0) S.seg[Rc] = ncombo;
+        wave_lds_sync();
+        // plane tests, one entry per lane
+        for (int c = sub; c < ncombo; c += kRunLanes) {
+          const unsigned e = S.list[c];
+          const int t = (int)(e >> 8), p = (int)(e & 255u);
+          d3 q0, q1, q2;
+          cell_sigma(M, k, p, tri_only, q0, q1, q2);
+          unsigned cm;
+          S.code[c] = run_unit_rule(S, t, cc, q0, q1, q2, cm) ? (unsigned short)(0x8000u | cm) : (unsigned short)0;
+        }
+        wave_lds_sync();
+        // each pair's survivors: their count and places, then the run's range
+        int cnt = 0;
+        if (sub < Rc) {
+          for (int c = S.seg[sub]; c < S.seg[sub + 1]; ++c)
+            if (S.code[c] & 0x8000u) S.rank[c] = (unsigned char)cnt++;
+        }
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kRunLanes; o <<= 1) {
+          const int v = __shfl_up(incl, o, kRunLanes);
+          if (sub >= o) incl += v;
+        }
+        const int total = __shfl(incl, kRunLanes - 1, kRunLanes);
+        if (sub < Rc) S.off[sub] = incl - cnt;
+        int ub = 0;
+        if (sub == 0 && total > 0) {
+          const int o = s_pool >= 0 ? atomicAdd(&s_pool_used, total) : kRunPool;
+          if (o + total <= kRunPool) {
+            ub = s_pool + o;
+          } else {
+            if (s_pool >= 0) atomicMin(&s_pool_fail, o);  // the pool's used part ends before this request
+            ub = atomicAdd(&M.regions[r].unit_fill, total);
+            if (ub + total > ursize) {
+              atomicMin(&M.regions[r].unit_okend, ub);  // the region's written part ends before this range
+              ub = -1;
+            } else {
+              ub += r * ursize;
+            }
+          }
+        }
+        ub = __shfl(ub, 0, kRunLanes);
+        if (sub < Rc) {
+          const int i = i0 + c0 + sub;
+          if (ub < 0) {  // no room: the deferred kernel computes the whole pair
+            M.item_ucnt[i] = -1;
+            M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
+          } else {
+            M.item_uoff[i] = ub + (incl - cnt);
+            M.item_ucnt[i] = cnt;
+          }
+        }
+        wave_lds_sync();
+        if (ub >= 0) {
+          for (int c = sub; c < ncombo; c += kRunLanes) {
+            const unsigned code = S.code[c];
+            if (code & 0x8000u) {
+              const unsigned e = S.list[c];
+              const int t = (int)(e >> 8);
+              const int u = ub + S.off[t] + S.rank[c];
+              M.unit_item[u] = i0 + c0 + t;
+              M.unit_code[u] = (e & 255u) | ((code & 0x7fffu) << 16);
+            }
+          }
+        }
+        wave_lds_sync();  // the group's LDS is reused by its next chunk or run
+      }
+    }
+    __syncthreads();
+    if (s_pool >= 0) {  // the pool's unused tail: units that no pair owns
+      const int end = min(s_pool_used, s_pool_fail);
+      for (int u = end + threadIdx.x; u < kRunPool; u += kRunBlock) M.unit_item[s_pool + u] = -1;
+    }
+    __syncthreads();  // s_head and the pool are reused by the next pass
+  }
+}
+
 // Stage 2: one lane per surviving (pair, surface tetrahedron): clip in
 // registers, up to three cutting planes; units with four (about 5% on the
 // distorted-grid workload) go to a list for k_flux_gen_units_deep, which runs
@@ -1525,8 +1907,8 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       const int u = r * rsize + lu;
       int c = -1, i = 0;
       unsigned code = 0;
-      if (lu < fill) {
-        i = M.unit_item[u];
+      if (lu < fill) i = M.unit_item[u];
+      if (lu < fill && i >= 0) {  // (units of no pair, the unused tail of a block's pool, are skipped)
         code = M.unit_code[u];
         const int nc = cut_count(unit_mask(code));
         const int8_t tg = M.tag_cell[M.item_cell[i]];
@@ -1573,7 +1955,7 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       const int uu = s_unit[q], ii = s_item[q];
       const unsigned cd = s_code[q];
       const int p = cd & 0xffff;
-      const unsigned cm = unit_mask(cd);
+      const unsigned w = (cd >> 16) & 63u;
       const int k = M.item_cell[ii];
       const Tet T = staged_tet(M, M.item_slot[ii], M.item_tm[ii]);
       const d3 cc = cell_centre(M, k);
@@ -1581,12 +1963,14 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
       d3 t0, t1, t2;
       cell_sigma(M, k, p, tri_only, t0, t1, t2);
       const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-      const TetCont TC = tet_container(cc, t0, t1, t2);
+      Tet X;
+      TetCont C;
+      unit_clip_value_setup(T, cc, t0, t1, t2, w, X, C);
       Leaf leaf;
       leaf.useH = M.tag_cell[k] == 0;
       leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
       leaf.hd = M.pC[k];
-      const double v = clip_masked_tet<3, false>(T, TC, cm, leaf);
+      const double v = clip_masked_tet<3, false>(X, C, w & 15u, leaf);
       M.unit_vol[uu] = s6 > 0.0 ? v : -v;
     }
     __syncthreads();  // the lists are reused by the next pass
@@ -1606,12 +1990,15 @@ __global__ __launch_bounds__(256) void k_flux_gen_units_deep(DevMesh M) {
     d3 t0, t1, t2;
     cell_sigma(M, k, code & 0xffff, tri_only, t0, t1, t2);
     double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-    TetCont TC = tet_container(cc, t0, t1, t2);
+    const unsigned w = (code >> 16) & 63u;
+    Tet X;
+    TetCont C;
+    unit_clip_value_setup(T, cc, t0, t1, t2, w, X, C);
     Leaf leaf;
     leaf.useH = M.tag_cell[k] == 0;
     leaf.hn = mk3(M.pnx[k], M.pny[k], M.pnz[k]);
     leaf.hd = M.pC[k];
-    double v = clip_masked_tet<4>(T, TC, unit_mask(code), leaf);
+    double v = clip_masked_tet<4>(X, C, w & 15u, leaf);
     M.unit_vol[u] = s6 > 0.0 ? v : -v;
   }
 }
@@ -1739,6 +2126,9 @@ __device__ inline double general_pair_volume_group(const DevMesh& M, int k, d3 c
   const int np = cell_piece_count(M, k);
   const bool tri_only = np == cf_count(M, k);
   double acc = 0.0;
+  const TetCont Tc = tet_container(T.p0, T.p1, T.p2, T.p3);
+  double sc[4];
+  apex_dists(Tc, cc, sc);
   for (int p0 = 0; p0 < np; p0 += kDeepLanes) {
     const int p = p0 + sub;
     bool kept = false;
@@ -1746,17 +2136,15 @@ __device__ inline double general_pair_volume_group(const DevMesh& M, int k, d3 c
     if (p < np) {
       d3 t0, t1, t2;
       cell_sigma(M, k, p, tri_only, t0, t1, t2);
-      if (box_overlap(tlo, thi, vmin(vmin(cc, t0), vmin(t1, t2)), vmax(vmax(cc, t0), vmax(t1, t2)))) {
+      unsigned w;
+      if (unit_rule(T, tlo, thi, Tc, sc, cc, t0, t1, t2, w)) {
         const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
-        if (s6 != 0.0) {
-          const TetCont TC = tet_container(cc, t0, t1, t2);
-          unsigned tm;
-          if (cut_mask(T, TC, tm)) {
-            const double v = clip_masked_tet(T, TC, tm, leaf);
-            val = s6 > 0.0 ? v : -v;
-            kept = true;
-          }
-        }
+        Tet X;
+        TetCont C;
+        unit_clip_value_setup(T, cc, t0, t1, t2, w, X, C);
+        const double v = clip_masked_tet(X, C, w & 15u, leaf);
+        val = s6 > 0.0 ? v : -v;
+        kept = true;
       }
     }
     const int nq = min(kDeepLanes, np - p0);
@@ -2818,7 +3206,8 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   }
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, kItemsBlock, 0, s>>>(M)));
   if (!M.all_box) {
-    if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
+    if (L.filter_lanes == 0) TIMED(K_FLUX_GEN, (k_flux_gen_runs<<<pair_grid, kRunBlock, 0, s>>>(M)));
+    else if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));
     else TIMED(K_FLUX_GEN, (k_flux_gen_filter<32><<<pair_grid, 256, 0, s>>>(M)));

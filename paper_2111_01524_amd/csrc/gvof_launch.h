@@ -26,7 +26,7 @@ struct LaunchCfg {
   int recon_threads = 128;
   int prep_blocks = 16384;
   int pair_blocks_per_region = 16;
-  int filter_lanes = 32;
+  int filter_lanes = 0;  // 0: the general-cell filter by runs
   int staged_faces = 0;
   int staged_pairs = 0;
   int prep_lanes = 64;
