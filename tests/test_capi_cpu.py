@@ -160,7 +160,7 @@ def test_launch_config_validation_without_gpu():
     try:
         c = gvof.gvof_get_launch_config(h)
         assert c.as_dict() == dict(sweep_threads=256, recon_threads=128, prep_blocks=16384,
-                                   pair_blocks_per_region=16, filter_lanes=32, staged_faces=0,
+                                   pair_blocks_per_region=16, filter_lanes=0, staged_faces=0,
                                    staged_pairs=0, prep_lanes=64)
         for bad in (dict(sweep_threads=96), dict(recon_threads=256), dict(prep_blocks=0),
                     dict(pair_blocks_per_region=300), dict(filter_lanes=12), dict(staged_faces=-1),
@@ -170,9 +170,10 @@ def test_launch_config_validation_without_gpu():
             with pytest.raises(gvof.GvofError):
                 gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
         d = c.as_dict()
-        d.update(sweep_threads=512, filter_lanes=64, prep_lanes=32)
-        gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
-        assert gvof.gvof_get_launch_config(h).as_dict() == d
+        for fl in (64, 8, 0):  # the per-pair filter's lane counts and 0, the runs filter
+            d.update(sweep_threads=512, filter_lanes=fl, prep_lanes=32)
+            gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
+            assert gvof.gvof_get_launch_config(h).as_dict() == d
         with pytest.raises(gvof.GvofError):  # not bound
             gvof.gvof_graph_launch(h)
     finally:

@@ -131,7 +131,9 @@ def test_full_size_distorted_mid_trajectory_launch_shapes(oracle_mod):
     default = gvof.gvof_launch_config(256, 128, 16384, 16, 32, 0, 0, 64).as_dict()
     shapes = [("autotuned", tuned), ("defaults", default),
               ("staging limits", dict(tuned, staged_faces=20000, staged_pairs=256 * 2000)),
-              ("tight pair buffer", dict(default, staged_pairs=256 * 200, filter_lanes=16, prep_lanes=32))]
+              ("tight pair buffer", dict(default, staged_pairs=256 * 200, filter_lanes=16, prep_lanes=32)),
+              ("runs filter", dict(default, filter_lanes=0)), ("per-pair filter, 8 lanes", dict(tuned, filter_lanes=8))]
+    first = None
     for name, cfgd in shapes:
         gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**cfgd))
         Fd = to_dev(torch, dev, F_mid)
@@ -147,3 +149,8 @@ def test_full_size_distorted_mid_trajectory_launch_shapes(oracle_mod):
         dF = max_abs(host(Fout), F1)
         log(f"  {name} {cfgd}: max|dVF|/V={dVF:.2e} max|dF|={dF:.2e}")
         assert dVF <= 1e-12 and dF <= 1e-12
+        # every shape (and so every filter and overflow path) gives the same values, bit for bit
+        if first is None:
+            first = (host(vf_g), host(Fout))
+        else:
+            assert np.array_equal(host(vf_g), first[0]) and np.array_equal(host(Fout), first[1]), name
