@@ -1449,12 +1449,17 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 // So each pair gets the units k_flux_gen_filter gives it, in the same order.
 // Cells with more than kRunLanes surface pieces leave their pairs to the
 // deferred kernel.
+// A block is one wavefront (two groups): its barriers then wait for no other
+// wavefront, so a group's long run holds up only its partner.  Each block
+// takes few pairs per pass and the grid has many blocks per region, so that
+// the runs are spread over every CU rather than queued behind each other.
 constexpr int kRunLanes = 32;
 constexpr int kRunTets = 10;
-constexpr int kRunBlock = 128;
+constexpr int kRunBlock = 64;
 constexpr int kRunGroups = kRunBlock / kRunLanes;
-constexpr int kRunChunk = 256;  // pairs scanned for runs per block pass
-constexpr int kRunPool = 448;   // units reserved per block pass, shared by the block's runs
+constexpr int kRunChunk = 64;             // pairs scanned for runs per block pass
+constexpr int kRunPool = 112;             // units reserved per block pass, shared by the block's runs
+constexpr int kRunBlocksPerRegion = 256;  // the grid: kItemRegions x this
 struct RunLds {
   double tv[kRunTets][12];  // flux tet vertices
   double tp[kRunTets][16];  // inward face planes: normals n0..n3, then offsets d0..d3
@@ -1558,10 +1563,10 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
     __syncthreads();
     // the first pair of every general run among pairs b .. b + kRunChunk - 1
 #pragma unroll
-    for (int h = 0; h < kRunChunk / kRunBlock; ++h) {
+    for (int h = 0; h * kRunBlock < kRunChunk; ++h) {
       const int li = b + threadIdx.x + h * kRunBlock;
       bool head = false;
-      if (li < fill) {
+      if (threadIdx.x + h * kRunBlock < kRunChunk && li < fill) {
         const int i = base + li;
         const int k = M.item_cell[i];
         head = !M.isbox[k] && (li == 0 || M.item_cell[i - 1] != k || M.item_slot[i - 1] != M.item_slot[i]);
@@ -3082,7 +3087,7 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
   }
   if (M.any_box) TIMED(K_FLUX, (k_flux_items_box<<<pair_grid, kItemsBlock, 0, s>>>(M)));
   if (!M.all_box) {
-    if (L.filter_lanes == 0) TIMED(K_FLUX_GEN, (k_flux_gen_runs<<<pair_grid, kRunBlock, 0, s>>>(M)));
+    if (L.filter_lanes == 0) TIMED(K_FLUX_GEN, (k_flux_gen_runs<<<kItemRegions * kRunBlocksPerRegion, kRunBlock, 0, s>>>(M)));
     else if (L.filter_lanes == 8) TIMED(K_FLUX_GEN, (k_flux_gen_filter<8><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));

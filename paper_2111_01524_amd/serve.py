@@ -1,23 +1,29 @@
 """Serving loop: advection jobs arriving over time, admitted under an HBM
-budget, advanced with continuous batching.
+budget, advanced with continuous (step-level) batching.
 
 The scheduler is written against a small executor interface so that its
-logic (arrival order, admission by budget, concurrent cohorts, completion and
-latency accounting) runs unchanged on the GPU executor and on a fake one with
-a virtual clock (the CPU tests).
+logic (arrival order, admission by budget and slots, joins at step
+boundaries, release on completion, latency accounting) runs unchanged on the
+GPU executor and on a fake one with a virtual clock (the CPU tests).
 
-Policy.  Every arriving job is sized first (its mesh topology and workspace
-size, on a host worker, while the device keeps running).  Sized jobs queue in
-arrival order; a job never overtakes an earlier arrival.  Whenever fewer than
-`max_cohorts` cohorts are starting or running, the jobs at the head of the
-queue that fit the remaining budget (at most `max_jobs_per_cohort` of them)
-are admitted together as one cohort: one batch handle, set up on a host worker
-and then resident until every job in it is done.  A job whose own footprint
-exceeds the whole budget is rejected.  Every running cohort keeps up to
-`depth` steps in flight on its own stream, so cohorts overlap on the device
-and new cohorts join while others run.  A job's result is ready when the copy
-of its fractions after its own last step has completed; latency = ready time
-- arrival time.
+Policy.
+  - Every arriving job is sized first (its mesh topology and device
+    footprint, on a host worker, while the device keeps running).
+  - Sized jobs queue in arrival order; a job never overtakes an earlier
+    arrival, nor one still being sized.
+  - The job at the head of the queue is admitted as soon as a slot is free
+    (at most `slots` jobs starting or running) and its footprint fits what is
+    left of the budget.  Its device state (mesh and workspace, velocities,
+    fractions; the PLIC planes live in the workspace) is set up on a host
+    worker and stays resident until the job is done.  A job larger than the
+    whole budget is rejected.
+  - At every step boundary of the loop each running job gets its next steps
+    enqueued (up to `depth` in flight per job, each job on its own stream), so
+    a job admitted while others run joins them at the next boundary and the
+    steps of all running jobs overlap on the device.
+  - A job's result is ready when the copy of its fractions after its own last
+    step has completed; latency = ready time - arrival time.  The job's slot
+    and its memory are released at that moment, and the queue head may start.
 """
 from __future__ import annotations
 
@@ -39,10 +45,11 @@ class Job:
     payload: object = None        # executor-specific inputs
     bytes: int = 0                # device footprint estimate, set by the executor
     t_admit: float | None = None
+    t_start: float | None = None  # set-up done: the job joins the running set
     t_done: float | None = None
     rejected: bool = False
     result: object = None
-    part: object = None           # executor state held between estimate and start
+    part: object = None           # executor state held between sizing and set-up
 
 
 @dataclass
@@ -50,7 +57,8 @@ class Report:
     jobs: list = field(default_factory=list)
     makespan: float = 0.0
     peak_bytes: int = 0
-    cohorts: int = 0
+    admitted: int = 0
+    max_running: int = 0          # most jobs starting or running at once
 
     def summary(self, arrival_window: float | None = None) -> dict:
         done = [j for j in self.jobs if j.t_done is not None]
@@ -60,34 +68,36 @@ class Report:
         win = arrival_window if arrival_window is not None else (max(j.arrival for j in self.jobs) if self.jobs else 0)
         out = {
             "jobs": len(self.jobs), "completed": len(done), "rejected": sum(j.rejected for j in self.jobs),
-            "cohorts": self.cohorts, "makespan_s": self.makespan, "peak_hbm_bytes": self.peak_bytes,
-            "face_steps": fs, "value": fs / self.makespan if self.makespan > 0 else 0.0,
+            "admitted": self.admitted, "max_concurrent_jobs": self.max_running, "makespan_s": self.makespan,
+            "peak_hbm_bytes": self.peak_bytes, "face_steps": fs,
+            "value": fs / self.makespan if self.makespan > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_queue_wait_s": float(wait.mean()) if wait.size else None,
         }
         if win and win > 0:
+            out["arrival_window_s"] = win
             out["offered_face_steps_per_s"] = sum(j.faces * j.nsteps for j in self.jobs) / win
         return out
 
 
 class Server:
-    def __init__(self, executor, budget_bytes: int, max_cohorts: int = 4, depth: int = 4,
-                 max_jobs_per_cohort: int | None = None, idle_sleep: float = 2e-4):
+    def __init__(self, executor, budget_bytes: int, slots: int = 16, depth: int = 2, idle_sleep: float = 2e-4):
         self.ex = executor
         self.budget = int(budget_bytes)
-        self.max_cohorts = max_cohorts
+        self.slots = slots
         self.depth = depth
-        self.max_jobs = max_jobs_per_cohort
         self.idle_sleep = idle_sleep
 
-    def run(self, jobs) -> Report:
+    def run(self, jobs, on_done=None) -> Report:
+        """Serve the jobs; on_done(job) is called when a job's result is ready."""
         ex = self.ex
-        pending = deque(sorted(jobs, key=lambda j: (j.arrival, j.id)))
+        key = lambda j: (j.arrival, j.id)  # noqa: E731
+        pending = deque(sorted(jobs, key=key))
         sizing: list = []             # arrived, being sized
         queue: list = []              # sized, in arrival order
-        starting: list = []           # (cohort, charged bytes)
-        running: list = []            # (cohort, charged bytes)
+        starting: list = []           # (job, handle, charged bytes)
+        running: list = []            # (job, handle, bytes)
         rep = Report(jobs=list(jobs))
         t0 = ex.now()
         used = 0
@@ -110,50 +120,50 @@ class Server:
                     queue.append(j)
                     progressed = True
             sizing = still
-            queue.sort(key=lambda j: (j.arrival, j.id))
-            # admission: the queue head in arrival order (nothing overtakes a job still being sized)
-            first_unsized = min((j.arrival, j.id) for j in sizing) if sizing else None
-            if queue and len(starting) + len(running) < self.max_cohorts:
-                take, extra = [], 0
-                while (queue and used + extra + queue[0].bytes <= self.budget
-                       and (first_unsized is None or (queue[0].arrival, queue[0].id) < first_unsized)
-                       and (self.max_jobs is None or len(take) < self.max_jobs)):
-                    take.append(queue.pop(0))
-                    extra += take[-1].bytes
-                if take:
-                    t_adm = ex.now() - t0
-                    for j in take:
-                        j.t_admit = t_adm
-                    starting.append((ex.submit_start(take), extra))
-                    used += extra
-                    rep.cohorts += 1
-                    rep.peak_bytes = max(rep.peak_bytes, used)
-                    progressed = True
+            queue.sort(key=key)
+            # admission: the queue head, while a slot is free and it fits (nothing overtakes a job still being sized)
+            first_unsized = min(key(j) for j in sizing) if sizing else None
+            while (queue and len(starting) + len(running) < self.slots and used + queue[0].bytes <= self.budget
+                   and (first_unsized is None or key(queue[0]) < first_unsized)):
+                j = queue.pop(0)
+                j.t_admit = ex.now() - t0
+                starting.append((j, ex.submit_start(j), j.bytes))
+                used += j.bytes
+                rep.admitted += 1
+                rep.peak_bytes = max(rep.peak_bytes, used)
+                rep.max_running = max(rep.max_running, len(starting) + len(running))
+                progressed = True
+            # set-ups that are done join the running jobs at this step boundary
             still = []
-            for c, charged in starting:
-                if ex.start_ready(c):
-                    exact = ex.cohort_bytes(c)
+            for j, h, charged in starting:
+                if ex.start_ready(h):
+                    exact = ex.job_bytes(h)
                     used += exact - charged
                     rep.peak_bytes = max(rep.peak_bytes, used)
-                    running.append((c, exact))
+                    j.t_start = ex.now() - t0
+                    running.append((j, h, exact))
                     progressed = True
                 else:
-                    still.append((c, charged))
+                    still.append((j, h, charged))
             starting = still
-            for c, _ in running:
-                while not ex.finished_enqueue(c) and ex.in_flight(c) < self.depth:
-                    ex.step(c)
+            # the step boundary: the next steps of every running job
+            for j, h, _ in running:
+                while ex.steps_left(h) and ex.in_flight(h) < self.depth:
+                    ex.step(h)
                     progressed = True
+            # completions: the slot and the memory come back at once
             keep = []
-            for c, nbytes in running:
-                for j, t in ex.poll(c):
-                    j.t_done = t - t0
-                    progressed = True
-                if ex.all_done(c):
-                    ex.release(c)
-                    used -= nbytes
-                else:
-                    keep.append((c, nbytes))
+            for j, h, nbytes in running:
+                t = ex.poll(h)
+                if t is None:
+                    keep.append((j, h, nbytes))
+                    continue
+                j.t_done = t - t0
+                ex.release(h)
+                if on_done is not None:
+                    on_done(j)
+                used -= nbytes
+                progressed = True
             running = keep
             if not progressed:
                 idle_all = not (sizing or queue or starting or running)
@@ -166,11 +176,12 @@ class Server:
 
 # ----------------------------------------------------------------------------- GPU executor
 class GpuExecutor:
-    """Cohorts as batch handles (BatchRun) on their own streams.  Job payloads
-    are problem inputs (inputs.problem_inputs); the device footprint of a job
-    is the workspace its mesh needs plus its resident arrays.  Sizing and
-    cohort set-up run on host worker threads (the library's calls release the
-    interpreter lock), so the loop keeps the device fed meanwhile."""
+    """Each running job is a resident single-problem handle with its own
+    stream.  Job payloads are problem inputs (inputs.problem_inputs); the
+    device footprint of a job is the workspace its mesh needs plus its
+    resident arrays.  Sizing and set-up run on host worker threads (the
+    library's calls release the interpreter lock), so the loop keeps the
+    device fed meanwhile."""
 
     def __init__(self, device, launch_config: dict | None = None, n_div: int = 10, workers: int = 2):
         import torch
@@ -192,13 +203,17 @@ class GpuExecutor:
     def shutdown(self):
         self.pool.shutdown(wait=True)
 
-    # -- sizing: the job's mesh handle (kept for its cohort) and its footprint
+    @staticmethod
+    def array_bytes(mesh, nsteps: int) -> int:
+        """Resident arrays of a job besides its workspace: u at faces and vertices, two fraction buffers."""
+        return 8 * (3 * mesh.nf + 3 * mesh.nv + 2 * mesh.nc) + 9 * nsteps
+
+    # -- sizing: the job's mesh handle (kept for its set-up) and its footprint
     def estimate(self, job):
         g, m = self.gvof, job.payload["mesh"]
         h = g.gvof_mesh_create(m.vx, m.vy, m.vz, m.fv_ptr, m.fv_idx, m.owner, m.neigh, m.nc)
         job.part = h
-        arrays = 8 * (3 * m.nf + 3 * m.nv + 2 * m.nc) + 9 * job.nsteps
-        job.bytes = g.gvof_mesh_workspace_bytes(h) + arrays
+        job.bytes = g.gvof_mesh_workspace_bytes(h) + self.array_bytes(m, job.nsteps)
 
     def submit_estimate(self, job):
         job._fut = self.pool.submit(self.estimate, job)
@@ -214,80 +229,78 @@ class GpuExecutor:
             self.gvof.gvof_mesh_destroy(job.part)
             job.part = None
 
-    # -- cohorts
-    def _start(self, jobs):
-        from .runtime import BatchRun
-        torch = self.torch
-        st = torch.cuda.Stream()
-        parts = [j.part for j in jobs]
-        for j in jobs:
-            j.part = None
-        R = BatchRun([j.payload for j in jobs], self.device, st, n_div=self.n_div, autotune=False,
-                     launch_config=self.launch_config, parts=parts)
-        for j in jobs:
-            j.result = torch.empty(j.cells, dtype=torch.float64, pin_memory=True)
+    # -- set-up: bind the handle to a workspace, upload the velocities, initialise the fractions
+    def _start(self, job):
+        torch, p = self.torch, job.payload
+        st = torch.cuda.Stream(self.device)
+        h, job.part = job.part, None
+        with torch.cuda.stream(st):
+            g = self.gvof.GvofMesh(p["mesh"], self.device, stream=st, handle=h)
+            if self.launch_config is not None:
+                d = self.gvof.gvof_get_launch_config(g.h).as_dict()
+                d.update(self.launch_config)
+                self.gvof.gvof_set_launch_config(g.h, self.gvof.gvof_launch_config(**d))
+            uf = torch.from_numpy(p["uf"]).to(self.device)
+            uv = torch.from_numpy(p["uv"]).to(self.device)
+            F = g.init_fraction(p["shape"][0], p["shape"][1], self.n_div)
+            Fn = torch.empty_like(F)
+        job.result = torch.empty(p["mesh"].nc, dtype=torch.float64, pin_memory=True)
         st.synchronize()
-        nbytes = int(R.B.ws_bytes) + sum(8 * (3 * j.payload["mesh"].nf + 3 * j.payload["mesh"].nv + 2 * j.cells)
-                                         + 9 * j.nsteps for j in jobs)
-        return dict(R=R, stream=st, events=deque(), pending=[], done=0, nbytes=nbytes)
+        nbytes = int(g.ws_bytes) + self.array_bytes(p["mesh"], job.nsteps)
+        return dict(job=job, g=g, stream=st, uf=uf, uv=uv, F=F, Fn=Fn, s=0, events=deque(), done_ev=None,
+                    nbytes=nbytes)
 
-    def submit_start(self, jobs):
-        return dict(jobs=jobs, fut=self.pool.submit(self._start, jobs))
+    def submit_start(self, job):
+        return dict(fut=self.pool.submit(self._start, job))
 
-    def start_ready(self, c):
-        if "R" in c:
+    def start_ready(self, h):
+        if "g" in h:
             return True
-        if not c["fut"].done():
+        if not h["fut"].done():
             return False
-        c.update(c["fut"].result())
+        h.update(h["fut"].result())
         return True
 
-    def cohort_bytes(self, c):
-        return c["nbytes"]
+    def job_bytes(self, h):
+        return h["nbytes"]
 
-    def finished_enqueue(self, c):
-        return c["R"].done
+    def steps_left(self, h):
+        return h["s"] < h["job"].nsteps
 
-    def in_flight(self, c):
-        ev = c["events"]
+    def in_flight(self, h):
+        ev = h["events"]
         while ev and ev[0].query():
             ev.popleft()
         return len(ev)
 
-    def step(self, c):
-        R, st = c["R"], c["stream"]
-        s = R.s
-        R.step()
-        with self.torch.cuda.stream(st):
-            for q in R.finishing_at(s):
-                j = c["jobs"][q]
-                j.result.copy_(R.fractions(q), non_blocking=True)
-                e = self.torch.cuda.Event()
-                e.record(st)
-                c["pending"].append((j, e))
-            e = self.torch.cuda.Event()
-            e.record(st)
-        c["events"].append(e)
+    def step(self, h):
+        torch, j, s = self.torch, h["job"], h["s"]
+        with torch.cuda.stream(h["stream"]):
+            h["g"].reconstruct(h["F"])
+            h["g"].advect_step(h["uf"], h["uv"], float(j.payload["dt_eff"][s]), h["F"], h["Fn"])
+            h["F"], h["Fn"] = h["Fn"], h["F"]
+            e = torch.cuda.Event()
+            e.record(h["stream"])
+            if s + 1 == j.nsteps:
+                j.result.copy_(h["F"], non_blocking=True)
+                h["done_ev"] = torch.cuda.Event()
+                h["done_ev"].record(h["stream"])
+        h["events"].append(e)
+        h["s"] = s + 1
 
-    def poll(self, c):
-        out, keep = [], []
-        for j, e in c["pending"]:
-            if e.query():
-                out.append((j, self.now()))
-                c["done"] += 1
-            else:
-                keep.append((j, e))
-        c["pending"] = keep
-        return out
+    def poll(self, h):
+        e = h["done_ev"]
+        if e is not None and e.query():
+            return self.now()
+        return None
 
-    def all_done(self, c):
-        return c["done"] == len(c["jobs"])
-
-    def release(self, c):
-        c["stream"].synchronize()
-        c["R"].status()
-        c["R"].close()
-        c["R"] = None
+    def release(self, h):
+        h["stream"].synchronize()
+        g = h["g"]
+        g.status()
+        g.close()
+        for k in ("g", "uf", "uv", "F", "Fn", "events", "done_ev"):
+            h[k] = None
 
 
 def jobs_from_specs(specs, problems):
