@@ -1458,7 +1458,7 @@ constexpr int kRunTets = 10;
 constexpr int kRunBlock = 64;
 constexpr int kRunGroups = kRunBlock / kRunLanes;
 constexpr int kRunChunk = 64;             // pairs scanned for runs per block pass
-constexpr int kRunPool = 112;             // units reserved per block pass, shared by the block's runs
+constexpr int kRunPool = 90;              // units reserved per block pass, shared by the block's runs
 constexpr int kRunBlocksPerRegion = 256;  // the grid: kItemRegions x this
 struct RunLds {
   double tv[kRunTets][12];  // flux tet vertices
@@ -1539,10 +1539,15 @@ __device__ inline bool run_unit_rule(const RunLds& S, int t, d3 cc, d3 q0, d3 q1
   return true;
 }
 
-__global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
+__global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
+  static_assert(kRunChunk == kRunBlock && kRunBlock == 64, "the pass scans one pair per lane of its wavefront");
   __shared__ RunLds SS[kRunGroups];
-  __shared__ int s_head[kRunChunk];
-  __shared__ int s_nhead;
+  // the pass's runs, in pair order: first pair, length (0 when the run goes on past the pass's pairs), cell,
+  // polyhedron slot, surface piece count, offset of the cell's cached surface triangles (-1: none), vertex mean
+  __shared__ int s_head[kRunChunk], s_len[kRunChunk], s_cell[kRunChunk], s_slot[kRunChunk], s_np[kRunChunk];
+  __shared__ int s_tro[kRunChunk];
+  __shared__ double s_cc[kRunChunk][3];
+  __shared__ unsigned short s_tm[kRunChunk];  // the pass's pairs' tetrahedron words
   // the block's pool of units: [s_pool, s_pool + kRunPool) of the unit buffer,
   // handed out to runs with LDS atomics (one device atomic per pass instead of
   // one per run); runs that do not fit take ranges of their own
@@ -1559,26 +1564,43 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
   RunLds& S = SS[grp];
   // every thread of a block makes the same number of passes (block barriers)
   for (int b = bsub * kRunChunk; b < fill; b += region_blocks() * kRunChunk) {
-    if (threadIdx.x == 0) s_nhead = 0;
-    __syncthreads();
-    // the first pair of every general run among pairs b .. b + kRunChunk - 1
-#pragma unroll
-    for (int h = 0; h * kRunBlock < kRunChunk; ++h) {
-      const int li = b + threadIdx.x + h * kRunBlock;
-      bool head = false;
-      if (threadIdx.x + h * kRunBlock < kRunChunk && li < fill) {
+    // pairs b .. b + 63, one per lane: where runs start (a pair of another face or cell than the pair
+    // before; past the filled pairs every lane counts as a start) and, for the first pair of each general
+    // run, what the run needs of its cell, loaded at once for all the pass's runs
+    int nh;
+    {
+      const int li = b + lane;
+      bool brk = true, head = false;
+      int k = 0, sl = 0;
+      unsigned tm = 0;
+      if (li < fill) {
         const int i = base + li;
-        const int k = M.item_cell[i];
-        head = !M.isbox[k] && (li == 0 || M.item_cell[i - 1] != k || M.item_slot[i - 1] != M.item_slot[i]);
+        k = M.item_cell[i];
+        sl = M.item_slot[i];
+        tm = M.item_tm[i];
+        brk = li == 0 || M.item_cell[i - 1] != k || M.item_slot[i - 1] != sl;
+        head = brk && !M.isbox[k];
       }
-      const unsigned long long bm = __ballot(head);
-      int wb = 0;
-      if (lane == 0 && bm) wb = atomicAdd(&s_nhead, __popcll(bm));
-      wb = __shfl(wb, 0);
-      if (head) s_head[wb + __popcll(bm & ((1ull << lane) - 1ull))] = li;
+      const unsigned long long bb = __ballot(brk), bh = __ballot(head);
+      nh = __popcll(bh);
+      if (head) {
+        const int h = __popcll(bh & ((1ull << lane) - 1ull));
+        const unsigned long long after = lane < 63 ? bb >> (lane + 1) : 0ull;
+        const int np = cell_piece_count(M, k);
+        const int o = M.tri_off[k], o1 = M.tri_off[k + 1];
+        s_head[h] = li;
+        s_len[h] = after ? 1 + __builtin_ctzll(after) : 0;
+        s_cell[h] = k;
+        s_slot[h] = sl;
+        s_np[h] = np;
+        s_tro[h] = (o1 > o && np == cf_count(M, k)) ? o : -1;
+        s_cc[h][0] = M.ccx[k];
+        s_cc[h][1] = M.ccy[k];
+        s_cc[h][2] = M.ccz[k];
+      }
+      s_tm[lane] = (unsigned short)tm;
     }
     __syncthreads();
-    const int nh = s_nhead;
     if (threadIdx.x == 0) {
       s_pool = -1;
       s_pool_used = 0;
@@ -1597,18 +1619,21 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
     for (int hh = grp; hh < nh; hh += kRunGroups) {  // group-uniform from here on
       const int li0 = s_head[hh];
       const int i0 = base + li0;
-      const int k = M.item_cell[i0], sl = M.item_slot[i0];
-      // run length: the following pairs of the same face and cell (at most 5 kMaxFaceVerts)
-      int R = 1;
-      for (int j0 = 1;; j0 += kRunLanes) {
-        const int lj = li0 + j0 + sub;
-        const bool same = lj < fill && M.item_cell[base + lj] == k && M.item_slot[base + lj] == sl;
-        const unsigned long long bm = (__ballot(same) & gmask) >> gbase;
-        const int lead = __builtin_ctzll(~bm);
-        R += lead;
-        if (lead < kRunLanes) break;
+      const int k = s_cell[hh], sl = s_slot[hh], np = s_np[hh], tro = s_tro[hh];
+      // run length: the following pairs of the same face and cell (at most 5 kMaxFaceVerts), known from the
+      // pass's starts unless the run goes on past the pass's pairs
+      int R = s_len[hh];
+      if (R == 0) {
+        R = 1;
+        for (int j0 = 1;; j0 += kRunLanes) {
+          const int lj = li0 + j0 + sub;
+          const bool same = lj < fill && M.item_cell[base + lj] == k && M.item_slot[base + lj] == sl;
+          const unsigned long long bm = (__ballot(same) & gmask) >> gbase;
+          const int lead = __builtin_ctzll(~bm);
+          R += lead;
+          if (lead < kRunLanes) break;
+        }
       }
-      const int np = cell_piece_count(M, k);
       if (np > kRunLanes) {  // more surface pieces than lanes: the deferred kernel takes these pairs
         for (int t = sub; t < R; t += kRunLanes) {
           M.item_ucnt[i0 + t] = -1;
@@ -1616,14 +1641,25 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
         }
         continue;
       }
-      const bool tri_only = np == cf_count(M, k);
-      const d3 cc = cell_centre(M, k);
+      const d3 cc = mk3(s_cc[hh][0], s_cc[hh][1], s_cc[hh][2]);
+      // surface tetrahedron p: from the cell's cached triangles when it has them
+      auto sigma = [&](int p, d3& t0, d3& t1, d3& t2) {
+        if (tro >= 0) {
+          const double* q = M.tri_xyz + 9 * (size_t)(tro + p);
+          t0 = mk3(q[0], q[1], q[2]);
+          t1 = mk3(q[3], q[4], q[5]);
+          t2 = mk3(q[6], q[7], q[8]);
+        } else {
+          cell_sigma(M, k, p, np == cf_count(M, k), t0, t1, t2);
+        }
+      };
       for (int c0 = 0; c0 < R; c0 += kRunTets) {
         const int Rc = min(kRunTets, R - c0);
         // the run's flux tets, staged in steps so that few values are live at once
         bool dead = true;
         if (sub < Rc) {
-          const Tet T = staged_tet(M, sl, M.item_tm[i0 + c0 + sub]);
+          const int lt = li0 - b + c0 + sub;
+          const Tet T = staged_tet(M, sl, lt < kRunChunk ? (unsigned)s_tm[lt] : (unsigned)M.item_tm[i0 + c0 + sub]);
           const d3 tlo = vmin(vmin(T.p0, T.p1), vmin(T.p2, T.p3)), thi = vmax(vmax(T.p0, T.p1), vmax(T.p2, T.p3));
           double* v = S.tv[sub];
           v[0] = T.p0.x; v[1] = T.p0.y; v[2] = T.p0.z; v[3] = T.p1.x; v[4] = T.p1.y; v[5] = T.p1.z;
@@ -1656,7 +1692,7 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
         d3 t0 = cc, t1 = cc, t2 = cc;
         bool flat = true;
         if (sub < np) {
-          cell_sigma(M, k, sub, tri_only, t0, t1, t2);
+          sigma(sub, t0, t1, t2);
           flat = det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0;
         }
         const d3 slo = vmin(vmin(cc, t0), vmin(t1, t2)), shi = vmax(vmax(cc, t0), vmax(t1, t2));
@@ -1683,7 +1719,7 @@ __global__ __launch_bounds__(kRunBlock) void k_flux_gen_runs(DevMesh M) {
           const unsigned e = S.list[c];
           const int t = (int)(e >> 8), p = (int)(e & 255u);
           d3 q0, q1, q2;
-          cell_sigma(M, k, p, tri_only, q0, q1, q2);
+          sigma(p, q0, q1, q2);
           unsigned cm;
           S.code[c] = run_unit_rule(S, t, cc, q0, q1, q2, cm) ? (unsigned short)(0x8000u | cm) : (unsigned short)0;
         }
@@ -1764,12 +1800,19 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   // As in the box-pair kernel, each block ranks its units by their work (the
   // number of cutting planes, 0..3, and whether the cell's interface cuts the
   // leaves) before clipping, so that most wavefronts run one kind of unit;
-  // kUnitsPerThread units per thread are ranked together.
+  // kUnitsPerThread units per thread are ranked together.  The ranking pass
+  // also loads what the clip needs of each unit's pair (cell, polyhedron
+  // slot, tetrahedron word, the cell's cached surface triangles), for its
+  // kUnitsPerThread units at once, and keeps it with the rank in LDS: the
+  // clip then waits for one round of loads instead of three in a row.
   constexpr int NCLS = 14;  // none; then per cut count 1..3, first cut keeping one or three; x interface
   constexpr int CHUNK = kItemsBlock * kUnitsPerThread;
   constexpr int VW = CHUNK / 64;
-  __shared__ int s_unit[CHUNK], s_item[CHUNK];
+  // per unit, at its place in the pass (h kItemsBlock + thread): what the clip needs; s_list, in rank order,
+  // holds those places
+  __shared__ int s_unit[CHUNK], s_cell[CHUNK], s_slot[CHUNK], s_tri[CHUNK], s_list[CHUNK];
   __shared__ unsigned s_code[CHUNK];
+  __shared__ unsigned short s_tm[CHUNK];
   __shared__ int s_off[VW][NCLS];
   __shared__ int s_n;
   const int rsize = M.unit_cap / kItemRegions;
@@ -1779,20 +1822,28 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   const unsigned long long below = (1ull << lane) - 1ull;
   // every thread of a block makes the same number of passes (block barriers)
   for (int b = sub * CHUNK; b < fill; b += region_blocks() * CHUNK) {
-    int cls[kUnitsPerThread], uh[kUnitsPerThread], ih[kUnitsPerThread];
-    unsigned codeh[kUnitsPerThread];
+    int cls[kUnitsPerThread];
     unsigned long long mh[kUnitsPerThread];
 #pragma unroll
     for (int h = 0; h < kUnitsPerThread; ++h) {
       const int lu = b + threadIdx.x + h * kItemsBlock;
       const int u = r * rsize + lu;
-      int c = -1, i = 0;
-      unsigned code = 0;
-      if (lu < fill) i = M.unit_item[u];
-      if (lu < fill && i >= 0) {  // (units of no pair, the unused tail of a block's pool, are skipped)
+      int c = -1, i = -1, k = 0, sl = 0, tro = -1;
+      unsigned code = 0, tm = 0;
+      if (lu < fill) {
+        i = M.unit_item[u];
         code = M.unit_code[u];
+      }
+      if (i >= 0) {  // (units of no pair, the unused tail of a block's pool, are skipped)
+        k = M.item_cell[i];
+        sl = M.item_slot[i];
+        tm = M.item_tm[i];
         const int nc = cut_count(unit_mask(code));
-        const int8_t tg = M.tag_cell[M.item_cell[i]];
+        const int8_t tg = M.tag_cell[k];
+        // the surface triangle's place in the bind-time cache, when the cell's pieces are its triangles
+        // and they are cached (else -1: the clip builds the piece itself)
+        const int o = M.tri_off[k], o1 = M.tri_off[k + 1];
+        tro = (o1 > o && cf_count(M, k) == cell_piece_count(M, k)) ? o + (int)(code & 0xffffu) : -1;
         const int wide = (int)((code >> (16 + kUnitWideBit)) & 1u);
         if (nc > 3) M.list_udeep[atomicAdd(&M.counters[CNT_UDEEP], 1)] = u;  // four cutting planes: the deep instance
         else c = nc == 0 ? (tg == 0 ? 1 : 0) : 2 + 4 * (nc - 1) + 2 * wide + (tg == 0 ? 1 : 0);
@@ -1805,10 +1856,14 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
         m = c == q ? bq : m;
       }
       cls[h] = c;
-      uh[h] = u;
-      ih[h] = i;
-      codeh[h] = code;
       mh[h] = m;
+      const int raw = h * kItemsBlock + threadIdx.x;
+      s_unit[raw] = u;
+      s_cell[raw] = k;
+      s_slot[raw] = sl;
+      s_tri[raw] = tro;
+      s_code[raw] = code;
+      s_tm[raw] = (unsigned short)tm;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1824,25 +1879,26 @@ __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < kUnitsPerThread; ++h) {
-      if (cls[h] >= 0) {
-        const int pos = s_off[h * (kItemsBlock / 64) + w][cls[h]] + __popcll(mh[h] & below);
-        s_unit[pos] = uh[h];
-        s_item[pos] = ih[h];
-        s_code[pos] = codeh[h];
-      }
+      if (cls[h] >= 0) s_list[s_off[h * (kItemsBlock / 64) + w][cls[h]] + __popcll(mh[h] & below)] = h * kItemsBlock + threadIdx.x;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < s_n; q += kItemsBlock) {  // ranks in order of work, most first
-      const int uu = s_unit[q], ii = s_item[q];
-      const unsigned cd = s_code[q];
+      const int raw = s_list[q];
+      const int uu = s_unit[raw], k = s_cell[raw], tro = s_tri[raw];
+      const unsigned cd = s_code[raw];
       const int p = cd & 0xffff;
       const unsigned w = (cd >> 16) & 63u;
-      const int k = M.item_cell[ii];
-      const Tet T = staged_tet(M, M.item_slot[ii], M.item_tm[ii]);
+      const Tet T = staged_tet(M, s_slot[raw], s_tm[raw]);
       const d3 cc = cell_centre(M, k);
-      const bool tri_only = cf_count(M, k) == cell_piece_count(M, k);
       d3 t0, t1, t2;
-      cell_sigma(M, k, p, tri_only, t0, t1, t2);
+      if (tro >= 0) {
+        const double* tq = M.tri_xyz + 9 * (size_t)tro;
+        t0 = mk3(tq[0], tq[1], tq[2]);
+        t1 = mk3(tq[3], tq[4], tq[5]);
+        t2 = mk3(tq[6], tq[7], tq[8]);
+      } else {
+        cell_sigma(M, k, p, cf_count(M, k) == cell_piece_count(M, k), t0, t1, t2);
+      }
       const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
       Tet X;
       TetCont C;
