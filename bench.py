@@ -1,16 +1,34 @@
-"""Throughput of the LSGIR + FMFPA (or EMFPA) VOF step on one MI355X.
+"""Throughput of the unsplit geometric VOF step (LSGIR + FMFPA) on one MI355X.
 
-Workload (default): 64^3 uniform hexahedra on the unit cube, sphere r=0.15 at
-(0.35, 0.35, 0.35) initialised by refinement (10 divisions), Enright 3D
-deformation field with period T=3, CFL 0.5 (constant dt from the largest face
-velocity, last step shortened to land on T), FP64.  One "step" is one pass of
-the whole hot path: reconstruction (tags, cut-off, LSGIR, plane constants)
-followed by the advection step (face flux volumes, FMFPA flux polyhedra with
-truncation, update).  The field is u0(x) cos(pi t/T): the library receives
-u0 at faces and vertices (resident in HBM) and dt * cos(pi t^{n+1/2}/T).
+Workloads (--workload):
+  batch      the default, the largest single-GPU workload: 256 independent
+             problems (seed 2): sides 16..48, Cartesian or distorted
+             (interior vertices moved by up to 0.25h per axis) with
+             probability 1/2, sphere r ~ U[0.1, 0.2] at U[0.3, 0.7]^3,
+             Enright 3D deformation with period T ~ U[1, 3], CFL 0.5; every
+             problem advances to its own T with its own time step; one step
+             of the batch is one replay of a captured HIP graph.
+  jittered   64^3 distorted grid (seed 1), sphere r = 0.15 at 0.35, Enright
+             field with T = 3, CFL 0.5.
+  cartesian  64^3 Cartesian grid, same body and field.
+All arithmetic is FP64.  One step = reconstruction (tags, cut-off, LSGIR,
+plane constants) + advection (V_d, FMFPA polyhedra, truncation, update) of
+every active problem.  The library receives u0 at faces and vertices
+(resident in HBM) and dt cos(pi t^{n+1/2}/T) per problem.
 
-Prints one JSON line.  `value` = faces x steps / wall time of the timed steps
-(all faces, boundary included), inputs resident in HBM.
+Timed steps.  An untimed pass runs the whole trajectory once and keeps the
+volume fractions before K steps spread evenly over it (step s_i =
+floor((i + 1/2) S / K)); W untimed warm-up steps follow; then each timed step
+restores its saved fractions (outside the timed events) and runs once,
+bracketed by HIP events on the library's stream.  So a short run measures
+the trajectory as a whole, not its first steps.  `value` = faces of the
+active problems summed over the timed steps / the summed event times (all
+faces, boundary included; inputs resident in HBM).
+
+Also reported: the same steps as graph replays (single-problem workloads) or
+eagerly (batch); the batch's problems advanced one by one (a sample);
+per-kernel times over the same steps with their rooflines; the oracle on the
+host's cores; the other workloads as sub-records.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -18,6 +36,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -26,72 +45,521 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face that needs a flux polyhedron (its
-# construction + truncation, and the truncation alone, which k_flux_items
-# performs), by flux polyhedron method, and per interfacial cell (LSGIR +
-# plane constant) on this workload, counted by the FLOP-counting build of the
-# CPU reference over a sample of the trajectory (oracle/count_flops.py).
-FLOPS_PER_FLUX_FACE = {"fmfpa": 38766.0, "emfpa": 49094.0, "nmfpa": 34525.0}
-FLOPS_PER_FLUX_FACE_TRUNCATION = {"fmfpa": 37578.0, "emfpa": 47629.0, "nmfpa": 34030.0}
-FLOPS_PER_RECON_CELL = 53202.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of k_flux_items_box on this workload (FETCH_SIZE and
-# WRITE_SIZE counters, scaled by the same counters on a plain copy kernel of
-# known size; profiles/hbm_traffic_cartesian64_enright.md), valid for the
-# kernel sources whose digest is recorded beside it.
-ITEMS_BOX_TRAFFIC_BYTES = 2.82545e7
-ITEMS_BOX_TRAFFIC_SOURCES = "eb4e382cf8ee7eb5"
-
-
-def kernel_sources_digest() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("gvof_kernels.hip", "clip.h", "gvof_dev.h"):
-        with open(os.path.join(ROOT, "paper_2111_01524_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=748)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--kind", default="cartesian", choices=["cartesian", "jittered"])
+    ap.add_argument("--steps", type=int, default=20, help="timed steps, spread evenly over the trajectory")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch", choices=["batch", "jittered", "cartesian"])
+    ap.add_argument("--n", type=int, default=64, help="grid side of the single-problem workloads")
     ap.add_argument("--method", default="fmfpa", choices=["fmfpa", "emfpa", "nmfpa"],
-                    help="flux polyhedra: face-matched (the default workload), edge-matched or non-matched")
+                    help="flux polyhedron of the single-problem workloads")
     ap.add_argument("--recon", default="lsgir", choices=["lsgir", "lsfir", "llcir", "elcir", "clcir"],
-                    help="interface normals: LSGIR (the default workload), LSFIR, LLCIR, ELCIR or CLCIR")
-    ap.add_argument("--lsfir-outer", type=int, default=1, help="LSFIR outer passes")
+                    help="interface reconstruction of the single-problem workloads")
+    ap.add_argument("--problems", type=int, default=256, help="problems of the batch workload")
+    ap.add_argument("--no-sub", action="store_true", help="skip the other workloads' sub-records")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-recon-leg", action="store_true",
-                    help="skip the leg that times the reconstruction alone (cells/s)")
-    ap.add_argument("--no-probes", action="store_true",
-                    help="skip the measured FP64 FMA and copy ceilings (reported beside the published peaks)")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--profile-all", action="store_true", help="time every kernel with events (diagnostics)")
-    ap.add_argument("--event-every", type=int, default=8,
-                    help="bracket the truncation kernel with HIP events on every n-th timed step (each pair of "
-                         "event records costs the stream a few microseconds)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shapes")
-    ap.add_argument("--launch-config", default=None,
-                    help="JSON object of launch-shape fields to set instead of autotuning (others keep their defaults)")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also run the batched workload with this many problems (256 = the full batch)")
-    ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--batch-warmup", type=int, default=2)
-    ap.add_argument("--single-steps", type=int, default=2, help="timed steps per problem of the one-by-one baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of each CPU baseline run")
+    ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch-config", default=None, help="JSON launch shapes instead of autotuning")
+    ap.add_argument("--single-sample", type=int, default=32, help="batch problems timed one by one")
     ap.add_argument("--served", type=int, default=0,
-                    help="also serve this many jobs of the served workload (Poisson arrivals at 20/s)")
+                    help="serve this many jobs of the served workload at --served-load of the capacity measured first "
+                         "(the served run alone: no other workload)")
+    ap.add_argument("--served-load", type=float, default=0.75, help="offered load, a fraction of the measured capacity")
+    ap.add_argument("--served-capacity-jobs", type=int, default=24,
+                    help="jobs (all arriving at once) of the capacity run")
     ap.add_argument("--served-budget-gb", type=float, default=200.0)
-    ap.add_argument("--served-cohort-jobs", type=int, default=2, help="most jobs per admitted cohort (0: no limit)")
-    ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only run a plain device copy of this many MiB, 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--served-slots", type=int, default=16)
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a plain copy of this many MiB, 5 times")
+    ap.add_argument("--dump-states", default=None,
+                    help="directory: save the fractions before each timed step and the launch shapes, per workload")
+    ap.add_argument("--load-states", default=None,
+                    help="directory written by --dump-states: take the states and shapes from there (no untimed pass, "
+                         "no tuning)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="run only the warm-up and timed steps of the main workload (for profiler runs that should "
+                         "see exactly those dispatches), print their times")
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ helpers
+def snapshot_steps(S: int, K: int):
+    """K steps spread evenly over a trajectory of S steps."""
+    return [min(S - 1, int(math.floor((i + 0.5) * S / K))) for i in range(K)]
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+class EventPairs:
+    """Per-step HIP events on one stream; the summed time of the bracketed work."""
+
+    def __init__(self, torch, n):
+        self.a = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+        self.b = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+    def ms(self):
+        return [a.elapsed_time(b) for a, b in zip(self.a, self.b)]
+
+
+def kernel_table(gvof, prof):
+    return {k: (v[0] / v[1] if v[1] else 0.0, v[1]) for k, v in prof.items()}
+
+
+# Work per unit, by workload and kernel, from the rocprofv3 runs summarised in
+# profiles/ (paper_2111_01524_amd/profile_summary.py): FP64 FLOPs of the active
+# lanes and HBM bytes per unit of the kernel's work (faces that need a flux
+# polyhedron, interface cells, or all faces / cells), measured over the same
+# timed steps of the same workload.
+def load_work_table():
+    p = os.path.join(ROOT, "profiles", "work_per_unit.json")
+    if os.path.exists(p):
+        with open(p) as f:
+            return json.load(f)
+    return {}
+
+
+def kernel_sources_digest() -> str:
+    """Digest of the kernel sources (the counters in profiles/ hold for the sources they were taken on)."""
+    from paper_2111_01524_amd.profile_summary import sources_digest
+    return sources_digest()
+
+
+# kernels whose work is FP64 arithmetic (the flux polyhedra, their truncation, the reconstruction); the others
+# are sweeps over faces, cells or vertices, bound by HBM
+ALU_KERNELS = {"k_flux_prep", "k_flux_items_box", "k_flux_gen_filter", "k_flux_gen_units", "k_flux_gen_units_deep",
+               "k_flux_deep", "k_recon"}
+
+
+def rooflines(kt, step_ms, counts, table, workload):
+    """Rooflines of every kernel taking 10% of the step or more, largest first.  A kernel's achieved rate is its
+    work per unit x the units of the timed steps (counted on the device) over its summed launch time over the same
+    steps (HIP events around each launch on the library's stream)."""
+    out = []
+    K = counts["steps"]
+    fresh = table.get("sources_digest") == kernel_sources_digest()
+    for k, (avg_ms, n) in sorted(kt.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        if n == 0 or avg_ms <= 0:
+            continue
+        per_step = avg_ms * n / K
+        if per_step < 0.1 * step_ms:
+            continue
+        ent = {"kernel": k, "avg_launch_ms": avg_ms, "launches": n, "ms_per_step": per_step,
+               "share_of_step": per_step / step_ms}
+        spec = table.get(workload, {}).get(k)
+        if spec:
+            units = counts[spec["unit"]]
+            secs = avg_ms * n / 1e3
+            tf = spec["flops"] * units / secs / 1e12
+            gb = spec["bytes"] * units / secs / 1e9
+            if k in ALU_KERNELS:
+                ent.update(bound="alu", unit="TFLOP/s", peak=FP64_VECTOR_PEAK_TFLOPS, achieved=tf,
+                           frac=tf / FP64_VECTOR_PEAK_TFLOPS)
+            else:
+                ent.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, achieved=gb, frac=gb / HBM_PEAK_GBS)
+            ent.update(counters_match_sources=fresh, flops_per_unit=spec["flops"], issued_flops_per_unit=spec["flops_issued"],
+                       hbm_bytes_per_unit=spec["bytes"], hbm_gbs=gb, hbm_frac=gb / HBM_PEAK_GBS,
+                       fp64_tflops=tf, unit_of_work=spec["unit"], units_per_launch=units / n,
+                       traffic=spec["bytes"] * units / n if fresh else None,
+                       profile_avg_launch_ms=spec["avg_launch_ms"],
+                       profile_units_per_launch=spec["units_per_launch"], work_source=spec["source"])
+        out.append(ent)
+    return out
+
+
+def dump_states(args, name, steps, snaps, launch_config):
+    if not args.dump_states or args.load_states:
+        return
+    os.makedirs(args.dump_states, exist_ok=True)
+    np.savez(os.path.join(args.dump_states, f"{name}.npz"), steps=np.array(steps),
+             F=np.stack([x.cpu().numpy() for x in snaps]), launch_config=json.dumps(launch_config))
+
+
+def load_states(args, name):
+    if not args.load_states:
+        return None
+    with np.load(os.path.join(args.load_states, f"{name}.npz")) as d:
+        return {"steps": [int(x) for x in d["steps"]], "F": d["F"], "launch_config": json.loads(str(d["launch_config"]))}
+
+
+# ------------------------------------------------------------------ single problem
+def single_leg(args, kind, dev, K, W):
+    import torch
+
+    from paper_2111_01524_amd import gvof, inputs
+
+    n, T_end, cfl = args.n, 3.0, 0.5
+    mesh = inputs.cartesian_mesh(n) if kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
+    st = torch.cuda.Stream()
+    g = gvof.GvofMesh(mesh, dev, stream=st, method=args.method, recon=args.recon)
+    scheme = f"{args.recon.upper()}+{args.method.upper()}"
+    name = kind if scheme == "LSGIR+FMFPA" else f"{kind}_{args.recon}_{args.method}"
+    uf, uv = inputs.velocity_enright(mesh)
+    dt = inputs.cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
+    sched = inputs.step_schedule(T_end, dt)
+    S = len(sched)
+    times = np.concatenate([[0.0], np.cumsum(sched)])
+    dteff = [sched[s] * inputs.enright_time_factor(times[s] + 0.5 * sched[s], T_end) for s in range(S)]
+    steps = snapshot_steps(S, K)
+    loaded = load_states(args, name)
+    with torch.cuda.stream(st):
+        ufd = torch.from_numpy(uf).to(dev)
+        uvd = torch.from_numpy(uv).to(dev)
+        F0 = g.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
+        Fa, Fb = F0.clone(), torch.empty_like(F0)
+        snaps = {}
+        if loaded is not None:
+            steps = loaded["steps"]
+            snaps = {s: torch.from_numpy(loaded["F"][i]).to(dev) for i, s in enumerate(steps)}
+        else:
+            for s in range(S):  # the untimed pass: fractions before each timed step
+                if s in steps:
+                    snaps[s] = Fa.clone()
+                g.reconstruct(Fa)
+                g.advect_step(ufd, uvd, dteff[s], Fa, Fb)
+                Fa, Fb = Fb, Fa
+        st.synchronize()
+        g.status()
+        tuned = None
+        if loaded is not None:
+            gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**loaded["launch_config"]))
+        elif args.launch_config:
+            d = gvof.gvof_get_launch_config(g.h).as_dict()
+            d.update(json.loads(args.launch_config))
+            gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**d))
+        elif not args.no_autotune:  # shapes measured where the interface is most stretched
+            sm = steps[len(steps) // 2]
+            Fm = snaps[sm].clone()
+            dtm = torch.tensor([dteff[sm]], dtype=torch.float64, device=dev)
+            act = torch.ones(1, dtype=torch.uint8, device=dev)
+            cfg, _ = gvof.gvof_autotune(g.h, ufd, uvd, dtm, act, Fm, Fb, 20)
+            tuned = cfg.as_dict()
+        dump_states(args, name, steps, [snaps[s] for s in steps], gvof.gvof_get_launch_config(g.h).as_dict())
+        Fw, Fo = torch.empty_like(F0), torch.empty_like(F0)
+
+        def one(s):
+            g.reconstruct(Fw)
+            g.advect_step(ufd, uvd, dteff[s], Fw, Fo)
+
+        for i in range(W):  # warm-up, untimed
+            Fw.copy_(snaps[steps[i % K]])
+            one(steps[i % K])
+        st.synchronize()
+        c0, f0 = gvof.gvof_work_totals(g.h)
+        ev = EventPairs(torch, K)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter()
+        for i, s in enumerate(steps):
+            Fw.copy_(snaps[s])
+            ev.a[i].record(st)
+            one(s)
+            ev.b[i].record(st)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter() - t_wall
+        g.status()
+        c1, f1 = gvof.gvof_work_totals(g.h)
+        ms = ev.ms()
+        if args.timed_only:
+            g.close()
+            return {"workload": f"{kind} {n}^3 Enright T=3, CFL 0.5, {scheme}", "name": name,
+                    "ms_per_step": sum(ms) / K, "timed_steps": steps,
+                    "interfacial_faces_per_step": (f1 - f0) / K, "interfacial_cells_per_step": (c1 - c0) / K,
+                    "faces_per_step": mesh.nf, "cells_per_step": mesh.nc}, None
+        # the same steps as replays of a captured step (one graph launch per step)
+        dtg = torch.zeros(1, dtype=torch.float64, device=dev)
+        actg = torch.ones(1, dtype=torch.uint8, device=dev)
+        Fg = torch.empty_like(F0)
+        Fg.copy_(snaps[steps[0]])
+        gvof.gvof_graph_capture(g.h, ufd, uvd, dtg, actg, Fg)
+        dt_rows = torch.tensor([dteff[s] for s in steps], dtype=torch.float64, device=dev)
+        evg = EventPairs(torch, K)
+        for i, s in enumerate(steps):
+            Fg.copy_(snaps[s])
+            dtg.copy_(dt_rows[i:i + 1])
+            evg.a[i].record(st)
+            gvof.gvof_graph_launch(g.h)
+            evg.b[i].record(st)
+        torch.cuda.synchronize()
+        g.status()
+        msg = evg.ms()
+        # per-kernel times over the same steps (events around every kernel; not in the values above)
+        kt, kcounts = None, None
+        if not args.no_kernels:
+            gvof.gvof_profile_read(g.h)
+            k0 = gvof.gvof_work_totals(g.h)
+            for i, s in enumerate(steps):
+                Fw.copy_(snaps[s])
+                gvof.gvof_profile_enable(g.h, (1 << gvof.GVOF_NUM_KERNELS) - 1)
+                one(s)
+                gvof.gvof_profile_enable(g.h, 0)
+            torch.cuda.synchronize()
+            kt = kernel_table(gvof, gvof.gvof_profile_read(g.h))
+            k1 = gvof.gvof_work_totals(g.h)
+            kcounts = {"steps": K, "interfacial_faces": k1[1] - k0[1], "interfacial_cells": k1[0] - k0[0],
+                       "faces": mesh.nf * K, "cells": mesh.nc * K}
+    tot = sum(ms)
+    res = {
+        "workload": f"{kind} {n}^3 unit cube, sphere r=0.15 at 0.35, Enright deformation T=3, CFL 0.5, {scheme}, "
+                    f"{S} steps per trajectory; timed steps {steps[0]}..{steps[-1]} spread evenly",
+        "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv, "trajectory_steps": S, "timed_steps": steps,
+        "value": mesh.nf * K / (tot / 1e3), "unit": "face·steps/s", "ms_per_step": tot / K,
+        "value_graph": mesh.nf * K / (sum(msg) / 1e3), "ms_per_step_graph": sum(msg) / K,
+        "cells_per_s": mesh.nc * K / (tot / 1e3),
+        "interfacial_faces_per_step": (f1 - f0) / K, "interfacial_cells_per_step": (c1 - c0) / K,
+        "launch_config": tuned if tuned is not None else gvof.gvof_get_launch_config(g.h).as_dict(),
+        "launch_config_autotuned": tuned is not None, "wall_s": t_wall,
+    }
+    if kt is not None:
+        res["kernels_ms_per_launch"] = {k: v[0] for k, v in kt.items() if v[1]}
+        res["rooflines"] = rooflines(kt, tot / K, kcounts, load_work_table(), name)
+    ctx = dict(mesh=mesh, uf=uf, uv=uv, dteff=dteff, steps=steps, snaps={s: v.cpu().numpy() for s, v in snaps.items()})
+    g.close()
+    del snaps, Fa, Fb, Fw, Fo, Fg
+    torch.cuda.empty_cache()
+    return res, ctx
+
+
+# ------------------------------------------------------------------ batch
+def batch_leg(args, problems, dev, K, W):
+    import torch
+
+    from paper_2111_01524_amd import gvof
+    from paper_2111_01524_amd.runtime import BatchRun
+
+    st = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    R = BatchRun(problems, dev, st, autotune=False, graph=False)
+    setup_s = time.perf_counter() - t0
+    S = R.max_steps
+    steps = snapshot_steps(S, K)
+    print(f"# batch bound: nf={R.B.nf} nc={R.B.nc} setup {setup_s:.1f} s, {S} steps", file=sys.stderr, flush=True)
+    snaps = {}
+    loaded = load_states(args, "batch")
+    with torch.cuda.stream(st):
+        if loaded is not None:
+            steps = loaded["steps"]
+            snaps = {s: torch.from_numpy(loaded["F"][i]).to(dev) for i, s in enumerate(steps)}
+        else:
+            while not R.done:  # the untimed pass
+                if R.s in steps:
+                    snaps[R.s] = R.F.clone()
+                R.step()
+                if R.s % 100 == 0:
+                    st.synchronize()
+                    print(f"# batch untimed pass: step {R.s}/{S}", file=sys.stderr, flush=True)
+        st.synchronize()
+        R.status()
+        tuned = None
+        if loaded is not None:
+            gvof.gvof_set_launch_config(R.B.h, gvof.gvof_launch_config(**loaded["launch_config"]))
+        elif args.launch_config:
+            d = gvof.gvof_get_launch_config(R.B.h).as_dict()
+            d.update(json.loads(args.launch_config))
+            gvof.gvof_set_launch_config(R.B.h, gvof.gvof_launch_config(**d))
+        elif not args.no_autotune:  # shapes measured in the middle of the pass
+            sm = steps[len(steps) // 2]
+            R.F.copy_(snaps[sm])
+            R.dt.copy_(R.dt_tab[sm])
+            R.act.copy_(R.act_tab[sm])
+            cfg, tms = R.B.autotune(R.uf, R.uv, R.dt, R.act, R.F, reps=2)
+            tuned = (cfg.as_dict(), tms)
+        dump_states(args, "batch", steps, [snaps[s] for s in steps], gvof.gvof_get_launch_config(R.B.h).as_dict())
+        # timed steps: graph replays; with --timed-only (the profiler runs) the same steps launched eagerly,
+        # as the per-kernel pass below launches them
+        graph = not args.timed_only
+        if graph:
+            R.B.capture(R.uf, R.uv, R.dt, R.act, R.F)
+            R.graph = True
+
+        def one(s):
+            R.dt.copy_(R.dt_tab[s])
+            R.act.copy_(R.act_tab[s])
+
+        def run():
+            if graph:
+                R.B.replay()
+            else:
+                R.B.step(R.uf, R.uv, R.dt, R.act, R.F)
+
+        for i in range(W):
+            R.F.copy_(snaps[steps[i % K]])
+            one(steps[i % K])
+            run()
+        st.synchronize()
+        ev = EventPairs(torch, K)
+        torch.cuda.synchronize()
+        c0, f0 = gvof.gvof_work_totals(R.B.h)
+        t_wall = time.perf_counter()
+        for i, s in enumerate(steps):
+            R.F.copy_(snaps[s])
+            one(s)
+            ev.a[i].record(st)
+            run()
+            ev.b[i].record(st)
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter() - t_wall
+        R.status()
+        c1, f1 = gvof.gvof_work_totals(R.B.h)
+        ms = ev.ms()
+        fs = sum(R.face_steps(s, s + 1) for s in steps)
+        cs = sum(int(R.act_host[s].astype(np.int64) @ R.nc_q) for s in steps)
+        if args.timed_only:
+            R.close()
+            return {"workload": f"batch of {R.nprob} problems (Enright, LSGIR+FMFPA)", "name": "batch",
+                    "ms_per_step": sum(ms) / K, "timed_steps": steps, "face_steps_timed": fs,
+                    "interfacial_faces_per_step": (f1 - f0) / K, "interfacial_cells_per_step": (c1 - c0) / K,
+                    "faces_per_step": fs / K, "cells_per_step": cs / K}, None
+        # the same steps eagerly (the kernels launched one by one), then per kernel
+        eve = EventPairs(torch, K)
+        for i, s in enumerate(steps):
+            R.F.copy_(snaps[s])
+            one(s)
+            eve.a[i].record(st)
+            R.B.step(R.uf, R.uv, R.dt, R.act, R.F)
+            eve.b[i].record(st)
+        torch.cuda.synchronize()
+        mse = eve.ms()
+        kt, kcounts = None, None
+        if not args.no_kernels:
+            gvof.gvof_profile_read(R.B.h)
+            k0 = gvof.gvof_work_totals(R.B.h)
+            for i, s in enumerate(steps):
+                R.F.copy_(snaps[s])
+                one(s)
+                gvof.gvof_profile_enable(R.B.h, (1 << gvof.GVOF_NUM_KERNELS) - 1)
+                R.B.step(R.uf, R.uv, R.dt, R.act, R.F)
+                gvof.gvof_profile_enable(R.B.h, 0)
+            torch.cuda.synchronize()
+            kt = kernel_table(gvof, gvof.gvof_profile_read(R.B.h))
+            k1 = gvof.gvof_work_totals(R.B.h)
+            kcounts = {"steps": K, "interfacial_faces": k1[1] - k0[1], "interfacial_cells": k1[0] - k0[0],
+                       "faces": fs, "cells": cs}
+    tot = sum(ms)
+    res = {
+        "workload": f"batch of {R.nprob} problems (seed 2): sides 16..48, Cartesian or distorted (+-0.25h), sphere "
+                    f"r~U[0.1,0.2] at U[0.3,0.7]^3, Enright deformation T~U[1,3], CFL 0.5, LSGIR+FMFPA; each problem "
+                    f"to its own end time ({S} batch steps); one graph launch per batch step; timed steps "
+                    f"{steps[0]}..{steps[-1]} spread evenly",
+        "problems": R.nprob, "faces": int(R.B.nf), "cells": int(R.B.nc), "trajectory_steps": S, "timed_steps": steps,
+        "value": fs / (tot / 1e3), "unit": "face·steps/s", "ms_per_step": tot / K,
+        "value_eager": fs / (sum(mse) / 1e3), "ms_per_step_eager": sum(mse) / K,
+        "face_steps_timed": fs, "setup_s": setup_s, "wall_s": t_wall,
+        "interfacial_faces_per_step": (f1 - f0) / K, "interfacial_cells_per_step": (c1 - c0) / K,
+        "launch_config": tuned[0] if tuned else gvof.gvof_get_launch_config(R.B.h).as_dict(),
+        "launch_config_autotuned": tuned is not None,
+    }
+    if kt is not None:
+        res["kernels_ms_per_launch"] = {k: v[0] for k, v in kt.items() if v[1]}
+        res["rooflines"] = rooflines(kt, sum(mse) / K, kcounts, load_work_table(), "batch")
+    # a sample of the problems one by one (single-problem calls, their own handles), at the same steps
+    # from the same states (a problem's fractions in the batch equal its fractions alone, bit for bit)
+    sample = list(range(0, R.nprob, max(1, R.nprob // max(1, args.single_sample))))[: args.single_sample]
+    tot1, fs1 = 0.0, 0
+    with torch.cuda.stream(st):
+        for q in sample:
+            p = problems[q]
+            g = gvof.GvofMesh(p["mesh"], dev, stream=st)
+            ufq, uvq = torch.from_numpy(p["uf"]).to(dev), torch.from_numpy(p["uv"]).to(dev)
+            Fq, Fo = torch.empty(p["mesh"].nc, dtype=torch.float64, device=dev), None
+            Fo = torch.empty_like(Fq)
+            act = [s for s in steps if s < p["nsteps"]]
+            evq = EventPairs(torch, len(act))
+            for j, s in enumerate(act):
+                Fq.copy_(snaps[s][R.B.cells(q)])
+                evq.a[j].record(st)
+                g.reconstruct(Fq)
+                g.advect_step(ufq, uvq, p["dt_eff"][s], Fq, Fo)
+                evq.b[j].record(st)
+            st.synchronize()
+            g.status()
+            tot1 += sum(evq.ms())
+            fs1 += p["mesh"].nf * len(act)
+            g.close()
+    res["one_by_one"] = {"value": fs1 / (tot1 / 1e3) if tot1 > 0 else None, "unit": "face·steps/s",
+                         "sample": f"{len(sample)} of the {R.nprob} problems, each alone through the single-problem "
+                                   f"calls at the timed steps where it is active, from the same states"}
+    res["speedup_vs_one_by_one"] = res["value"] / res["one_by_one"]["value"] if tot1 > 0 else None
+    ctx = dict(problems=problems, steps=steps, cell_off=R.B.cell_off, snaps={s: v.cpu().numpy() for s, v in snaps.items()})
+    R.close()
+    del snaps
+    torch.cuda.empty_cache()
+    return res, ctx
+
+
+# ------------------------------------------------------------------ CPU baseline
+def cpu_run(jobs, budget_s, threads):
+    """The oracle (as it stands) on (mesh, F, u_f, u_v, dt) jobs until the budget is spent: face-steps/s and the
+    reconstruct / advect split."""
+    from oracle import oracle as O
+    used = O.set_threads(threads)
+    rec = adv = 0.0
+    fs = done = 0
+    t0 = time.perf_counter()
+    cache = {}
+    for key, mesh, F, uf, uv, dt in jobs:
+        om = cache.get(key)
+        if om is None:
+            om = cache[key] = O.OracleMesh(mesh)
+        a = time.perf_counter()
+        Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
+        b = time.perf_counter()
+        om.advect(pl, tc, tf, uf, uv, dt, Fc)
+        c = time.perf_counter()
+        rec += b - a
+        adv += c - b
+        fs += mesh.nf
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return {"value": fs / (rec + adv), "threads": used, "steps": done, "reconstruct_s": rec, "advect_s": adv}
+
+
+def cpu_baseline(jobs_all, jobs_one, budget_s, what):
+    allc = cpu_run(jobs_all, budget_s, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
+    one = cpu_run(jobs_one, budget_s, 1)
+    return {"value": allc["value"], "unit": "face·steps/s", "cores": allc["threads"], "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{what}: {allc['steps']} (problem, step) states with all threads in {allc['reconstruct_s'] + allc['advect_s']:.1f} s",
+            "reconstruct_s": allc["reconstruct_s"], "advect_s": allc["advect_s"],
+            "one_thread": {"value": one["value"], "steps": one["steps"], "reconstruct_s": one["reconstruct_s"],
+                           "advect_s": one["advect_s"]}}
+
+
+def batch_cpu_jobs(ctx):
+    """(problem, step) states of the batch's timed steps: problems in a spread order, each at every timed step
+    where it is active, so that a bounded run covers problems of every size and kind and the whole trajectory."""
+    P, steps, off = ctx["problems"], ctx["steps"], ctx["cell_off"]
+    order = sorted(range(len(P)), key=lambda q: (q % 16, q))
+    jobs = []
+    for q in order:
+        for s in steps:
+            if s < P[q]["nsteps"]:
+                jobs.append((q, P[q]["mesh"], ctx["snaps"][s][off[q]:off[q + 1]], P[q]["uf"], P[q]["uv"],
+                             P[q]["dt_eff"][s]))
+    return jobs
+
+
+def single_cpu_jobs(ctx):
+    m = ctx["mesh"]
+    return [(0, m, ctx["snaps"][s], ctx["uf"], ctx["uv"], ctx["dteff"][s]) for s in ctx["steps"]]
+
+
+# ------------------------------------------------------------------ main
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,192 +568,74 @@ def main():
     if args.copy_probe > 0:
         copy_probe(args.copy_probe)
         return
-    batch_problems = None
-    if args.batch > 0:
-        # host-side inputs first, in spawned workers, before anything touches the GPU
-        from paper_2111_01524_amd import batch_inputs, inputs as _inputs
-        t0 = time.perf_counter()
-        batch_problems = batch_inputs.generate(_inputs.batch_problem_specs(args.batch))
-        batch_gen_s = time.perf_counter() - t0
-        print(f"# batch inputs: {args.batch} problems in {batch_gen_s:.1f} s", file=sys.stderr, flush=True)
-    served = None
+    K, W = args.steps, args.warmup
     if args.served > 0:
+        import torch
+        print(json.dumps(served_leg(args, torch.device("cuda:0"))), flush=True)
+        return
+    problems = None
+    if args.workload == "batch":
         from paper_2111_01524_amd import batch_inputs, inputs as _inputs
         t0 = time.perf_counter()
-        sspecs = _inputs.served_job_specs()[: args.served]
-        served = (sspecs, batch_inputs.generate(sspecs))
-        print(f"# served inputs: {args.served} jobs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        problems = batch_inputs.generate(_inputs.batch_problem_specs(args.problems))
+        print(f"# batch inputs: {len(problems)} problems in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
     import torch
 
-    from paper_2111_01524_amd import gvof, inputs
-
     dev = torch.device("cuda:0")
-    n, T_end, cfl = args.n, 3.0, 0.5
-    mesh = inputs.cartesian_mesh(n) if args.kind == "cartesian" else inputs.jittered_mesh(n, seed=1)
-    g = gvof.GvofMesh(mesh, dev, method=args.method, recon=args.recon, lsfir_outer=args.lsfir_outer)
-    uf, uv = inputs.velocity_enright(mesh)
-    dt = inputs.cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
-    sched = inputs.step_schedule(T_end, dt)
-    times = np.concatenate([[0.0], np.cumsum(sched)])
-    dteff = [sched[s] * inputs.enright_time_factor(times[s] + 0.5 * sched[s], T_end) for s in range(len(sched))]
-    ufd = torch.from_numpy(uf).to(dev)
-    uvd = torch.from_numpy(uv).to(dev)
-    F0 = g.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
-    tuned = None
-    if args.launch_config:
-        d = gvof.gvof_get_launch_config(g.h).as_dict()
-        d.update(json.loads(args.launch_config))
-        gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**d))
-    elif not args.no_autotune:
-        # launch shapes measured at the middle of the trajectory, where the
-        # interface is most stretched (the timed steps restart from F0)
-        s_mid = len(sched) // 2
-        Fm, Fn = F0.clone(), torch.empty_like(F0)
-        for s in range(s_mid):
-            g.reconstruct(Fm)
-            g.advect_step(ufd, uvd, dteff[s], Fm, Fn)
-            Fm, Fn = Fn, Fm
-        dtm = torch.tensor([dteff[s_mid]], dtype=torch.float64, device=dev)
-        act0 = torch.ones(1, dtype=torch.uint8, device=dev)
-        cfg, tms = gvof.gvof_autotune(g.h, ufd, uvd, dtm, act0, Fm, Fn, 20)
-        tuned = cfg.as_dict()
-        del Fm, Fn
-    torch.cuda.synchronize()
-    state = {"s": 0}
-
-    # ping-pong without copies
-    bufs = [F0.clone(), torch.empty_like(F0)]
-
-    def step_pp(reconstructs=1):
-        s = state["s"]
-        if s == len(sched):
-            bufs[0].copy_(F0)
-            s = 0
-        for _ in range(reconstructs):
-            g.reconstruct(bufs[0])
-        g.advect_step(ufd, uvd, dteff[s], bufs[0], bufs[1])
-        bufs[0], bufs[1] = bufs[1], bufs[0]
-        state["s"] = s + 1
-
-    for _ in range(args.warmup):
-        step_pp()
-    torch.cuda.synchronize()
-    g.status()
-    c0, f0 = gvof.gvof_work_totals(g.h)
-    mask = (1 << gvof.GVOF_NUM_KERNELS) - 1 if args.profile_all else (1 << 5)  # k_flux_items_box
-    every = 1 if args.profile_all else max(1, args.event_every)
-    gvof.gvof_profile_read(g.h)  # clear
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for i in range(args.steps):
-        # the kernel's launch time is sampled on every `every`-th step, evenly over the timed region
-        if i % every == 0:
-            gvof.gvof_profile_enable(g.h, mask)
-        step_pp()
-        if i % every == 0:
-            gvof.gvof_profile_enable(g.h, 0)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    ms_total = e0.elapsed_time(e1)
-    prof = gvof.gvof_profile_read(g.h)
-    gvof.gvof_profile_enable(g.h, 0)
-    g.status()
-    c1, f1 = gvof.gvof_work_totals(g.h)
-    ncells_work, nfaces_work = c1 - c0, f1 - f0
-    K = args.steps
-    value = mesh.nf * K / (ms_total / 1e3)
-    # Reconstruction time: the same warm-up and timed steps again with
-    # gvof_reconstruct called twice per step.  The second call sees the
-    # fractions it has already cut off and repeats the same work, so the
-    # difference of the two timed runs is the reconstruction time.
-    recon_ms = None
-    if not args.no_recon_leg:
-        bufs[0].copy_(F0)
-        state["s"] = 0
-        for _ in range(args.warmup):
-            step_pp()
-        torch.cuda.synchronize()
-        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        r0.record(stream)
-        for _ in range(args.steps):
-            step_pp(reconstructs=2)
-        r1.record(stream)
-        torch.cuda.synchronize()
-        g.status()
-        recon_ms = (r0.elapsed_time(r1) - ms_total) / args.steps
-    flux_ms, flux_n = prof["k_flux_items_box"]
-    flux_ms_avg = flux_ms / max(flux_n, 1)
-    flops_per_face = FLOPS_PER_FLUX_FACE_TRUNCATION[args.method]
-    flux_flops_per_launch = flops_per_face * nfaces_work / K  # one launch per step
-    achieved_tflops = flux_flops_per_launch / (flux_ms_avg / 1e3) / 1e12 if flux_ms_avg > 0 else 0.0
+    if args.workload == "batch":
+        head, ctx = batch_leg(args, problems, dev, K, W)
+    else:
+        head, ctx = single_leg(args, args.workload, dev, K, W)
+    if args.timed_only:
+        print(json.dumps(head), flush=True)
+        return
+    subs = []
+    sub_ctx = {}
+    if not args.no_sub:
+        for kind in ("jittered", "cartesian"):
+            if kind != args.workload:
+                print(f"# sub-record: {kind}", file=sys.stderr, flush=True)
+                r, c = single_leg(args, kind, dev, K, W)
+                subs.append(r)
+                sub_ctx[kind] = c
     out = {
         "metric": "face·step flux updates/s",
-        "value": value,
+        "value": head["value"],
         "unit": "face·steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": ms_total / K,
+        "warmup": W,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": f"{args.kind} {n}^3 unit cube, sphere r=0.15 at 0.35, Enright deformation T=3, CFL 0.5, "
-                        f"{args.recon.upper()}{f' ({args.lsfir_outer} outer)' if args.recon == 'lsfir' else ''}"
-                        f"+{args.method.upper()}, {len(sched)} steps per trajectory",
-            "faces": mesh.nf, "cells": mesh.nc, "vertices": mesh.nv,
-        },
-        "cells_per_s": (mesh.nc / (recon_ms / 1e3) if recon_ms and recon_ms > 0 else None),
-        "reconstruct_ms_per_step": recon_ms,
-        "interfacial_faces_steps_per_s": nfaces_work / (ms_total / 1e3),
-        "launch_config": tuned if tuned is not None else gvof.gvof_get_launch_config(g.h).as_dict(),
-        "launch_config_autotuned": tuned is not None,
-        "interfacial_faces_per_step": nfaces_work / K,
-        "interfacial_cells_per_step": ncells_work / K,
-        "wall_s": t_wall,
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_flux_items_box",
-            "achieved": achieved_tflops,
-            "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": (ITEMS_BOX_TRAFFIC_BYTES
-                        if kernel_sources_digest() == ITEMS_BOX_TRAFFIC_SOURCES and args.method == "fmfpa"
-                        and args.kind == "cartesian" and n == 64 else None),
-            "traffic_unit": "bytes per launch (HBM, counters)",
-            "avg_launch_ms": flux_ms_avg,
-            "flops_per_unit": flops_per_face,
-            "unit_of_work": "face needing a flux polyhedron (truncation FLOPs)",
-            "units_per_launch": nfaces_work / K,
-            "launches_timed": flux_n,
-        },
+        "config": {k: head[k] for k in ("workload", "faces", "cells") if k in head},
     }
+    if "problems" in head:
+        out["config"]["problems"] = head["problems"]
+    rl = head.get("rooflines") or []
+    if rl:
+        out["roofline"] = rl[0]
+        out["rooflines"] = rl
+    for k in head:
+        if k not in ("value", "unit", "ms_per_step", "workload", "faces", "cells", "problems", "rooflines"):
+            out[k] = head[k]
     if not args.no_probes:
-        # measured ceilings: an FP64 FMA loop (libgvof_probe) and a plain copy
         from paper_2111_01524_amd import probe
-        fma_tflops = probe.measure_fp64_fma(dev)
-        out["probes"] = {"fp64_fma_tflops": fma_tflops, "copy_gbs": probe.measure_copy(dev)}
-        out["roofline"]["peak_measured"] = fma_tflops
-        out["roofline"]["frac_measured"] = achieved_tflops / fma_tflops
-    if args.profile_all:
-        out["kernels_ms_per_launch"] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
-    if batch_problems is not None:
-        del g, bufs, ufd, uvd
-        torch.cuda.empty_cache()
-        out["batched"] = batched_leg(args, batch_problems, dev)
-    if served is not None:
-        torch.cuda.empty_cache()
-        out["served"] = served_leg(args, served, dev)
+        out["probes"] = {"fp64_fma_tflops": probe.measure_fp64_fma(dev), "copy_gbs": probe.measure_copy(dev)}
+    if subs:
+        out["sub_records"] = subs
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, uf, uv, sched, dteff, args.cpu_seconds, args.method, args.recon,
-                                           args.lsfir_outer)
+        if args.workload == "batch":
+            jobs = batch_cpu_jobs(ctx)
+            out["cpu_baseline"] = cpu_baseline(jobs, jobs, args.cpu_seconds,
+                                               "the batch's problems at its timed steps, from the same states")
+        else:
+            jobs = single_cpu_jobs(ctx)
+            out["cpu_baseline"] = cpu_baseline(jobs, jobs, args.cpu_seconds, "the timed steps, from the same states")
     print(json.dumps(out), flush=True)
 
 
@@ -302,115 +652,67 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 5}), flush=True)
 
 
-def served_leg(args, served, dev):
-    """The served workload: the first jobs of the seeded Poisson arrival
-    stream (20 jobs/s, sides 32..128, both grid kinds, 50..500 steps), each
-    arriving at its own time with its inputs in host memory; admitted under
-    the HBM budget into cohorts that run concurrently; latency from arrival to
-    the job's fractions in host memory."""
-    from paper_2111_01524_amd import serve
+def served_specs(n: int, seed: int = 3, seeds_per_side: int = 4):
+    """The served workload's first n jobs (Poisson arrivals at 20/s, sides 32..128, half distorted, 50..500
+    steps), with the distorted grids drawn from a pool of seeds_per_side jitter seeds per side."""
+    from paper_2111_01524_amd import inputs
+    specs = inputs.served_job_specs(duration_s=2.0 * n / 20.0 + 10.0, rate=20.0, seed=seed)[:n]
+    for s in specs:
+        s["jitter_seed"] = 5000 + s["jitter_seed"] % seeds_per_side
+    return specs
 
-    specs, problems = served
-    jobs = serve.jobs_from_specs(specs, problems)
-    ex = serve.GpuExecutor(dev)
-    srv = serve.Server(ex, budget_bytes=int(args.served_budget_gb * 1e9), max_cohorts=4, depth=4,
-                       max_jobs_per_cohort=args.served_cohort_jobs or None)
-    rep = srv.run(jobs)
-    window = max(s["arrival"] for s in specs)
+
+def served_leg(args, dev):
+    """A capacity run (the first jobs all arriving at once), then args.served jobs whose Poisson arrivals are
+    slowed so that the offered load is args.served_load x that capacity.  Latency = result ready - arrival."""
+    from paper_2111_01524_amd import batch_inputs, inputs, serve
+
+    n_cap, N = args.served_capacity_jobs, args.served
+    specs = served_specs(max(N, n_cap))
+    t0 = time.perf_counter()
+    G = batch_inputs.grids(specs)
+    problems = [inputs.problem_inputs(s, grids=G) for s in specs]
+    print(f"# served: {len(specs)} jobs on {len(G)} grids, inputs in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    budget = int(args.served_budget_gb * 1e9)
+
+    def progress(tag, n):
+        cnt = [0]
+
+        def cb(j):
+            cnt[0] += 1
+            if cnt[0] % 4 == 0 or cnt[0] == n:
+                print(f"# served {tag}: {cnt[0]}/{n} done", file=sys.stderr, flush=True)
+        return cb
+
+    cap_specs = [dict(s, arrival=0.0) for s in specs[:n_cap]]
+    rep = serve.Server(serve.GpuExecutor(dev), budget, slots=args.served_slots).run(
+        serve.jobs_from_specs(cap_specs, problems[:n_cap]), progress("capacity", n_cap))
+    cap = rep.summary(arrival_window=0.0)
+    capacity = cap["value"]
+    fs = [p["mesh"].nf * p["nsteps"] for p in problems[:N]]
+    rate = args.served_load * capacity / (sum(fs) / N)  # jobs per second
+    sus_specs = [dict(s, arrival=s["arrival"] * 20.0 / rate) for s in specs[:N]]
+    jobs = serve.jobs_from_specs(sus_specs, problems[:N])
+    rep = serve.Server(serve.GpuExecutor(dev), budget, slots=args.served_slots).run(jobs, progress("sustained", N))
+    window = max(s["arrival"] for s in sus_specs)
     S = rep.summary(arrival_window=window)
-    S["unit"] = "face·steps/s"
-    S["workload"] = (f"first {len(specs)} jobs of the Poisson stream (20/s, seed 3), arrivals over {window:.2f} s, "
-                     f"sides {sorted(set(s['side'] for s in specs))}, budget {args.served_budget_gb:g} GB, "
-                     f"at most 4 cohorts of {args.served_cohort_jobs or 'any number of'} jobs")
-    S["latency_includes_queueing"] = True
-    return S
-
-
-def batched_leg(args, problems, dev):
-    """The batched workload (independent problems of uneven sizes and grid
-    kinds, each with its own sphere, period and time step) advanced together:
-    one captured step per graph launch, launch shapes autotuned, against the
-    same problems advanced one after another through the single-problem calls."""
-    import torch
-
-    from paper_2111_01524_amd import gvof
-    from paper_2111_01524_amd.runtime import BatchRun
-
-    st = torch.cuda.Stream()
-    t0 = time.perf_counter()
-    R = BatchRun(problems, dev, st)
-    setup_s = time.perf_counter() - t0
-    print(f"# batch bound: nf={R.B.nf} nc={R.B.nc} setup {setup_s:.1f} s tuned {R.tuned}", file=sys.stderr, flush=True)
-    W, K = args.batch_warmup, args.batch_steps
-    for _ in range(W):
-        R.step()
-    st.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(K):
-        R.step()
-    e1.record(st)
-    st.synchronize()
-    R.status()
-    ms = e0.elapsed_time(e1)
-    fs = R.face_steps(W, W + K)
-    res = {
-        "workload": f"{R.nprob} problems, sides 16..48, Cartesian or distorted (+-0.25h), sphere r~U[0.1,0.2], "
-                    f"centre~U[0.3,0.7]^3, Enright period T~U[1,3], CFL 0.5; steps {W}..{W + K - 1}",
-        "faces": int(R.B.nf), "cells": int(R.B.nc),
-        "value": fs / (ms / 1e3), "unit": "face·steps/s", "ms_per_step": ms / K, "steps": K, "warmup": W,
-        "launch_config": R.tuned[0] if R.tuned else None, "autotune_ms_per_step": R.tuned[1] if R.tuned else None,
-        "setup_s": setup_s,
+    lat = np.array([j.t_done - j.arrival for j in jobs if j.t_done is not None])
+    run = np.array([j.t_done - j.t_start for j in jobs if j.t_done is not None])
+    return {
+        "metric": "served face·steps/s; p50/p99 latency", "unit": "face·steps/s",
+        "workload": f"served jobs (seed 3): sides 32/64/96/128, Cartesian or distorted (+-0.25h; 4 jitter seeds per "
+                    f"side), sphere r~U[0.1,0.2] at U[0.3,0.7]^3, Enright deformation T~U[1,3], CFL 0.5, 50..500 "
+                    f"steps, LSGIR+FMFPA; budget {args.served_budget_gb:g} GB, {args.served_slots} slots",
+        "capacity": {"jobs": n_cap, "value": capacity, "makespan_s": cap["makespan_s"],
+                     "how": "all jobs arriving at t=0, face·steps / makespan"},
+        "target_load": args.served_load, "arrival_rate_jobs_per_s": rate,
+        "sustained": S,
+        "latency_s": {"p50": S["p50_latency_s"], "p90": float(np.percentile(lat, 90)), "p99": S["p99_latency_s"],
+                      "max": float(lat.max())},
+        "run_time_s": {"p50": float(np.percentile(run, 50)), "p99": float(np.percentile(run, 99))},
+        "offered_vs_capacity": S.get("offered_face_steps_per_s", 0.0) / capacity if capacity else None,
     }
-    R.close()
-    del R
-    torch.cuda.empty_cache()
-    # the same problems one after another, each on its own handle, single-problem calls
-    Ks = args.single_steps
-    tot_ms, tot_fs = 0.0, 0
-    with torch.cuda.stream(st):
-        for qi, p in enumerate(problems):
-            if qi % 32 == 0:
-                print(f"# one-by-one: problem {qi}/{len(problems)}", file=sys.stderr, flush=True)
-            g = gvof.GvofMesh(p["mesh"], dev, stream=st)
-            ufd, uvd = torch.from_numpy(p["uf"]).to(dev), torch.from_numpy(p["uv"]).to(dev)
-            F = g.init_fraction(p["shape"][0], p["shape"][1], 10)
-            g.reconstruct(F)
-            g.advect_step(ufd, uvd, p["dt_eff"][0], F, F)
-            e0.record(st)
-            for s in range(1, 1 + Ks):
-                g.reconstruct(F)
-                g.advect_step(ufd, uvd, p["dt_eff"][min(s, p["nsteps"] - 1)], F, F)
-            e1.record(st)
-            st.synchronize()
-            tot_ms += e0.elapsed_time(e1)
-            tot_fs += p["mesh"].nf * Ks
-            g.status()
-            g.close()
-            del g, F, ufd, uvd
-    res["one_by_one"] = {"value": tot_fs / (tot_ms / 1e3), "unit": "face·steps/s",
-                         "sample": f"every problem alone, steps 1..{Ks} after one untimed step, sum of event times"}
-    res["speedup_vs_one_by_one"] = res["value"] / res["one_by_one"]["value"]
-    return res
-
-
-def cpu_baseline(mesh, uf, uv, sched, dteff, budget_s, method, recon, lsfir_outer):
-    """The CPU reference (as it stands) on the host cores: the first steps of the same trajectory."""
-    from oracle import oracle as O
-    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1))
-    om = O.OracleMesh(mesh, method=method, recon=recon, lsfir_outer=lsfir_outer)
-    F = om.init_fraction("sphere", [0.35, 0.35, 0.35, 0.15], 10)
-    t0 = time.perf_counter()
-    done = 0
-    while done < len(sched):
-        Fc, Fs, tn, tf, tc, pl = om.reconstruct(F)
-        F, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dteff[done], Fc)
-        done += 1
-        if time.perf_counter() - t0 > budget_s and done >= 2:
-            break
-    el = time.perf_counter() - t0
-    return {"value": mesh.nf * done / el, "unit": "face·steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} steps of the same trajectory from t=0 on the full mesh ({el:.1f} s)"}
 
 
 if __name__ == "__main__":

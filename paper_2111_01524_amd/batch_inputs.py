@@ -1,27 +1,30 @@
-"""Parallel host-side generation of many problems' inputs (grids, Enright
-field, time steps, bodies) with a spawned process pool: the generators are
-numpy-bound and independent per problem.  Spawned workers import only numpy
-and the input generators, never the GPU runtime."""
+"""Host-side generation of many problems' inputs (grids, Enright field, time
+steps, bodies) on a pool of threads: the generators spend their time in numpy,
+which releases the interpreter lock, and a thread pool starts no process (so
+it also runs under a profiler that has already initialised the GPU)."""
 from __future__ import annotations
 
-import multiprocessing as mp
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 from . import inputs
 
 
-def _one(args):
-    spec, steps = args
-    return inputs.problem_inputs(spec, steps=steps)
+def _workers(n_items: int, workers: int | None) -> int:
+    return workers or min(16, os.cpu_count() or 1, max(1, n_items))
 
 
 def generate(specs, workers: int | None = None, steps=None):
     """problem_inputs(spec) for every spec, in order (steps: None, or one count per spec)."""
     steps = steps if steps is not None else [None] * len(specs)
-    work = list(zip(specs, steps))
-    n = workers or min(16, os.cpu_count() or 1, max(1, len(work)))
-    if n <= 1 or len(work) <= 1:
-        return [_one(w) for w in work]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(n) as pool:
-        return pool.map(_one, work, chunksize=1)
+    with ThreadPoolExecutor(_workers(len(specs), workers)) as pool:
+        return list(pool.map(lambda w: inputs.problem_inputs(w[0], steps=w[1]), zip(specs, steps)))
+
+
+def grids(specs, workers: int | None = None) -> dict:
+    """inputs.grid_inputs of every distinct grid among the specs (grid_key -> inputs), built in parallel."""
+    uniq = {}
+    for s in specs:
+        uniq.setdefault(inputs.grid_key(s), s)
+    with ThreadPoolExecutor(_workers(len(uniq), workers)) as pool:
+        return dict(zip(uniq, pool.map(inputs.grid_inputs, uniq.values())))

@@ -364,16 +364,28 @@ def served_job_specs(duration_s: float = 60.0, rate: float = 20.0, seed: int = 3
     return jobs
 
 
-def problem_inputs(spec: dict, cfl: float = 0.5, steps: int | None = None) -> dict:
+def grid_key(spec: dict):
+    """What a problem's grid and velocity field depend on."""
+    return (int(spec["side"]), spec["kind"], int(spec["jitter_seed"]) if spec["kind"] == "jittered" else 0)
+
+
+def grid_inputs(spec: dict, cfl: float = 0.5):
+    """A problem's grid, the Enright field u0 at its faces and vertices, and its CFL time step."""
+    n = int(spec["side"])
+    mesh = cartesian_mesh(n) if spec["kind"] == "cartesian" else jittered_mesh(n, seed=int(spec["jitter_seed"]))
+    uf, uv = velocity_enright(mesh)
+    return mesh, uf, uv, cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
+
+
+def problem_inputs(spec: dict, cfl: float = 0.5, steps: int | None = None, grids: dict | None = None) -> dict:
     """Inputs of one batched or served problem: its grid, the Enright field
     u0 at faces and vertices, the body, and the effective time step of every
     step, dt_s * cos(pi t_{s+1/2} / T) (the field's time factor folded into dt).
     The problem runs to its own period T, or for `steps` steps (served jobs,
-    spec["steps"]) of the CFL time step."""
-    n = int(spec["side"])
-    mesh = cartesian_mesh(n) if spec["kind"] == "cartesian" else jittered_mesh(n, seed=int(spec["jitter_seed"]))
-    uf, uv = velocity_enright(mesh)
-    dt = cfl_dt(mesh, np.abs(uf).max(axis=1), cfl)
+    spec["steps"]) of the CFL time step.  `grids` (grid_key -> grid_inputs)
+    lends grids already built; problems then share their arrays."""
+    g = grids.get(grid_key(spec)) if grids is not None else None
+    mesh, uf, uv, dt = g if g is not None else grid_inputs(spec, cfl)
     T = float(spec["period"])
     nsteps = steps if steps is not None else spec.get("steps")
     sched = step_schedule(T, dt) if nsteps is None else [dt] * int(nsteps)
