@@ -1489,38 +1489,43 @@ __device__ inline TetCont run_planes(const RunLds& S, int t) {
   return C;
 }
 
+// Face plane l of the tetrahedron (a, b, c, d), as tet_container computes it
+// (c and d already swapped for a negative orientation).
+__device__ __forceinline__ Plane tet_face_plane(int l, d3 a, d3 b, d3 c, d3 d) {
+  const d3 N = l == 0 ? crossf(c - a, b - a) : (l == 1 ? crossf(b - a, d - a) : (l == 2 ? crossf(d - a, c - a) : crossf(c - b, d - b)));
+  return Plane{mk3(-N.x, -N.y, -N.z), dotf(N, l == 3 ? b : a)};
+}
 // unit_rule for entry (flux tet t, surface tetrahedron q0 q1 q2 about cc) of a
-// run, with the flux tet's data read from LDS as each test needs it and the
-// surface tetrahedron's planes computed one at a time, as tet_container
-// computes them (fewer live registers); the same operations, so the same
-// decisions and the same unit word.
-__device__ inline bool run_unit_rule(const RunLds& S, int t, d3 cc, d3 q0, d3 q1, d3 q2, unsigned& word) {
-  word = 0;
-  {
-    const double* bx = S.tb[t];
-    if (!box_overlap(mk3(bx[0], bx[1], bx[2]), mk3(bx[3], bx[4], bx[5]), vmin(vmin(cc, q0), vmin(q1, q2)),
-                     vmax(vmax(cc, q0), vmax(q1, q2))))
-      return false;
+// run's list, which holds only pairs whose boxes meet and whose surface
+// tetrahedron is not flat (neg: its orientation is negative).  The flux tet's
+// data come from LDS as each test needs them; the surface tetrahedron's planes
+// are computed one at a time by the fixed formulas tet_container applies
+// (unrolled, so no plane is picked at run time).  The same operations on the
+// same values as unit_rule, so the same decisions and the same unit word.
+__device__ __forceinline__ void run_forward_plane(const Plane& P, const Tet& T, int l, unsigned& cm, unsigned& wa,
+                                                  bool& out) {
+  const double s0 = P.dist(T.p0), s1 = P.dist(T.p1), s2 = P.dist(T.p2), s3 = P.dist(T.p3);
+  if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) out = true;
+  if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+    if (cm == 0u) wa = wide_bit(s0, s1, s2, s3);
+    cm |= 1u << l;
   }
-  const double s6 = det3f(q0 - cc, q1 - cc, q2 - cc);
-  if (s6 == 0.0) return false;
+}
+__device__ inline bool run_unit_rule(const RunLds& S, int t, bool neg, d3 cc, d3 q0, d3 q1, d3 q2, unsigned& word) {
+  word = 0;
   unsigned cm = 0, wa = 0;
   {
     const Tet T = run_tet(S, t);
-    const d3 a = cc, b = q0, c = s6 < 0.0 ? q2 : q1, d = s6 < 0.0 ? q1 : q2;
-#pragma unroll 1
-    for (int l = 0; l < 4; ++l) {
-      const d3 u = l == 0 ? c - a : (l == 1 ? b - a : (l == 2 ? d - a : c - b));
-      const d3 w = l == 0 ? b - a : (l == 1 ? d - a : (l == 2 ? c - a : d - b));
-      const d3 N = crossf(u, w);
-      const Plane P{mk3(-N.x, -N.y, -N.z), dotf(N, l == 3 ? b : a)};
-      const double s0 = P.dist(T.p0), s1 = P.dist(T.p1), s2 = P.dist(T.p2), s3 = P.dist(T.p3);
-      if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
-      if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
-        if (cm == 0u) wa = wide_bit(s0, s1, s2, s3);
-        cm |= 1u << l;
-      }
-    }
+    const d3 a = cc, b = q0, c = neg ? q2 : q1, d = neg ? q1 : q2;
+    bool out = false;
+    run_forward_plane(tet_face_plane(0, a, b, c, d), T, 0, cm, wa, out);
+    if (out) return false;
+    run_forward_plane(tet_face_plane(1, a, b, c, d), T, 1, cm, wa, out);
+    if (out) return false;
+    run_forward_plane(tet_face_plane(2, a, b, c, d), T, 2, cm, wa, out);
+    if (out) return false;
+    run_forward_plane(tet_face_plane(3, a, b, c, d), T, 3, cm, wa, out);
+    if (out) return false;
   }
   unsigned rm = 0, wb = 0;
   const double* q = S.tp[t];
@@ -1690,10 +1695,12 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
         // boxes: bit t set when flux tet t's box meets this lane's surface tetrahedron's
         unsigned pb = 0;
         d3 t0 = cc, t1 = cc, t2 = cc;
-        bool flat = true;
+        bool flat = true, neg = false;
         if (sub < np) {
           sigma(sub, t0, t1, t2);
-          flat = det3f(t0 - cc, t1 - cc, t2 - cc) == 0.0;
+          const double s6 = det3f(t0 - cc, t1 - cc, t2 - cc);
+          flat = s6 == 0.0;
+          neg = s6 < 0.0;
         }
         const d3 slo = vmin(vmin(cc, t0), vmin(t1, t2)), shi = vmax(vmax(cc, t0), vmax(t1, t2));
         if (sub < np && !flat) {
@@ -1709,7 +1716,7 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
           const bool in = (pb >> t) & 1u;
           const unsigned long long bt = __ballot(in) & gmask;
           if (sub == 0) S.seg[t] = ncombo;
-          if (in) S.list[ncombo + __popcll(bt & lbelow)] = (unsigned short)((t << 8) | sub);
+          if (in) S.list[ncombo + __popcll(bt & lbelow)] = (unsigned short)((t << 8) | (neg ? 32u : 0u) | sub);
           ncombo += __popcll(bt);
         }
         if (sub == 0) S.seg[Rc] = ncombo;
@@ -1717,11 +1724,12 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
         // plane tests, one entry per lane
         for (int c = sub; c < ncombo; c += kRunLanes) {
           const unsigned e = S.list[c];
-          const int t = (int)(e >> 8), p = (int)(e & 255u);
+          const int t = (int)(e >> 8), p = (int)(e & 31u);
           d3 q0, q1, q2;
           sigma(p, q0, q1, q2);
           unsigned cm;
-          S.code[c] = run_unit_rule(S, t, cc, q0, q1, q2, cm) ? (unsigned short)(0x8000u | cm) : (unsigned short)0;
+          S.code[c] = run_unit_rule(S, t, (e & 32u) != 0u, cc, q0, q1, q2, cm) ? (unsigned short)(0x8000u | cm)
+                                                                            : (unsigned short)0;
         }
         wave_lds_sync();
         // each pair's survivors: their count and places, then the run's range
@@ -1774,7 +1782,7 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
               const int t = (int)(e >> 8);
               const int u = ub + S.off[t] + S.rank[c];
               M.unit_item[u] = i0 + c0 + t;
-              M.unit_code[u] = (e & 255u) | ((code & 0x7fffu) << 16);
+              M.unit_code[u] = (e & 31u) | ((code & 0x7fffu) << 16);
             }
           }
         }
