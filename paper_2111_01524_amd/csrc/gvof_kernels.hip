@@ -1679,14 +1679,10 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
           const bool swp = det3f(T.p1 - T.p0, T.p2 - T.p0, T.p3 - T.p0) < 0.0;
           const d3 a = T.p0, b = T.p1, c = swp ? T.p3 : T.p2, d = swp ? T.p2 : T.p3;
           double* q = S.tp[sub];
-#pragma unroll 1
-          for (int l = 0; l < 4; ++l) {
-            const d3 u = l == 0 ? c - a : (l == 1 ? b - a : (l == 2 ? d - a : c - b));
-            const d3 w = l == 0 ? b - a : (l == 1 ? d - a : (l == 2 ? c - a : d - b));
-            const d3 N = crossf(u, w);
-            const double off = dotf(N, l == 3 ? b : a);
-            const Plane P{mk3(-N.x, -N.y, -N.z), off};
-            q[3 * l] = P.n.x; q[3 * l + 1] = P.n.y; q[3 * l + 2] = P.n.z; q[12 + l] = off;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {  // (each plane by its fixed formula, stored before the next)
+            const Plane P = tet_face_plane(l, a, b, c, d);
+            q[3 * l] = P.n.x; q[3 * l + 1] = P.n.y; q[3 * l + 2] = P.n.z; q[12 + l] = P.d;
             S.tsc[sub][l] = P.dist(cc);
           }
         }
