@@ -1502,11 +1502,20 @@ __device__ __forceinline__ Plane tet_face_plane(int l, d3 a, d3 b, d3 c, d3 d) {
 // are computed one at a time by the fixed formulas tet_container applies
 // (unrolled, so no plane is picked at run time).  The same operations on the
 // same values as unit_rule, so the same decisions and the same unit word.
+// (unit_rule's "largest distance <= 0" and "smallest distance < 0" as
+// comparisons of the four distances: the same decisions for finite values,
+// in compares that need no canonicalising of max / min operands)
+__device__ __forceinline__ bool all_nonpos(double s0, double s1, double s2, double s3) {
+  return s0 <= 0.0 && s1 <= 0.0 && s2 <= 0.0 && s3 <= 0.0;
+}
+__device__ __forceinline__ bool any_neg(double s0, double s1, double s2, double s3) {
+  return s0 < 0.0 || s1 < 0.0 || s2 < 0.0 || s3 < 0.0;
+}
 __device__ __forceinline__ void run_forward_plane(const Plane& P, const Tet& T, int l, unsigned& cm, unsigned& wa,
                                                   bool& out) {
   const double s0 = P.dist(T.p0), s1 = P.dist(T.p1), s2 = P.dist(T.p2), s3 = P.dist(T.p3);
-  if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) out = true;
-  if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+  if (all_nonpos(s0, s1, s2, s3)) out = true;
+  if (any_neg(s0, s1, s2, s3)) {
     if (cm == 0u) wa = wide_bit(s0, s1, s2, s3);
     cm |= 1u << l;
   }
@@ -1533,8 +1542,8 @@ __device__ inline bool run_unit_rule(const RunLds& S, int t, bool neg, d3 cc, d3
   for (int l = 0; l < 4; ++l) {
     const Plane P{mk3(q[3 * l], q[3 * l + 1], q[3 * l + 2]), q[12 + l]};
     const double s0 = S.tsc[t][l], s1 = P.dist(q0), s2 = P.dist(q1), s3 = P.dist(q2);
-    if (fmax(fmax(s0, s1), fmax(s2, s3)) <= 0.0) return false;
-    if (fmin(fmin(s0, s1), fmin(s2, s3)) < 0.0) {
+    if (all_nonpos(s0, s1, s2, s3)) return false;
+    if (any_neg(s0, s1, s2, s3)) {
       if (rm == 0u) wb = wide_bit(s0, s1, s2, s3);
       rm |= 1u << l;
     }

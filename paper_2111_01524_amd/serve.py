@@ -183,7 +183,8 @@ class GpuExecutor:
     library's calls release the interpreter lock), so the loop keeps the
     device fed meanwhile."""
 
-    def __init__(self, device, launch_config: dict | None = None, n_div: int = 10, workers: int = 2):
+    def __init__(self, device, launch_config: dict | None = None, n_div: int = 10, workers: int = 2,
+                 reserve_cap_bytes: int | None = None):
         import torch
 
         from . import gvof
@@ -193,6 +194,11 @@ class GpuExecutor:
         self.launch_config = launch_config
         self.n_div = n_div
         self.pool = ThreadPoolExecutor(max_workers=workers)
+        # torch's caching allocator keeps a released job's blocks for its stream; jobs of other sizes on other
+        # streams then allocate afresh, so the cache can outgrow the budget.  Past this cap (by default 85% of
+        # the device), a set-up about to allocate and a release hand the unused blocks back to the device.
+        total = torch.cuda.get_device_properties(device).total_memory
+        self.reserve_cap = int(reserve_cap_bytes if reserve_cap_bytes is not None else 0.85 * total)
 
     def now(self):
         return time.perf_counter()
@@ -232,6 +238,8 @@ class GpuExecutor:
     # -- set-up: bind the handle to a workspace, upload the velocities, initialise the fractions
     def _start(self, job):
         torch, p = self.torch, job.payload
+        if torch.cuda.memory_reserved(self.device) + job.bytes > self.reserve_cap:
+            torch.cuda.empty_cache()
         st = torch.cuda.Stream(self.device)
         h, job.part = job.part, None
         with torch.cuda.stream(st):
@@ -301,6 +309,8 @@ class GpuExecutor:
         g.close()
         for k in ("g", "uf", "uv", "F", "Fn", "events", "done_ev"):
             h[k] = None
+        if self.torch.cuda.memory_reserved(self.device) > self.reserve_cap:
+            self.torch.cuda.empty_cache()
 
 
 def jobs_from_specs(specs, problems):
