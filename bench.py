@@ -562,6 +562,7 @@ def single_cpu_jobs(ctx):
 
 # ------------------------------------------------------------------ main
 def main():
+    t_start = time.perf_counter()
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -642,6 +643,7 @@ def main():
             r["cpu_baseline"] = cpu_baseline(jobs, jobs, 0.5 * args.cpu_seconds,
                                              "the timed steps, from the same states")
     print(json.dumps(out), flush=True)
+    print(f"# bench done in {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
 
 
 def copy_probe(mib: int):
