@@ -332,10 +332,12 @@ int gvof_graph_launch(gvof_mesh* m);
  *   sweep_threads           block size of the vertex / face / cell sweeps (multiple of 64, 64..1024)
  *   recon_threads           block size of the reconstruction kernel (64 or 128)
  *   prep_blocks             grid of the flux-polyhedron staging kernel, blocks of one wavefront (1..2^20)
- *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256)
+ *   pair_blocks_per_region  blocks serving each of the 256 regions of the pair buffer (1..256) in the box-cell
+ *                           truncation, the per-pair general-cell filter, the unit kernel and the sums
  *   filter_lanes            general-cell filter: 0 takes each run of a face's pairs with one cell together
- *                           (32 lanes, the default); 8, 16, 32, 64 give each (face, cell, flux tetrahedron)
- *                           pair that many lanes.  Every choice gives the same units.
+ *                           (a group of 32 lanes per run, two groups per one-wavefront block, over a grid
+ *                           of its own; the default); 8, 16, 32, 64 give each (face, cell, flux
+ *                           tetrahedron) pair that many lanes.  Every choice gives the same units.
  *   staged_faces            most faces whose flux work is staged per step (0: as many as the workspace
  *                           holds); the others are computed whole by the overflow kernel, with the same
  *                           values.  Not tuned by gvof_autotune.
