@@ -1436,16 +1436,20 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
 // gives the same units).  The staging kernel writes a face's pairs candidate
 // by candidate, so the pairs of one face with one cell are consecutive in the
 // pair buffer: a run, whose flux tets all meet the same surface tetrahedra.
-// A group of kRunLanes lanes takes a run and
+// A block first scans its pairs, one per lane, for where runs start and end,
+// and loads each run's cell data (piece count, vertex mean, the offset of its
+// cached surface triangles) for all its runs at once.  A group of kRunLanes
+// lanes then takes a run and
 //  - stages up to kRunTets of its flux tets in LDS (vertices, box, inward
-//    face planes);
+//    face planes, distances of the cell's vertex mean from those planes);
 //  - gives each surface tetrahedron a lane, which loads it once for the run
 //    and tests its box against every flux tet's;
 //  - lists the (flux tet, surface tetrahedron) pairs whose boxes meet, flux
-//    tet by flux tet in surface order, and gives the list's entries one lane
-//    each for the plane tests of unit_rule (the rule every path applies);
+//    tet by flux tet in surface order, with the surface tetrahedron's
+//    orientation, and gives the list's entries one lane each for the plane
+//    tests of unit_rule (the rule every path applies);
 //  - writes each pair's survivors in surface order into a range of the unit
-//    buffer reserved with one atomic per run.
+//    buffer, taken from a pool the block reserves once per pass.
 // So each pair gets the units k_flux_gen_filter gives it, in the same order.
 // Cells with more than kRunLanes surface pieces leave their pairs to the
 // deferred kernel.
@@ -1464,7 +1468,7 @@ struct RunLds {
   double tv[kRunTets][12];  // flux tet vertices
   double tp[kRunTets][16];  // inward face planes: normals n0..n3, then offsets d0..d3
   double tb[kRunTets][6];   // box: lo, hi
-  unsigned short list[kRunTets * kRunLanes];  // flux tet << 8 | surface tetrahedron
+  unsigned short list[kRunTets * kRunLanes];  // flux tet << 8 | 32 if negatively oriented | surface tetrahedron
   unsigned short code[kRunTets * kRunLanes];  // survivor: 0x8000 | unit word (cut mask, first-cut width)
   unsigned char rank[kRunTets * kRunLanes];   // survivor's place among its pair's units
   double tsc[kRunTets][4];  // distances of the cell's vertex mean from each flux tet's face planes
@@ -1475,20 +1479,6 @@ __device__ inline Tet run_tet(const RunLds& S, int t) {
   const double* v = S.tv[t];
   return Tet{mk3(v[0], v[1], v[2]), mk3(v[3], v[4], v[5]), mk3(v[6], v[7], v[8]), mk3(v[9], v[10], v[11])};
 }
-__device__ inline TetCont run_planes(const RunLds& S, int t) {
-  const double* q = S.tp[t];
-  TetCont C;
-  C.n0 = mk3(q[0], q[1], q[2]);
-  C.n1 = mk3(q[3], q[4], q[5]);
-  C.n2 = mk3(q[6], q[7], q[8]);
-  C.n3 = mk3(q[9], q[10], q[11]);
-  C.d0 = q[12];
-  C.d1 = q[13];
-  C.d2 = q[14];
-  C.d3_ = q[15];
-  return C;
-}
-
 // Face plane l of the tetrahedron (a, b, c, d), as tet_container computes it
 // (c and d already swapped for a negative orientation).
 __device__ __forceinline__ Plane tet_face_plane(int l, d3 a, d3 b, d3 c, d3 d) {

@@ -49,14 +49,18 @@ UNIT = {"k_flux_prep": "interfacial_faces", "k_flux_items_box": "interfacial_fac
 
 
 def sources_digest() -> str:
-    """Digest of the HIP sources the kernels are built from."""
+    """Digest of the code of the HIP sources the kernels are built from (comments and whitespace excluded,
+    so that editing a comment does not disown the counters taken on the same kernels)."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+            with open(os.path.join(d, f)) as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(f.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
