@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gvof.h"
@@ -142,6 +143,72 @@ void gvof_params_default(gvof_params* p) {
   p->lsfir_tol = 1e-3;
 }
 
+}  // extern "C"
+
+// fn(begin, end, t) over nt contiguous ranges of [0, n), on worker threads.
+template <class Fn>
+static int parallel_ranges(int n, Fn fn) {
+  const int nt = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, n / 4096 + 1}));
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back([&, t] { fn((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt), t); });
+  fn(0, (int)((long)n / nt), 0);
+  for (auto& x : th) x.join();
+  return nt;
+}
+
+// Per-cell sorted lists built by worker threads over contiguous ranges of
+// cells and joined in cell order, so the result is the serial one.  body(c,
+// list) fills cell c's list and returns 0, or an error code for the first
+// failing cell (the lowest failing cell is reported, as a serial loop would).
+template <class Body>
+static int per_cell_lists(int nc, std::vector<int>& ptr, std::vector<int>& idx, int& bad_cell, Body body) {
+  const int nt = std::max(1, std::min<int>({(int)std::thread::hardware_concurrency(), 16, nc / 4096 + 1}));
+  std::vector<std::vector<int>> part(nt);
+  std::vector<std::vector<int>> cnt(nt);
+  std::vector<int> err(nt, 0), errc(nt, -1);
+  auto work = [&](int t) {
+    const int c0 = (int)((long)nc * t / nt), c1 = (int)((long)nc * (t + 1) / nt);
+    std::vector<int> list;
+    cnt[t].reserve(c1 - c0);
+    for (int c = c0; c < c1; ++c) {
+      list.clear();
+      const int e = body(c, list);
+      if (e) {
+        err[t] = e;
+        errc[t] = c;
+        return;
+      }
+      cnt[t].push_back((int)list.size());
+      part[t].insert(part[t].end(), list.begin(), list.end());
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  for (int t = 0; t < nt; ++t)
+    if (err[t]) {
+      bad_cell = errc[t];
+      return err[t];
+    }
+  ptr.assign(nc + 1, 0);
+  size_t total = 0;
+  for (int t = 0; t < nt; ++t) total += part[t].size();
+  idx.clear();
+  idx.reserve(total);
+  int c = 0;
+  for (int t = 0; t < nt; ++t) {
+    for (int n : cnt[t]) {
+      ptr[c + 1] = ptr[c] + n;
+      ++c;
+    }
+    idx.insert(idx.end(), part[t].begin(), part[t].end());
+  }
+  return 0;
+}
+
+extern "C" {
+
 int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double* vy, const double* vz, int32_t nf,
                      const int32_t* fv_ptr, const int32_t* fv_idx, const int32_t* owner, const int32_t* neigh,
                      int32_t nc, const gvof_params* params) {
@@ -217,40 +284,44 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
       return fail(nullptr, GVOF_E_MESH, "cell %d has fewer than 4 faces", c);
     }
   // cell -> distinct vertices (ascending)
-  m->cv_ptr.assign(nc + 1, 0);
-  std::vector<int> tmp;
-  std::vector<int> cv;
-  cv.reserve(nfv * 2);
-  for (int c = 0; c < nc; ++c) {
-    tmp.clear();
-    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
-      int e = m->cf_idx[i];
-      int f = e >= 0 ? e : ~e;
-      for (int j = fv_ptr[f]; j < fv_ptr[f + 1]; ++j) tmp.push_back(fv_idx[j]);
-    }
-    std::sort(tmp.begin(), tmp.end());
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    int npoly = 0;
-    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
-      int e = m->cf_idx[i];
-      int f = e >= 0 ? e : ~e;
-      if (fv_ptr[f + 1] - fv_ptr[f] > 3) ++npoly;
-    }
-    if ((int)tmp.size() > gvof::kMaxCellVerts || (int)tmp.size() + 1 + npoly > gvof::kMaxLevels) {
+  {
+    const bool iso = (m->p.flags & (GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR)) != 0;
+    int bad = -1;
+    const int e = per_cell_lists(nc, m->cv_ptr, m->cv_idx, bad, [&](int c, std::vector<int>& tmp) {
+      int npoly = 0;
+      for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+        const int e2 = m->cf_idx[i], f = e2 >= 0 ? e2 : ~e2;
+        for (int j = fv_ptr[f]; j < fv_ptr[f + 1]; ++j) tmp.push_back(fv_idx[j]);
+        if (fv_ptr[f + 1] - fv_ptr[f] > 3) ++npoly;
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      if ((int)tmp.size() > gvof::kMaxCellVerts || (int)tmp.size() + 1 + npoly > gvof::kMaxLevels) return 1;
+      if (iso && m->cf_ptr[c + 1] - m->cf_ptr[c] > gvof::kMaxIsoFaces) return 2;
+      return 0;
+    });
+    if (e) {
+      const int c = bad;
+      int nvc = 0, npoly = 0;
+      {
+        std::vector<int> tmp;
+        for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+          const int e2 = m->cf_idx[i], f = e2 >= 0 ? e2 : ~e2;
+          for (int j = fv_ptr[f]; j < fv_ptr[f + 1]; ++j) tmp.push_back(fv_idx[j]);
+          if (fv_ptr[f + 1] - fv_ptr[f] > 3) ++npoly;
+        }
+        std::sort(tmp.begin(), tmp.end());
+        nvc = (int)(std::unique(tmp.begin(), tmp.end()) - tmp.begin());
+      }
+      const int nfc = m->cf_ptr[c + 1] - m->cf_ptr[c];
       delete m;
-      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %zu vertices and %d polygon faces (limits %d / %d levels)", c,
-                  tmp.size(), npoly, gvof::kMaxCellVerts, gvof::kMaxLevels);
-    }
-    const int nfc = m->cf_ptr[c + 1] - m->cf_ptr[c];
-    if ((m->p.flags & (GVOF_FLAG_LLCIR | GVOF_FLAG_ELCIR | GVOF_FLAG_CLCIR)) && nfc > gvof::kMaxIsoFaces) {
-      delete m;
+      if (e == 1)
+        return fail(nullptr, GVOF_E_LIMIT, "cell %d has %d vertices and %d polygon faces (limits %d / %d levels)", c,
+                    nvc, npoly, gvof::kMaxCellVerts, gvof::kMaxLevels);
       return fail(nullptr, GVOF_E_LIMIT, "cell %d has %d faces (the isosurface reconstructions take at most %d)", c,
                   nfc, gvof::kMaxIsoFaces);
     }
-    cv.insert(cv.end(), tmp.begin(), tmp.end());
-    m->cv_ptr[c + 1] = (int)cv.size();
   }
-  m->cv_idx.swap(cv);
   // vertex -> cells (ascending)
   m->vc_ptr.assign(nv + 1, 0);
   for (int v : m->cv_idx) m->vc_ptr[v + 1]++;
@@ -267,28 +338,33 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
       return fail(nullptr, GVOF_E_MESH, "vertex %d belongs to no cell", v);
     }
   // vertex-sharing neighbours (ascending, itself excluded)
-  m->nb_ptr.assign(nc + 1, 0);
-  std::vector<int> nb;
-  nb.reserve((size_t)nc * 27);
-  for (int c = 0; c < nc; ++c) {
-    tmp.clear();
-    for (int i = m->cv_ptr[c]; i < m->cv_ptr[c + 1]; ++i) {
-      int v = m->cv_idx[i];
-      for (int j = m->vc_ptr[v]; j < m->vc_ptr[v + 1]; ++j)
-        if (m->vc_idx[j] != c) tmp.push_back(m->vc_idx[j]);
-    }
-    std::sort(tmp.begin(), tmp.end());
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    if ((int)tmp.size() > gvof::kMaxNeighbours) {
+  {
+    int bad = -1;
+    const int e = per_cell_lists(nc, m->nb_ptr, m->nb_idx, bad, [&](int c, std::vector<int>& tmp) {
+      for (int i = m->cv_ptr[c]; i < m->cv_ptr[c + 1]; ++i) {
+        const int v = m->cv_idx[i];
+        for (int j = m->vc_ptr[v]; j < m->vc_ptr[v + 1]; ++j)
+          if (m->vc_idx[j] != c) tmp.push_back(m->vc_idx[j]);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      return (int)tmp.size() > gvof::kMaxNeighbours ? 1 : 0;
+    });
+    if (e) {
+      const int c = bad;
+      std::vector<int> tmp;
+      for (int i = m->cv_ptr[c]; i < m->cv_ptr[c + 1]; ++i) {
+        const int v = m->cv_idx[i];
+        for (int j = m->vc_ptr[v]; j < m->vc_ptr[v + 1]; ++j)
+          if (m->vc_idx[j] != c) tmp.push_back(m->vc_idx[j]);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      const long n = std::unique(tmp.begin(), tmp.end()) - tmp.begin();
       delete m;
-      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %zu vertex neighbours (limit %d)", c, tmp.size(),
-                  gvof::kMaxNeighbours);
+      return fail(nullptr, GVOF_E_LIMIT, "cell %d has %ld vertex neighbours (limit %d)", c, n, gvof::kMaxNeighbours);
     }
-    m->max_nb = std::max(m->max_nb, (int)tmp.size());
-    nb.insert(nb.end(), tmp.begin(), tmp.end());
-    m->nb_ptr[c + 1] = (int)nb.size();
+    for (int c = 0; c < nc; ++c) m->max_nb = std::max(m->max_nb, m->nb_ptr[c + 1] - m->nb_ptr[c]);
   }
-  m->nb_idx.swap(nb);
   m->voff = {0, nv};
   m->foff = {0, nf};
   m->coff = {0, nc};
@@ -306,54 +382,60 @@ int gvof_mesh_create(gvof_mesh** out, int32_t nv, const double* vx, const double
 static void cell_counts(gvof_mesh* m) {
   m->cell_np.assign(m->nc, 0);
   m->tri_off.assign(m->nc + 1, 0);
-  for (int c = 0; c < m->nc; ++c) {
-    int np = 0;
-    bool tri_only = true;
-    for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
-      int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
-      int k = m->fv_ptr[f + 1] - m->fv_ptr[f];
-      np += k == 3 ? 1 : k;
-      tri_only = tri_only && k == 3;
+  // per cell: its surface triangles, whether it is bounded by triangles only, and whether it is a box cell
+  // (the box test of the geometry kernel: 8 vertices, 6 quadrilateral faces, every vertex a corner of the
+  // enclosing box); the counts of general-cell faces are summed per range, then over the ranges
+  std::vector<long> gen(16, 0);
+  parallel_ranges(m->nc, [&](int c0, int c1, int t) {
+    long gf = 0;
+    for (int c = c0; c < c1; ++c) {
+      int np = 0;
+      bool tri_only = true;
+      for (int i = m->cf_ptr[c]; i < m->cf_ptr[c + 1]; ++i) {
+        int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
+        int k = m->fv_ptr[f + 1] - m->fv_ptr[f];
+        np += k == 3 ? 1 : k;
+        tri_only = tri_only && k == 3;
+      }
+      m->cell_np[c] = (short)np;
+      m->tri_off[c + 1] = tri_only ? np : 0;  // the counts; the offsets follow below
+      const int vb = m->cv_ptr[c], vn = m->cv_ptr[c + 1] - vb;
+      const int fb = m->cf_ptr[c], fn = m->cf_ptr[c + 1] - fb;
+      bool box = vn == 8 && fn == 6;
+      for (int i = fb; box && i < fb + fn; ++i) {
+        const int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
+        box = m->fv_ptr[f + 1] - m->fv_ptr[f] == 4;
+      }
+      if (box) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = vb; i < vb + vn; ++i) {
+          const int v = m->cv_idx[i];
+          const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p[a]);
+            hi[a] = std::max(hi[a], p[a]);
+          }
+        }
+        int mask = 0;
+        for (int i = vb; box && i < vb + vn; ++i) {
+          const int v = m->cv_idx[i];
+          const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
+          int bit = 0;
+          for (int a = 0; a < 3; ++a) {
+            if (p[a] != lo[a] && p[a] != hi[a]) box = false;
+            bit |= (p[a] == hi[a] ? 1 : 0) << a;
+          }
+          mask |= 1 << bit;
+        }
+        box = box && mask == 255 && lo[0] < hi[0] && lo[1] < hi[1] && lo[2] < hi[2];
+      }
+      if (!box) gf += fn;
     }
-    m->cell_np[c] = (short)np;
-    m->tri_off[c + 1] = m->tri_off[c] + (tri_only ? np : 0);
-  }
-  // faces of general cells (the box test of the geometry kernel: 8 vertices,
-  // 6 quadrilateral faces, every vertex a corner of the enclosing box)
+    gen[t] = gf;
+  });
+  for (int c = 0; c < m->nc; ++c) m->tri_off[c + 1] += m->tri_off[c];
   m->gen_faces = 0;
-  for (int c = 0; c < m->nc; ++c) {
-    const int vb = m->cv_ptr[c], vn = m->cv_ptr[c + 1] - vb;
-    const int fb = m->cf_ptr[c], fn = m->cf_ptr[c + 1] - fb;
-    bool box = vn == 8 && fn == 6;
-    for (int i = fb; box && i < fb + fn; ++i) {
-      const int e = m->cf_idx[i], f = e >= 0 ? e : ~e;
-      box = m->fv_ptr[f + 1] - m->fv_ptr[f] == 4;
-    }
-    if (box) {
-      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-      for (int i = vb; i < vb + vn; ++i) {
-        const int v = m->cv_idx[i];
-        const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
-        for (int a = 0; a < 3; ++a) {
-          lo[a] = std::min(lo[a], p[a]);
-          hi[a] = std::max(hi[a], p[a]);
-        }
-      }
-      int mask = 0;
-      for (int i = vb; box && i < vb + vn; ++i) {
-        const int v = m->cv_idx[i];
-        const double p[3] = {m->vx[v], m->vy[v], m->vz[v]};
-        int bit = 0;
-        for (int a = 0; a < 3; ++a) {
-          if (p[a] != lo[a] && p[a] != hi[a]) box = false;
-          bit |= (p[a] == hi[a] ? 1 : 0) << a;
-        }
-        mask |= 1 << bit;
-      }
-      box = box && mask == 255 && lo[0] < hi[0] && lo[1] < hi[1] && lo[2] < hi[2];
-    }
-    if (!box) m->gen_faces += fn;
-  }
+  for (long g : gen) m->gen_faces += g;
 }
 
 // ------------------------------------------------------------------ workspace layout
