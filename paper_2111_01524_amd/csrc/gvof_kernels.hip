@@ -1469,12 +1469,19 @@ struct RunLds {
   double tp[kRunTets][16];  // inward face planes: normals n0..n3, then offsets d0..d3
   double tb[kRunTets][6];   // box: lo, hi
   unsigned short list[kRunTets * kRunLanes];  // flux tet << 8 | 32 if negatively oriented | surface tetrahedron
-  unsigned short code[kRunTets * kRunLanes];  // survivor: 0x8000 | unit word (cut mask, first-cut width)
-  unsigned char rank[kRunTets * kRunLanes];   // survivor's place among its pair's units
+  unsigned char code[kRunTets * kRunLanes];   // survivor's unit word (cut mask, first-cut width, direction)
   double tsc[kRunTets][4];  // distances of the cell's vertex mean from each flux tet's face planes
   int seg[kRunTets + 1];                      // start of each flux tet's part of the list
-  int off[kRunTets];                          // each pair's first unit within the run's range
+  // survivors of the list's entries 32 j .. 32 j + 31 (bit per entry), and how many survive before them;
+  // one word past the list's end holds no survivor
+  unsigned keep[kRunTets + 1];
+  int before[kRunTets + 1];
 };
+// Survivors among the first x entries of a run's list.
+__device__ inline int run_survivors_before(const RunLds& S, int x) {
+  const int j = x / kRunLanes, b = x % kRunLanes;
+  return S.before[j] + __popc(S.keep[j] & ((1u << b) - 1u));
+}
 __device__ inline Tet run_tet(const RunLds& S, int t) {
   const double* v = S.tv[t];
   return Tet{mk3(v[0], v[1], v[2]), mk3(v[3], v[4], v[5]), mk3(v[6], v[7], v[8]), mk3(v[9], v[10], v[11])};
@@ -1716,31 +1723,42 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
         }
         if (sub == 0) S.seg[Rc] = ncombo;
         wave_lds_sync();
-        // plane tests, one entry per lane
-        for (int c = sub; c < ncombo; c += kRunLanes) {
-          const unsigned e = S.list[c];
-          const int t = (int)(e >> 8), p = (int)(e & 31u);
-          d3 q0, q1, q2;
-          sigma(p, q0, q1, q2);
-          unsigned cm;
-          S.code[c] = run_unit_rule(S, t, (e & 32u) != 0u, cc, q0, q1, q2, cm) ? (unsigned short)(0x8000u | cm)
-                                                                            : (unsigned short)0;
+        // plane tests, one entry per lane, 32 entries a round; each round's survivors as a bit word, and
+        // the count of survivors before it
+        const int nw = (ncombo + kRunLanes - 1) / kRunLanes;
+        int total = 0;
+        for (int j = 0; j < nw; ++j) {
+          const int c = j * kRunLanes + sub;
+          bool keep = false;
+          if (c < ncombo) {
+            const unsigned e = S.list[c];
+            const int t = (int)(e >> 8), p = (int)(e & 31u);
+            d3 q0, q1, q2;
+            sigma(p, q0, q1, q2);
+            unsigned cm;
+            keep = run_unit_rule(S, t, (e & 32u) != 0u, cc, q0, q1, q2, cm);
+            S.code[c] = (unsigned char)cm;
+          }
+          const unsigned kw = (unsigned)((__ballot(keep) & gmask) >> gbase);
+          if (sub == 0) {
+            S.keep[j] = kw;
+            S.before[j] = total;
+          }
+          total += __popc(kw);
+        }
+        if (sub == 0) {
+          S.keep[nw] = 0u;
+          S.before[nw] = total;
         }
         wave_lds_sync();
-        // each pair's survivors: their count and places, then the run's range
-        int cnt = 0;
+        // the run's units are its survivors in list order (flux tet by flux tet, each in surface order), so a
+        // survivor's unit is the run's first plus the survivors before it, and a pair's units start at the
+        // survivors before its part of the list
+        int first = 0, cnt = 0;
         if (sub < Rc) {
-          for (int c = S.seg[sub]; c < S.seg[sub + 1]; ++c)
-            if (S.code[c] & 0x8000u) S.rank[c] = (unsigned char)cnt++;
+          first = run_survivors_before(S, S.seg[sub]);
+          cnt = run_survivors_before(S, S.seg[sub + 1]) - first;
         }
-        int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < kRunLanes; o <<= 1) {
-          const int v = __shfl_up(incl, o, kRunLanes);
-          if (sub >= o) incl += v;
-        }
-        const int total = __shfl(incl, kRunLanes - 1, kRunLanes);
-        if (sub < Rc) S.off[sub] = incl - cnt;
         int ub = 0;
         if (sub == 0 && total > 0) {
           const int o = s_pool >= 0 ? atomicAdd(&s_pool_used, total) : kRunPool;
@@ -1764,20 +1782,20 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
             M.item_ucnt[i] = -1;
             M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
           } else {
-            M.item_uoff[i] = ub + (incl - cnt);
+            M.item_uoff[i] = ub + first;
             M.item_ucnt[i] = cnt;
           }
         }
         wave_lds_sync();
         if (ub >= 0) {
-          for (int c = sub; c < ncombo; c += kRunLanes) {
-            const unsigned code = S.code[c];
-            if (code & 0x8000u) {
+          for (int j = 0; j < nw; ++j) {
+            const unsigned kw = S.keep[j];
+            if ((kw >> sub) & 1u) {
+              const int c = j * kRunLanes + sub;
               const unsigned e = S.list[c];
-              const int t = (int)(e >> 8);
-              const int u = ub + S.off[t] + S.rank[c];
-              M.unit_item[u] = i0 + c0 + t;
-              M.unit_code[u] = (e & 31u) | ((code & 0x7fffu) << 16);
+              const int u = ub + S.before[j] + __popc(kw & ((1u << sub) - 1u));
+              M.unit_item[u] = i0 + c0 + (int)(e >> 8);
+              M.unit_code[u] = (e & 31u) | ((unsigned)S.code[c] << 16);
             }
           }
         }
