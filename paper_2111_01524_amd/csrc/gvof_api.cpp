@@ -487,6 +487,7 @@ size_t carve(gvof_mesh* m, char* base, DevMesh* dm) {
   d.vc_den = C.take<double>(nv);
   d.nb_ptr = C.take<int>(nc + 1);
   d.nb_idx = C.take<int>(std::max<size_t>(m->nb_idx.size(), 1));
+  d.face_nb = C.take<int4>(nf);
   d.cell_np = C.take<short>(nc);
   d.tri_off = C.take<int>(nc + 1);
   d.tri_xyz = C.take<double>(9 * std::max<size_t>(m->tri_off.empty() ? 0 : m->tri_off.back(), 1));

@@ -33,6 +33,9 @@ struct DevMesh {
   const int *vc_ptr, *vc_idx;  // vertex -> cells ascending
   double *vc_w, *vc_den;       // node-value weights per vertex-cell entry, and their sum per vertex (set at bind)
   const int *nb_ptr, *nb_idx;  // cell -> vertex-sharing cells ascending (itself excluded)
+  // per face (set at bind): where the owner's and the neighbour's lists lie in nb_idx, as
+  // (owner's first, owner's count, neighbour's first, neighbour's count); 0, 0 for a boundary face's neighbour
+  int4* face_nb;
   const short* cell_np;        // surface triangles of each cell (triangles as they are, polygons fanned)
   // surface triangles of the cells bounded by triangles only, in the order and
   // orientation face_triangle gives them: cell c's are triangles

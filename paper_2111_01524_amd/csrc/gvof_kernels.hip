@@ -93,6 +93,12 @@ __global__ void k_face_geom(DevMesh M) {
     M.Sx[f] = 0.5 * A.x;
     M.Sy[f] = 0.5 * A.y;
     M.Sz[f] = 0.5 * A.z;
+    // the owner's and the neighbour's vertex-neighbour lists, so that the staging kernel finds them with
+    // one load indexed by the face
+    const int o = M.owner[f], nb = M.neigh[f];
+    const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
+    const int nbb = nb >= 0 ? M.nb_ptr[nb] : 0, nbn = nb >= 0 ? M.nb_ptr[nb + 1] - nbb : 0;
+    M.face_nb[f] = make_int4(ob, on, nbb, nbn);
   }
 }
 
@@ -926,10 +932,14 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     const d3 c = mk3(M.fcx[f], M.fcy[f], M.fcz[f]);
     const d3 Sv = mk3(M.Sx[f], M.Sy[f], M.Sz[f]);
     const double vd = M.Vd[f];
-    const int nbs = nbr >= 0 ? nbr : o;
-    const int ob = M.nb_ptr[o], on = M.nb_ptr[o + 1] - ob;
-    const int nbb0 = M.nb_ptr[nbs], nbn0 = M.nb_ptr[nbs + 1] - nbb0;
-    const int nbb = nbr >= 0 ? nbb0 : 0, nbn = nbr >= 0 ? nbn0 : 0;
+    const int4 fnb = M.face_nb[f];
+    const int ob = fnb.x, on = fnb.y, nbb = fnb.z, nbn = fnb.w;
+    // the face's problem: its step (face_dt) and its domain's box (for the coverage test), loaded here with
+    // the face's other data rather than behind the polyhedron's LDS phases
+    const int pid = problem_of(M, M.face_pid, f);
+    const double fdt = M.prob_dt ? M.prob_dt[pid] : dt;
+    const double* db = M.dom_box + 6 * pid;
+    const d3 dlo = mk3(db[0], db[1], db[2]), dhi = mk3(db[3], db[4], db[5]);
     const int L = 1 + on + (nbr >= 0 ? 1 + nbn : 0);
     // listed cells j = sub + G r (r < NR); lanes past the list read the owner
     int kq[NR];
@@ -976,7 +986,6 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       S.cbox[j] = bq[r];
     }
     constexpr bool em = METHOD == kEMFPA, nm = METHOD == kNMFPA;
-    const double fdt = face_dt(M, f, dt);
     if (em || nm) {  // the lane holding x_i, u_i moves it back (EMFPA: then the centres)
       if (sub < I) {
         const d3 b = mk3(x.x - fdt * u.x, x.y - fdt * u.y, x.z - fdt * u.z);
@@ -1007,7 +1016,7 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     // coverage: every point of the polyhedron in the box of a listed cell
     // (lanes past the list hold the owner, itself listed)
     const int npt = slot_points(METHOD, I);
-    unsigned cov = outside_bits(M, S, f, I, npt, c);
+    unsigned cov = ~cover_bits(S, I, npt, c, dlo, dhi);  // points outside the domain's box need no cell
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int j = sub + G * r;
@@ -1327,6 +1336,9 @@ __device__ inline int cell_piece_count(const DevMesh& M, int k) { return M.cell_
 // planes that cut the flux tet, bit 16 + kUnitWideBit set when the first of
 // those cuts keeps three tetrahedra.
 __device__ inline unsigned unit_mask(unsigned code) { return (code >> 16) & 15u; }
+// A pair's unit count carries this bit when its flux tet is negatively oriented (the sign of the pair's
+// sum), so the per-pair sum needs no second look at the tet.
+constexpr int kUcntNeg = 1 << 30;
 
 template <int LPP>
 __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
@@ -1349,7 +1361,8 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
     const int np = cell_piece_count(M, k);
     const bool tri_only = np == cf_count(M, k);
     const TetCont Tc = tet_container(T.p0, T.p1, T.p2, T.p3);
-    const bool live = tet6(T) != 0.0;  // a flat flux tet has no units
+    const double sT = tet6(T);
+    const bool live = sT != 0.0;  // a flat flux tet has no units
     double sc[4];
     apex_dists(Tc, cc, sc);
     // test of surface tetrahedron p against T: keep, and the mask of its planes that cut T
@@ -1379,7 +1392,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
           M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
         } else {
           M.item_uoff[i] = base;
-          M.item_ucnt[i] = count;
+          M.item_ucnt[i] = count | (sT < 0.0 ? kUcntNeg : 0);
         }
       }
       return base;
@@ -1667,7 +1680,7 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
       for (int c0 = 0; c0 < R; c0 += kRunTets) {
         const int Rc = min(kRunTets, R - c0);
         // the run's flux tets, staged in steps so that few values are live at once
-        bool dead = true;
+        bool dead = true, negt = false;
         if (sub < Rc) {
           const int lt = li0 - b + c0 + sub;
           const Tet T = staged_tet(M, sl, lt < kRunChunk ? (unsigned)s_tm[lt] : (unsigned)M.item_tm[i0 + c0 + sub]);
@@ -1677,7 +1690,9 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
           v[6] = T.p2.x; v[7] = T.p2.y; v[8] = T.p2.z; v[9] = T.p3.x; v[10] = T.p3.y; v[11] = T.p3.z;
           double* bx = S.tb[sub];
           bx[0] = tlo.x; bx[1] = tlo.y; bx[2] = tlo.z; bx[3] = thi.x; bx[4] = thi.y; bx[5] = thi.z;
-          dead = tet6(T) == 0.0;
+          const double sT = tet6(T);
+          dead = sT == 0.0;
+          negt = sT < 0.0;
         }
         wave_lds_sync();
         if (sub < Rc) {  // face planes, as tet_container computes them, one at a time
@@ -1783,7 +1798,7 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
             M.list_deep[atomicAdd(&M.counters[CNT_DEEP], 1)] = i;
           } else {
             M.item_uoff[i] = ub + first;
-            M.item_ucnt[i] = cnt;
+            M.item_ucnt[i] = cnt | (negt ? kUcntNeg : 0);
           }
         }
         wave_lds_sync();
@@ -1970,11 +1985,10 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
     const int i = r * rsize + li;
     const int k = M.item_cell[i];
     if (M.isbox[k]) continue;
-    const int cnt = M.item_ucnt[i];
-    if (cnt < 0) continue;  // deferred
-    // the flux tet (for its sign) first, then the units eight at a time,
-    // loads in flight together and added in order
-    const Tet T = staged_tet(M, M.item_slot[i], M.item_tm[i]);
+    const int cw = M.item_ucnt[i];
+    if (cw < 0) continue;  // deferred
+    const int cnt = cw & (kUcntNeg - 1);
+    // the units eight at a time, loads in flight together and added in order
     const double* v = M.unit_vol + M.item_uoff[i];
     double acc = 0.0;
     int q = 0;
@@ -1986,7 +2000,7 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
       for (int j = 0; j < 8; ++j) acc += t[j];
     }
     for (; q < cnt; ++q) acc += v[q];
-    M.item_vol[i] = tet6(T) < 0.0 ? -acc : acc;
+    M.item_vol[i] = (cw & kUcntNeg) ? -acc : acc;
   }
 }
 
