@@ -346,6 +346,8 @@ int gvof_graph_launch(gvof_mesh* m);
  *                           at least 256); faces and pairs that do not fit are computed by the overflow and
  *                           deferred kernels, with the same values.  Not tuned by gvof_autotune.
  *   prep_lanes              lanes per face in the staging kernel (64: one face per wavefront, 32: two)
+ *   units_rank              general-cell units ranked by their work together per thread of the unit kernel
+ *                           (4 or 8: blocks of 256 threads rank 1024 or 2048 units at a time)
  */
 typedef struct gvof_launch_config {
   int32_t sweep_threads;
@@ -356,6 +358,7 @@ typedef struct gvof_launch_config {
   int32_t staged_faces;
   int32_t staged_pairs;
   int32_t prep_lanes;
+  int32_t units_rank;
 } gvof_launch_config;
 int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c);
 int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c);

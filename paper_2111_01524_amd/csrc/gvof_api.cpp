@@ -1131,6 +1131,7 @@ static void cfg_out(const gvof::LaunchCfg& c, gvof_launch_config* o) {
   o->staged_faces = c.staged_faces;
   o->staged_pairs = c.staged_pairs;
   o->prep_lanes = c.prep_lanes;
+  o->units_rank = c.units_rank;
 }
 
 int gvof_get_launch_config(const gvof_mesh* m, gvof_launch_config* c) {
@@ -1156,6 +1157,8 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
   if (c->staged_pairs < 0) return fail(m, GVOF_E_ARG, "staged_pairs=%d (>= 0)", c->staged_pairs);
   if (c->prep_lanes != 32 && c->prep_lanes != 64)
     return fail(m, GVOF_E_ARG, "prep_lanes=%d (32 or 64)", c->prep_lanes);
+  if (c->units_rank != 4 && c->units_rank != 8)
+    return fail(m, GVOF_E_ARG, "units_rank=%d (4 or 8)", c->units_rank);
   m->cfg.sweep_threads = c->sweep_threads;
   m->cfg.recon_threads = c->recon_threads;
   m->cfg.prep_blocks = c->prep_blocks;
@@ -1164,6 +1167,7 @@ int gvof_set_launch_config(gvof_mesh* m, const gvof_launch_config* c) {
   m->cfg.staged_faces = c->staged_faces;
   m->cfg.staged_pairs = c->staged_pairs;
   m->cfg.prep_lanes = c->prep_lanes;
+  m->cfg.units_rank = c->units_rank;
   drop_graph(m);
   return GVOF_OK;
 }
@@ -1219,6 +1223,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   const int sweep[] = {128, 256, 512, 1024};
   const int recon[] = {64, 128};
   const int plan[] = {64, 32};
+  const int urank[] = {4, 8};
   auto sweep_param = [&](int gvof::LaunchCfg::*field, const int* vals, int nvals) -> int {
     for (int i = 0; i < nvals; ++i) {
       if (cur.*field == vals[i]) continue;
@@ -1238,6 +1243,7 @@ int gvof_autotune(gvof_mesh* m, const double* u_face, const double* u_vert, cons
   if ((r = sweep_param(&gvof::LaunchCfg::prep_blocks, prep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::pair_blocks_per_region, pbr, 5))) return r;
   if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::filter_lanes, lanes, 5))) return r;
+  if (!m->dm.all_box && (r = sweep_param(&gvof::LaunchCfg::units_rank, urank, 2))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::sweep_threads, sweep, 4))) return r;
   if ((r = sweep_param(&gvof::LaunchCfg::recon_threads, recon, 2))) return r;
   m->cfg = cur;

@@ -1831,16 +1831,20 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
 // distorted-grid workload) go to a list for k_flux_gen_units_deep, which runs
 // the same register clip one level deeper (so every unit has one value
 // whichever kernel computes it).
-constexpr int kUnitsPerThread = 4;  // units ranked together per block: kItemsBlock x this
+// kUnitsPerThread units per thread are ranked together (a launch shape: 4 or 8,
+// kItemsBlock x this units a block pass; a wider window gives more wavefronts
+// of one kind where the units are mixed, as in a batch of many problems, at
+// the cost of longer passes).
+template <int kUnitsPerThread>
 __global__ __launch_bounds__(kItemsBlock) void k_flux_gen_units(DevMesh M) {
   // As in the box-pair kernel, each block ranks its units by their work (the
   // number of cutting planes, 0..3, and whether the cell's interface cuts the
-  // leaves) before clipping, so that most wavefronts run one kind of unit;
-  // kUnitsPerThread units per thread are ranked together.  The ranking pass
-  // also loads what the clip needs of each unit's pair (cell, polyhedron
-  // slot, tetrahedron word, the cell's cached surface triangles), for its
-  // kUnitsPerThread units at once, and keeps it with the rank in LDS: the
-  // clip then waits for one round of loads instead of three in a row.
+  // leaves) before clipping, so that most wavefronts run one kind of unit.
+  // The ranking pass also loads what the clip needs of each unit's pair
+  // (cell, polyhedron slot, tetrahedron word, the cell's cached surface
+  // triangles), for its kUnitsPerThread units at once, and keeps it with the
+  // rank in LDS: the clip then waits for one round of loads instead of three
+  // in a row.
   constexpr int NCLS = 14;  // none; then per cut count 1..3, first cut keeping one or three; x interface
   constexpr int CHUNK = kItemsBlock * kUnitsPerThread;
   constexpr int VW = CHUNK / 64;
@@ -3193,7 +3197,8 @@ hipError_t launch_advect(const DevMesh& M0, const double* uf, const double* uv, 
     else if (L.filter_lanes == 16) TIMED(K_FLUX_GEN, (k_flux_gen_filter<16><<<pair_grid, 256, 0, s>>>(M)));
     else if (L.filter_lanes == 64) TIMED(K_FLUX_GEN, (k_flux_gen_filter<64><<<pair_grid, 256, 0, s>>>(M)));
     else TIMED(K_FLUX_GEN, (k_flux_gen_filter<32><<<pair_grid, 256, 0, s>>>(M)));
-    TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<<<pair_grid, kItemsBlock, 0, s>>>(M)));
+    if (L.units_rank == 8) TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<8><<<pair_grid, kItemsBlock, 0, s>>>(M)));
+    else TIMED(K_FLUX_GEN_UNITS, (k_flux_gen_units<4><<<pair_grid, kItemsBlock, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_UDEEP, (k_flux_gen_units_deep<<<1024, 256, 0, s>>>(M)));
     TIMED(K_FLUX_GEN_SUM, (k_flux_gen_sum<<<pair_grid, 256, 0, s>>>(M)));
   }

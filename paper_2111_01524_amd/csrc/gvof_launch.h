@@ -20,7 +20,8 @@ struct Prof {
 // kernels, lanes per pair of the general-cell filter, the most faces and
 // (face, cell, flux tet) pairs staged per step (0: as many as the workspace
 // holds; what does not fit goes to the overflow and deferred kernels, which
-// give the same values), and lanes per face of the staging kernel.
+// give the same values), lanes per face of the staging kernel, and units
+// ranked together per thread of the general-cell unit kernel.
 struct LaunchCfg {
   int sweep_threads = 256;
   int recon_threads = 128;
@@ -30,6 +31,7 @@ struct LaunchCfg {
   int staged_faces = 0;
   int staged_pairs = 0;
   int prep_lanes = 64;
+  int units_rank = 4;  // general-cell units ranked together per thread of the unit kernel (4 or 8)
 };
 hipError_t launch_zero(int* p, int n, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& M, hipStream_t s);

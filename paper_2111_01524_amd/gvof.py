@@ -45,7 +45,7 @@ class gvof_shape(C.Structure):
 class gvof_launch_config(C.Structure):
     _fields_ = [("sweep_threads", C.c_int32), ("recon_threads", C.c_int32), ("prep_blocks", C.c_int32),
                 ("pair_blocks_per_region", C.c_int32), ("filter_lanes", C.c_int32), ("staged_faces", C.c_int32),
-                ("staged_pairs", C.c_int32), ("prep_lanes", C.c_int32)]
+                ("staged_pairs", C.c_int32), ("prep_lanes", C.c_int32), ("units_rank", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -161,17 +161,17 @@ def test_launch_config_validation_without_gpu():
         c = gvof.gvof_get_launch_config(h)
         assert c.as_dict() == dict(sweep_threads=256, recon_threads=128, prep_blocks=16384,
                                    pair_blocks_per_region=16, filter_lanes=0, staged_faces=0,
-                                   staged_pairs=0, prep_lanes=64)
+                                   staged_pairs=0, prep_lanes=64, units_rank=4)
         for bad in (dict(sweep_threads=96), dict(recon_threads=256), dict(prep_blocks=0),
                     dict(pair_blocks_per_region=300), dict(filter_lanes=12), dict(staged_faces=-1),
-                    dict(staged_pairs=-1), dict(prep_lanes=16)):
+                    dict(staged_pairs=-1), dict(prep_lanes=16), dict(units_rank=6)):
             d = c.as_dict()
             d.update(bad)
             with pytest.raises(gvof.GvofError):
                 gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
         d = c.as_dict()
-        for fl in (64, 8, 0):  # the per-pair filter's lane counts and 0, the runs filter
-            d.update(sweep_threads=512, filter_lanes=fl, prep_lanes=32)
+        for fl, ur in ((64, 8), (8, 4), (0, 8)):  # the per-pair filter's lane counts and 0, the runs filter
+            d.update(sweep_threads=512, filter_lanes=fl, prep_lanes=32, units_rank=ur)
             gvof.gvof_set_launch_config(h, gvof.gvof_launch_config(**d))
             assert gvof.gvof_get_launch_config(h).as_dict() == d
         with pytest.raises(gvof.GvofError):  # not bound

@@ -157,22 +157,22 @@ def test_launch_shapes_do_not_change_results(gv, method):
     # limits that make regions of the pair and unit buffers overflow (those faces and pairs are
     # computed by the overflow and deferred kernels)
     for odd in (dict(sweep_threads=64, recon_threads=64, prep_blocks=3, pair_blocks_per_region=1, filter_lanes=16,
-                     staged_faces=0, staged_pairs=0, prep_lanes=32),
+                     staged_faces=0, staged_pairs=0, prep_lanes=32, units_rank=8),
                 dict(sweep_threads=1024, recon_threads=128, prep_blocks=100, pair_blocks_per_region=64,
-                     filter_lanes=64, staged_faces=7, staged_pairs=0, prep_lanes=64),
+                     filter_lanes=64, staged_faces=7, staged_pairs=0, prep_lanes=64, units_rank=4),
                 dict(sweep_threads=256, recon_threads=128, prep_blocks=16384, pair_blocks_per_region=16,
-                     filter_lanes=8, staged_faces=0, staged_pairs=256 * 20, prep_lanes=32),
+                     filter_lanes=8, staged_faces=0, staged_pairs=256 * 20, prep_lanes=32, units_rank=8),
                 dict(sweep_threads=512, recon_threads=64, prep_blocks=4096, pair_blocks_per_region=8,
-                     filter_lanes=16, staged_faces=0, staged_pairs=256 * 60, prep_lanes=64),
+                     filter_lanes=16, staged_faces=0, staged_pairs=256 * 60, prep_lanes=64, units_rank=4),
                 dict(sweep_threads=256, recon_threads=64, prep_blocks=7, pair_blocks_per_region=4,
-                     filter_lanes=32, staged_faces=0, staged_pairs=0, prep_lanes=32)):
+                     filter_lanes=32, staged_faces=0, staged_pairs=0, prep_lanes=32, units_rank=8)):
         gv.gvof_set_launch_config(B.h, gv.gvof_launch_config(**odd))
         F2 = to_dev(torch, dev, F0)
         B.step(uf, uv, dt, act, F2)
         log(f"{odd}: max diff {max_abs(host(F2), F_tuned):.3g}")
         assert np.array_equal(host(F2), F_tuned), odd
     with pytest.raises(gv.GvofError):
-        gv.gvof_set_launch_config(B.h, gv.gvof_launch_config(100, 64, 3, 1, 16, 0, 0, 64))
+        gv.gvof_set_launch_config(B.h, gv.gvof_launch_config(100, 64, 3, 1, 16, 0, 0, 64, 4))
     B.status()
 
 

@@ -128,11 +128,12 @@ def test_full_size_distorted_mid_trajectory_launch_shapes(oracle_mod):
     F1, Vd, VF, up, bad = om.advect(pl, tc, tf, uf, uv, dteff[s_mid], Fc)
     assert bad == 0
     log(f"oracle step {s_mid}: tag-0 cells {(tc == 0).sum()} faces {(tf == 0).sum()}")
-    default = gvof.gvof_launch_config(256, 128, 16384, 16, 32, 0, 0, 64).as_dict()
+    default = gvof.gvof_launch_config(256, 128, 16384, 16, 32, 0, 0, 64, 4).as_dict()
     shapes = [("autotuned", tuned), ("defaults", default),
               ("staging limits", dict(tuned, staged_faces=20000, staged_pairs=256 * 2000)),
               ("tight pair buffer", dict(default, staged_pairs=256 * 200, filter_lanes=16, prep_lanes=32)),
-              ("runs filter", dict(default, filter_lanes=0)), ("per-pair filter, 8 lanes", dict(tuned, filter_lanes=8))]
+              ("runs filter", dict(default, filter_lanes=0)), ("per-pair filter, 8 lanes", dict(tuned, filter_lanes=8)),
+              ("the other unit ranking window", dict(tuned, units_rank=12 - tuned["units_rank"]))]
     first = None
     for name, cfgd in shapes:
         gvof.gvof_set_launch_config(g.h, gvof.gvof_launch_config(**cfgd))
