@@ -1185,12 +1185,14 @@ __device__ inline int region_items(const DevMesh& M, int r, int rsize) {
 // children of the first cut (one or three) and with whether the cell's
 // interface cuts the leaves, and a wavefront runs as long as its slowest
 // lane (and runs every path one of its lanes takes), so each block first
-// ranks its 256 pairs by that work in LDS (a counting sort, most work first)
+// ranks its pairs by that work in LDS (a counting sort, most work first)
 // and each thread then clips the pair at its rank: most wavefronts see pairs
 // of one kind.  Each pair's volume goes to its own slot, so the order changes
-// no result.
+// no result.  A block pass ranks 1024 pairs: where general-cell pairs share
+// the buffer (a batch of problems on both kinds of grid) only the box pairs
+// among them are clipped, and fewer would leave most lanes of the clip idle.
 constexpr int kItemsBlock = 256;
-constexpr int kItemsPerThread = 2;  // pairs ranked together per block: kItemsBlock x this
+constexpr int kItemsPerThread = 4;  // pairs ranked together per block: kItemsBlock x this
 __global__ __launch_bounds__(kItemsBlock) void k_flux_items_box(DevMesh M) {
   constexpr int CHUNK = kItemsBlock * kItemsPerThread;
   constexpr int VW = CHUNK / 64;  // the chunk as wavefront-sized runs ("virtual wavefronts")
