@@ -66,7 +66,7 @@ struct DevMesh {
   int item_cap;
   struct RegionCounters* regions;  // kItemRegions, one cache line each
   // general-cell pairs: surviving (pair, surface tetrahedron) units
-  int *item_uoff, *item_ucnt;  // per pair
+  int *item_uoff, *item_ucnt;  // per pair: first unit, unit count (-1: deferred, -2: a box-cell pair)
   int* unit_item;
   unsigned* unit_code;         // surface tetrahedron index, cutting-plane mask << 16, first-cut width bit
   int unit_cap;                // units staged per step at most (kItemRegions regions)

@@ -1355,7 +1355,10 @@ __global__ __launch_bounds__(256) void k_flux_gen_filter(DevMesh M) {
   for (int li = sub * halves + half; li < fill; li += region_blocks() * halves) {
     const int i = r * rsize + li;
     const int k = M.item_cell[i];
-    if (M.isbox[k]) continue;
+    if (M.isbox[k]) {
+      if (hl == 0) M.item_ucnt[i] = -2;  // a box-cell pair has no units: the general-pair sum skips it
+      continue;
+    }
     unsigned tm = M.item_tm[i];
     Tet T = staged_tet(M, M.item_slot[i], tm);
     const d3 cc = cell_centre(M, k);
@@ -1605,7 +1608,9 @@ __global__ __launch_bounds__(kRunBlock, 3) void k_flux_gen_runs(DevMesh M) {
         sl = M.item_slot[i];
         tm = M.item_tm[i];
         brk = li == 0 || M.item_cell[i - 1] != k || M.item_slot[i - 1] != sl;
-        head = brk && !M.isbox[k];
+        const bool box = M.any_box && M.isbox[k] != 0;
+        if (box) M.item_ucnt[i] = -2;  // a box-cell pair has no units: the general-pair sum skips it
+        head = brk && !box;
       }
       const unsigned long long bb = __ballot(brk), bh = __ballot(head);
       nh = __popcll(bh);
@@ -1999,10 +2004,8 @@ __global__ __launch_bounds__(256) void k_flux_gen_sum(DevMesh M) {
   const int fill = region_items(M, r, rsize);
   for (int li = sub * blockDim.x + threadIdx.x; li < fill; li += region_blocks() * blockDim.x) {
     const int i = r * rsize + li;
-    const int k = M.item_cell[i];
-    if (M.isbox[k]) continue;
     const int cw = M.item_ucnt[i];
-    if (cw < 0) continue;  // deferred
+    if (cw < 0) continue;  // a box-cell pair (-2) or a deferred one (-1)
     const int cnt = cw & (kUcntNeg - 1);
     // the units eight at a time, loads in flight together and added in order
     const double* v = M.unit_vol + M.item_uoff[i];
