@@ -178,6 +178,8 @@ def rooflines(kt, step_ms, counts, table, workload):
                        traffic=spec["bytes"] * units / n if fresh else None,
                        profile_avg_launch_ms=spec["avg_launch_ms"],
                        profile_units_per_launch=spec["units_per_launch"], work_source=spec["source"])
+            if "valu_issue_frac" in spec:  # the profiled run's VALU issue time over its run time (what binds it)
+                ent["profile_valu_issue_frac"] = spec["valu_issue_frac"]
         out.append(ent)
     return out
 

@@ -118,6 +118,13 @@ def calibration(run, mib):
     return nbytes / per_f, nbytes / per_w, (kf, per_f, per_w)
 
 
+# VALU issue time of a kernel: its wave64 VALU instructions at 4 cycles each (16 lanes per SIMD), over every
+# SIMD of the chip (256 compute units x 4) at the peak engine clock, against its run time
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+CYCLES_PER_VALU = 4
+
+
 def summarise(run, workload, cal, out_dir, cmds):
     res = json.load(open(os.path.join(run, f"{workload}.json")))
     K = len(res["timed_steps"])
@@ -146,15 +153,17 @@ def summarise(run, workload, cal, out_dir, cmds):
         live = issued * lanes
         hbm = fe.get(k, {}).get("FETCH_SIZE", 0.0) * cal[0] + wr.get(k, {}).get("WRITE_SIZE", 0.0) * cal[1]
         sec = ns * 1e-9
+        valu_issue = CYCLES_PER_VALU * c.get("SQ_INSTS_VALU", 0.0) / (SIMDS * CLOCK_HZ) / sec if sec else 0.0
         row = dict(kernel=k, launches=n, avg_us=ns / n / 1e3, share=ns / step_ns, fp64_issued=issued / n,
                    active_lanes=lanes, fp64_live=live / n, fp64_share=fp64_share, hbm_bytes=hbm / n,
-                   tflops_live=live / sec / 1e12 if sec else 0.0, gbs=hbm / sec / 1e9 if sec else 0.0)
+                   tflops_live=live / sec / 1e12 if sec else 0.0, gbs=hbm / sec / 1e9 if sec else 0.0,
+                   valu_issue=valu_issue)
         rows.append(row)
         u = UNIT.get(k)
         if u and units[u] > 0:
             table[k] = {"unit": u, "flops": live / units[u], "flops_issued": issued / units[u],
                         "bytes": hbm / units[u], "traffic": hbm / n, "avg_launch_ms": ns / n / 1e6,
-                        "units_per_launch": units[u] / n, "active_lanes": lanes,
+                        "units_per_launch": units[u] / n, "active_lanes": lanes, "valu_issue_frac": valu_issue,
                         "source": f"profiles/counters_{workload}.md"}
     name = f"counters_{workload}.md"
     with open(os.path.join(out_dir, name), "w") as f:
@@ -170,11 +179,12 @@ def summarise(run, workload, cal, out_dir, cmds):
                 f"+ WRITE_SIZE x {cal[1]:.1f}.\n\n")
         f.write("| kernel | launches | avg µs | share of step | FP64 lane FLOPs issued / launch | active lanes | "
                 "FP64 FLOPs of active lanes / launch | FP64 share of VALU | TFLOP/s (active) | HBM bytes / launch "
-                "| GB/s |\n|---|---|---|---|---|---|---|---|---|---|---|\n")
+                "| GB/s | VALU issue time / kernel time |\n|---|---|---|---|---|---|---|---|---|---|---|---|\n")
         for r in rows:
             f.write(f"| {r['kernel']} | {r['launches']} | {r['avg_us']:.2f} | {r['share']:.3f} | "
                     f"{r['fp64_issued']:.4g} | {r['active_lanes']:.3f} | {r['fp64_live']:.4g} | "
-                    f"{r['fp64_share']:.2f} | {r['tflops_live']:.2f} | {r['hbm_bytes']:.4g} | {r['gbs']:.0f} |\n")
+                    f"{r['fp64_share']:.2f} | {r['tflops_live']:.2f} | {r['hbm_bytes']:.4g} | {r['gbs']:.0f} | "
+                    f"{r['valu_issue']:.2f} |\n")
         f.write("\nWork per unit (what bench.py's rooflines use): FP64 FLOPs of active lanes and HBM bytes per "
                 "unit of the kernel's work.\n\n| kernel | unit | FLOPs / unit | issued FLOPs / unit | HBM bytes / "
                 "unit |\n|---|---|---|---|---|\n")

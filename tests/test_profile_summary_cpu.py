@@ -72,6 +72,8 @@ def test_summary_counts_and_definitions(run, tmp_path):
     assert e["traffic"] == pytest.approx(1000 * 2048.0 + 500 * 1024.0)
     assert e["unit"] == "interfacial_faces" and t["k_face_sweep"]["unit"] == "faces"
     assert e["avg_launch_ms"] == pytest.approx(2.0)
+    # 100 VALU instructions a launch at 4 cycles over 1024 SIMDs at 2.4 GHz, against 2 ms a launch
+    assert e["valu_issue_frac"] == pytest.approx(4 * 100 / (1024 * 2.4e9) / 2e-3)
     text = (out / "counters_jittered.md").read_text()
     rows = [ln.split("|")[1].strip() for ln in text.splitlines() if ln.startswith("| ")]
     assert "k_face_geom" not in rows and "__amd_rocclr_copyBuffer" not in rows  # set-up kernels, state copies
@@ -98,5 +100,6 @@ def test_bench_roofline_recomputes_from_the_table(run, tmp_path):
     assert r["achieved"] == pytest.approx(t["k_flux_gen_filter"]["flops"] * 50000 * K / (2.0 * K * 1e-3) / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
     assert r["traffic"] == pytest.approx(t["k_flux_gen_filter"]["traffic"])
+    assert r["profile_valu_issue_frac"] == pytest.approx(t["k_flux_gen_filter"]["valu_issue_frac"])
     table["sources_digest"] = "stale"
     assert bench.rooflines(kt, 2.26, counts, table, "jittered")[0]["traffic"] is None
