@@ -907,7 +907,7 @@ __device__ inline void write_pair(const DevMesh& M, int i, int it, int cell, uns
 // each instance's registers to its own path); vel holds the vertex
 // velocities (FMFPA, EMFPA) or the face velocities (NMFPA).
 template <int G, int METHOD>
-__global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const double* __restrict__ vel, double dt) {
+__global__ __launch_bounds__(kFluxLanes, 4) void k_flux_prep(DevMesh M, const double* __restrict__ vel, double dt) {
   static_assert(G == 32 || G == 64, "lanes per face");
   constexpr int NG = kFluxLanes / G;  // faces per wavefront
   constexpr int NR = kFluxLanes / G;  // rounds of G lanes over the first 64 listed cells
@@ -1013,14 +1013,24 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
     }
     d3 plo, phi;
     poly_box(S, I, c, plo, phi);
-    // coverage: every point of the polyhedron in the box of a listed cell
-    // (lanes past the list hold the owner, itself listed)
+    // coverage: every point of the polyhedron in the box of a listed cell, or outside the domain's box
+    // (lanes past the list hold the owner, itself listed).  The first G listed cells (the owner, its
+    // neighbours, ...) nearly always hold every point, so the other cells and the domain's box are tested
+    // only when a point is left over: the same flag, for a fraction of the tests.
     const int npt = slot_points(METHOD, I);
-    unsigned cov = ~cover_bits(S, I, npt, c, dlo, dhi);  // points outside the domain's box need no cell
+    const unsigned need = needed_bits(I, npt);
+    unsigned cov = cover_bits(S, I, npt, c, mk3(S.clox[sub], S.cloy[sub], S.cloz[sub]),
+                              mk3(S.chix[sub], S.chiy[sub], S.chiz[sub]));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int j = sub + G * r;
-      cov |= cover_bits(S, I, npt, c, mk3(S.clox[j], S.cloy[j], S.cloz[j]), mk3(S.chix[j], S.chiy[j], S.chiz[j]));
+    for (int o2 = 1; o2 < G; o2 <<= 1) cov |= __shfl_xor(cov, o2);
+    const bool covered = (cov & need) == need;  // uniform over the group
+    if (!covered) {
+#pragma unroll
+      for (int r = 1; r < NR; ++r) {
+        const int j = sub + G * r;
+        cov |= cover_bits(S, I, npt, c, mk3(S.clox[j], S.cloy[j], S.cloz[j]), mk3(S.chix[j], S.chiy[j], S.chiz[j]));
+      }
+      cov |= ~cover_bits(S, I, npt, c, dlo, dhi);  // points outside the domain's box need no cell
     }
     double* P = M.poly + (size_t)it * M.pts_per_slot * 3;
     // the points, the face centre (the flux tets' common vertex), the lateral centres
@@ -1066,9 +1076,9 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       signed char kb = 0;
       if (j < L) {
         k = candidate_cell(M, j, o, ob, on, nbr, nbb);
-        klo = mk3(M.lox[k], M.loy[k], M.loz[k]);  // every listed cell's box: the coverage test
+        klo = mk3(M.lox[k], M.loy[k], M.loz[k]);
         khi = mk3(M.hix[k], M.hiy[k], M.hiz[k]);
-        cov |= cover_bits(S, I, npt, c, klo, khi);
+        if (!covered) cov |= cover_bits(S, I, npt, c, klo, khi);  // the coverage test, if a point is left
         keep = M.tag_cell[k] != -1 && !(k == o || sorted_contains(S.onb, on, k));
         if (keep) {
           kb = M.isbox[k];
@@ -1087,9 +1097,11 @@ __global__ __launch_bounds__(kFluxLanes) void k_flux_prep(DevMesh M, const doubl
       }
       ncand += __popcll(bm);
     }
+    if (!covered) {
 #pragma unroll
-    for (int o2 = 1; o2 < G; o2 <<= 1) cov |= __shfl_xor(cov, o2);
-    if (sub == 0 && (cov & needed_bits(I, npt)) != needed_bits(I, npt)) atomicOr(&M.counters[CNT_ERR], ERR_COVER);
+      for (int o2 = 1; o2 < G; o2 <<= 1) cov |= __shfl_xor(cov, o2);
+      if (sub == 0 && (cov & need) != need) atomicOr(&M.counters[CNT_ERR], ERR_COVER);
+    }
     wave_lds_sync();
     if (ncand > kPrepCand) {
       if (sub == 0) {
